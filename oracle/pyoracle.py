@@ -1,0 +1,185 @@
+"""ctypes front end of the FP64 CPU oracle (monc_oracle.c).
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, the smoke check and the
+CPU-baseline leg of the benchmark, never by the product library.
+
+All arrays use the [(nx+4)][(ny+4)][nz] float64 layout (2-deep lateral halo,
+z fastest).  Functions return new arrays and raise on error codes.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "monc_oracle.c")
+LIB = os.path.join(HERE, "libmonc_oracle.so")
+
+OR_OK, OR_EINVAL, OR_ECFL = 0, -1, -3
+
+
+class CourantError(RuntimeError):
+    pass
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (no contraction, no fast-math)."""
+    if force or not os.path.exists(LIB):
+        cmd = ["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
+               "-std=c11", "-shared", "-fPIC", "-o", LIB + ".tmp", SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(LIB + ".tmp", LIB)
+    return LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build()
+        L = C.CDLL(LIB)
+        dp = C.POINTER(C.c_double)
+        i = C.c_int
+        d = C.c_double
+        L.oracle_halo_fill.argtypes = [dp, i, i, i]
+        L.oracle_pw.argtypes = [dp, dp, dp, dp, dp, dp, i, i, i, d, d, dp, dp, dp,
+                                i, i, i, i]
+        L.oracle_tvd.argtypes = [dp, dp, dp, dp, dp, i, i, i, d, d, dp, dp, dp, d,
+                                 i, i, i, i, dp]
+        L.oracle_ultimate_face.argtypes = [d, d, d, d]
+        L.oracle_ultimate_face.restype = d
+        L.oracle_divergence.argtypes = [dp, dp, dp, dp, i, i, i, d, d, dp, dp, dp]
+        L.oracle_step.argtypes = [C.POINTER(dp), C.POINTER(dp), i, i, i, i, d, d,
+                                  dp, dp, dp, d]
+        L.oracle_budgets.argtypes = [dp, dp, dp, dp, dp, dp, i, C.POINTER(dp),
+                                     C.POINTER(dp), i, i, i, d, d, dp, dp, dp, dp,
+                                     dp]
+        L.oracle_max_courant.argtypes = [dp, dp, dp, i, i, i, d, d, dp, d]
+        L.oracle_max_courant.restype = d
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _shape(a):
+    nx, ny, nz = a.shape
+    return nx - 4, ny - 4, nz
+
+
+def _check(rc, what):
+    if rc == OR_ECFL:
+        raise CourantError(f"{what}: Courant number above 1")
+    if rc != OR_OK:
+        raise ValueError(f"{what}: oracle returned {rc}")
+
+
+def halo_fill(f: np.ndarray) -> np.ndarray:
+    out = np.ascontiguousarray(f, dtype=np.float64).copy()
+    nx, ny, nz = _shape(out)
+    _check(lib().oracle_halo_fill(_p(out), nx, ny, nz), "halo_fill")
+    return out
+
+
+def _prof(g):
+    return (np.ascontiguousarray(g.rdz, np.float64), np.ascontiguousarray(g.rho, np.float64),
+            np.ascontiguousarray(g.rhon, np.float64))
+
+
+def pw(u, v, w, g, region=None):
+    """PW tendencies (su, sv, sw); halos of u, v, w must be valid."""
+    nx, ny, nz = _shape(u)
+    i0, i1, j0, j1 = region or (0, nx, 0, ny)
+    su, sv, sw = (np.zeros_like(u) for _ in range(3))
+    rdz, rho, rhon = _prof(g)
+    rc = lib().oracle_pw(_p(u), _p(v), _p(w), _p(su), _p(sv), _p(sw), nx, ny, nz,
+                         g.dx, g.dy, _p(rdz), _p(rho), _p(rhon), i0, i1, j0, j1)
+    _check(rc, "pw")
+    return su, sv, sw
+
+
+def tvd(u, v, w, phi, g, dt, region=None, allow_cfl=False):
+    """TVD tendency of one scalar; halos (depth 2) must be valid."""
+    nx, ny, nz = _shape(u)
+    i0, i1, j0, j1 = region or (0, nx, 0, ny)
+    s = np.zeros_like(phi)
+    rdz, rho, rhon = _prof(g)
+    cmax = C.c_double(0.0)
+    rc = lib().oracle_tvd(_p(u), _p(v), _p(w), _p(phi), _p(s), nx, ny, nz, g.dx, g.dy,
+                          _p(rdz), _p(rho), _p(rhon), float(dt), i0, i1, j0, j1,
+                          C.byref(cmax))
+    if not (allow_cfl and rc == OR_ECFL):
+        _check(rc, "tvd")
+    return s
+
+
+def ultimate_face(phiU, phiC, phiD, c):
+    return lib().oracle_ultimate_face(float(phiU), float(phiC), float(phiD), float(c))
+
+
+def divergence(u, v, w, g):
+    nx, ny, nz = _shape(u)
+    d = np.zeros_like(u)
+    rdz, rho, rhon = _prof(g)
+    _check(lib().oracle_divergence(_p(u), _p(v), _p(w), _p(d), nx, ny, nz, g.dx, g.dy,
+                                   _p(rdz), _p(rho), _p(rhon)), "divergence")
+    return d
+
+
+def step(state, g, dt, allow_cfl=False):
+    """One forward step.  state = [u, v, w, scalars...] (padded arrays).
+    Returns the new state (the inputs' halos are refreshed in place)."""
+    nx, ny, nz = _shape(state[0])
+    nscal = len(state) - 3
+    out = [np.full_like(s, np.nan) for s in state]
+    arr_in = (C.POINTER(C.c_double) * len(state))(*[_p(s) for s in state])
+    arr_out = (C.POINTER(C.c_double) * len(state))(*[_p(s) for s in out])
+    rdz, rho, rhon = _prof(g)
+    rc = lib().oracle_step(arr_in, arr_out, nscal, nx, ny, nz, g.dx, g.dy, _p(rdz),
+                           _p(rho), _p(rhon), float(dt))
+    if not (allow_cfl and rc == OR_ECFL):
+        _check(rc, "step")
+    return out
+
+
+BUDGET_NAMES = ["C_u", "C_v", "C_w", "P_u", "Q_u", "P_v", "Q_v", "P_w", "Q_w",
+                "C_w_closed"]
+
+
+def budgets(u, v, w, su, sv, sw, phis, sphis, g):
+    """Budgets of one evaluation; returns (dict of values, dict of |term| sums)."""
+    nx, ny, nz = _shape(u)
+    nscal = len(phis)
+    out = np.zeros(10 + 3 * nscal)
+    absout = np.zeros(9)
+    rdz, rho, rhon = _prof(g)
+    P = C.POINTER(C.c_double)
+    ph = (P * max(nscal, 1))(*[_p(a) for a in phis])
+    sph = (P * max(nscal, 1))(*[_p(a) for a in sphis])
+    rc = lib().oracle_budgets(_p(u), _p(v), _p(w), _p(su), _p(sv), _p(sw), nscal, ph,
+                              sph, nx, ny, nz, g.dx, g.dy, _p(rdz), _p(rho), _p(rhon),
+                              _p(out), _p(absout))
+    _check(rc, "budgets")
+    vals = {n: out[q] for q, n in enumerate(BUDGET_NAMES)}
+    for s in range(nscal):
+        vals[f"C_s{s}"] = out[10 + 3 * s]
+        vals[f"M_s{s}"] = out[10 + 3 * s + 1]
+        vals[f"min_s{s}"] = out[10 + 3 * s + 2]
+    scales = {n: absout[q] for q, n in enumerate(BUDGET_NAMES[:9])}
+    return vals, scales
+
+
+def max_courant(u, v, w, g, dt):
+    nx, ny, nz = _shape(u)
+    rdz = np.ascontiguousarray(g.rdz, np.float64)
+    return lib().oracle_max_courant(_p(u), _p(v), _p(w), nx, ny, nz, g.dx, g.dy,
+                                    _p(rdz), float(dt))

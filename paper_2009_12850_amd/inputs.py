@@ -1,0 +1,245 @@
+"""Seeded synthetic inputs for the MONC advection path.
+
+This module only draws and lays out inputs; it holds none of the advection
+arithmetic.  Both the CPU oracle (tests) and the HIP path (tests, bench) are fed
+from it, so they always see the same arrays.
+
+The paper's test case (the "tank experiment" of warm and cold bubbles,
+Sec. 4) is not available, so fields are smooth random flows of the same kind:
+each field is a normalised sum of 8 low-wavenumber modes plus small noise, on a
+vertically stretched grid with an exponential reference density.
+
+Recipe (all FP64, NumPy PCG64, fixed draw order):
+  geometry  H = 3000 m, dz_k = dz0 * 1.02**k with dz0 = H*0.02/(1.02**nz - 1);
+            z_{k+1/2} = cumulative sum of dz (top faces), zn_k = z_{k+1/2} - dz_k/2,
+            rho_k = 1.2 exp(-z_{k+1/2}/8000), rhon_k = 1.2 exp(-zn_k/8000), rdz = 1/dz.
+  modes     per field, 8 modes; each draws integer kx, ky in [-3, 3] (not both 0),
+            vertical index m in {0,1,2}, phase ~ U[0, 2pi), weight r ~ U[0.5, 1];
+            mode = r cos(2pi(kx x/Lx + ky y/Ly) + phase) Z_m(z), with
+            Z_m = cos(pi m z/H) for u, v and scalars and sin(pi (m+1) z/H) for w;
+            the sum is divided by sum(r).  Each field is evaluated at its own
+            C-grid position (u on +x faces, v on +y faces, w on top faces,
+            scalars at centres; cell centre x_i = (i+1/2) dx).
+  values    u, v, w = amp*sum + N(0, 0.01^2), then w = 0 on the lid level;
+            theta = 300 + 2*sum + N(0, 0.01^2);
+            q_n = 1e-3 exp(0.5*sum + N(0, 0.01^2))  (positive, log-normal).
+Field order is u, v, w, theta, q1, q2, ...; each field draws its modes, then its
+noise, before the next field starts.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+H_TOP = 3000.0
+STRETCH = 1.02
+
+
+@dataclasses.dataclass
+class Geometry:
+    nx: int
+    ny: int
+    nz: int
+    dx: float
+    dy: float
+    rdz: np.ndarray   # [nz] 1/dz_k
+    rho: np.ndarray   # [nz] density at the top face of cell k
+    rhon: np.ndarray  # [nz] density at the centre of cell k
+    z_face: np.ndarray  # [nz] height of the top face of cell k
+    z_centre: np.ndarray  # [nz] height of the centre of cell k
+
+
+def make_geometry(nx: int, ny: int, nz: int, dx: float = 50.0, dy: float = 50.0,
+                  height: float = H_TOP, ratio: float = STRETCH) -> Geometry:
+    """Stretched vertical grid and exponential reference density profiles."""
+    k = np.arange(nz, dtype=np.float64)
+    dz0 = height * (ratio - 1.0) / (ratio ** nz - 1.0)
+    dz = dz0 * ratio ** k
+    z_face = np.cumsum(dz)
+    z_centre = z_face - 0.5 * dz
+    rho = 1.2 * np.exp(-z_face / 8000.0)
+    rhon = 1.2 * np.exp(-z_centre / 8000.0)
+    return Geometry(nx, ny, nz, float(dx), float(dy), 1.0 / dz, rho, rhon,
+                    z_face, z_centre)
+
+
+def _draw_modes(rng: np.random.Generator, nmodes: int = 8):
+    modes = []
+    for _ in range(nmodes):
+        while True:
+            kx, ky = (int(a) for a in rng.integers(-3, 4, size=2))
+            if kx != 0 or ky != 0:
+                break
+        m = int(rng.integers(0, 3))
+        phase = float(rng.uniform(0.0, 2.0 * math.pi))
+        r = float(rng.uniform(0.5, 1.0))
+        modes.append((kx, ky, m, phase, r))
+    return modes
+
+
+def _mode_sum(g: Geometry, modes, xs: np.ndarray, ys: np.ndarray,
+              zs: np.ndarray, vertical_sine: bool) -> np.ndarray:
+    """Normalised sum of the modes at positions xs (nx), ys (ny), zs (nz)."""
+    lx, ly = g.nx * g.dx, g.ny * g.dy
+    horiz = np.empty((g.nx * g.ny, len(modes)))
+    vert = np.empty((len(modes), g.nz))
+    for n, (kx, ky, m, phase, r) in enumerate(modes):
+        ax = 2.0 * math.pi * kx * xs / lx
+        by = 2.0 * math.pi * ky * ys / ly + phase
+        # cos(a + b) = cos a cos b - sin a sin b, as an outer product
+        h = np.outer(np.cos(ax), np.cos(by)) - np.outer(np.sin(ax), np.sin(by))
+        horiz[:, n] = r * h.reshape(-1)
+        if vertical_sine:
+            vert[n] = np.sin(math.pi * (m + 1) * zs / H_TOP)
+        else:
+            vert[n] = np.cos(math.pi * m * zs / H_TOP)
+    total_r = sum(md[4] for md in modes)
+    return (horiz @ vert).reshape(g.nx, g.ny, g.nz) / total_r
+
+
+def scalar_names(nscal: int):
+    return ["th"] + [f"q{n}" for n in range(1, nscal)]
+
+
+def make_fields(g: Geometry, nscal: int, seed: int, amp: float = 5.0,
+                noise: float = 0.01) -> dict:
+    """Interior fields (nx, ny, nz) for u, v, w and nscal scalars (th, q1, ...)."""
+    rng = np.random.default_rng(seed)
+    xc = (np.arange(g.nx) + 0.5) * g.dx
+    xf = (np.arange(g.nx) + 1.0) * g.dx
+    yc = (np.arange(g.ny) + 0.5) * g.dy
+    yf = (np.arange(g.ny) + 1.0) * g.dy
+    out = {}
+    names = ["u", "v", "w"] + scalar_names(nscal)
+    for name in names:
+        modes = _draw_modes(rng)
+        if name == "u":
+            s = _mode_sum(g, modes, xf, yc, g.z_centre, False)
+        elif name == "v":
+            s = _mode_sum(g, modes, xc, yf, g.z_centre, False)
+        elif name == "w":
+            s = _mode_sum(g, modes, xc, yc, g.z_face, True)
+        else:
+            s = _mode_sum(g, modes, xc, yc, g.z_centre, False)
+        eps = rng.standard_normal(size=s.shape) * noise
+        if name in ("u", "v", "w"):
+            f = amp * s + eps
+            if name == "w":
+                f[:, :, g.nz - 1] = 0.0
+        elif name == "th":
+            f = 300.0 + 2.0 * s + eps
+        else:
+            f = 1e-3 * np.exp(0.5 * s + eps)
+        out[name] = f
+    return out
+
+
+def make_divfree_velocity(g: Geometry, seed: int, amp: float = 5.0) -> dict:
+    """u, v, w whose anelastic mass divergence vanishes to round-off.
+
+    Built from three periodic potentials on the C-grid: A (x-z, at
+    (x_{i+1/2}, y_j, z_{k+1/2})), B (y-z) and C (x-y corners), with A = B = 0
+    on the lid level so that w vanishes there and on the ground:
+        rhon_k u = -rdz_k (A_k - A_{k-1}) + rhon_k (C_j - C_{j-1})/dy
+        rhon_k v = -rdz_k (B_k - B_{k-1}) - rhon_k (C_i - C_{i-1})/dx
+        rho_k  w =  (A_i - A_{i-1})/dx + (B_j - B_{j-1})/dy,   A_{-1} = B_{-1} = 0.
+    The result is scaled so that the largest speed component equals amp.
+    """
+    rng = np.random.default_rng(seed)
+    xf = (np.arange(g.nx) + 1.0) * g.dx
+    yc = (np.arange(g.ny) + 0.5) * g.dy
+    xc = (np.arange(g.nx) + 0.5) * g.dx
+    yf = (np.arange(g.ny) + 1.0) * g.dy
+    pa = _mode_sum(g, _draw_modes(rng), xf, yc, g.z_face, True)
+    pb = _mode_sum(g, _draw_modes(rng), xc, yf, g.z_face, True)
+    pc = _mode_sum(g, _draw_modes(rng), xf, yf, g.z_centre, False)
+    pa[:, :, g.nz - 1] = 0.0
+    pb[:, :, g.nz - 1] = 0.0
+    pa *= g.dx * g.rhon.max()
+    pb *= g.dy * g.rhon.max()
+    pc *= g.dx
+
+    def build(a, b, c):
+        zero = np.zeros((g.nx, g.ny, 1))
+        a_km = np.concatenate([zero, a[:, :, :-1]], axis=2)
+        b_km = np.concatenate([zero, b[:, :, :-1]], axis=2)
+        rdz = g.rdz[None, None, :]
+        rhon = g.rhon[None, None, :]
+        rho = g.rho[None, None, :]
+        u = (-rdz * (a - a_km) + rhon * (c - np.roll(c, 1, axis=1)) / g.dy) / rhon
+        v = (-rdz * (b - b_km) - rhon * (c - np.roll(c, 1, axis=0)) / g.dx) / rhon
+        w = ((a - np.roll(a, 1, axis=0)) / g.dx + (b - np.roll(b, 1, axis=1)) / g.dy) / rho
+        w[:, :, g.nz - 1] = 0.0
+        return u, v, w
+
+    u, v, w = build(pa, pb, pc)
+    scale = amp / max(np.abs(u).max(), np.abs(v).max(), np.abs(w).max())
+    u, v, w = build(pa * scale, pb * scale, pc * scale)
+    return {"u": u, "v": v, "w": w}
+
+
+def pad(f: np.ndarray, fill: float = np.nan) -> np.ndarray:
+    """Embed an interior (nx, ny, nz) array in the [(nx+4)][(ny+4)][nz] layout.
+
+    The 2-deep lateral halo is left as `fill` (NaN by default, so that a kernel
+    that reads an unfilled halo is caught)."""
+    nx, ny, nz = f.shape
+    out = np.full((nx + 4, ny + 4, nz), fill, dtype=np.float64)
+    out[2:nx + 2, 2:ny + 2, :] = f
+    return out
+
+
+def interior(a: np.ndarray) -> np.ndarray:
+    return a[2:-2, 2:-2, :]
+
+
+# ---------------------------------------------------------------------------
+# The five workloads (sizes, fields and seeds)
+# ---------------------------------------------------------------------------
+@dataclasses.dataclass
+class Workload:
+    name: str
+    nx: int
+    ny: int
+    nz: int
+    nscal: int
+    seed: int
+    dt: float = 0.5
+    steps: int = 1
+    dx: float = 50.0
+
+
+WORKLOADS = {
+    # one PW + TVD evaluation, 32^3, u v w th q1
+    "tiny32": Workload("tiny32", 32, 32, 32, 2, seed=1),
+    # 100 forward steps, 512x512x128, u v w th q1 q2 q3
+    "steps512": Workload("steps512", 512, 512, 128, 4, seed=2, steps=100),
+    # headline throughput, 1024x1024x128, u v w th q1
+    "big1024": Workload("big1024", 1024, 1024, 128, 2, seed=3),
+}
+
+
+def make_workload(name: str):
+    w = WORKLOADS[name]
+    g = make_geometry(w.nx, w.ny, w.nz, w.dx, w.dx)
+    f = make_fields(g, w.nscal, w.seed)
+    return w, g, f
+
+
+def ensemble_members(n: int = 64, seed: int = 4):
+    """Geometry draws for the uneven ensemble: nx, ny in {64, 96, ..., 256},
+    nz in {64, 96}, wind amplitude ~ U[2, 10] m/s, dx = dy ~ U[25, 100] m,
+    member m seeded 1000 + m."""
+    rng = np.random.default_rng(seed)
+    sizes = np.arange(64, 257, 32)
+    members = []
+    for m in range(n):
+        nx = int(rng.choice(sizes))
+        ny = int(rng.choice(sizes))
+        nz = int(rng.choice([64, 96]))
+        amp = float(rng.uniform(2.0, 10.0))
+        dx = float(rng.uniform(25.0, 100.0))
+        members.append(dict(nx=nx, ny=ny, nz=nz, amp=amp, dx=dx, seed=1000 + m))
+    return members
