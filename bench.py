@@ -1,0 +1,212 @@
+"""Benchmark of the MONC advection step on one MI355X.
+
+One step = one call of monc_step on the 1024 x 1024 x 128 grid with u, v, w,
+theta, q1 in FP64: halo fill, Piacsek-Williams momentum + ULTIMATE/TVD scalar
+source terms, forward update into the second buffer, and the FP64 budgets.
+Inputs are seeded synthetic fields, resident in HBM before timing starts.
+
+Prints one JSON line: grid-point updates per second (nx*ny*nz per step),
+the roofline of the dominant kernel (HBM-bound stencil, algorithmic bytes =
+one read and one write of every field), the oracle timed on the host cores on
+a bounded sample, and the precision forms (FP32 / BF16 tendencies).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK = 8.0e12  # B/s, MI355X HBM3E
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=50)
+    p.add_argument("--warmup", type=int, default=5)
+    p.add_argument("--workload", default="big1024")
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-forms", action="store_true")
+    p.add_argument("--cpu-seconds", type=float, default=12.0)
+    return p.parse_args()
+
+
+def event_time_ms(torch, stream, fn, reps):
+    """Average duration of fn() on `stream`, bracketed by HIP events."""
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(stream):
+        start.record(stream)
+        for _ in range(reps):
+            fn()
+        end.record(stream)
+    end.synchronize()
+    return start.elapsed_time(end) / reps
+
+
+def cpu_baseline(seconds):
+    """The FP64 oracle, unchanged, on a 256 x 256 x 128 slab of the same kind
+    of input (5 fields), stepped until about `seconds` of CPU work is done."""
+    from oracle import pyoracle as O
+    from paper_2009_12850_amd import inputs as I
+    O.build(force=False)
+    g = I.make_geometry(256, 256, 128)
+    f = I.make_fields(g, 2, seed=3, padded=True)
+    st = [f[n] for n in ["u", "v", "w", "th", "q1"]]
+    O.step(st, g, 0.5)  # warm-up
+    n = 0
+    t0 = time.perf_counter()
+    while True:
+        st = O.step(st, g, 0.5)
+        n += 1
+        el = time.perf_counter() - t0
+        if el >= seconds:
+            break
+    pts = 256 * 256 * 128 * n
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count()
+    omp = os.environ.get("OMP_NUM_THREADS")
+    if omp:
+        cores = min(cores, int(omp))
+    return {"value": pts / el, "unit": "grid-point updates/s", "cores": cores,
+            "kind": "oracle",
+            "sample": f"{n} oracle steps of a 256x256x128 grid, 5 fields "
+                      f"(u v w th q1), {el:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the advection "
+              "path has no multi-GPU leg in this build", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_2009_12850_amd import _lib as M
+    from paper_2009_12850_amd import inputs as I
+
+    M.lib()
+    dev = torch.device("cuda:0")
+    w = I.WORKLOADS[args.workload]
+    log(f"generating {args.workload} inputs")
+    g = I.make_geometry(w.nx, w.ny, w.nz, w.dx, w.dx)
+    names = ["u", "v", "w"] + I.scalar_names(w.nscal)
+    f = I.make_fields(g, w.nscal, w.seed, padded=True)
+    A = [torch.from_numpy(f.pop(n)).to(dev) for n in names]
+    del f
+    B = [torch.empty_like(a) for a in A]
+    prof = [torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in (g.rdz, g.rho, g.rhon)]
+    budgets = torch.zeros(M.MONC_NBUDGET, dtype=torch.float64, device=dev)
+    ws = torch.empty(M.monc_step_workspace_bytes(w.nx, w.ny, w.nz, w.nscal),
+                     dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+    npts = w.nx * w.ny * w.nz
+    nf = len(names)
+    state = [A, B]
+
+    def step(budget=True):
+        M.monc_step(state[0], state[1], g.dx, g.dy, prof, w.dt,
+                    budgets if budget else None, ws if budget else None, stream)
+        state.reverse()
+
+    log("warmup")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    bh = budgets.cpu().numpy()
+    status = M.monc_budgets_check(bh)
+    log(f"timing {args.steps} steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ms = event_time_ms(torch, stream, step, args.steps)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / args.steps * 1e3
+    value = npts / (ms * 1e-3)
+
+    # dominant kernel: the fused advection-step launch (no budget pass)
+    k_ms = event_time_ms(torch, stream, lambda: step(False), args.steps)
+    bytes_alg = 16.0 * nf * npts  # read + write of every FP64 field
+    achieved = bytes_alg / (k_ms * 1e-3)
+    roofline = {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9,
+                "unit": "GB/s", "frac": achieved / HBM_PEAK, "traffic": None,
+                "kernel": "monc_step (fused PW+TVD+update, FP64)",
+                "bytes_per_launch": bytes_alg, "launch_ms": k_ms}
+
+    forms = None
+    if not args.no_forms:
+        log("precision forms")
+        forms = {}
+        tend64 = [torch.empty_like(a) for a in A]
+        M.monc_halo_fill(state[0], stream)
+        t64 = event_time_ms(torch, stream, lambda: M.monc_advect(
+            M.MONC_F64, state[0], tend64, g.dx, g.dy, prof, w.dt, stream=stream), args.steps)
+        forms["f64_tendencies"] = {"ms": t64, "gpups": npts / (t64 * 1e-3),
+                                   "hbm_frac": 16.0 * nf * npts / (t64 * 1e-3) / HBM_PEAK}
+        del tend64
+        phi0 = [300.0] + [0.0] * (w.nscal - 1)
+        offs = [0.0, 0.0, 0.0] + phi0
+        for dt_name, code, tdt in (("f32", M.MONC_F32, torch.float32),
+                                   ("bf16", M.MONC_BF16, torch.int16)):
+            work = [torch.empty(a.shape, dtype=tdt, device=dev) for a in A]
+            M.monc_cast_working(code, state[0], work, offs, stream)
+            outs = [torch.empty(a.shape, dtype=torch.float32, device=dev) for a in A]
+            t = event_time_ms(torch, stream, lambda: M.monc_advect(
+                code, work, outs, g.dx, g.dy, prof, w.dt, phi0=phi0, stream=stream),
+                args.steps)
+            eb = 4 if code == M.MONC_F32 else 2
+            forms[f"{dt_name}_tendencies"] = {
+                "ms": t, "gpups": npts / (t * 1e-3),
+                "hbm_frac": (eb + 4.0) * nf * npts / (t * 1e-3) / HBM_PEAK,
+                "speedup_vs_f64": t64 / t}
+            del work, outs
+        mixed = lambda: M.monc_step_mixed(state[0], state[1], phi0, g.dx, g.dy, prof, w.dt,
+                                          None, None, stream)
+        tm = event_time_ms(torch, stream, mixed, args.steps)
+        forms["mixed_step"] = {"ms": tm, "gpups": npts / (tm * 1e-3)}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        cpu = cpu_baseline(args.cpu_seconds)
+
+    rec = {
+        "metric": "advection grid-point updates/s + % HBM peak; FP64 plain vs FP32/batched/learned",
+        "value": value,
+        "unit": "grid-point updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "wall_ms_per_step": wall,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded smooth random flow + noise, stretched grid)",
+        "config": {"workload": f"{args.workload}: {w.nx}x{w.ny}x{w.nz}, fields "
+                               f"{' '.join(names)}, FP64 step (PW + TVD + update + budgets)",
+                   "nx": w.nx, "ny": w.ny, "nz": w.nz, "fields": nf, "dt": w.dt},
+        "status": M.lib().monc_strerror(status).decode(),
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "forms": forms,
+    }
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,185 @@
+/*
+ * monc_adv.h -- C ABI of the MI355X advection library (libmoncadv.so).
+ *
+ * The operation is the advection component of the MONC LES dynamical core
+ * (Brown et al., arXiv 2009.12850): Sec. 2.1 names advection as the single
+ * longest-running component and lists the prognostic fields u, v, w, theta
+ * and any number of q fields; Sec. 3 describes the dynamics group, where every
+ * component adds a source term ("tendency") that "step fields" integrates
+ * last; Sec. 3.1 names the two schemes, the energy-conserving Piacsek-Williams
+ * scheme (momentum) and Leonard's positivity-preserving ULTIMATE scheme
+ * (scalars); Sec. 4.1 describes the single-precision variant.  The exact
+ * discretisation implemented here is stated in monc_adv_scheme below.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Layout.   Every field is a dense [(nx+4)][(ny+4)][nz] array, z fastest, with
+ *           a 2-deep periodic halo in x and y and none in z.  Interior element
+ *           (i,j,k), 0 <= i < nx, 0 <= j < ny, 0 <= k < nz, lives at
+ *           ((i+2)*(ny+4) + (j+2))*nz + k.  Profiles rdz, rho, rhon are [nz]
+ *           float64 arrays: rdz[k] = 1/dz_k (thickness of cell k), rho[k] =
+ *           reference density on the top face of cell k, rhon[k] = at its
+ *           centre.  w[k] is the vertical velocity on the top face of cell k;
+ *           w[nz-1] is the lid and is treated as 0 whatever it holds.
+ * Memory.   All array pointers are DEVICE pointers owned by the caller; the
+ *           library keeps no pointer after a call returns and allocates no
+ *           device memory outside an ensemble plan.  Scratch space is passed
+ *           in as `workspace`, sized by the matching *_workspace_bytes call.
+ * Streams.  `stream` is a hipStream_t (NULL = the default stream).  Calls only
+ *           enqueue work and never synchronise; results are ready when the
+ *           stream is.
+ * Errors.   Calls return MONC_OK or a negative code.  Arguments are validated
+ *           before any HIP call (MONC_EINVAL, detail in monc_last_error(),
+ *           which is thread-local).  A launch failure returns MONC_EHIP.
+ *           Conditions found on the device (Courant number > 1, non-finite
+ *           values) are written into the budgets array and turned into codes
+ *           by monc_budgets_check() after the caller has synchronised.
+ * Aliasing. Outputs must not alias inputs.
+ * Limits.   nx, ny >= 1; 2 <= nz <= MONC_MAX_NZ; nscal <= MONC_MAX_SCALARS;
+ *           dx, dy > 0; dt > 0 wherever TVD is involved.
+ */
+#ifndef MONC_ADV_H
+#define MONC_ADV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef void *monc_stream_t;
+
+enum {
+    MONC_OK = 0,
+    MONC_EINVAL = -1,
+    MONC_EHIP = -2,
+    MONC_ECFL = -3,
+    MONC_ENONFINITE = -4,
+    MONC_EUNSUPPORTED = -5
+};
+
+#define MONC_MAX_SCALARS 8
+#define MONC_MAX_NZ 256
+
+/* Storage types of the precision form (Sec. 4.1 marshals the fields into a
+ * narrower type before advection and widens the source terms afterwards). */
+enum { MONC_F64 = 0, MONC_F32 = 1, MONC_BF16 = 2 };
+
+/* Budgets written by monc_step* when `budgets` is non-NULL (float64 array of
+ * MONC_NBUDGET entries, device memory).  They describe the INPUT state of the
+ * step and the tendencies computed from it:
+ *   C_*  conservation sums: C_u = sum rhon dz su, C_v likewise,
+ *        C_w = sum_{k<nz-1} rho dzn sw, C_s = sum rhon dz s_phi (all ~0 except
+ *        C_w, which equals sum_ij (rho_0 w_0^2 - rho_{nz-2} w_{nz-2}^2)/4);
+ *   P_*, Q_*  the two sides of the kinetic-energy identity of the PW scheme:
+ *        P_u = sum rhon dz u su, Q_u = -sum dz (u^2/2)(D_i + D_{i+1})/2,
+ *        P_w = sum rho dzn w sw, Q_w = -sum (w^2/2)(dz_k D_k + dz_{k+1} D_{k+1})/2,
+ *        where D is the anelastic mass divergence of a cell;
+ *   COURANT  the largest |u|dt/dx, |v|dt/dy, |w_k| dt/dzn_k over all faces;
+ *   NONFINITE number of non-finite values written (output state or tendencies);
+ *   M_s = sum rhon dz phi_s and MIN_s = min phi_s of the input scalars.
+ * Sums run in a fixed order for a given grid, so they are bitwise repeatable. */
+enum {
+    MONC_B_CU = 0, MONC_B_CV, MONC_B_CW, MONC_B_PU, MONC_B_QU, MONC_B_PV,
+    MONC_B_QV, MONC_B_PW, MONC_B_QW, MONC_B_COURANT, MONC_B_NONFINITE,
+    MONC_B_SCALAR0 /* scalar s: C_s at 11+3s, M_s at 12+3s, MIN_s at 13+3s */
+};
+#define MONC_NBUDGET (MONC_B_SCALAR0 + 3 * MONC_MAX_SCALARS)
+
+/* ---------------------------------------------------------------------------
+ * a1. Periodic halo fill (the halo swap that opens every timestep, Sec. 2.1,
+ * on a single periodic domain).  fields: host array of nfields device
+ * pointers; each field's 2-deep x-y halo, corners included, becomes a copy of
+ * the interior at the wrapped index.  Bitwise copy.
+ * ------------------------------------------------------------------------- */
+int monc_halo_fill(int nfields, double *const *fields, int nx, int ny, int nz,
+                   monc_stream_t stream);
+int monc_halo_fill_f32(int nfields, float *const *fields, int nx, int ny, int nz,
+                       monc_stream_t stream);
+int monc_halo_fill_bf16(int nfields, uint16_t *const *fields, int nx, int ny,
+                        int nz, monc_stream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * a3. Piacsek-Williams momentum source terms (Sec. 3.1, energy-conserving
+ * scheme) in FP64.  Inputs u, v, w with valid halos; outputs su, sv, sw
+ * (interior written, halo untouched; sw[...][nz-1] = 0).
+ * ------------------------------------------------------------------------- */
+int monc_advect_pw(const double *u, const double *v, const double *w,
+                   double *su, double *sv, double *sw, int nx, int ny, int nz,
+                   double dx, double dy, const double *rdz, const double *rho,
+                   const double *rhon, monc_stream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * a4. ULTIMATE-limited QUICKEST (TVD) scalar source terms (Sec. 3.1,
+ * positivity-preserving scheme) in FP64, for nscal scalars at once.  q and sq
+ * are host arrays of nscal device pointers.  Halos (depth 2) of u, v, w and
+ * every q must be valid.  dt enters through the Courant numbers.
+ * ------------------------------------------------------------------------- */
+int monc_advect_tvd(const double *u, const double *v, const double *w,
+                    int nscal, const double *const *q, double *const *sq,
+                    int nx, int ny, int nz, double dx, double dy,
+                    const double *rdz, const double *rho, const double *rhon,
+                    double dt, monc_stream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * a3+a4 fused: PW for u, v, w and TVD for nscal scalars in one pass, in the
+ * storage type `dtype` (MONC_F64: double in, double out; MONC_F32: float in,
+ * float out; MONC_BF16: bfloat16 bits in, float out).  in = host array of
+ * 3+nscal device pointers (u, v, w, scalars), out likewise.  phi0 (host array
+ * of nscal doubles, may be NULL = zeros) gives the constant each stored scalar
+ * is an anomaly from: the source term returned is that of phi0 + stored value,
+ * i.e. the stored anomaly's term minus phi0*D/rhon (exact by the affine
+ * equivariance of the flux form).  Halos must be valid.
+ * ------------------------------------------------------------------------- */
+int monc_advect(int dtype, const void *const *in, void *const *out, int nscal,
+                const double *phi0, int nx, int ny, int nz, double dx,
+                double dy, const double *rdz, const double *rho,
+                const double *rhon, double dt, monc_stream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * a1-a6. One forward step of the whole path ("step fields" integrates the
+ * source terms last, Sec. 3): halo fill of state_in (its halo is rewritten),
+ * PW + TVD from state_in, state_out = state_in + dt * s, w lid = 0, and
+ * optionally the FP64 budgets.  state_in/state_out: host arrays of 3+nscal
+ * device pointers, FP64, state_out must not alias state_in (state_out's halo
+ * is left stale; the next step refills it).  budgets: device float64
+ * [MONC_NBUDGET] or NULL.  workspace: device memory of at least
+ * monc_step_workspace_bytes(nx, ny, nz, nscal) bytes when budgets != NULL.
+ * ------------------------------------------------------------------------- */
+size_t monc_step_workspace_bytes(int nx, int ny, int nz, int nscal);
+int monc_step(double *const *state_in, double *const *state_out, int nscal,
+              int nx, int ny, int nz, double dx, double dy, const double *rdz,
+              const double *rho, const double *rhon, double dt,
+              double *budgets, void *workspace, monc_stream_t stream);
+
+/* a7. The same step with the tendencies computed in FP32 from the FP64 state
+ * (scalars first reduced by phi0 in FP64, then rounded) and accumulated in
+ * FP64: the single-precision advection of Sec. 4.1 without a separate
+ * marshalling pass.  Budgets stay FP64. */
+int monc_step_mixed(double *const *state_in, double *const *state_out,
+                    int nscal, const double *phi0, int nx, int ny, int nz,
+                    double dx, double dy, const double *rdz, const double *rho,
+                    const double *rhon, double dt, double *budgets,
+                    void *workspace, monc_stream_t stream);
+
+/* a7. Marshalling (Sec. 4.1): write a narrower working copy of FP64 fields.
+ * dtype MONC_F32 or MONC_BF16 (round to nearest even); work[f] receives
+ * src[f] - offset[f] (offset may be NULL = zeros) over the whole padded array,
+ * halo included. */
+int monc_cast_working(int dtype, int nfields, const double *const *src,
+                      void *const *work, const double *offset, int nx, int ny,
+                      int nz, monc_stream_t stream);
+
+/* Map a budgets array (HOST copy, after synchronising) to a status:
+ * MONC_ENONFINITE if any non-finite value was written, MONC_ECFL if the
+ * largest Courant number exceeds 1, else MONC_OK. */
+int monc_budgets_check(const double *host_budgets);
+
+const char *monc_strerror(int code);
+const char *monc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MONC_ADV_H */

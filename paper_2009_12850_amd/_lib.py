@@ -1,0 +1,269 @@
+"""Thin ctypes binding of libmoncadv.so.
+
+Argument marshalling only: every step of the advection path runs in the
+library's HIP kernels.  torch supplies device memory (``tensor.data_ptr()``)
+and the stream (``torch.cuda.current_stream().cuda_stream``).  If the library
+has not been built, loading raises -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmoncadv.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "monc_adv.h")
+
+MONC_OK, MONC_EINVAL, MONC_EHIP, MONC_ECFL, MONC_ENONFINITE, MONC_EUNSUPPORTED = \
+    0, -1, -2, -3, -4, -5
+MONC_F64, MONC_F32, MONC_BF16 = 0, 1, 2
+MONC_MAX_SCALARS = 8
+MONC_MAX_NZ = 256
+B_CU, B_CV, B_CW, B_PU, B_QU, B_PV, B_QV, B_PW, B_QW, B_COURANT, B_NONFINITE = range(11)
+B_SCALAR0 = 11
+MONC_NBUDGET = B_SCALAR0 + 3 * MONC_MAX_SCALARS
+
+
+class MoncError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{msg} (code {code})")
+        self.code = code
+
+
+_lib = None
+
+vp = C.c_void_p
+ip = C.c_int
+dp = C.c_double
+PP = C.POINTER(C.c_void_p)
+DPTR = C.POINTER(C.c_double)
+
+_SIGS = {
+    "monc_halo_fill": ([ip, PP, ip, ip, ip, vp], ip),
+    "monc_halo_fill_f32": ([ip, PP, ip, ip, ip, vp], ip),
+    "monc_halo_fill_bf16": ([ip, PP, ip, ip, ip, vp], ip),
+    "monc_advect_pw": ([vp, vp, vp, vp, vp, vp, ip, ip, ip, dp, dp, vp, vp, vp, vp], ip),
+    "monc_advect_tvd": ([vp, vp, vp, ip, PP, PP, ip, ip, ip, dp, dp, vp, vp, vp, dp, vp], ip),
+    "monc_advect": ([ip, PP, PP, ip, DPTR, ip, ip, ip, dp, dp, vp, vp, vp, dp, vp], ip),
+    "monc_step_workspace_bytes": ([ip, ip, ip, ip], C.c_size_t),
+    "monc_step": ([PP, PP, ip, ip, ip, ip, dp, dp, vp, vp, vp, dp, vp, vp, vp], ip),
+    "monc_step_mixed": ([PP, PP, ip, DPTR, ip, ip, ip, dp, dp, vp, vp, vp, dp, vp, vp, vp],
+                        ip),
+    "monc_cast_working": ([ip, ip, PP, PP, DPTR, ip, ip, ip, vp], ip),
+    "monc_budgets_check": ([DPTR], ip),
+    "monc_strerror": ([ip], C.c_char_p),
+    "monc_last_error": ([], C.c_char_p),
+}
+
+
+def lib():
+    """Load libmoncadv.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"{LIB_PATH} is missing: build it with "
+                "`python -m paper_2009_12850_amd.build` (there is no fallback path)")
+        L = C.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def header_symbols():
+    """Names of every function declared in include/monc_adv.h."""
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(monc_[a-z0-9_]+)\s*\(", text)))
+
+
+def _check(rc: int, what: str):
+    if rc != MONC_OK:
+        msg = lib().monc_last_error().decode()
+        raise MoncError(rc, f"{what}: {msg}")
+
+
+# ---------------------------------------------------------------------------
+# torch glue
+# ---------------------------------------------------------------------------
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream=None):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t, dtype=None, shape=None, what="tensor"):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{what} must be a torch tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{what} must be on a HIP device (got {t.device})")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{what} must be {dtype} (got {t.dtype})")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{what} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return C.c_void_p(t.data_ptr())
+
+
+def _ptrs(ts, dtype, shape, what):
+    arr = (C.c_void_p * max(len(ts), 1))()
+    for n, t in enumerate(ts):
+        arr[n] = _ptr(t, dtype, shape, f"{what}[{n}]").value
+    return arr
+
+
+def _grid(t):
+    nx4, ny4, nz = t.shape
+    return nx4 - 4, ny4 - 4, nz
+
+
+def _prof(prof):
+    torch = _torch()
+    rdz, rho, rhon = prof
+    nz = rdz.shape[0]
+    return [_ptr(p, torch.float64, (nz,), n) for p, n in zip((rdz, rho, rhon),
+                                                             ("rdz", "rho", "rhon"))]
+
+
+_DT = {}
+
+
+def _dtypes():
+    torch = _torch()
+    if not _DT:
+        _DT.update({MONC_F64: torch.float64, MONC_F32: torch.float32,
+                    MONC_BF16: torch.int16})
+    return _DT
+
+
+# ---------------------------------------------------------------------------
+# Entry points (same names as the C ABI)
+# ---------------------------------------------------------------------------
+def monc_halo_fill(fields, stream=None):
+    torch = _torch()
+    dt = fields[0].dtype
+    nx, ny, nz = _grid(fields[0])
+    shape = tuple(fields[0].shape)
+    fn = {torch.float64: "monc_halo_fill", torch.float32: "monc_halo_fill_f32",
+          torch.int16: "monc_halo_fill_bf16", torch.bfloat16: "monc_halo_fill_bf16"}[dt]
+    arr = _ptrs(fields, dt, shape, "fields")
+    _check(getattr(lib(), fn)(len(fields), arr, nx, ny, nz, _stream(stream)), fn)
+
+
+def monc_advect_pw(u, v, w, su, sv, sw, dx, dy, prof, stream=None):
+    torch = _torch()
+    nx, ny, nz = _grid(u)
+    sh = tuple(u.shape)
+    ps = [_ptr(t, torch.float64, sh, n) for t, n in
+          zip((u, v, w, su, sv, sw), ("u", "v", "w", "su", "sv", "sw"))]
+    _check(lib().monc_advect_pw(*ps, nx, ny, nz, float(dx), float(dy), *_prof(prof),
+                                _stream(stream)), "monc_advect_pw")
+
+
+def monc_advect_tvd(u, v, w, q, sq, dx, dy, prof, dt, stream=None):
+    torch = _torch()
+    nx, ny, nz = _grid(u)
+    sh = tuple(u.shape)
+    ps = [_ptr(t, torch.float64, sh, n) for t, n in zip((u, v, w), ("u", "v", "w"))]
+    qa = _ptrs(q, torch.float64, sh, "q")
+    sa = _ptrs(sq, torch.float64, sh, "sq")
+    _check(lib().monc_advect_tvd(*ps, len(q), qa, sa, nx, ny, nz, float(dx), float(dy),
+                                 *_prof(prof), float(dt), _stream(stream)),
+           "monc_advect_tvd")
+
+
+def monc_advect(dtype, inputs, outputs, dx, dy, prof, dt, phi0=None, stream=None):
+    """Fused PW + TVD source terms.  inputs = [u, v, w, scalars...] in the
+    storage dtype (float64, float32, or int16 holding bfloat16 bits); outputs
+    float64 for MONC_F64, float32 otherwise."""
+    torch = _torch()
+    nx, ny, nz = _grid(inputs[0])
+    sh = tuple(inputs[0].shape)
+    nscal = len(inputs) - 3
+    ia = _ptrs(inputs, _dtypes()[dtype], sh, "in")
+    odt = torch.float64 if dtype == MONC_F64 else torch.float32
+    oa = _ptrs(outputs, odt, sh, "out")
+    p0 = None
+    if phi0 is not None:
+        p0 = (C.c_double * max(nscal, 1))(*[float(x) for x in phi0])
+    _check(lib().monc_advect(dtype, ia, oa, nscal, p0, nx, ny, nz, float(dx), float(dy),
+                             *_prof(prof), float(dt), _stream(stream)), "monc_advect")
+
+
+def monc_step_workspace_bytes(nx, ny, nz, nscal):
+    return int(lib().monc_step_workspace_bytes(nx, ny, nz, nscal))
+
+
+def monc_step(state_in, state_out, dx, dy, prof, dt, budgets=None, workspace=None,
+              stream=None, mixed=False, phi0=None):
+    torch = _torch()
+    nx, ny, nz = _grid(state_in[0])
+    sh = tuple(state_in[0].shape)
+    nscal = len(state_in) - 3
+    ia = _ptrs(state_in, torch.float64, sh, "state_in")
+    oa = _ptrs(state_out, torch.float64, sh, "state_out")
+    b = None if budgets is None else _ptr(budgets, torch.float64, (MONC_NBUDGET,), "budgets")
+    ws = None if workspace is None else _ptr(workspace, None, None, "workspace")
+    if workspace is not None:
+        need = monc_step_workspace_bytes(nx, ny, nz, nscal)
+        if workspace.numel() * workspace.element_size() < need:
+            raise ValueError(f"workspace needs {need} bytes")
+    if mixed:
+        p0 = (C.c_double * max(nscal, 1))(*([float(x) for x in phi0] if phi0 is not None
+                                            else [0.0] * max(nscal, 1)))
+        rc = lib().monc_step_mixed(ia, oa, nscal, p0, nx, ny, nz, float(dx), float(dy),
+                                   *_prof(prof), float(dt), b, ws, _stream(stream))
+        _check(rc, "monc_step_mixed")
+    else:
+        rc = lib().monc_step(ia, oa, nscal, nx, ny, nz, float(dx), float(dy), *_prof(prof),
+                             float(dt), b, ws, _stream(stream))
+        _check(rc, "monc_step")
+
+
+def monc_step_mixed(state_in, state_out, phi0, dx, dy, prof, dt, budgets=None,
+                    workspace=None, stream=None):
+    monc_step(state_in, state_out, dx, dy, prof, dt, budgets, workspace, stream,
+              mixed=True, phi0=phi0)
+
+
+def monc_cast_working(dtype, src, work, offset=None, stream=None):
+    torch = _torch()
+    nx, ny, nz = _grid(src[0])
+    sh = tuple(src[0].shape)
+    sa = _ptrs(src, torch.float64, sh, "src")
+    wa = _ptrs(work, _dtypes()[dtype], sh, "work")
+    off = None
+    if offset is not None:
+        off = (C.c_double * len(src))(*[float(x) for x in offset])
+    _check(lib().monc_cast_working(dtype, len(src), sa, wa, off, nx, ny, nz,
+                                   _stream(stream)), "monc_cast_working")
+
+
+def monc_budgets_check(host_budgets):
+    import numpy as np
+    arr = np.ascontiguousarray(host_budgets, dtype=np.float64)
+    return int(lib().monc_budgets_check(arr.ctypes.data_as(DPTR)))
+
+
+def budgets_dict(b, nscal):
+    """Name the entries of a host budgets array."""
+    names = ["C_u", "C_v", "C_w", "P_u", "Q_u", "P_v", "Q_v", "P_w", "Q_w", "courant",
+             "nonfinite"]
+    out = {n: float(b[q]) for q, n in enumerate(names)}
+    for s in range(nscal):
+        out[f"C_s{s}"] = float(b[B_SCALAR0 + 3 * s])
+        out[f"M_s{s}"] = float(b[B_SCALAR0 + 3 * s + 1])
+        out[f"min_s{s}"] = float(b[B_SCALAR0 + 3 * s + 2])
+    return out

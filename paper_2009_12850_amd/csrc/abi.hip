@@ -1,0 +1,307 @@
+// abi.hip -- the extern "C" entry points of libmoncadv.so: argument checks
+// (before any HIP call), launch sequencing on the caller's stream, and error
+// reporting.  See include/monc_adv.h for the contract of every call.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+
+#include <string>
+
+#include "monc_internal.hpp"
+
+using namespace monc;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+int hip_status(hipError_t e, const char* where) {
+    if (e == hipSuccess) return MONC_OK;
+    return fail(MONC_EHIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+int check_grid(int nx, int ny, int nz) {
+    if (nx < 1 || ny < 1) return fail(MONC_EINVAL, "nx, ny must be >= 1 (got %d, %d)", nx, ny);
+    if (nz < 2 || nz > MONC_MAX_NZ)
+        return fail(MONC_EINVAL, "nz must be in [2, %d] (got %d)", MONC_MAX_NZ, nz);
+    const double n = (double)(nx + 4) * (ny + 4) * nz;
+    if (n > 4.0e12) return fail(MONC_EINVAL, "grid too large");
+    return MONC_OK;
+}
+
+int check_spacing(double dx, double dy) {
+    if (!(dx > 0) || !(dy > 0) || !isfinite(dx) || !isfinite(dy))
+        return fail(MONC_EINVAL, "dx, dy must be finite and > 0 (got %g, %g)", dx, dy);
+    return MONC_OK;
+}
+
+int check_dt(double dt) {
+    if (!(dt > 0) || !isfinite(dt)) return fail(MONC_EINVAL, "dt must be finite and > 0 (got %g)", dt);
+    return MONC_OK;
+}
+
+int check_prof(const double* rdz, const double* rho, const double* rhon) {
+    if (!rdz || !rho || !rhon) return fail(MONC_EINVAL, "profile pointer is NULL");
+    return MONC_OK;
+}
+
+int check_nscal(int nscal) {
+    if (nscal < 0 || nscal > MONC_MAX_SCALARS)
+        return fail(MONC_EINVAL, "nscal must be in [0, %d] (got %d)", MONC_MAX_SCALARS, nscal);
+    return MONC_OK;
+}
+
+template <typename P>
+int check_ptrs(int n, P const* arr, const char* what) {
+    if (!arr) return fail(MONC_EINVAL, "%s: pointer array is NULL", what);
+    for (int f = 0; f < n; f++)
+        if (!arr[f]) return fail(MONC_EINVAL, "%s[%d] is NULL", what, f);
+    return MONC_OK;
+}
+
+// No output may alias an input.
+int check_alias(int nin, const void* const* in, int nout, const void* const* out) {
+    for (int a = 0; a < nout; a++) {
+        for (int b = 0; b < nin; b++)
+            if (out[a] == in[b]) return fail(MONC_EINVAL, "output %d aliases input %d", a, b);
+        for (int b = 0; b < a; b++)
+            if (out[a] == out[b]) return fail(MONC_EINVAL, "outputs %d and %d alias", a, b);
+    }
+    return MONC_OK;
+}
+
+#define TRY(x)                      \
+    do {                            \
+        int _rc = (x);              \
+        if (_rc != MONC_OK) return _rc; \
+    } while (0)
+
+void fill_args(AdvArgs& a, int nx, int ny, int nz, double dx, double dy, double dt,
+               const double* rdz, const double* rho, const double* rhon, int nscal) {
+    for (int f = 0; f < 3 + MAXS; f++) {
+        a.in[f] = nullptr;
+        a.out[f] = nullptr;
+    }
+    for (int s = 0; s < MAXS; s++) a.phi0[s] = 0.0;
+    a.nscal = nscal;
+    a.nx = nx;
+    a.ny = ny;
+    a.nz = nz;
+    a.dx = dx;
+    a.dy = dy;
+    a.dt = dt;
+    a.rdz = rdz;
+    a.rho = rho;
+    a.rhon = rhon;
+    a.partials = nullptr;
+}
+
+int do_halo(int bytes, int nfields, void* const* fields, int nx, int ny, int nz,
+            monc_stream_t stream) {
+    TRY(check_grid(nx, ny, nz));
+    if (nfields < 1 || nfields > 3 + MONC_MAX_SCALARS)
+        return fail(MONC_EINVAL, "nfields must be in [1, %d]", 3 + MONC_MAX_SCALARS);
+    TRY(check_ptrs(nfields, fields, "fields"));
+    return hip_status(launch_halo(bytes, nfields, fields, nx, ny, nz, (hipStream_t)stream),
+                      "halo_fill");
+}
+
+int do_step(double* const* state_in, double* const* state_out, int nscal,
+            const double* phi0, int nx, int ny, int nz, double dx, double dy,
+            const double* rdz, const double* rho, const double* rhon, double dt,
+            double* budgets, void* workspace, monc_stream_t stream, bool mixed) {
+    TRY(check_grid(nx, ny, nz));
+    TRY(check_spacing(dx, dy));
+    TRY(check_dt(dt));
+    TRY(check_prof(rdz, rho, rhon));
+    TRY(check_nscal(nscal));
+    const int nf = 3 + nscal;
+    TRY(check_ptrs(nf, state_in, "state_in"));
+    TRY(check_ptrs(nf, state_out, "state_out"));
+    TRY(check_alias(nf, (const void* const*)state_in, nf, (const void* const*)state_out));
+    if (budgets && !workspace)
+        return fail(MONC_EINVAL, "budgets requested but workspace is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    TRY(hip_status(launch_halo(8, nf, (void* const*)state_in, nx, ny, nz, s), "step/halo"));
+    AdvArgs a;
+    fill_args(a, nx, ny, nz, dx, dy, dt, rdz, rho, rhon, nscal);
+    for (int f = 0; f < nf; f++) {
+        a.in[f] = state_in[f];
+        a.out[f] = state_out[f];
+    }
+    if (phi0)
+        for (int q = 0; q < nscal; q++) a.phi0[q] = phi0[q];
+    a.partials = budgets ? (double*)workspace : nullptr;
+    TRY(hip_status(launch_advect(MONC_F64, STEP, true, true, mixed, a, s), "step/advect"));
+    if (budgets)
+        TRY(hip_status(launch_budget_final((const double*)workspace,
+                                           step_blocks(nx, ny, nz), budgets, s),
+                       "step/budgets"));
+    return MONC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int monc_halo_fill(int nfields, double* const* fields, int nx, int ny, int nz,
+                   monc_stream_t stream) {
+    return do_halo(8, nfields, (void* const*)fields, nx, ny, nz, stream);
+}
+
+int monc_halo_fill_f32(int nfields, float* const* fields, int nx, int ny, int nz,
+                       monc_stream_t stream) {
+    return do_halo(4, nfields, (void* const*)fields, nx, ny, nz, stream);
+}
+
+int monc_halo_fill_bf16(int nfields, uint16_t* const* fields, int nx, int ny, int nz,
+                        monc_stream_t stream) {
+    return do_halo(2, nfields, (void* const*)fields, nx, ny, nz, stream);
+}
+
+int monc_advect_pw(const double* u, const double* v, const double* w, double* su,
+                   double* sv, double* sw, int nx, int ny, int nz, double dx, double dy,
+                   const double* rdz, const double* rho, const double* rhon,
+                   monc_stream_t stream) {
+    TRY(check_grid(nx, ny, nz));
+    TRY(check_spacing(dx, dy));
+    TRY(check_prof(rdz, rho, rhon));
+    const void* in[3] = {u, v, w};
+    const void* out[3] = {su, sv, sw};
+    TRY(check_ptrs(3, in, "velocity"));
+    TRY(check_ptrs(3, out, "tendency"));
+    TRY(check_alias(3, in, 3, out));
+    AdvArgs a;
+    fill_args(a, nx, ny, nz, dx, dy, 1.0, rdz, rho, rhon, 0);
+    for (int f = 0; f < 3; f++) {
+        a.in[f] = in[f];
+        a.out[f] = (void*)out[f];
+    }
+    return hip_status(launch_advect(MONC_F64, TEND, true, false, false, a, (hipStream_t)stream),
+                      "advect_pw");
+}
+
+int monc_advect_tvd(const double* u, const double* v, const double* w, int nscal,
+                    const double* const* q, double* const* sq, int nx, int ny, int nz,
+                    double dx, double dy, const double* rdz, const double* rho,
+                    const double* rhon, double dt, monc_stream_t stream) {
+    TRY(check_grid(nx, ny, nz));
+    TRY(check_spacing(dx, dy));
+    TRY(check_dt(dt));
+    TRY(check_prof(rdz, rho, rhon));
+    TRY(check_nscal(nscal));
+    if (nscal < 1) return fail(MONC_EINVAL, "monc_advect_tvd needs nscal >= 1");
+    const void* vel[3] = {u, v, w};
+    TRY(check_ptrs(3, vel, "velocity"));
+    TRY(check_ptrs(nscal, q, "q"));
+    TRY(check_ptrs(nscal, sq, "sq"));
+    const void* in[3 + MONC_MAX_SCALARS];
+    for (int f = 0; f < 3; f++) in[f] = vel[f];
+    for (int s = 0; s < nscal; s++) in[3 + s] = q[s];
+    TRY(check_alias(3 + nscal, in, nscal, (const void* const*)sq));
+    AdvArgs a;
+    fill_args(a, nx, ny, nz, dx, dy, dt, rdz, rho, rhon, nscal);
+    for (int f = 0; f < 3 + nscal; f++) a.in[f] = in[f];
+    for (int s = 0; s < nscal; s++) a.out[3 + s] = sq[s];
+    return hip_status(launch_advect(MONC_F64, TEND, false, true, false, a, (hipStream_t)stream),
+                      "advect_tvd");
+}
+
+int monc_advect(int dtype, const void* const* in, void* const* out, int nscal,
+                const double* phi0, int nx, int ny, int nz, double dx, double dy,
+                const double* rdz, const double* rho, const double* rhon, double dt,
+                monc_stream_t stream) {
+    if (dtype != MONC_F64 && dtype != MONC_F32 && dtype != MONC_BF16)
+        return fail(MONC_EINVAL, "unknown dtype %d", dtype);
+    TRY(check_grid(nx, ny, nz));
+    TRY(check_spacing(dx, dy));
+    TRY(check_prof(rdz, rho, rhon));
+    TRY(check_nscal(nscal));
+    if (nscal > 0) TRY(check_dt(dt));
+    const int nf = 3 + nscal;
+    TRY(check_ptrs(nf, in, "in"));
+    TRY(check_ptrs(nf, out, "out"));
+    TRY(check_alias(nf, in, nf, (const void* const*)out));
+    AdvArgs a;
+    fill_args(a, nx, ny, nz, dx, dy, nscal > 0 ? dt : 1.0, rdz, rho, rhon, nscal);
+    for (int f = 0; f < nf; f++) {
+        a.in[f] = in[f];
+        a.out[f] = out[f];
+    }
+    if (phi0)
+        for (int s = 0; s < nscal; s++) a.phi0[s] = phi0[s];
+    return hip_status(
+        launch_advect(dtype, TEND, true, nscal > 0, false, a, (hipStream_t)stream), "advect");
+}
+
+size_t monc_step_workspace_bytes(int nx, int ny, int nz, int nscal) {
+    (void)nscal;
+    if (nx < 1 || ny < 1 || nz < 1) return 0;
+    return (size_t)step_blocks(nx, ny, nz) * NB * sizeof(double);
+}
+
+int monc_step(double* const* state_in, double* const* state_out, int nscal, int nx,
+              int ny, int nz, double dx, double dy, const double* rdz, const double* rho,
+              const double* rhon, double dt, double* budgets, void* workspace,
+              monc_stream_t stream) {
+    return do_step(state_in, state_out, nscal, nullptr, nx, ny, nz, dx, dy, rdz, rho, rhon,
+                   dt, budgets, workspace, stream, false);
+}
+
+int monc_step_mixed(double* const* state_in, double* const* state_out, int nscal,
+                    const double* phi0, int nx, int ny, int nz, double dx, double dy,
+                    const double* rdz, const double* rho, const double* rhon, double dt,
+                    double* budgets, void* workspace, monc_stream_t stream) {
+    return do_step(state_in, state_out, nscal, phi0, nx, ny, nz, dx, dy, rdz, rho, rhon,
+                   dt, budgets, workspace, stream, true);
+}
+
+int monc_cast_working(int dtype, int nfields, const double* const* src, void* const* work,
+                      const double* offset, int nx, int ny, int nz, monc_stream_t stream) {
+    if (dtype != MONC_F32 && dtype != MONC_BF16)
+        return fail(MONC_EINVAL, "cast dtype must be MONC_F32 or MONC_BF16");
+    TRY(check_grid(nx, ny, nz));
+    if (nfields < 1 || nfields > 3 + MONC_MAX_SCALARS)
+        return fail(MONC_EINVAL, "nfields must be in [1, %d]", 3 + MONC_MAX_SCALARS);
+    TRY(check_ptrs(nfields, src, "src"));
+    TRY(check_ptrs(nfields, work, "work"));
+    const long n = (long)(nx + 4) * (ny + 4) * nz;
+    return hip_status(launch_cast(dtype, nfields, src, work, offset, n, (hipStream_t)stream),
+                      "cast_working");
+}
+
+int monc_budgets_check(const double* b) {
+    if (!b) return fail(MONC_EINVAL, "budgets is NULL");
+    if (b[MONC_B_NONFINITE] > 0)
+        return fail(MONC_ENONFINITE, "%.0f non-finite values written", b[MONC_B_NONFINITE]);
+    if (!(b[MONC_B_COURANT] <= 1.0))
+        return fail(MONC_ECFL, "largest Courant number %g exceeds 1", b[MONC_B_COURANT]);
+    return MONC_OK;
+}
+
+const char* monc_strerror(int code) {
+    switch (code) {
+        case MONC_OK: return "ok";
+        case MONC_EINVAL: return "invalid argument";
+        case MONC_EHIP: return "HIP runtime error";
+        case MONC_ECFL: return "Courant number above 1";
+        case MONC_ENONFINITE: return "non-finite value produced";
+        case MONC_EUNSUPPORTED: return "unsupported configuration";
+    }
+    return "unknown error";
+}
+
+const char* monc_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,47 @@
+// monc_internal.hpp -- launch interfaces shared by the library's HIP sources.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/monc_adv.h"
+
+namespace monc {
+
+constexpr int MAXS = MONC_MAX_SCALARS;
+constexpr int NB = MONC_NBUDGET;
+
+enum Mode { TEND = 0, STEP = 1 };
+
+// Everything one advection launch needs.  Pointers are device pointers; the
+// storage type of in/out depends on the instantiation.
+struct AdvArgs {
+    const void* in[3 + MAXS];   // u, v, w, scalars
+    void* out[3 + MAXS];        // tendencies (TEND) or new state (STEP)
+    double phi0[MAXS];          // anomaly offsets of the scalars
+    int nscal;
+    int nx, ny, nz;
+    double dx, dy, dt;
+    const double* rdz;
+    const double* rho;
+    const double* rhon;
+    double* partials;           // [nblocks][NB] budget partials, or null
+};
+
+// Number of workgroups of the fused step launch (fixed for a grid so budget
+// sums are repeatable), and the budget workspace it needs.
+int step_blocks(int nx, int ny, int nz);
+
+// Launchers (return hipError_t of the launch).
+hipError_t launch_halo(int elem_bytes, int nfields, void* const* fields, int nx,
+                       int ny, int nz, hipStream_t s);
+hipError_t launch_advect(int dtype, int mode, bool pw, bool tvd, bool mixed,
+                         const AdvArgs& a, hipStream_t s);
+hipError_t launch_budget_final(const double* partials, int nblocks,
+                               double* budgets, hipStream_t s);
+hipError_t launch_cast(int dtype, int nfields, const double* const* src,
+                       void* const* dst, const double* offset, long n,
+                       hipStream_t s);
+
+}  // namespace monc

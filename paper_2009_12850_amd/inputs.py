@@ -23,8 +23,9 @@ Recipe (all FP64, NumPy PCG64, fixed draw order):
   values    u, v, w = amp*sum + N(0, 0.01^2), then w = 0 on the lid level;
             theta = 300 + 2*sum + N(0, 0.01^2);
             q_n = 1e-3 exp(0.5*sum + N(0, 0.01^2))  (positive, log-normal).
-Field order is u, v, w, theta, q1, q2, ...; each field draws its modes, then its
-noise, before the next field starts.
+Field order is u, v, w, theta, q1, q2, ...; field number n draws its modes and
+then its noise from its own generator, seeded with [seed, n], so that fields can
+be generated in parallel threads.
 """
 from __future__ import annotations
 
@@ -103,36 +104,62 @@ def scalar_names(nscal: int):
     return ["th"] + [f"q{n}" for n in range(1, nscal)]
 
 
-def make_fields(g: Geometry, nscal: int, seed: int, amp: float = 5.0,
-                noise: float = 0.01) -> dict:
-    """Interior fields (nx, ny, nz) for u, v, w and nscal scalars (th, q1, ...)."""
-    rng = np.random.default_rng(seed)
+def _one_field(g: Geometry, name: str, n: int, seed: int, amp: float, noise: float,
+               out: np.ndarray) -> None:
+    rng = np.random.default_rng([seed, n])
     xc = (np.arange(g.nx) + 0.5) * g.dx
     xf = (np.arange(g.nx) + 1.0) * g.dx
     yc = (np.arange(g.ny) + 0.5) * g.dy
     yf = (np.arange(g.ny) + 1.0) * g.dy
-    out = {}
+    modes = _draw_modes(rng)
+    if name == "u":
+        s = _mode_sum(g, modes, xf, yc, g.z_centre, False)
+    elif name == "v":
+        s = _mode_sum(g, modes, xc, yf, g.z_centre, False)
+    elif name == "w":
+        s = _mode_sum(g, modes, xc, yc, g.z_face, True)
+    else:
+        s = _mode_sum(g, modes, xc, yc, g.z_centre, False)
+    eps = rng.standard_normal(size=s.shape)
+    eps *= noise
+    if name in ("u", "v", "w"):
+        s *= amp
+        s += eps
+        if name == "w":
+            s[:, :, g.nz - 1] = 0.0
+    elif name == "th":
+        s *= 2.0
+        s += eps
+        s += 300.0
+    else:
+        s *= 0.5
+        s += eps
+        np.exp(s, out=s)
+        s *= 1e-3
+    out[...] = s
+
+
+def make_fields(g: Geometry, nscal: int, seed: int, amp: float = 5.0,
+                noise: float = 0.01, padded: bool = False, threads: int = 8) -> dict:
+    """Fields u, v, w and nscal scalars (th, q1, ...), interior (nx, ny, nz)
+    arrays, or [(nx+4)][(ny+4)][nz] arrays with a NaN halo if padded."""
+    import concurrent.futures as cf
     names = ["u", "v", "w"] + scalar_names(nscal)
+    out = {}
+    views = {}
     for name in names:
-        modes = _draw_modes(rng)
-        if name == "u":
-            s = _mode_sum(g, modes, xf, yc, g.z_centre, False)
-        elif name == "v":
-            s = _mode_sum(g, modes, xc, yf, g.z_centre, False)
-        elif name == "w":
-            s = _mode_sum(g, modes, xc, yc, g.z_face, True)
+        if padded:
+            a = np.full((g.nx + 4, g.ny + 4, g.nz), np.nan)
+            out[name] = a
+            views[name] = a[2:g.nx + 2, 2:g.ny + 2, :]
         else:
-            s = _mode_sum(g, modes, xc, yc, g.z_centre, False)
-        eps = rng.standard_normal(size=s.shape) * noise
-        if name in ("u", "v", "w"):
-            f = amp * s + eps
-            if name == "w":
-                f[:, :, g.nz - 1] = 0.0
-        elif name == "th":
-            f = 300.0 + 2.0 * s + eps
-        else:
-            f = 1e-3 * np.exp(0.5 * s + eps)
-        out[name] = f
+            out[name] = np.empty((g.nx, g.ny, g.nz))
+            views[name] = out[name]
+    with cf.ThreadPoolExecutor(max_workers=max(1, min(threads, len(names)))) as ex:
+        futs = [ex.submit(_one_field, g, name, n, seed, amp, noise, views[name])
+                for n, name in enumerate(names)]
+        for f in futs:
+            f.result()
     return out
 
 
@@ -221,10 +248,10 @@ WORKLOADS = {
 }
 
 
-def make_workload(name: str):
+def make_workload(name: str, padded: bool = False):
     w = WORKLOADS[name]
     g = make_geometry(w.nx, w.ny, w.nz, w.dx, w.dx)
-    f = make_fields(g, w.nscal, w.seed)
+    f = make_fields(g, w.nscal, w.seed, padded=padded)
     return w, g, f
 
 

@@ -1,0 +1,124 @@
+"""C-ABI checks that need no GPU: the library loads, exports every declared
+symbol, and rejects bad arguments before touching the HIP runtime."""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+from paper_2009_12850_amd import _lib as M
+
+FAKE = C.c_void_p(0x1000)  # never dereferenced: every call below fails validation
+
+
+def test_library_exports_every_header_symbol():
+    L = M.lib()
+    syms = M.header_symbols()
+    assert len(syms) >= 12
+    for s in syms:
+        assert hasattr(L, s), s
+
+
+def test_binding_covers_header():
+    for s in M.header_symbols():
+        assert s in M._SIGS, s
+
+
+def _prof3():
+    return FAKE, FAKE, FAKE
+
+
+@pytest.mark.parametrize("nx,ny,nz", [(0, 4, 4), (4, 0, 4), (4, 4, 1), (4, 4, 257)])
+def test_advect_pw_rejects_bad_grid(nx, ny, nz):
+    L = M.lib()
+    rc = L.monc_advect_pw(FAKE, FAKE, FAKE, C.c_void_p(0x2000), C.c_void_p(0x3000),
+                          C.c_void_p(0x4000), nx, ny, nz, 50.0, 50.0, *_prof3(), None)
+    assert rc == M.MONC_EINVAL
+    assert L.monc_last_error()
+
+
+@pytest.mark.parametrize("dx,dy", [(0.0, 1.0), (1.0, -1.0), (float("nan"), 1.0),
+                                   (float("inf"), 1.0)])
+def test_advect_pw_rejects_bad_spacing(dx, dy):
+    L = M.lib()
+    rc = L.monc_advect_pw(FAKE, FAKE, FAKE, C.c_void_p(0x2000), C.c_void_p(0x3000),
+                          C.c_void_p(0x4000), 4, 4, 4, dx, dy, *_prof3(), None)
+    assert rc == M.MONC_EINVAL
+
+
+def test_advect_pw_rejects_null_and_alias():
+    L = M.lib()
+    rc = L.monc_advect_pw(None, FAKE, FAKE, C.c_void_p(0x2000), C.c_void_p(0x3000),
+                          C.c_void_p(0x4000), 4, 4, 4, 1.0, 1.0, *_prof3(), None)
+    assert rc == M.MONC_EINVAL
+    rc = L.monc_advect_pw(FAKE, C.c_void_p(0x5000), C.c_void_p(0x6000), FAKE,
+                          C.c_void_p(0x3000), C.c_void_p(0x4000), 4, 4, 4, 1.0, 1.0,
+                          *_prof3(), None)
+    assert rc == M.MONC_EINVAL and b"alias" in L.monc_last_error()
+    rc = L.monc_advect_pw(FAKE, FAKE, FAKE, C.c_void_p(0x2000), C.c_void_p(0x3000),
+                          C.c_void_p(0x4000), 4, 4, 4, 1.0, 1.0, None, FAKE, FAKE, None)
+    assert rc == M.MONC_EINVAL
+
+
+def _arr(ptrs):
+    a = (C.c_void_p * len(ptrs))()
+    for n, p in enumerate(ptrs):
+        a[n] = p
+    return a
+
+
+def test_step_rejects_bad_arguments():
+    L = M.lib()
+    ins = _arr([0x1000 + 0x100 * n for n in range(5)])
+    outs = _arr([0x9000 + 0x100 * n for n in range(5)])
+    ok = dict(nscal=2, nx=8, ny=8, nz=8, dx=1.0, dy=1.0, dt=0.5)
+
+    def call(**kw):
+        a = dict(ok, **kw)
+        return L.monc_step(kw.get("ins", ins), kw.get("outs", outs), a["nscal"], a["nx"],
+                           a["ny"], a["nz"], a["dx"], a["dy"], *_prof3(), a["dt"],
+                           kw.get("budgets", None), kw.get("ws", None), None)
+
+    assert call(dt=0.0) == M.MONC_EINVAL
+    assert call(dt=float("nan")) == M.MONC_EINVAL
+    assert call(nscal=9) == M.MONC_EINVAL
+    assert call(nscal=-1) == M.MONC_EINVAL
+    assert call(outs=_arr([0x1000, 0x9100, 0x9200, 0x9300, 0x9400])) == M.MONC_EINVAL
+    assert call(ins=_arr([0x1000, 0, 0x1200, 0x1300, 0x1400])) == M.MONC_EINVAL
+    assert call(budgets=FAKE, ws=None) == M.MONC_EINVAL
+    assert call(nz=300) == M.MONC_EINVAL
+
+
+def test_advect_rejects_unknown_dtype_and_tvd_needs_scalars():
+    L = M.lib()
+    ins = _arr([0x1000 + 0x100 * n for n in range(5)])
+    outs = _arr([0x9000 + 0x100 * n for n in range(5)])
+    rc = L.monc_advect(7, ins, outs, 2, None, 8, 8, 8, 1.0, 1.0, *_prof3(), 0.5, None)
+    assert rc == M.MONC_EINVAL
+    q = _arr([0x1300])
+    sq = _arr([0x9300])
+    rc = L.monc_advect_tvd(FAKE, C.c_void_p(0x1100), C.c_void_p(0x1200), 0, q, sq, 8, 8,
+                           8, 1.0, 1.0, *_prof3(), 0.5, None)
+    assert rc == M.MONC_EINVAL
+    rc = L.monc_cast_working(M.MONC_F64, 1, q, sq, None, 8, 8, 8, None)
+    assert rc == M.MONC_EINVAL
+
+
+def test_budgets_check_maps_device_flags():
+    b = np.zeros(M.MONC_NBUDGET)
+    b[M.B_COURANT] = 0.3
+    assert M.monc_budgets_check(b) == M.MONC_OK
+    b[M.B_COURANT] = 1.5
+    assert M.monc_budgets_check(b) == M.MONC_ECFL
+    b[M.B_COURANT] = float("nan")
+    assert M.monc_budgets_check(b) == M.MONC_ECFL
+    b[M.B_COURANT] = 0.3
+    b[M.B_NONFINITE] = 2
+    assert M.monc_budgets_check(b) == M.MONC_ENONFINITE
+
+
+def test_strerror_and_workspace():
+    L = M.lib()
+    assert L.monc_strerror(M.MONC_ECFL) == b"Courant number above 1"
+    assert L.monc_strerror(12345) == b"unknown error"
+    assert M.monc_step_workspace_bytes(1024, 1024, 128, 2) > 0
+    assert M.monc_step_workspace_bytes(0, 4, 4, 2) == 0
