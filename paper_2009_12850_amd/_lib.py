@@ -61,6 +61,10 @@ def lib():
     """Load libmoncadv.so (raises if it has not been built)."""
     global _lib
     if _lib is None:
+        # torch must be loaded first: it carries its own copy of the HIP
+        # runtime (same soname), and the library must bind to that copy so that
+        # torch's device pointers and streams are valid in both.
+        import torch  # noqa: F401
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(
                 f"{LIB_PATH} is missing: build it with "
