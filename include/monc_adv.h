@@ -60,7 +60,7 @@ enum {
 };
 
 #define MONC_MAX_SCALARS 8
-#define MONC_MAX_NZ 256
+#define MONC_MAX_NZ 128
 
 /* Storage types of the precision form (Sec. 4.1 marshals the fields into a
  * narrower type before advection and widens the source terms afterwards). */

@@ -19,7 +19,7 @@ MONC_OK, MONC_EINVAL, MONC_EHIP, MONC_ECFL, MONC_ENONFINITE, MONC_EUNSUPPORTED =
     0, -1, -2, -3, -4, -5
 MONC_F64, MONC_F32, MONC_BF16 = 0, 1, 2
 MONC_MAX_SCALARS = 8
-MONC_MAX_NZ = 256
+MONC_MAX_NZ = 128
 B_CU, B_CV, B_CW, B_PU, B_QU, B_PV, B_QV, B_PW, B_QW, B_COURANT, B_NONFINITE = range(11)
 B_SCALAR0 = 11
 MONC_NBUDGET = B_SCALAR0 + 3 * MONC_MAX_SCALARS

@@ -1,0 +1,585 @@
+// march.hpp -- the fused MONC advection kernel for gfx950 ("column march").
+//
+// Evaluates the Piacsek-Williams momentum source terms and the ULTIMATE /
+// QUICKEST scalar source terms (Brown et al., Sec. 3.1) for every interior
+// point, optionally integrates them ("step fields", Sec. 3) and accumulates
+// FP64 budget partials, in one pass over the fields.
+//
+// Work decomposition.  A workgroup of 8 waves owns TJ = 8/NCH consecutive
+// columns j0..j0+TJ-1; a column of nz <= 64*NCH levels is split into NCH
+// chunks of 64 levels, one wave per (column, chunk), lane l <-> level
+// k = 64*chunk + l.  The workgroup marches along x through a segment of
+// planes i0..i1-1.
+//   * x-neighbours: a register window per column (planes i-1..i+1 for the
+//     velocities, i-1..i+2 for scalars), each plane read from HBM once and
+//     prefetched one plane ahead;
+//   * y-neighbours: LDS slices of the current planes, 1 halo column each
+//     side for velocities (two planes per velocity, double-buffered by plane
+//     parity) and 2 for scalars; the halo columns are loaded round-robin by
+//     the waves, one plane ahead;
+//   * z-neighbours of values: the same LDS slices at k +- 1, +- 2;
+//   * every face flux is computed once: the x-face i-1/2 is carried in
+//     registers from the previous plane, the y-face j-1/2 is read from the
+//     neighbouring wave through LDS, the z-face k-1/2 from the neighbouring
+//     lane through a cross-lane shuffle (across a chunk boundary, through a
+//     small LDS array).
+// Per plane: store slices, barrier, compute values and faces, barrier, finish.
+#pragma once
+
+#include <type_traits>
+
+#include "monc_internal.hpp"
+#include "monc_scheme.hpp"
+
+namespace monc {
+
+struct MarchArgs {
+    AdvArgs a;
+    int s0;          // first scalar of this launch's group
+    int ns;          // number of scalars in the group
+    int ti;          // planes per x-segment
+    int njt;         // tiles along y
+    int nseg;        // segments along x
+    int first_pass;  // this launch writes every budget slot it does not own
+};
+
+// Per-level coefficient table kept in LDS.
+enum {
+    LV_ZTERM = 0, LV_RHOKM, LV_RHO, LV_RHOKP, LV_ALPHA, LV_BETA, LV_RHOINV, LV_RDZN,
+    LV_RHON, LV_RHONINV, LV_RDZ, LV_RFZ, LV_MASS, LV_WMASS, LV_DZ, NLEV
+};
+
+template <typename Ts>
+__device__ __forceinline__ Ts zero_of() {
+    return Ts(0);
+}
+template <>
+__device__ __forceinline__ bf16 zero_of<bf16>() {
+    bf16 z;
+    z.bits = 0;
+    return z;
+}
+
+// storage -> compute, subtracting `off` first when the storage is FP64
+template <typename T, typename Ts>
+__device__ __forceinline__ T cvt(Ts x, double off) {
+    if constexpr (std::is_same<Ts, double>::value) {
+        return (T)(x - off);
+    } else if constexpr (std::is_same<Ts, float>::value) {
+        return (T)x;
+    } else {
+        return __uint_as_float(((uint32_t)x.bits) << 16);
+    }
+}
+template <typename T, typename Ts>
+__device__ __forceinline__ T cvt0(Ts x) {
+    if constexpr (std::is_same<Ts, bf16>::value) {
+        return __uint_as_float(((uint32_t)x.bits) << 16);
+    } else {
+        return (T)x;
+    }
+}
+
+constexpr int MARCH_WAVES = 8;
+
+__host__ __device__ constexpr int march_nq(int ns, int nch) {
+    return ((6 + 4 * ns) * nch + MARCH_WAVES - 1) / MARCH_WAVES;
+}
+
+template <typename T, int NS, int NCH>
+__host__ __device__ constexpr size_t march_lds_bytes() {
+    constexpr int TJ = MARCH_WAVES / NCH;
+    return (size_t)(6 * (TJ + 2) + NS * (TJ + 4) + NS * (TJ + 1) + NLEV) * (64 * NCH) *
+               sizeof(T) +
+           (size_t)(NS > 0 ? NS : 1) * MARCH_WAVES * sizeof(T);
+}
+
+__device__ __forceinline__ int bud_op(int q) {
+    if (q == MONC_B_COURANT) return 1;
+    if (q >= MONC_B_SCALAR0 && (q - MONC_B_SCALAR0) % 3 == 2) return 2;
+    return 0;
+}
+__device__ __forceinline__ double bud_comb(double a, double b, int op) {
+    return op == 0 ? a + b : (op == 1 ? fmax(a, b) : fmin(a, b));
+}
+__device__ __forceinline__ double bud_ident(int op) {
+    return op == 2 ? __builtin_huge_val() : 0.0;
+}
+
+template <typename Ts, typename T, int MODE, bool PW, int NS, bool BUD, int NCH>
+__global__ void __launch_bounds__(MARCH_WAVES * 64) advect_march(MarchArgs m) {
+    using To = typename std::conditional<std::is_same<T, double>::value, double, float>::type;
+    constexpr int TJ = MARCH_WAVES / NCH;
+    constexpr int NZP = 64 * NCH;
+    constexpr int VC = TJ + 2;  // velocity slice columns: j0-1 .. j0+TJ
+    constexpr int SC = TJ + 4;  // scalar slice columns:   j0-2 .. j0+TJ+1
+    constexpr int FC = TJ + 1;  // y-faces j0-1/2 .. j0+TJ-1/2
+    constexpr int NSA = NS > 0 ? NS : 1;
+    constexpr int NQ = march_nq(NS, NCH);
+    constexpr int NACC = MONC_B_SCALAR0 + 3 * NS;
+
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* const vel = reinterpret_cast<T*>(smem_raw);  // [3][2][VC][NZP]
+    T* const sph = vel + 6 * VC * NZP;              // [NS][SC][NZP]
+    T* const sfy = sph + NS * SC * NZP;             // [NS][FC][NZP]
+    T* const lev = sfy + NS * FC * NZP;             // [NLEV][NZP]
+    T* const fzc = lev + NLEV * NZP;                // [NS][TJ][NCH] chunk-top faces
+
+    const AdvArgs& a = m.a;
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const long sx = (long)(ny + 4) * nz;
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const int cc = wv / NCH;  // column within the tile
+    const int ch = wv % NCH;  // chunk within the column
+    const int k = 64 * ch + lane;
+    const int ns = NS > 0 ? m.ns : 0;
+
+    // Tiles: consecutive tiles along y go to the same XCD (workgroups are
+    // dealt to the 8 XCDs round-robin), so neighbouring tiles share halo
+    // columns through that XCD's L2.
+    int b = blockIdx.x;
+    const int nb = gridDim.x;
+    if ((nb & 7) == 0) b = (b & 7) * (nb >> 3) + (b >> 3);
+    const int jt = b % m.njt, seg = b / m.njt;
+    const int j0 = jt * TJ;
+    const int i0 = seg * m.ti;
+    const int i1 = min(i0 + m.ti, nx);
+    const int j = j0 + cc;
+    const bool own_ok = j <= ny + 1;  // column exists in the padded array
+    const bool active = j < ny;       // interior column: compute and store
+    const bool kin = k < nz;
+    const bool kb = k >= 1, kt = k + 1 < nz, ktt = k + 2 < nz;
+
+    const double dt = a.dt;
+    // ---- level table (row a2: vertical geometry from rdz, rho, rhon) ----
+    for (int kk = threadIdx.x; kk < NZP; kk += MARCH_WAVES * 64) {
+        double v[NLEV];
+#pragma unroll
+        for (int q = 0; q < NLEV; q++) v[q] = 0.0;
+        if (kk < nz) {
+            const double rdzk = a.rdz[kk], rhonk = a.rhon[kk], rhok = a.rho[kk];
+            const double dzk = 1.0 / rdzk;
+            v[LV_ZTERM] = rdzk / (4.0 * rhonk);
+            v[LV_RHOKM] = kk > 0 ? a.rho[kk - 1] : 0.0;
+            v[LV_RHO] = rhok;
+            v[LV_RHOKP] = kk < nz - 1 ? a.rho[kk + 1] : 0.0;
+            v[LV_RHOINV] = 1.0 / rhok;
+            v[LV_RHON] = rhonk;
+            v[LV_RHONINV] = 1.0 / rhonk;
+            v[LV_RDZ] = rdzk;
+            v[LV_MASS] = rhonk * dzk;
+            v[LV_DZ] = dzk;
+            if (kk < nz - 1) {
+                const double dzk1 = 1.0 / a.rdz[kk + 1];
+                const double dzn = 0.5 * (dzk + dzk1);
+                v[LV_RDZN] = 1.0 / dzn;
+                v[LV_ALPHA] = dzk * rhonk / (2.0 * dzn);
+                v[LV_BETA] = dzk1 * a.rhon[kk + 1] / (2.0 * dzn);
+                v[LV_RFZ] = dzn / dt;
+                v[LV_WMASS] = rhok * dzn;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < NLEV; q++) lev[q * NZP + kk] = (T)v[q];
+    }
+
+    const T r4dx = (T)(0.25 / a.dx), r4dy = (T)(0.25 / a.dy);
+    const T r2dx = (T)(0.5 / a.dx), r2dy = (T)(0.5 / a.dy);
+    const T rdx = (T)(1.0 / a.dx), rdy = (T)(1.0 / a.dy);
+    const T cfx = (T)(dt / a.dx), cfy = (T)(dt / a.dy);
+    const T rfx = (T)(a.dx / dt), rfy = (T)(a.dy / dt);
+    const T dtc = (T)dt;
+
+    const Ts* __restrict__ Up = (const Ts*)a.in[0];
+    const Ts* __restrict__ Vp = (const Ts*)a.in[1];
+    const Ts* __restrict__ Wp = (const Ts*)a.in[2];
+    const Ts* Qp[NSA];
+    double off[NSA];
+    T phi0c[NSA];
+#pragma unroll
+    for (int s = 0; s < NS; s++) {
+        Qp[s] = s < ns ? (const Ts*)a.in[3 + m.s0 + s] : nullptr;
+        off[s] = (MODE == STEP && s < ns) ? a.phi0[m.s0 + s] : 0.0;
+        phi0c[s] = s < ns ? (T)a.phi0[m.s0 + s] : (T)0;
+    }
+
+    auto gbase = [&](int ii, int jj) -> long {
+        return (long)(ii + 2) * sx + (long)(jj + 2) * nz;
+    };
+    // one chunk of one column (plane ii, column jj, levels 64*chunk + lane);
+    // the lid level of w reads as 0
+    auto ldc = [&](const Ts* __restrict__ p, int ii, int jj, int chunk, bool isw) -> Ts {
+        const int kk = 64 * chunk + lane;
+        Ts x = zero_of<Ts>();
+        if (kk < nz && !(isw && kk >= nz - 1)) x = p[gbase(ii, jj) + kk];
+        return x;
+    };
+    auto vslot = [&](int f, int plane) -> T* {
+        return vel + (size_t)((f * 2 + (plane & 1)) * VC) * NZP;
+    };
+    auto field_ptr = [&](int f) -> const Ts* {
+        if (f == 0) return Up;
+        if (f == 1) return Vp;
+        if (f == 2) return Wp;
+        const Ts* p = Up;
+#pragma unroll
+        for (int s = 0; s < NS; s++)
+            if (f == 3 + s) p = Qp[s];
+        return p;
+    };
+    // Halo job q of the slices stored at plane step i (for each chunk):
+    // velocities u(i), v(i+1), w(i+1) at columns j0-1 and j0+TJ; scalar s at
+    // plane i, columns j0-2, j0-1, j0+TJ, j0+TJ+1.
+    const int nj = (6 + 4 * ns) * NCH;
+    auto job = [&](int id, int& f, int& dpl, int& jj, int& c, int& chunk) {
+        chunk = id % NCH;
+        const int h = id / NCH;
+        if (h < 6) {
+            f = h >> 1;
+            dpl = f == 0 ? 0 : 1;
+            const bool right = h & 1;
+            jj = right ? j0 + TJ : j0 - 1;
+            c = right ? TJ + 1 : 0;
+        } else {
+            const int s = (h - 6) >> 2, q = (h - 6) & 3;
+            f = 3 + s;
+            dpl = 0;
+            jj = q == 0 ? j0 - 2 : (q == 1 ? j0 - 1 : (q == 2 ? j0 + TJ : j0 + TJ + 1));
+            c = q == 0 ? 0 : (q == 1 ? 1 : (q == 2 ? TJ + 2 : TJ + 3));
+        }
+    };
+    auto job_load = [&](int id, int i) -> Ts {
+        Ts x = zero_of<Ts>();
+        if (id < nj) {
+            int f, dpl, jj, c, chunk;
+            job(id, f, dpl, jj, c, chunk);
+            if (jj <= ny + 1) x = ldc(field_ptr(f), i + dpl, jj, chunk, f == 2);
+        }
+        return x;
+    };
+    auto job_store = [&](int id, int i, Ts x) {
+        if (id >= nj) return;
+        int f, dpl, jj, c, chunk;
+        job(id, f, dpl, jj, c, chunk);
+        if (jj > ny + 1) return;
+        T* dst;
+        double o = 0.0;
+        if (f < 3) {
+            dst = vslot(f, i + dpl) + (size_t)c * NZP;
+        } else {
+            const int s = f - 3;
+            dst = sph + (size_t)(s * SC + c) * NZP;
+#pragma unroll
+            for (int q = 0; q < NS; q++)
+                if (q == s) o = off[q];
+        }
+        dst[64 * chunk + lane] = cvt<T, Ts>(x, o);
+    };
+
+    // ---- register windows ----
+    Ts U[3], V[3], W[3];   // planes i-1, i, i+1 of the own column
+    Ts P[NSA][4];          // planes i-1 .. i+2
+    T FXm[NSA];            // flux through the x-face i-1/2
+    Ts HB[NQ];             // halo columns of the next plane step
+    double acc[BUD ? NACC : 1];
+    if constexpr (BUD) {
+#pragma unroll
+        for (int q = 0; q < NACC; q++) acc[q] = bud_ident(bud_op(q));
+    }
+
+    // ---- prologue: windows at i0, the carried x-face, the first slices ----
+    __syncthreads();  // level table visible
+#pragma unroll
+    for (int p = 0; p < 3; p++) {
+        U[p] = own_ok ? ldc(Up, i0 - 1 + p, j, ch, false) : zero_of<Ts>();
+        V[p] = own_ok ? ldc(Vp, i0 - 1 + p, j, ch, false) : zero_of<Ts>();
+        W[p] = own_ok ? ldc(Wp, i0 - 1 + p, j, ch, true) : zero_of<Ts>();
+    }
+    const int kl = k < NZP ? k : NZP - 1;
+#pragma unroll
+    for (int s = 0; s < NS; s++) {
+        Ts Pm2 = zero_of<Ts>();
+#pragma unroll
+        for (int p = 0; p < 4; p++) P[s][p] = zero_of<Ts>();
+        if (own_ok && s < ns) {
+            Pm2 = ldc(Qp[s], i0 - 2, j, ch, false);
+#pragma unroll
+            for (int p = 0; p < 4; p++) P[s][p] = ldc(Qp[s], i0 - 1 + p, j, ch, false);
+        }
+        FXm[s] = tvd_flux<T>(cvt0<T, Ts>(U[0]), cvt<T, Ts>(Pm2, off[s]), cvt<T, Ts>(P[s][0], off[s]),
+                             cvt<T, Ts>(P[s][1], off[s]), cvt<T, Ts>(P[s][2], off[s]), cfx, rfx,
+                             lev[LV_RHON * NZP + kl]);
+    }
+    if (own_ok) {
+        vslot(0, i0 - 1)[(cc + 1) * NZP + k] = cvt0<T, Ts>(U[0]);
+        vslot(1, i0)[(cc + 1) * NZP + k] = cvt0<T, Ts>(V[1]);
+        vslot(2, i0)[(cc + 1) * NZP + k] = cvt0<T, Ts>(W[1]);
+    }
+    // halo columns of u(i0-1), v(i0), w(i0)
+    for (int id = wv; id < 6 * NCH; id += MARCH_WAVES) {
+        const int chunk = id % NCH, h = id / NCH;
+        const int f = h >> 1;
+        const bool right = h & 1;
+        const int jj = right ? j0 + TJ : j0 - 1;
+        const int c = right ? TJ + 1 : 0;
+        const int pl = f == 0 ? i0 - 1 : i0;
+        if (jj > ny + 1) continue;
+        const Ts x = ldc(field_ptr(f), pl, jj, chunk, f == 2);
+        vslot(f, pl)[(size_t)c * NZP + 64 * chunk + lane] = cvt0<T, Ts>(x);
+    }
+#pragma unroll
+    for (int q = 0; q < NQ; q++) HB[q] = job_load(wv + MARCH_WAVES * q, i0);
+
+    // ---- the march ----
+    for (int i = i0; i < i1; i++) {
+        // slices of step i
+        if (own_ok) {
+            vslot(0, i)[(cc + 1) * NZP + k] = cvt0<T, Ts>(U[1]);
+            vslot(1, i + 1)[(cc + 1) * NZP + k] = cvt0<T, Ts>(V[2]);
+            vslot(2, i + 1)[(cc + 1) * NZP + k] = cvt0<T, Ts>(W[2]);
+#pragma unroll
+            for (int s = 0; s < NS; s++)
+                sph[(size_t)(s * SC + cc + 2) * NZP + k] = cvt<T, Ts>(P[s][1], off[s]);
+        }
+#pragma unroll
+        for (int q = 0; q < NQ; q++) job_store(wv + MARCH_WAVES * q, i, HB[q]);
+        // prefetch of step i+1: own column and halo columns
+        Ts NU = zero_of<Ts>(), NV = zero_of<Ts>(), NW = zero_of<Ts>();
+        Ts NP[NSA];
+        const bool more = i + 1 < i1;
+        if (more && own_ok) {
+            NU = ldc(Up, i + 2, j, ch, false);
+            NV = ldc(Vp, i + 2, j, ch, false);
+            NW = ldc(Wp, i + 2, j, ch, true);
+#pragma unroll
+            for (int s = 0; s < NS; s++)
+                if (s < ns) NP[s] = ldc(Qp[s], i + 3, j, ch, false);
+        }
+        if (more) {
+#pragma unroll
+            for (int q = 0; q < NQ; q++) HB[q] = job_load(wv + MARCH_WAVES * q, i + 1);
+        }
+        __syncthreads();
+
+        const T* u_i = vslot(0, i);
+        const T* u_im = vslot(0, i - 1);
+        const T* v_i = vslot(1, i);
+        const T* v_ip = vslot(1, i + 1);
+        const T* w_i = vslot(2, i);
+        const T* w_ip = vslot(2, i + 1);
+        const int cv = cc + 1;
+        const int cs = cc + 2;
+        const long g = gbase(i, j) + k;
+        const bool store = active && kin;
+        auto Lc = [&](const T* slot, int c, int kk, bool ok) -> T {
+            return ok ? slot[c * NZP + kk] : (T)0;
+        };
+
+        // Scalars keep across the face barrier only a partial sum and their
+        // top-face flux; momentum is finished (and stored) before it.
+        T part[NSA], fzk[NSA];
+        const T uc = cvt0<T, Ts>(U[1]), um = cvt0<T, Ts>(U[0]);
+        const T vc = cvt0<T, Ts>(V[1]);
+        const T wc = cvt0<T, Ts>(W[1]);
+        const T vs = v_i[(cv - 1) * NZP + k];
+        const T wb = Lc(w_i, cv, k - 1, kb);
+        const T rhon = lev[LV_RHON * NZP + k];
+        const T rho = lev[LV_RHO * NZP + k];
+        const T rho_km = lev[LV_RHOKM * NZP + k];
+        const T rdz = lev[LV_RDZ * NZP + k];
+        const T rhon_inv = lev[LV_RHONINV * NZP + k];
+        // anelastic mass divergence of this cell
+        const T D = rhon * ((uc - um) * rdx + (vc - vs) * rdy) + rdz * (rho * wc - rho_km * wb);
+        if constexpr (PW) {
+            const T up = cvt0<T, Ts>(U[2]);
+            const T vw = cvt0<T, Ts>(V[0]), ve = cvt0<T, Ts>(V[2]);
+            const T ww = cvt0<T, Ts>(W[0]), we = cvt0<T, Ts>(W[2]);
+            Level<T> L;
+            L.zterm = lev[LV_ZTERM * NZP + k];
+            L.rho_km = rho_km;
+            L.rho = rho;
+            L.rho_kp = lev[LV_RHOKP * NZP + k];
+            L.alpha = lev[LV_ALPHA * NZP + k];
+            L.beta = lev[LV_BETA * NZP + k];
+            L.rho_inv = lev[LV_RHOINV * NZP + k];
+            L.rdzn = lev[LV_RDZN * NZP + k];
+            const T us = u_i[(cv - 1) * NZP + k], un = u_i[(cv + 1) * NZP + k];
+            const T ub = Lc(u_i, cv, k - 1, kb), ut = Lc(u_i, cv, k + 1, kt);
+            const T u_nw = u_im[(cv + 1) * NZP + k], u_wt = Lc(u_im, cv, k + 1, kt);
+            const T vn = v_i[(cv + 1) * NZP + k];
+            const T vb = Lc(v_i, cv, k - 1, kb), vt = Lc(v_i, cv, k + 1, kt);
+            const T v_st = Lc(v_i, cv - 1, k + 1, kt), v_es = v_ip[(cv - 1) * NZP + k];
+            const T ws = w_i[(cv - 1) * NZP + k], wn = w_i[(cv + 1) * NZP + k];
+            const T wt = Lc(w_i, cv, k + 1, kt), w_nb = Lc(w_i, cv + 1, k - 1, kb);
+            const T w_eb = Lc(w_ip, cv, k - 1, kb);
+            const T su = pw_su<T>(um, uc, up, us, un, ub, ut, vs, v_es, vc, ve, wb, w_eb, wc, we,
+                                  L, r4dx, r4dy);
+            const T sv = pw_sv<T>(vw, vc, ve, vs, vn, vb, vt, um, u_nw, uc, un, wb, w_nb, wc, wn,
+                                  L, r4dx, r4dy);
+            const T sw = kt ? pw_sw<T>(uc, ut, um, u_wt, vc, vt, vs, v_st, wc, ww, we, ws, wn, wb,
+                                       wt, L, r2dx, r2dy)
+                            : (T)0;
+            if (store) {
+                if constexpr (MODE == TEND) {
+                    ((To*)a.out[0])[g] = (To)su;
+                    ((To*)a.out[1])[g] = (To)sv;
+                    ((To*)a.out[2])[g] = (To)sw;
+                } else {
+                    const double nu = (double)U[1] + dt * (double)su;
+                    const double nv = (double)V[1] + dt * (double)sv;
+                    const double nw = kt ? (double)W[1] + dt * (double)sw : 0.0;
+                    ((double*)a.out[0])[g] = nu;
+                    ((double*)a.out[1])[g] = nv;
+                    ((double*)a.out[2])[g] = nw;
+                    if constexpr (BUD) {
+                        const double ucd = (double)U[1], umd = (double)U[0];
+                        const double vcd = (double)V[1], vsd = (double)vs;
+                        const double wcd = (double)W[1], wbd = (double)wb;
+                        const double Dd = (double)D;
+                        const double mass = (double)lev[LV_MASS * NZP + k];
+                        const double wmass = (double)lev[LV_WMASS * NZP + k];
+                        const double dzk = (double)lev[LV_DZ * NZP + k];
+                        acc[MONC_B_CU] += mass * (double)su;
+                        acc[MONC_B_CV] += mass * (double)sv;
+                        acc[MONC_B_PU] += mass * ucd * (double)su;
+                        acc[MONC_B_PV] += mass * vcd * (double)sv;
+                        acc[MONC_B_QU] += -0.25 * dzk * Dd * (ucd * ucd + umd * umd);
+                        acc[MONC_B_QV] += -0.25 * dzk * Dd * (vcd * vcd + vsd * vsd);
+                        acc[MONC_B_QW] += -0.25 * dzk * Dd * (wcd * wcd + wbd * wbd);
+                        acc[MONC_B_CW] += wmass * (double)sw;
+                        acc[MONC_B_PW] += wmass * wcd * (double)sw;
+                        const double cr =
+                            fmax(fmax(fabs(ucd) * dt / a.dx, fabs(vcd) * dt / a.dy),
+                                 fabs(wcd) * dt * (double)L.rdzn);
+                        acc[MONC_B_COURANT] = fmax(acc[MONC_B_COURANT], cr);
+                        acc[MONC_B_NONFINITE] +=
+                            (double)((!isfinite(nu)) + (!isfinite(nv)) + (!isfinite(nw)));
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < NS; s++) {
+            if (s >= ns) continue;
+            const T* ph = sph + (size_t)s * SC * NZP;
+            const T pm = cvt<T, Ts>(P[s][0], off[s]);
+            const T pc = cvt<T, Ts>(P[s][1], off[s]);
+            const T pe = cvt<T, Ts>(P[s][2], off[s]);
+            const T pee = cvt<T, Ts>(P[s][3], off[s]);
+            const T fxp = tvd_flux<T>(uc, pm, pc, pe, pee, cfx, rfx, rhon);
+            const T ps = ph[(cs - 1) * NZP + k], pn = ph[(cs + 1) * NZP + k],
+                    pnn = ph[(cs + 2) * NZP + k];
+            const T fyp = tvd_flux<T>(vc, ps, pc, pn, pnn, cfy, rfy, rhon);
+            sfy[(size_t)(s * FC + cc + 1) * NZP + k] = fyp;
+            if (cc == 0) {
+                sfy[(size_t)(s * FC) * NZP + k] =
+                    tvd_flux<T>(vs, ph[(cs - 2) * NZP + k], ps, pc, pn, cfy, rfy, rhon);
+            }
+            T fz = 0;
+            if (kt) {
+                const T pb = Lc(ph, cs, k - 1, kb);
+                const T pt = ph[cs * NZP + k + 1];
+                const T ptt = Lc(ph, cs, k + 2, ktt);
+                const bool pos = wc >= (T)0;
+                if ((pos && k == 0) || (!pos && !ktt)) {
+                    fz = upwind_flux<T>(wc, pc, pt, rho);
+                } else {
+                    fz = tvd_flux<T>(wc, pb, pc, pt, ptt, dtc * lev[LV_RDZN * NZP + k],
+                                     lev[LV_RFZ * NZP + k], rho);
+                }
+            }
+            fzk[s] = fz;
+            if (NCH > 1 && lane == 63) fzc[(s * TJ + cc) * NCH + ch] = fz;
+            // everything but the faces shared with the neighbours (j-1/2,
+            // k-1/2); stored values are anomalies from phi0: add the term of
+            // the constant
+            part[s] = -rhon_inv * ((fxp - FXm[s]) * rdx + fyp * rdy + rdz * fz) -
+                      phi0c[s] * D * rhon_inv;
+            FXm[s] = fxp;
+        }
+        __syncthreads();
+
+        // finish the scalars: the y-face below from LDS, the z-face below from
+        // the neighbouring lane (or the chunk below)
+#pragma unroll
+        for (int s = 0; s < NS; s++) {
+            if (s >= ns) continue;
+            const T up1 = __shfl_up(fzk[s], 1, 64);
+            T fzm = up1;
+            if (lane == 0) fzm = ch == 0 ? (T)0 : fzc[(s * TJ + cc) * NCH + ch - 1];
+            const T fym = sfy[(size_t)(s * FC + cc) * NZP + k];
+            const T val = part[s] + rhon_inv * (fym * rdy + rdz * fzm);
+            if (store) {
+                if constexpr (MODE == TEND) {
+                    ((To*)a.out[3 + m.s0 + s])[g] = (To)val;
+                } else {
+                    const double nsv = (double)P[s][1] + dt * (double)val;
+                    ((double*)a.out[3 + m.s0 + s])[g] = nsv;
+                    if constexpr (BUD) {
+                        const double ph = (double)P[s][1];
+                        const double mass = (double)lev[LV_MASS * NZP + k];
+                        acc[MONC_B_SCALAR0 + 3 * s] += mass * (double)val;
+                        acc[MONC_B_SCALAR0 + 3 * s + 1] += mass * ph;
+                        acc[MONC_B_SCALAR0 + 3 * s + 2] = fmin(acc[MONC_B_SCALAR0 + 3 * s + 2], ph);
+                        acc[MONC_B_NONFINITE] += (double)(!isfinite(nsv));
+                    }
+                }
+            }
+        }
+
+        // rotate the windows
+        U[0] = U[1];
+        U[1] = U[2];
+        V[0] = V[1];
+        V[1] = V[2];
+        W[0] = W[1];
+        W[1] = W[2];
+        if (more && own_ok) {
+            U[2] = NU;
+            V[2] = NV;
+            W[2] = NW;
+        }
+#pragma unroll
+        for (int s = 0; s < NS; s++) {
+            P[s][0] = P[s][1];
+            P[s][1] = P[s][2];
+            P[s][2] = P[s][3];
+            if (more && own_ok && s < ns) P[s][3] = NP[s];
+        }
+    }
+
+    if constexpr (BUD) {
+        // block reduction in a fixed order, reusing the LDS
+        __syncthreads();
+        double* red = reinterpret_cast<double*>(smem_raw);  // [waves][NACC]
+#pragma unroll
+        for (int q = 0; q < NACC; q++) {
+            const int op = bud_op(q);
+            double v = acc[q];
+            for (int o = 32; o > 0; o >>= 1) v = bud_comb(v, __shfl_xor(v, o, 64), op);
+            if (lane == 0) red[wv * NACC + q] = v;
+        }
+        __syncthreads();
+        if (threadIdx.x < NB) {
+            const int q = threadIdx.x;
+            const int op = bud_op(q);
+            double* row = a.partials + (size_t)blockIdx.x * NB;
+            const bool scalar_slot = q >= MONC_B_SCALAR0;
+            const int s = scalar_slot ? (q - MONC_B_SCALAR0) / 3 : -1;
+            const bool mine_scalar = scalar_slot && s >= m.s0 && s < m.s0 + ns;
+            const bool mine_mom = !scalar_slot && PW;
+            if (mine_scalar || mine_mom || q == MONC_B_NONFINITE) {
+                const int lq = scalar_slot ? q - 3 * m.s0 : q;
+                double v = red[lq];
+                for (int w2 = 1; w2 < MARCH_WAVES; w2++) v = bud_comb(v, red[w2 * NACC + lq], op);
+                if (q == MONC_B_NONFINITE && !m.first_pass) v += row[q];
+                row[q] = v;
+            } else if (m.first_pass) {
+                row[q] = bud_ident(op);
+            }
+        }
+    }
+}
+
+}  // namespace monc

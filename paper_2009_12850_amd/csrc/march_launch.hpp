@@ -1,0 +1,87 @@
+// march_launch.hpp -- host-side launch of the column-march kernel for one
+// storage type / compute type / mode.  Included by one source file per
+// combination so the instantiations compile in parallel.
+#pragma once
+
+#include "march.hpp"
+
+namespace monc {
+
+struct Tiling {
+    int tj, ti, njt, nseg, nblocks;
+};
+Tiling march_tiling(int nx, int ny, int nz);
+
+template <typename Ts, typename T, int MODE, bool PW, int NS, bool BUD, int R>
+hipError_t launch_one(const MarchArgs& m, const Tiling& t, hipStream_t s) {
+    auto kern = advect_march<Ts, T, MODE, PW, NS, BUD, R>;
+    constexpr size_t lds = march_lds_bytes<T, NS, R>();
+    static bool attr_done = false;
+    if (!attr_done) {
+        hipError_t e = hipFuncSetAttribute((const void*)kern,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        attr_done = true;
+    }
+    kern<<<t.nblocks, MARCH_WAVES * 64, lds, s>>>(m);
+    return hipGetLastError();
+}
+
+template <typename Ts, typename T, int MODE, bool PW, bool BUD, int R>
+hipError_t launch_ns(const MarchArgs& m, const Tiling& t, hipStream_t s) {
+    switch (m.ns) {
+        case 0:
+            if constexpr (PW) return launch_one<Ts, T, MODE, PW, 0, BUD, R>(m, t, s);
+            break;
+        case 1: return launch_one<Ts, T, MODE, PW, 1, BUD, R>(m, t, s);
+        case 2: return launch_one<Ts, T, MODE, PW, 2, BUD, R>(m, t, s);
+        case 3: return launch_one<Ts, T, MODE, PW, 3, BUD, R>(m, t, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <typename Ts, typename T, int MODE, bool PW, bool BUD>
+hipError_t launch_r(const MarchArgs& m, const Tiling& t, hipStream_t s) {
+    if (m.a.nz <= 64) return launch_ns<Ts, T, MODE, PW, BUD, 1>(m, t, s);
+    return launch_ns<Ts, T, MODE, PW, BUD, 2>(m, t, s);
+}
+
+// Launch the whole evaluation: scalars in groups of at most 3 per pass (2
+// when budgets are accumulated) so that a wave's state fits its 256
+// registers without spilling; the first pass also does the momentum (if
+// requested).
+template <typename Ts, typename T, int MODE>
+hipError_t launch_march_t(bool pw, bool tvd, const AdvArgs& a, hipStream_t s) {
+    const Tiling t = march_tiling(a.nx, a.ny, a.nz);
+    const bool bud = a.partials != nullptr;
+    const int nscal = tvd ? a.nscal : 0;
+    const int group = bud ? 2 : 3;
+    int s0 = 0;
+    bool first = true;
+    do {
+        MarchArgs m;
+        m.a = a;
+        m.s0 = s0;
+        m.ns = nscal - s0 < group ? nscal - s0 : group;
+        m.ti = t.ti;
+        m.njt = t.njt;
+        m.nseg = t.nseg;
+        m.first_pass = first ? 1 : 0;
+        const bool with_pw = pw && first;
+        hipError_t e;
+        if (with_pw) {
+            e = bud ? launch_r<Ts, T, MODE, true, true>(m, t, s)
+                    : launch_r<Ts, T, MODE, true, false>(m, t, s);
+        } else {
+            if (m.ns == 0) break;
+            e = bud ? launch_r<Ts, T, MODE, false, true>(m, t, s)
+                    : launch_r<Ts, T, MODE, false, false>(m, t, s);
+        }
+        if (e != hipSuccess) return e;
+        s0 += m.ns;
+        first = false;
+    } while (s0 < nscal);
+    return hipSuccess;
+}
+
+}  // namespace monc

@@ -99,20 +99,17 @@ __global__ void __launch_bounds__(256) budget_final(const double* __restrict__ p
                                                     int nblocks, double* __restrict__ out) {
     __shared__ double red[4];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int q = 0; q < NB; q++) {
-        const int op = bop(q);
-        double v = op == 2 ? __builtin_huge_val() : 0.0;
-        for (int b = threadIdx.x; b < nblocks; b += 256)
-            v = bcomb(v, partials[(long)b * NB + q], op);
-        for (int o = 32; o > 0; o >>= 1) v = bcomb(v, __shfl_xor(v, o, 64), op);
-        if (lane == 0) red[wave] = v;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            double r = red[0];
-            for (int w = 1; w < 4; w++) r = bcomb(r, red[w], op);
-            out[q] = r;
-        }
-        __syncthreads();
+    const int q = blockIdx.x;  // one workgroup per budget entry
+    const int op = bop(q);
+    double v = op == 2 ? __builtin_huge_val() : 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += 256) v = bcomb(v, partials[(long)b * NB + q], op);
+    for (int o = 32; o > 0; o >>= 1) v = bcomb(v, __shfl_xor(v, o, 64), op);
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double r = red[0];
+        for (int w = 1; w < 4; w++) r = bcomb(r, red[w], op);
+        out[q] = r;
     }
 }
 
@@ -163,7 +160,7 @@ hipError_t launch_cast(int dtype, int nfields, const double* const* src,
 
 hipError_t launch_budget_final(const double* partials, int nblocks, double* budgets,
                                hipStream_t s) {
-    budget_final<<<1, 256, 0, s>>>(partials, nblocks, budgets);
+    budget_final<<<NB, 256, 0, s>>>(partials, nblocks, budgets);
     return hipGetLastError();
 }
 
