@@ -40,6 +40,9 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-forms", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=12.0)
+    p.add_argument("--calibrate-copy", action="store_true",
+                   help="also run a plain 1 GiB device-to-device copy (reference for "
+                        "the HBM byte counters)")
     return p.parse_args()
 
 
@@ -123,6 +126,13 @@ def main():
                     budgets if budget else None, ws if budget else None, stream)
         state.reverse()
 
+    if args.calibrate_copy:
+        src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     log("warmup")
     for _ in range(args.warmup):
         step()

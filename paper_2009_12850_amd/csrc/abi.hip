@@ -146,7 +146,7 @@ int do_step(double* const* state_in, double* const* state_out, int nscal,
     TRY(hip_status(launch_advect(MONC_F64, STEP, true, true, mixed, a, s), "step/advect"));
     if (budgets)
         TRY(hip_status(launch_budget_final((const double*)workspace,
-                                           step_blocks(nx, ny, nz), budgets, s),
+                                           step_grid(nx, ny, nz, mixed), budgets, s),
                        "step/budgets"));
     return MONC_OK;
 }

@@ -11,13 +11,13 @@ hipError_t launch_march_bf16(bool pw, bool tvd, const AdvArgs& a, hipStream_t s)
 hipError_t launch_march_step64(bool pw, bool tvd, const AdvArgs& a, hipStream_t s);
 hipError_t launch_march_stepmix(bool pw, bool tvd, const AdvArgs& a, hipStream_t s);
 
-// Tiles of 8 columns along y (4 when a column needs two 64-level chunks); the
-// x range is cut into segments so that the grid holds about 1024 workgroups
-// (4 per CU), each marching >= 8 planes.  MONC_TI overrides the segment
-// length (experiments).
-Tiling march_tiling(int nx, int ny, int nz) {
+// Tiles of `waves` columns along y (half as many when a column needs two
+// 64-level chunks); the x range is cut into segments so that the grid holds
+// about 1024 workgroups (4 per CU), each marching >= 8 planes.  MONC_TI
+// overrides the segment length (experiments).
+Tiling march_tiling(int nx, int ny, int nz, int waves) {
     Tiling t;
-    t.tj = nz <= 64 ? 8 : 4;
+    t.tj = nz <= 64 ? waves : waves / 2;
     t.njt = (ny + t.tj - 1) / t.tj;
     int nseg = 1024 / t.njt;
     const int max_seg = nx / 8 > 0 ? nx / 8 : 1;
@@ -35,7 +35,13 @@ Tiling march_tiling(int nx, int ny, int nz) {
     return t;
 }
 
-int step_blocks(int nx, int ny, int nz) { return march_tiling(nx, ny, nz).nblocks; }
+// Both step variants hold FP64 state, so they run 8-wave workgroups.
+int step_grid(int nx, int ny, int nz, bool mixed) {
+    (void)mixed;
+    return march_tiling(nx, ny, nz, 8).nblocks;
+}
+
+int step_blocks(int nx, int ny, int nz) { return step_grid(nx, ny, nz, false); }
 
 hipError_t launch_advect(int dtype, int mode, bool pw, bool tvd, bool mixed,
                          const AdvArgs& a, hipStream_t s) {

@@ -80,17 +80,28 @@ __device__ __forceinline__ T cvt0(Ts x) {
     }
 }
 
-constexpr int MARCH_WAVES = 8;
-
-__host__ __device__ constexpr int march_nq(int ns, int nch) {
-    return ((6 + 4 * ns) * nch + MARCH_WAVES - 1) / MARCH_WAVES;
+// Waves per workgroup: 8 when FP64 values are held (a wave needs up to 256
+// registers), 16 when storage and compute are both 32-bit or narrower.
+template <typename Ts, typename T>
+__host__ __device__ constexpr int march_waves() {
+    return (sizeof(T) == 8 || sizeof(Ts) == 8) ? 8 : 16;
 }
 
-template <typename T, int NS, int NCH>
+__host__ __device__ constexpr int march_nq(int ns, int nch, int wv) {
+    return ((6 + 4 * ns) * nch + wv - 1) / wv;
+}
+
+// LDS columns hold levels -2 .. 64*NCH+1; the two levels below and above are
+// zero, so neighbour reads at k-1, k+1, k+2 need no bounds checks.
+template <int NCH>
+__host__ __device__ constexpr int march_csz() { return 64 * NCH + 4; }
+
+template <typename Ts, typename T, int NS, int NCH>
 __host__ __device__ constexpr size_t march_lds_bytes() {
+    constexpr int MARCH_WAVES = march_waves<Ts, T>();
     constexpr int TJ = MARCH_WAVES / NCH;
-    return (size_t)(6 * (TJ + 2) + NS * (TJ + 4) + NS * (TJ + 1) + NLEV) * (64 * NCH) *
-               sizeof(T) +
+    return (size_t)(6 * (TJ + 2) + NS * (TJ + 4)) * march_csz<NCH>() * sizeof(T) +
+           (size_t)(NS * (TJ + 1) + NLEV) * (64 * NCH) * sizeof(T) +
            (size_t)(NS > 0 ? NS : 1) * MARCH_WAVES * sizeof(T);
 }
 
@@ -107,33 +118,35 @@ __device__ __forceinline__ double bud_ident(int op) {
 }
 
 template <typename Ts, typename T, int MODE, bool PW, int NS, bool BUD, int NCH>
-__global__ void __launch_bounds__(MARCH_WAVES * 64) advect_march(MarchArgs m) {
+__global__ void __launch_bounds__((march_waves<Ts, T>() * 64)) advect_march(MarchArgs m) {
     using To = typename std::conditional<std::is_same<T, double>::value, double, float>::type;
+    constexpr int MARCH_WAVES = march_waves<Ts, T>();
     constexpr int TJ = MARCH_WAVES / NCH;
     constexpr int NZP = 64 * NCH;
-    constexpr int VC = TJ + 2;  // velocity slice columns: j0-1 .. j0+TJ
-    constexpr int SC = TJ + 4;  // scalar slice columns:   j0-2 .. j0+TJ+1
-    constexpr int FC = TJ + 1;  // y-faces j0-1/2 .. j0+TJ-1/2
+    constexpr int CSZ = march_csz<NCH>();  // LDS column stride (padded)
+    constexpr int VC = TJ + 2;             // velocity slice columns: j0-1 .. j0+TJ
+    constexpr int SC = TJ + 4;             // scalar slice columns:   j0-2 .. j0+TJ+1
+    constexpr int FC = TJ + 1;             // y-faces j0-1/2 .. j0+TJ-1/2
     constexpr int NSA = NS > 0 ? NS : 1;
-    constexpr int NQ = march_nq(NS, NCH);
+    constexpr int NQ = march_nq(NS, NCH, MARCH_WAVES);
+    constexpr int NJ = (6 + 4 * NS) * NCH;
     constexpr int NACC = MONC_B_SCALAR0 + 3 * NS;
 
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    T* const vel = reinterpret_cast<T*>(smem_raw);  // [3][2][VC][NZP]
-    T* const sph = vel + 6 * VC * NZP;              // [NS][SC][NZP]
-    T* const sfy = sph + NS * SC * NZP;             // [NS][FC][NZP]
+    T* const vel = reinterpret_cast<T*>(smem_raw);  // [3][2][VC][CSZ]
+    T* const sph = vel + 6 * VC * CSZ;              // [NS][SC][CSZ]
+    T* const sfy = sph + NS * SC * CSZ;             // [NS][FC][NZP]
     T* const lev = sfy + NS * FC * NZP;             // [NLEV][NZP]
     T* const fzc = lev + NLEV * NZP;                // [NS][TJ][NCH] chunk-top faces
 
     const AdvArgs& a = m.a;
     const int nx = a.nx, ny = a.ny, nz = a.nz;
-    const long sx = (long)(ny + 4) * nz;
+    const size_t sx = (size_t)(ny + 4) * nz;
     const int lane = threadIdx.x & 63;
-    const int wv = threadIdx.x >> 6;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int cc = wv / NCH;  // column within the tile
     const int ch = wv % NCH;  // chunk within the column
     const int k = 64 * ch + lane;
-    const int ns = NS > 0 ? m.ns : 0;
 
     // Tiles: consecutive tiles along y go to the same XCD (workgroups are
     // dealt to the 8 XCDs round-robin), so neighbouring tiles share halo
@@ -149,7 +162,7 @@ __global__ void __launch_bounds__(MARCH_WAVES * 64) advect_march(MarchArgs m) {
     const bool own_ok = j <= ny + 1;  // column exists in the padded array
     const bool active = j < ny;       // interior column: compute and store
     const bool kin = k < nz;
-    const bool kb = k >= 1, kt = k + 1 < nz, ktt = k + 2 < nz;
+    const bool store = active && kin;
 
     const double dt = a.dt;
     // ---- level table (row a2: vertical geometry from rdz, rho, rhon) ----
@@ -183,6 +196,11 @@ __global__ void __launch_bounds__(MARCH_WAVES * 64) advect_march(MarchArgs m) {
 #pragma unroll
         for (int q = 0; q < NLEV; q++) lev[q * NZP + kk] = (T)v[q];
     }
+    // zero the padding levels of every slice column
+    for (int t = threadIdx.x; t < (6 * VC + NS * SC) * 4; t += MARCH_WAVES * 64) {
+        const int col = t >> 2, w4 = t & 3;
+        vel[(size_t)col * CSZ + (w4 < 2 ? w4 : NZP + w4)] = (T)0;
+    }
 
     const T r4dx = (T)(0.25 / a.dx), r4dy = (T)(0.25 / a.dy);
     const T r2dx = (T)(0.5 / a.dx), r2dy = (T)(0.5 / a.dy);
@@ -191,50 +209,44 @@ __global__ void __launch_bounds__(MARCH_WAVES * 64) advect_march(MarchArgs m) {
     const T rfx = (T)(a.dx / dt), rfy = (T)(a.dy / dt);
     const T dtc = (T)dt;
 
-    const Ts* __restrict__ Up = (const Ts*)a.in[0];
-    const Ts* __restrict__ Vp = (const Ts*)a.in[1];
-    const Ts* __restrict__ Wp = (const Ts*)a.in[2];
-    const Ts* Qp[NSA];
+    // field pointers: 0..2 velocities, 3.. the scalars of this group
+    const Ts* fptr[3 + NSA];
+    fptr[0] = (const Ts*)a.in[0];
+    fptr[1] = (const Ts*)a.in[1];
+    fptr[2] = (const Ts*)a.in[2];
     double off[NSA];
     T phi0c[NSA];
 #pragma unroll
     for (int s = 0; s < NS; s++) {
-        Qp[s] = s < ns ? (const Ts*)a.in[3 + m.s0 + s] : nullptr;
-        off[s] = (MODE == STEP && s < ns) ? a.phi0[m.s0 + s] : 0.0;
-        phi0c[s] = s < ns ? (T)a.phi0[m.s0 + s] : (T)0;
+        fptr[3 + s] = (const Ts*)a.in[3 + m.s0 + s];
+        off[s] = MODE == STEP ? a.phi0[m.s0 + s] : 0.0;
+        phi0c[s] = (T)a.phi0[m.s0 + s];
     }
-
-    auto gbase = [&](int ii, int jj) -> long {
-        return (long)(ii + 2) * sx + (long)(jj + 2) * nz;
-    };
-    // one chunk of one column (plane ii, column jj, levels 64*chunk + lane);
-    // the lid level of w reads as 0
-    auto ldc = [&](const Ts* __restrict__ p, int ii, int jj, int chunk, bool isw) -> Ts {
-        const int kk = 64 * chunk + lane;
+    // plane ii of field pointer p (uniform), element at byte offset boff
+    auto plane = [&](const Ts* p, int ii) -> const Ts* { return p + (size_t)(ii + 2) * sx; };
+    auto ld = [&](const Ts* pl, uint32_t boff, bool ok) -> Ts {
         Ts x = zero_of<Ts>();
-        if (kk < nz && !(isw && kk >= nz - 1)) x = p[gbase(ii, jj) + kk];
+        if (ok) x = *(const Ts*)((const char*)pl + boff);
         return x;
     };
-    auto vslot = [&](int f, int plane) -> T* {
-        return vel + (size_t)((f * 2 + (plane & 1)) * VC) * NZP;
-    };
-    auto field_ptr = [&](int f) -> const Ts* {
-        if (f == 0) return Up;
-        if (f == 1) return Vp;
-        if (f == 2) return Wp;
-        const Ts* p = Up;
+    // own column: byte offset within a plane, and which levels load (the lid
+    // level of w reads as 0)
+    const uint32_t own_boff = (uint32_t)(((j + 2) * nz + k) * (int)sizeof(Ts));
+    const bool ok_s = own_ok && kin;
+    const bool ok_w = own_ok && k < nz - 1;
+
+    // Halo jobs of one plane step, for each chunk: velocities u(i), v(i+1),
+    // w(i+1) at columns j0-1 and j0+TJ; scalar s at plane i, columns j0-2,
+    // j0-1, j0+TJ, j0+TJ+1.  Job id = wv + 8 q; decoded once here.
+    int hj_f[NQ], hj_dpl[NQ], hj_lds[NQ];
+    const Ts* hj_ptr[NQ];
+    uint32_t hj_boff[NQ];
+    bool hj_ok[NQ];
 #pragma unroll
-        for (int s = 0; s < NS; s++)
-            if (f == 3 + s) p = Qp[s];
-        return p;
-    };
-    // Halo job q of the slices stored at plane step i (for each chunk):
-    // velocities u(i), v(i+1), w(i+1) at columns j0-1 and j0+TJ; scalar s at
-    // plane i, columns j0-2, j0-1, j0+TJ, j0+TJ+1.
-    const int nj = (6 + 4 * ns) * NCH;
-    auto job = [&](int id, int& f, int& dpl, int& jj, int& c, int& chunk) {
-        chunk = id % NCH;
-        const int h = id / NCH;
+    for (int q = 0; q < NQ; q++) {
+        const int id = wv + MARCH_WAVES * q;
+        const int chunk = id % NCH, h = id / NCH;
+        int f, dpl, jj, c;
         if (h < 6) {
             f = h >> 1;
             dpl = f == 0 ? 0 : 1;
@@ -242,46 +254,57 @@ __global__ void __launch_bounds__(MARCH_WAVES * 64) advect_march(MarchArgs m) {
             jj = right ? j0 + TJ : j0 - 1;
             c = right ? TJ + 1 : 0;
         } else {
-            const int s = (h - 6) >> 2, q = (h - 6) & 3;
+            const int s = (h - 6) >> 2, qq = (h - 6) & 3;
             f = 3 + s;
             dpl = 0;
-            jj = q == 0 ? j0 - 2 : (q == 1 ? j0 - 1 : (q == 2 ? j0 + TJ : j0 + TJ + 1));
-            c = q == 0 ? 0 : (q == 1 ? 1 : (q == 2 ? TJ + 2 : TJ + 3));
+            jj = qq == 0 ? j0 - 2 : (qq == 1 ? j0 - 1 : (qq == 2 ? j0 + TJ : j0 + TJ + 1));
+            c = qq == 0 ? 0 : (qq == 1 ? 1 : (qq == 2 ? TJ + 2 : TJ + 3));
         }
+        const int kk = 64 * chunk + lane;
+        const bool valid = id < NJ && jj <= ny + 1;
+        hj_f[q] = valid ? f : 0;
+        const Ts* fp = fptr[0];
+#pragma unroll
+        for (int f2 = 1; f2 < 3 + NS; f2++)
+            if (hj_f[q] == f2) fp = fptr[f2];
+        hj_ptr[q] = fp;
+        hj_dpl[q] = dpl;
+        hj_ok[q] = valid && kk < nz && !(f == 2 && kk >= nz - 1);
+        hj_boff[q] = valid ? (uint32_t)(((jj + 2) * nz + kk) * (int)sizeof(Ts)) : 0u;
+        // LDS element offset (velocity slots: parity added per step)
+        hj_lds[q] = f < 3 ? ((f * 2) * VC + c) * CSZ + 2 + kk
+                          : (int)(sph - vel) + ((f - 3) * SC + c) * CSZ + 2 + kk;
+        if (!valid) hj_lds[q] = -1;
+    }
+    auto job_load = [&](int q, int i) -> Ts {
+        return ld(plane(hj_ptr[q], i + hj_dpl[q]), hj_boff[q], hj_ok[q]);
     };
-    auto job_load = [&](int id, int i) -> Ts {
-        Ts x = zero_of<Ts>();
-        if (id < nj) {
-            int f, dpl, jj, c, chunk;
-            job(id, f, dpl, jj, c, chunk);
-            if (jj <= ny + 1) x = ldc(field_ptr(f), i + dpl, jj, chunk, f == 2);
-        }
-        return x;
-    };
-    auto job_store = [&](int id, int i, Ts x) {
-        if (id >= nj) return;
-        int f, dpl, jj, c, chunk;
-        job(id, f, dpl, jj, c, chunk);
-        if (jj > ny + 1) return;
-        T* dst;
+    auto job_store = [&](int q, int i, Ts x) {
+        if (hj_lds[q] < 0) return;
+        const int f = hj_f[q];
+        int e = hj_lds[q];
         double o = 0.0;
         if (f < 3) {
-            dst = vslot(f, i + dpl) + (size_t)c * NZP;
+            e += ((i + hj_dpl[q]) & 1) * VC * CSZ;
         } else {
-            const int s = f - 3;
-            dst = sph + (size_t)(s * SC + c) * NZP;
 #pragma unroll
-            for (int q = 0; q < NS; q++)
-                if (q == s) o = off[q];
+            for (int s = 0; s < NS; s++)
+                if (f == 3 + s) o = off[s];
         }
-        dst[64 * chunk + lane] = cvt<T, Ts>(x, o);
+        vel[e] = cvt<T, Ts>(x, o);
     };
+    // own column slot addresses
+    auto vslot = [&](int f, int plane_i) -> T* {
+        return vel + (size_t)((f * 2 + (plane_i & 1)) * VC) * CSZ;
+    };
+    const int ownv = (cc + 1) * CSZ + 2 + k;  // own column in a velocity slot
+    const int owns = (cc + 2) * CSZ + 2 + k;  // own column in a scalar slice
 
     // ---- register windows ----
-    Ts U[3], V[3], W[3];   // planes i-1, i, i+1 of the own column
-    Ts P[NSA][4];          // planes i-1 .. i+2
-    T FXm[NSA];            // flux through the x-face i-1/2
-    Ts HB[NQ];             // halo columns of the next plane step
+    Ts U[3], V[3], W[3];  // planes i-1, i, i+1 of the own column
+    Ts P[NSA][4];         // planes i-1 .. i+2
+    T FXm[NSA];           // flux through the x-face i-1/2 (rhon factored out)
+    Ts HB[NQ];            // halo columns of the next plane step
     double acc[BUD ? NACC : 1];
     if constexpr (BUD) {
 #pragma unroll
@@ -292,29 +315,23 @@ __global__ void __launch_bounds__(MARCH_WAVES * 64) advect_march(MarchArgs m) {
     __syncthreads();  // level table visible
 #pragma unroll
     for (int p = 0; p < 3; p++) {
-        U[p] = own_ok ? ldc(Up, i0 - 1 + p, j, ch, false) : zero_of<Ts>();
-        V[p] = own_ok ? ldc(Vp, i0 - 1 + p, j, ch, false) : zero_of<Ts>();
-        W[p] = own_ok ? ldc(Wp, i0 - 1 + p, j, ch, true) : zero_of<Ts>();
+        U[p] = ld(plane(fptr[0], i0 - 1 + p), own_boff, ok_s);
+        V[p] = ld(plane(fptr[1], i0 - 1 + p), own_boff, ok_s);
+        W[p] = ld(plane(fptr[2], i0 - 1 + p), own_boff, ok_w);
     }
-    const int kl = k < NZP ? k : NZP - 1;
 #pragma unroll
     for (int s = 0; s < NS; s++) {
-        Ts Pm2 = zero_of<Ts>();
+        const Ts Pm2 = ld(plane(fptr[3 + s], i0 - 2), own_boff, ok_s);
 #pragma unroll
-        for (int p = 0; p < 4; p++) P[s][p] = zero_of<Ts>();
-        if (own_ok && s < ns) {
-            Pm2 = ldc(Qp[s], i0 - 2, j, ch, false);
-#pragma unroll
-            for (int p = 0; p < 4; p++) P[s][p] = ldc(Qp[s], i0 - 1 + p, j, ch, false);
-        }
+        for (int p = 0; p < 4; p++) P[s][p] = ld(plane(fptr[3 + s], i0 - 1 + p), own_boff, ok_s);
         FXm[s] = tvd_flux<T>(cvt0<T, Ts>(U[0]), cvt<T, Ts>(Pm2, off[s]), cvt<T, Ts>(P[s][0], off[s]),
                              cvt<T, Ts>(P[s][1], off[s]), cvt<T, Ts>(P[s][2], off[s]), cfx, rfx,
-                             lev[LV_RHON * NZP + kl]);
+                             (T)1);
     }
     if (own_ok) {
-        vslot(0, i0 - 1)[(cc + 1) * NZP + k] = cvt0<T, Ts>(U[0]);
-        vslot(1, i0)[(cc + 1) * NZP + k] = cvt0<T, Ts>(V[1]);
-        vslot(2, i0)[(cc + 1) * NZP + k] = cvt0<T, Ts>(W[1]);
+        vslot(0, i0 - 1)[ownv] = cvt0<T, Ts>(U[0]);
+        vslot(1, i0)[ownv] = cvt0<T, Ts>(V[1]);
+        vslot(2, i0)[ownv] = cvt0<T, Ts>(W[1]);
     }
     // halo columns of u(i0-1), v(i0), w(i0)
     for (int id = wv; id < 6 * NCH; id += MARCH_WAVES) {
@@ -325,40 +342,43 @@ __global__ void __launch_bounds__(MARCH_WAVES * 64) advect_march(MarchArgs m) {
         const int c = right ? TJ + 1 : 0;
         const int pl = f == 0 ? i0 - 1 : i0;
         if (jj > ny + 1) continue;
-        const Ts x = ldc(field_ptr(f), pl, jj, chunk, f == 2);
-        vslot(f, pl)[(size_t)c * NZP + 64 * chunk + lane] = cvt0<T, Ts>(x);
+        const int kk = 64 * chunk + lane;
+        const bool ok = kk < nz && !(f == 2 && kk >= nz - 1);
+        const Ts* fp = f == 0 ? fptr[0] : (f == 1 ? fptr[1] : fptr[2]);
+        const Ts x = ld(plane(fp, pl), (uint32_t)(((jj + 2) * nz + kk) * (int)sizeof(Ts)), ok);
+        vslot(f, pl)[c * CSZ + 2 + kk] = cvt0<T, Ts>(x);
     }
 #pragma unroll
-    for (int q = 0; q < NQ; q++) HB[q] = job_load(wv + MARCH_WAVES * q, i0);
+    for (int q = 0; q < NQ; q++) HB[q] = job_load(q, i0);
+
+    // per-level constants of this lane
+    const bool bottom = k == 0;           // the ground face is below
+    const bool top2 = k + 2 >= nz;        // no far-upwind cell above the top face
 
     // ---- the march ----
     for (int i = i0; i < i1; i++) {
         // slices of step i
         if (own_ok) {
-            vslot(0, i)[(cc + 1) * NZP + k] = cvt0<T, Ts>(U[1]);
-            vslot(1, i + 1)[(cc + 1) * NZP + k] = cvt0<T, Ts>(V[2]);
-            vslot(2, i + 1)[(cc + 1) * NZP + k] = cvt0<T, Ts>(W[2]);
+            vslot(0, i)[ownv] = cvt0<T, Ts>(U[1]);
+            vslot(1, i + 1)[ownv] = cvt0<T, Ts>(V[2]);
+            vslot(2, i + 1)[ownv] = cvt0<T, Ts>(W[2]);
 #pragma unroll
-            for (int s = 0; s < NS; s++)
-                sph[(size_t)(s * SC + cc + 2) * NZP + k] = cvt<T, Ts>(P[s][1], off[s]);
+            for (int s = 0; s < NS; s++) sph[s * SC * CSZ + owns] = cvt<T, Ts>(P[s][1], off[s]);
         }
 #pragma unroll
-        for (int q = 0; q < NQ; q++) job_store(wv + MARCH_WAVES * q, i, HB[q]);
+        for (int q = 0; q < NQ; q++) job_store(q, i, HB[q]);
         // prefetch of step i+1: own column and halo columns
+        const bool more = i + 1 < i1;
         Ts NU = zero_of<Ts>(), NV = zero_of<Ts>(), NW = zero_of<Ts>();
         Ts NP[NSA];
-        const bool more = i + 1 < i1;
-        if (more && own_ok) {
-            NU = ldc(Up, i + 2, j, ch, false);
-            NV = ldc(Vp, i + 2, j, ch, false);
-            NW = ldc(Wp, i + 2, j, ch, true);
-#pragma unroll
-            for (int s = 0; s < NS; s++)
-                if (s < ns) NP[s] = ldc(Qp[s], i + 3, j, ch, false);
-        }
         if (more) {
+            NU = ld(plane(fptr[0], i + 2), own_boff, ok_s);
+            NV = ld(plane(fptr[1], i + 2), own_boff, ok_s);
+            NW = ld(plane(fptr[2], i + 2), own_boff, ok_w);
 #pragma unroll
-            for (int q = 0; q < NQ; q++) HB[q] = job_load(wv + MARCH_WAVES * q, i + 1);
+            for (int s = 0; s < NS; s++) NP[s] = ld(plane(fptr[3 + s], i + 3), own_boff, ok_s);
+#pragma unroll
+            for (int q = 0; q < NQ; q++) HB[q] = job_load(q, i + 1);
         }
         __syncthreads();
 
@@ -368,22 +388,23 @@ __global__ void __launch_bounds__(MARCH_WAVES * 64) advect_march(MarchArgs m) {
         const T* v_ip = vslot(1, i + 1);
         const T* w_i = vslot(2, i);
         const T* w_ip = vslot(2, i + 1);
-        const int cv = cc + 1;
-        const int cs = cc + 2;
-        const long g = gbase(i, j) + k;
-        const bool store = active && kin;
-        auto Lc = [&](const T* slot, int c, int kk, bool ok) -> T {
-            return ok ? slot[c * NZP + kk] : (T)0;
-        };
+        const size_t gplane = (size_t)(i + 2) * sx;
 
         // Scalars keep across the face barrier only a partial sum and their
         // top-face flux; momentum is finished (and stored) before it.
-        T part[NSA], fzk[NSA];
+        T part[NSA], fzk[NSA], fxp[NSA];
         const T uc = cvt0<T, Ts>(U[1]), um = cvt0<T, Ts>(U[0]);
+        // x-faces first: they need registers only, and overlap the LDS reads
+#pragma unroll
+        for (int s = 0; s < NS; s++) {
+            fxp[s] = tvd_flux<T>(uc, cvt<T, Ts>(P[s][0], off[s]), cvt<T, Ts>(P[s][1], off[s]),
+                                 cvt<T, Ts>(P[s][2], off[s]), cvt<T, Ts>(P[s][3], off[s]), cfx,
+                                 rfx, (T)1);
+        }
         const T vc = cvt0<T, Ts>(V[1]);
         const T wc = cvt0<T, Ts>(W[1]);
-        const T vs = v_i[(cv - 1) * NZP + k];
-        const T wb = Lc(w_i, cv, k - 1, kb);
+        const T vs = v_i[ownv - CSZ];
+        const T wb = w_i[ownv - 1];
         const T rhon = lev[LV_RHON * NZP + k];
         const T rho = lev[LV_RHO * NZP + k];
         const T rho_km = lev[LV_RHOKM * NZP + k];
@@ -404,34 +425,34 @@ __global__ void __launch_bounds__(MARCH_WAVES * 64) advect_march(MarchArgs m) {
             L.beta = lev[LV_BETA * NZP + k];
             L.rho_inv = lev[LV_RHOINV * NZP + k];
             L.rdzn = lev[LV_RDZN * NZP + k];
-            const T us = u_i[(cv - 1) * NZP + k], un = u_i[(cv + 1) * NZP + k];
-            const T ub = Lc(u_i, cv, k - 1, kb), ut = Lc(u_i, cv, k + 1, kt);
-            const T u_nw = u_im[(cv + 1) * NZP + k], u_wt = Lc(u_im, cv, k + 1, kt);
-            const T vn = v_i[(cv + 1) * NZP + k];
-            const T vb = Lc(v_i, cv, k - 1, kb), vt = Lc(v_i, cv, k + 1, kt);
-            const T v_st = Lc(v_i, cv - 1, k + 1, kt), v_es = v_ip[(cv - 1) * NZP + k];
-            const T ws = w_i[(cv - 1) * NZP + k], wn = w_i[(cv + 1) * NZP + k];
-            const T wt = Lc(w_i, cv, k + 1, kt), w_nb = Lc(w_i, cv + 1, k - 1, kb);
-            const T w_eb = Lc(w_ip, cv, k - 1, kb);
+            const T us = u_i[ownv - CSZ], un = u_i[ownv + CSZ];
+            const T ub = u_i[ownv - 1], ut = u_i[ownv + 1];
+            const T u_nw = u_im[ownv + CSZ], u_wt = u_im[ownv + 1];
+            const T vn = v_i[ownv + CSZ];
+            const T vb = v_i[ownv - 1], vt = v_i[ownv + 1];
+            const T v_st = v_i[ownv - CSZ + 1], v_es = v_ip[ownv - CSZ];
+            const T ws = w_i[ownv - CSZ], wn = w_i[ownv + CSZ];
+            const T wt = w_i[ownv + 1], w_nb = w_i[ownv + CSZ - 1];
+            const T w_eb = w_ip[ownv - 1];
             const T su = pw_su<T>(um, uc, up, us, un, ub, ut, vs, v_es, vc, ve, wb, w_eb, wc, we,
                                   L, r4dx, r4dy);
             const T sv = pw_sv<T>(vw, vc, ve, vs, vn, vb, vt, um, u_nw, uc, un, wb, w_nb, wc, wn,
                                   L, r4dx, r4dy);
-            const T sw = kt ? pw_sw<T>(uc, ut, um, u_wt, vc, vt, vs, v_st, wc, ww, we, ws, wn, wb,
-                                       wt, L, r2dx, r2dy)
-                            : (T)0;
+            const T swc = pw_sw<T>(uc, ut, um, u_wt, vc, vt, vs, v_st, wc, ww, we, ws, wn, wb, wt,
+                                   L, r2dx, r2dy);
+            const T sw = k < nz - 1 ? swc : (T)0;
             if (store) {
                 if constexpr (MODE == TEND) {
-                    ((To*)a.out[0])[g] = (To)su;
-                    ((To*)a.out[1])[g] = (To)sv;
-                    ((To*)a.out[2])[g] = (To)sw;
+                    *(To*)((char*)((To*)a.out[0] + gplane) + own_boff / sizeof(Ts) * sizeof(To)) = (To)su;
+                    *(To*)((char*)((To*)a.out[1] + gplane) + own_boff / sizeof(Ts) * sizeof(To)) = (To)sv;
+                    *(To*)((char*)((To*)a.out[2] + gplane) + own_boff / sizeof(Ts) * sizeof(To)) = (To)sw;
                 } else {
                     const double nu = (double)U[1] + dt * (double)su;
                     const double nv = (double)V[1] + dt * (double)sv;
-                    const double nw = kt ? (double)W[1] + dt * (double)sw : 0.0;
-                    ((double*)a.out[0])[g] = nu;
-                    ((double*)a.out[1])[g] = nv;
-                    ((double*)a.out[2])[g] = nw;
+                    const double nw = k < nz - 1 ? (double)W[1] + dt * (double)sw : 0.0;
+                    *(double*)((char*)((double*)a.out[0] + gplane) + own_boff) = nu;
+                    *(double*)((char*)((double*)a.out[1] + gplane) + own_boff) = nv;
+                    *(double*)((char*)((double*)a.out[2] + gplane) + own_boff) = nw;
                     if constexpr (BUD) {
                         const double ucd = (double)U[1], umd = (double)U[0];
                         const double vcd = (double)V[1], vsd = (double)vs;
@@ -459,44 +480,33 @@ __global__ void __launch_bounds__(MARCH_WAVES * 64) advect_march(MarchArgs m) {
                 }
             }
         }
+        const T rfz = lev[LV_RFZ * NZP + k];
+        const T cfz = dtc * lev[LV_RDZN * NZP + k];
 #pragma unroll
         for (int s = 0; s < NS; s++) {
-            if (s >= ns) continue;
-            const T* ph = sph + (size_t)s * SC * NZP;
-            const T pm = cvt<T, Ts>(P[s][0], off[s]);
+            const T* ph = sph + s * SC * CSZ;
             const T pc = cvt<T, Ts>(P[s][1], off[s]);
-            const T pe = cvt<T, Ts>(P[s][2], off[s]);
-            const T pee = cvt<T, Ts>(P[s][3], off[s]);
-            const T fxp = tvd_flux<T>(uc, pm, pc, pe, pee, cfx, rfx, rhon);
-            const T ps = ph[(cs - 1) * NZP + k], pn = ph[(cs + 1) * NZP + k],
-                    pnn = ph[(cs + 2) * NZP + k];
-            const T fyp = tvd_flux<T>(vc, ps, pc, pn, pnn, cfy, rfy, rhon);
-            sfy[(size_t)(s * FC + cc + 1) * NZP + k] = fyp;
+            // lateral fluxes are computed without the common rhon factor
+            const T ps = ph[owns - CSZ], pn = ph[owns + CSZ], pnn = ph[owns + 2 * CSZ];
+            const T fyp = tvd_flux<T>(vc, ps, pc, pn, pnn, cfy, rfy, (T)1);
+            sfy[(s * FC + cc + 1) * NZP + k] = fyp;
             if (cc == 0) {
-                sfy[(size_t)(s * FC) * NZP + k] =
-                    tvd_flux<T>(vs, ph[(cs - 2) * NZP + k], ps, pc, pn, cfy, rfy, rhon);
+                sfy[(s * FC) * NZP + k] =
+                    tvd_flux<T>(vs, ph[owns - 2 * CSZ], ps, pc, pn, cfy, rfy, (T)1);
             }
-            T fz = 0;
-            if (kt) {
-                const T pb = Lc(ph, cs, k - 1, kb);
-                const T pt = ph[cs * NZP + k + 1];
-                const T ptt = Lc(ph, cs, k + 2, ktt);
-                const bool pos = wc >= (T)0;
-                if ((pos && k == 0) || (!pos && !ktt)) {
-                    fz = upwind_flux<T>(wc, pc, pt, rho);
-                } else {
-                    fz = tvd_flux<T>(wc, pb, pc, pt, ptt, dtc * lev[LV_RDZN * NZP + k],
-                                     lev[LV_RFZ * NZP + k], rho);
-                }
-            }
+            // top face k+1/2.  Where the far-upwind cell is outside the column
+            // it is replaced by the upwind cell, which makes the limiter return
+            // the upwind value (first-order upwind); on the lid w is zero.
+            const T pb = ph[owns - 1], pt = ph[owns + 1], ptt = ph[owns + 2];
+            const T fz = tvd_flux<T>(wc, bottom ? pc : pb, pc, pt, top2 ? pt : ptt, cfz, rfz, rho);
             fzk[s] = fz;
             if (NCH > 1 && lane == 63) fzc[(s * TJ + cc) * NCH + ch] = fz;
             // everything but the faces shared with the neighbours (j-1/2,
             // k-1/2); stored values are anomalies from phi0: add the term of
             // the constant
-            part[s] = -rhon_inv * ((fxp - FXm[s]) * rdx + fyp * rdy + rdz * fz) -
+            part[s] = -((fxp[s] - FXm[s]) * rdx + fyp * rdy) - rhon_inv * rdz * fz -
                       phi0c[s] * D * rhon_inv;
-            FXm[s] = fxp;
+            FXm[s] = fxp[s];
         }
         __syncthreads();
 
@@ -504,24 +514,24 @@ __global__ void __launch_bounds__(MARCH_WAVES * 64) advect_march(MarchArgs m) {
         // the neighbouring lane (or the chunk below)
 #pragma unroll
         for (int s = 0; s < NS; s++) {
-            if (s >= ns) continue;
             const T up1 = __shfl_up(fzk[s], 1, 64);
             T fzm = up1;
             if (lane == 0) fzm = ch == 0 ? (T)0 : fzc[(s * TJ + cc) * NCH + ch - 1];
-            const T fym = sfy[(size_t)(s * FC + cc) * NZP + k];
-            const T val = part[s] + rhon_inv * (fym * rdy + rdz * fzm);
+            const T fym = sfy[(s * FC + cc) * NZP + k];
+            const T val = part[s] + fym * rdy + rhon_inv * rdz * fzm;
             if (store) {
+                To* op = (To*)a.out[3 + m.s0 + s] + gplane;
                 if constexpr (MODE == TEND) {
-                    ((To*)a.out[3 + m.s0 + s])[g] = (To)val;
+                    *(To*)((char*)op + own_boff / sizeof(Ts) * sizeof(To)) = (To)val;
                 } else {
                     const double nsv = (double)P[s][1] + dt * (double)val;
-                    ((double*)a.out[3 + m.s0 + s])[g] = nsv;
+                    *(double*)((char*)op + own_boff) = nsv;
                     if constexpr (BUD) {
-                        const double ph = (double)P[s][1];
+                        const double phd = (double)P[s][1];
                         const double mass = (double)lev[LV_MASS * NZP + k];
                         acc[MONC_B_SCALAR0 + 3 * s] += mass * (double)val;
-                        acc[MONC_B_SCALAR0 + 3 * s + 1] += mass * ph;
-                        acc[MONC_B_SCALAR0 + 3 * s + 2] = fmin(acc[MONC_B_SCALAR0 + 3 * s + 2], ph);
+                        acc[MONC_B_SCALAR0 + 3 * s + 1] += mass * phd;
+                        acc[MONC_B_SCALAR0 + 3 * s + 2] = fmin(acc[MONC_B_SCALAR0 + 3 * s + 2], phd);
                         acc[MONC_B_NONFINITE] += (double)(!isfinite(nsv));
                     }
                 }
@@ -531,21 +541,19 @@ __global__ void __launch_bounds__(MARCH_WAVES * 64) advect_march(MarchArgs m) {
         // rotate the windows
         U[0] = U[1];
         U[1] = U[2];
+        U[2] = NU;
         V[0] = V[1];
         V[1] = V[2];
+        V[2] = NV;
         W[0] = W[1];
         W[1] = W[2];
-        if (more && own_ok) {
-            U[2] = NU;
-            V[2] = NV;
-            W[2] = NW;
-        }
+        W[2] = NW;
 #pragma unroll
         for (int s = 0; s < NS; s++) {
             P[s][0] = P[s][1];
             P[s][1] = P[s][2];
             P[s][2] = P[s][3];
-            if (more && own_ok && s < ns) P[s][3] = NP[s];
+            P[s][3] = more ? NP[s] : zero_of<Ts>();
         }
     }
 
@@ -567,7 +575,7 @@ __global__ void __launch_bounds__(MARCH_WAVES * 64) advect_march(MarchArgs m) {
             double* row = a.partials + (size_t)blockIdx.x * NB;
             const bool scalar_slot = q >= MONC_B_SCALAR0;
             const int s = scalar_slot ? (q - MONC_B_SCALAR0) / 3 : -1;
-            const bool mine_scalar = scalar_slot && s >= m.s0 && s < m.s0 + ns;
+            const bool mine_scalar = scalar_slot && s >= m.s0 && s < m.s0 + NS;
             const bool mine_mom = !scalar_slot && PW;
             if (mine_scalar || mine_mom || q == MONC_B_NONFINITE) {
                 const int lq = scalar_slot ? q - 3 * m.s0 : q;

@@ -10,12 +10,12 @@ namespace monc {
 struct Tiling {
     int tj, ti, njt, nseg, nblocks;
 };
-Tiling march_tiling(int nx, int ny, int nz);
+Tiling march_tiling(int nx, int ny, int nz, int waves);
 
 template <typename Ts, typename T, int MODE, bool PW, int NS, bool BUD, int R>
 hipError_t launch_one(const MarchArgs& m, const Tiling& t, hipStream_t s) {
     auto kern = advect_march<Ts, T, MODE, PW, NS, BUD, R>;
-    constexpr size_t lds = march_lds_bytes<T, NS, R>();
+    constexpr size_t lds = march_lds_bytes<Ts, T, NS, R>();
     static bool attr_done = false;
     if (!attr_done) {
         hipError_t e = hipFuncSetAttribute((const void*)kern,
@@ -23,7 +23,7 @@ hipError_t launch_one(const MarchArgs& m, const Tiling& t, hipStream_t s) {
         if (e != hipSuccess) return e;
         attr_done = true;
     }
-    kern<<<t.nblocks, MARCH_WAVES * 64, lds, s>>>(m);
+    kern<<<t.nblocks, march_waves<Ts, T>() * 64, lds, s>>>(m);
     return hipGetLastError();
 }
 
@@ -52,7 +52,7 @@ hipError_t launch_r(const MarchArgs& m, const Tiling& t, hipStream_t s) {
 // requested).
 template <typename Ts, typename T, int MODE>
 hipError_t launch_march_t(bool pw, bool tvd, const AdvArgs& a, hipStream_t s) {
-    const Tiling t = march_tiling(a.nx, a.ny, a.nz);
+    const Tiling t = march_tiling(a.nx, a.ny, a.nz, march_waves<Ts, T>());
     const bool bud = a.partials != nullptr;
     const int nscal = tvd ? a.nscal : 0;
     const int group = bud ? 2 : 3;

@@ -32,6 +32,8 @@ struct AdvArgs {
 // Number of workgroups of the fused step launch (fixed for a grid so budget
 // sums are repeatable), and the budget workspace it needs.
 int step_blocks(int nx, int ny, int nz);
+// exact number of workgroups (= budget partial rows) of a step launch
+int step_grid(int nx, int ny, int nz, bool mixed);
 
 // Launchers (return hipError_t of the launch).
 hipError_t launch_halo(int elem_bytes, int nfields, void* const* fields, int nx,

@@ -1,0 +1,206 @@
+"""GPU tests of the precision forms, the multi-pass scalar groups, ragged
+column heights, and the 100-step run with budgets checked every step.
+
+FP32 tendencies (from FP32 working copies, scalars stored as anomalies from a
+constant) must stay within 1e-5 of the FP64 oracle (per field, relative to the
+field's largest value); BF16 storage is reported against a looser bound that
+follows from its 8-bit mantissa.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from gpu_util import case, dev, oracle_tendencies, prof_dev, rel_err, to_dev, torch
+from oracle import pyoracle as O
+from paper_2009_12850_amd import _lib as M
+from paper_2009_12850_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+TOL64 = 1e-13
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _setup():
+    O.build(force=False)
+    M.lib()
+
+
+def narrow_tendencies(host, g, dt, dtype, phi0):
+    T = torch()
+    d = to_dev(host)
+    tdt = T.float32 if dtype == M.MONC_F32 else T.int16
+    work = [T.empty(x.shape, dtype=tdt, device=dev()) for x in d]
+    offs = [0.0, 0.0, 0.0] + list(phi0)
+    M.monc_cast_working(dtype, d, work, offs)
+    out = [T.zeros(x.shape, dtype=T.float32, device=dev()) for x in d]
+    M.monc_advect(dtype, work, out, g.dx, g.dy, prof_dev(g), dt, phi0=phi0)
+    T.cuda.synchronize()
+    return [o.double().cpu().numpy() for o in out]
+
+
+@pytest.mark.parametrize("shape", [(32, 32, 32), (40, 36, 128), (17, 23, 96)])
+def test_fp32_tendencies_within_1e5_of_oracle(shape):
+    nx, ny, nz = shape
+    say(f"fp32 {shape}")
+    g, host = case(nx, ny, nz, 2, seed=600 + nx)
+    dt = 0.5
+    ref = oracle_tendencies(host, g, dt)
+    got = narrow_tendencies(host, g, dt, M.MONC_F32, [300.0, 0.0])
+    errs = [rel_err(a, b) for a, b in zip(got, ref)]
+    say(f"  fp32 relative errors {['%.2e' % e for e in errs]}")
+    assert max(errs) <= 1e-5, errs
+
+
+@pytest.mark.parametrize("shape", [(32, 32, 32), (40, 36, 128)])
+def test_bf16_storage_error_is_bounded(shape):
+    nx, ny, nz = shape
+    say(f"bf16 {shape}")
+    g, host = case(nx, ny, nz, 2, seed=610 + nx)
+    dt = 0.5
+    ref = oracle_tendencies(host, g, dt)
+    got = narrow_tendencies(host, g, dt, M.MONC_BF16, [300.0, 0.0])
+    errs = [rel_err(a, b) for a, b in zip(got, ref)]
+    say(f"  bf16 relative errors {['%.2e' % e for e in errs]}")
+    # 8 significant bits: a few 2^-8 after the differences of the stencils
+    assert max(errs) <= 0.05, errs
+
+
+def test_anomaly_offset_is_exact_in_fp64():
+    """Storing theta as an anomaly and passing phi0 gives the FP64 tendency of
+    the full field (affine equivariance of the flux form)."""
+    g, host = case(24, 20, 32, 2, seed=620)
+    dt = 0.5
+    ref = oracle_tendencies(host, g, dt)
+    T = torch()
+    anom = [h.copy() for h in host]
+    anom[3] = anom[3] - 300.0
+    d = to_dev(anom)
+    out = [T.zeros_like(x) for x in d]
+    M.monc_advect(M.MONC_F64, d, out, g.dx, g.dy, prof_dev(g), dt, phi0=[300.0, 0.0])
+    T.cuda.synchronize()
+    assert rel_err(out[3].cpu().numpy(), ref[3]) <= 1e-12
+
+
+def test_mixed_step_matches_oracle_to_fp32_accuracy():
+    say("mixed step")
+    g, host = case(40, 36, 64, 2, seed=630)
+    dt = 0.5
+    ref = O.step([h.copy() for h in host], g, dt)
+    T = torch()
+    d = to_dev(host)
+    out = [T.full_like(x, float("nan")) for x in d]
+    b = T.zeros(M.MONC_NBUDGET, dtype=T.float64, device=dev())
+    ws = T.empty(M.monc_step_workspace_bytes(40, 36, 64, 2), dtype=T.uint8, device=dev())
+    M.monc_step_mixed(d, out, [300.0, 0.0], g.dx, g.dy, prof_dev(g), dt, b, ws)
+    T.cuda.synchronize()
+    for n in range(5):
+        e = rel_err(out[n].cpu().numpy() - host[n], ref[n] - host[n])
+        assert e <= 1e-5, (n, e)
+    bh = b.cpu().numpy()
+    assert M.monc_budgets_check(bh) == M.MONC_OK
+    # the state itself stays FP64: increments are added to the FP64 values
+    assert out[3].dtype == T.float64
+
+
+@pytest.mark.parametrize("nscal", [5, 8])
+def test_many_scalars_use_several_passes(nscal):
+    say(f"nscal {nscal}")
+    g, host = case(21, 18, 40, nscal, seed=640 + nscal)
+    dt = 0.5
+    ref = oracle_tendencies(host, g, dt)
+    T = torch()
+    d = to_dev(host)
+    out = [T.zeros_like(x) for x in d]
+    M.monc_advect(M.MONC_F64, d, out, g.dx, g.dy, prof_dev(g), dt)
+    T.cuda.synchronize()
+    for n, (a, r) in enumerate(zip(out, ref)):
+        assert rel_err(a.cpu().numpy(), r) <= TOL64, n
+    # the step with budgets (scalars in passes of two)
+    stp = O.step([h.copy() for h in host], g, dt)
+    out = [T.full_like(x, float("nan")) for x in d]
+    b = T.zeros(M.MONC_NBUDGET, dtype=T.float64, device=dev())
+    ws = T.empty(M.monc_step_workspace_bytes(21, 18, 40, nscal), dtype=T.uint8, device=dev())
+    M.monc_step(d, out, g.dx, g.dy, prof_dev(g), dt, b, ws)
+    T.cuda.synchronize()
+    for n in range(3 + nscal):
+        assert rel_err(out[n].cpu().numpy() - host[n], stp[n] - host[n]) <= TOL64, n
+    ob, sc = O.budgets(*host[:3], *ref[:3], host[3:], ref[3:], g)
+    gb = M.budgets_dict(b.cpu().numpy(), nscal)
+    for s in range(nscal):
+        assert abs(gb[f"M_s{s}"] - ob[f"M_s{s}"]) <= 1e-13 * abs(ob[f"M_s{s}"])
+        assert gb[f"min_s{s}"] == ob[f"min_s{s}"]
+    assert gb["nonfinite"] == 0
+
+
+@pytest.mark.parametrize("shape", [(12, 10, 96), (9, 7, 65), (11, 13, 64), (6, 5, 3)])
+def test_ragged_column_heights(shape):
+    nx, ny, nz = shape
+    say(f"ragged nz {shape}")
+    g, host = case(nx, ny, nz, 2, seed=650 + nz)
+    dt = 0.5
+    ref = oracle_tendencies(host, g, dt)
+    T = torch()
+    d = to_dev(host)
+    out = [T.zeros_like(x) for x in d]
+    M.monc_advect(M.MONC_F64, d, out, g.dx, g.dy, prof_dev(g), dt)
+    T.cuda.synchronize()
+    for n, (a, r) in enumerate(zip(out, ref)):
+        assert rel_err(a.cpu().numpy(), r) <= TOL64, n
+
+
+def test_steps512_budgets_every_step():
+    """512 x 512 x 128, u v w th q1 q2 q3, 100 forward steps at dt = 0.5 s with
+    the budgets checked after every step: momentum and scalar mass conserved,
+    the KE identity closes, the w boundary term matches its closed form, mass
+    changes by exactly dt*C, q stays positive, no Courant violation."""
+    w, g, f = I.make_workload("steps512", padded=True)
+    names = ["u", "v", "w"] + I.scalar_names(w.nscal)
+    say("steps512: oracle budgets of the first state")
+    hosts = [O.halo_fill(f.pop(n)) for n in names]
+    tend = oracle_tendencies(hosts, g, w.dt)
+    ob, sc = O.budgets(*hosts[:3], *tend[:3], hosts[3:], tend[3:], g)
+    scal_scale = [np.sum(np.abs(I.interior(t)) * (g.rhon / g.rdz)[None, None, :]) for t in tend[3:]]
+    del tend
+    T = torch()
+    A = [T.from_numpy(h).to(dev()) for h in hosts]
+    del hosts
+    B = [T.empty_like(x) for x in A]
+    prof = prof_dev(g)
+    b = T.zeros(M.MONC_NBUDGET, dtype=T.float64, device=dev())
+    ws = T.empty(M.monc_step_workspace_bytes(w.nx, w.ny, w.nz, w.nscal), dtype=T.uint8,
+                 device=dev())
+    rho = T.from_numpy(g.rho).to(dev())
+    prev = None
+    for step in range(w.steps):
+        M.monc_step(A, B, g.dx, g.dy, prof, w.dt, b, ws)
+        wt = A[2][2:-2, 2:-2]
+        closed = float((rho[0] * wt[:, :, 0] ** 2 - rho[w.nz - 2] * wt[:, :, w.nz - 2] ** 2).sum() / 4)
+        bh = b.cpu().numpy()
+        gb = M.budgets_dict(bh, w.nscal)
+        assert M.monc_budgets_check(bh) == M.MONC_OK, (step, gb["courant"], gb["nonfinite"])
+        if step == 0:
+            for name in ["C_u", "C_v", "C_w", "P_u", "Q_u", "P_v", "Q_v", "P_w", "Q_w"]:
+                assert abs(gb[name] - ob[name]) <= 1e-12 * sc[name], name
+        assert abs(gb["C_u"]) <= 1e-12 * sc["C_u"], step
+        assert abs(gb["C_v"]) <= 1e-12 * sc["C_v"], step
+        assert abs(gb["C_w"] - closed) <= 1e-12 * sc["C_w"], step
+        for c in "uvw":
+            assert abs(gb[f"P_{c}"] - gb[f"Q_{c}"]) <= 1e-11 * sc[f"P_{c}"], (step, c)
+        for s in range(w.nscal):
+            assert abs(gb[f"C_s{s}"]) <= 1e-12 * scal_scale[s], (step, s)
+            if prev is not None:
+                drift = gb[f"M_s{s}"] - prev[f"M_s{s}"] - w.dt * prev[f"C_s{s}"]
+                assert abs(drift) <= 1e-13 * abs(gb[f"M_s{s}"]) + 1e-9, (step, s, drift)
+        for s in range(1, w.nscal):
+            assert gb[f"min_s{s}"] > 0.0, (step, s)
+        prev = gb
+        A, B = B, A
+        if step % 20 == 0:
+            say(f"  step {step}: courant {gb['courant']:.3f} C_u {gb['C_u']:.2e} "
+                f"P_u-Q_u {gb['P_u'] - gb['Q_u']:.2e}")
