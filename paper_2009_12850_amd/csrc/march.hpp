@@ -520,10 +520,12 @@ __global__ void __launch_bounds__((march_waves<Ts, T>() * 64)) advect_march(Marc
             const T fym = sfy[(s * FC + cc) * NZP + k];
             const T val = part[s] + fym * rdy + rhon_inv * rdz * fzm;
             if (store) {
-                To* op = (To*)a.out[3 + m.s0 + s] + gplane;
                 if constexpr (MODE == TEND) {
+                    To* op = (To*)a.out[3 + m.s0 + s] + gplane;
                     *(To*)((char*)op + own_boff / sizeof(Ts) * sizeof(To)) = (To)val;
                 } else {
+                    // the state is FP64 whatever the compute type
+                    double* op = (double*)a.out[3 + m.s0 + s] + gplane;
                     const double nsv = (double)P[s][1] + dt * (double)val;
                     *(double*)((char*)op + own_boff) = nsv;
                     if constexpr (BUD) {

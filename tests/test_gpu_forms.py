@@ -67,8 +67,12 @@ def test_bf16_storage_error_is_bounded(shape):
     got = narrow_tendencies(host, g, dt, M.MONC_BF16, [300.0, 0.0])
     errs = [rel_err(a, b) for a, b in zip(got, ref)]
     say(f"  bf16 relative errors {['%.2e' % e for e in errs]}")
-    # 8 significant bits: a few 2^-8 after the differences of the stencils
-    assert max(errs) <= 0.05, errs
+    # BF16 keeps 8 significant bits: each stored value is off by up to 2^-9
+    # of itself, while neighbouring cells differ by only about 1% (the noise
+    # level), so the fluxes' differences can be off by tens of percent of
+    # themselves.  The bound only guards against a broken path; the errors
+    # are what the precision form reports.
+    assert max(errs) <= 0.25, errs
 
 
 def test_anomaly_offset_is_exact_in_fp64():
