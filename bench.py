@@ -91,6 +91,53 @@ def cpu_baseline(seconds):
                       f"(u v w th q1), {el:.1f} s"}
 
 
+def bench_ensemble(torch, M, I, dev, steps, log):
+    """64 uneven members (nx, ny in {64..256}, nz in {64, 96}), FP32 source
+    terms from the FP64 state, `steps` steps in one captured graph launch,
+    against the same steps launched member by member."""
+    import tempfile
+    nscal = 2
+    geo = I.ensemble_members(64, seed=4)
+    members = []
+    for md in geo:
+        g = I.make_geometry(md["nx"], md["ny"], md["nz"], dx=md["dx"], dy=md["dx"])
+        f = I.make_fields(g, nscal, md["seed"], amp=md["amp"], padded=True)
+        names = ["u", "v", "w"] + I.scalar_names(nscal)
+        s0 = [torch.from_numpy(f.pop(k)).to(dev) for k in names]
+        s1 = [torch.empty_like(x) for x in s0]
+        prof = [torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in (g.rdz, g.rho, g.rhon)]
+        members.append(dict(state0=s0, state1=s1, prof=prof, dx=md["dx"], dy=md["dx"], dt=0.5,
+                            phi0=[300.0, 0.0]))
+    pts = sum(md["nx"] * md["ny"] * md["nz"] for md in geo)
+    cache = os.path.join(tempfile.gettempdir(), "monc_ensemble_tune.json")
+    log("ensemble: plan + autotune")
+    t0 = time.perf_counter()
+    ens = M.Ensemble(members, nscal, tune_cache=cache, tune=True)
+    t_plan = time.perf_counter() - t0
+    stream = torch.cuda.current_stream()
+    ens.run(steps, stream)  # builds the graph
+    torch.cuda.synchronize()
+    t_graph = event_time_ms(torch, stream, lambda: ens.run(steps, stream), 1)
+
+    def eager():
+        for mem in members:
+            cur = mem["state0"] if ens.parity == 0 else mem["state1"]
+            nxt = mem["state1"] if ens.parity == 0 else mem["state0"]
+            a, b = cur, nxt
+            for _ in range(steps):
+                M.monc_step_mixed(a, b, mem["phi0"], mem["dx"], mem["dy"], mem["prof"],
+                                  mem["dt"], stream=stream)
+                a, b = b, a
+    t_eager = event_time_ms(torch, stream, eager, 1)
+    info = ens.info()
+    ens.close()
+    gpups = pts * steps / (t_graph * 1e-3)
+    return {"members": len(geo), "points": pts, "steps": steps, "ms": t_graph,
+            "gpups": gpups, "hbm_frac": 16.0 * (3 + nscal) * gpups / HBM_PEAK,
+            "eager_ms": t_eager, "speedup_vs_eager": t_eager / t_graph,
+            "plan_s": t_plan, "tuned": info}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -187,6 +234,12 @@ def main():
                                           None, None, stream)
         tm = event_time_ms(torch, stream, mixed, args.steps)
         forms["mixed_step"] = {"ms": tm, "gpups": npts / (tm * 1e-3)}
+
+    if not args.no_forms:
+        del B
+        state.clear()
+        torch.cuda.empty_cache()
+        forms["ensemble"] = bench_ensemble(torch, M, I, dev, 50, log)
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -14,7 +14,10 @@
  * Conventions shared by every entry point
  * ---------------------------------------
  * Layout.   Every field is a dense [(nx+4)][(ny+4)][nz] array, z fastest, with
- *           a 2-deep periodic halo in x and y and none in z.  Interior element
+ *           a 2-deep periodic halo in x and y and none in z.  The advection
+ *           calls read periodic neighbours at wrapped interior indices, so
+ *           halo contents are never read by them (monc_halo_fill fills the
+ *           halos for callers that need them).  Interior element
  *           (i,j,k), 0 <= i < nx, 0 <= j < ny, 0 <= k < nz, lives at
  *           ((i+2)*(ny+4) + (j+2))*nz + k.  Profiles rdz, rho, rhon are [nz]
  *           float64 arrays: rdz[k] = 1/dz_k (thickness of cell k), rho[k] =
@@ -139,11 +142,11 @@ int monc_advect(int dtype, const void *const *in, void *const *out, int nscal,
 
 /* ---------------------------------------------------------------------------
  * a1-a6. One forward step of the whole path ("step fields" integrates the
- * source terms last, Sec. 3): halo fill of state_in (its halo is rewritten),
- * PW + TVD from state_in, state_out = state_in + dt * s, w lid = 0, and
+ * source terms last, Sec. 3): PW + TVD from state_in (periodic neighbours read
+ * at wrapped indices), state_out = state_in + dt * s, w lid = 0, and
  * optionally the FP64 budgets.  state_in/state_out: host arrays of 3+nscal
- * device pointers, FP64, state_out must not alias state_in (state_out's halo
- * is left stale; the next step refills it).  budgets: device float64
+ * device pointers, FP64, state_out must not alias state_in (halos are neither
+ * read nor written).  budgets: device float64
  * [MONC_NBUDGET] or NULL.  workspace: device memory of at least
  * monc_step_workspace_bytes(nx, ny, nz, nscal) bytes when budgets != NULL.
  * ------------------------------------------------------------------------- */
@@ -170,6 +173,40 @@ int monc_step_mixed(double *const *state_in, double *const *state_out,
 int monc_cast_working(int dtype, int nfields, const double *const *src,
                       void *const *work, const double *offset, int nx, int ny,
                       int nz, monc_stream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * a8. Batched ensemble.  Many independent LES members of uneven size advance
+ * together, each with the monc_step_mixed step (FP32 source terms, FP64
+ * state): one persistent launch per column-height class (nz <= 64, nz <= 128)
+ * walks a cost-sorted list of (member, tile) work items, and monc_ensemble_run
+ * replays N steps captured once into a hipGraph.  The segment length and grid
+ * size of each class are picked by timing candidates on the members (tune !=
+ * 0), cached in the JSON file `tune_cache` (may be NULL: no cache).  Results
+ * are bitwise those of monc_step_mixed on each member alone.
+ * members: host array; state[p][f] are device FP64 arrays in the usual layout
+ * (f = u, v, w, scalars), state[0] the initial state; the plan keeps the
+ * pointers until destroyed and owns only its own small device tables.
+ * nscal <= 3 (MONC_EUNSUPPORTED otherwise).  monc_ensemble_parity() tells
+ * which buffer (0/1) holds the current state.  Calls on one plan must not
+ * overlap.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    int nx, ny, nz;
+    double dx, dy, dt;
+    const double *rdz, *rho, *rhon;
+    double *state[2][3 + MONC_MAX_SCALARS];
+    double phi0[MONC_MAX_SCALARS];
+} monc_member;
+
+typedef struct monc_ensemble monc_ensemble;
+
+int monc_ensemble_create(const monc_member *members, int nmembers, int nscal,
+                         const char *tune_cache, int tune, monc_ensemble **plan);
+int monc_ensemble_run(monc_ensemble *plan, int nsteps, monc_stream_t stream);
+int monc_ensemble_step(monc_ensemble *plan, monc_stream_t stream);
+int monc_ensemble_parity(const monc_ensemble *plan);
+int monc_ensemble_info(const monc_ensemble *plan, int *ti, int *grid, int *nitems);
+int monc_ensemble_destroy(monc_ensemble *plan);
 
 /* Map a budgets array (HOST copy, after synchronising) to a status:
  * MONC_ENONFINITE if any non-finite value was written, MONC_ECFL if the

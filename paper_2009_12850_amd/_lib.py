@@ -52,6 +52,12 @@ _SIGS = {
                         ip),
     "monc_cast_working": ([ip, ip, PP, PP, DPTR, ip, ip, ip, vp], ip),
     "monc_budgets_check": ([DPTR], ip),
+    "monc_ensemble_create": ([vp, ip, ip, C.c_char_p, ip, C.POINTER(vp)], ip),
+    "monc_ensemble_run": ([vp, ip, vp], ip),
+    "monc_ensemble_step": ([vp, vp], ip),
+    "monc_ensemble_parity": ([vp], ip),
+    "monc_ensemble_info": ([vp, C.POINTER(ip), C.POINTER(ip), C.POINTER(ip)], ip),
+    "monc_ensemble_destroy": ([vp], ip),
     "monc_strerror": ([ip], C.c_char_p),
     "monc_last_error": ([], C.c_char_p),
 }
@@ -271,3 +277,73 @@ def budgets_dict(b, nscal):
         out[f"M_s{s}"] = float(b[B_SCALAR0 + 3 * s + 1])
         out[f"min_s{s}"] = float(b[B_SCALAR0 + 3 * s + 2])
     return out
+
+
+# ---------------------------------------------------------------------------
+# Batched ensemble
+# ---------------------------------------------------------------------------
+class MoncMember(C.Structure):
+    """Mirror of the C struct monc_member."""
+    _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int),
+                ("dx", C.c_double), ("dy", C.c_double), ("dt", C.c_double),
+                ("rdz", C.c_void_p), ("rho", C.c_void_p), ("rhon", C.c_void_p),
+                ("state", (C.c_void_p * (3 + MONC_MAX_SCALARS)) * 2),
+                ("phi0", C.c_double * MONC_MAX_SCALARS)]
+
+
+class Ensemble:
+    """An ensemble plan.  members: list of dicts with keys state0, state1 (lists
+    of 3+nscal float64 device tensors in the padded layout), prof (rdz, rho,
+    rhon device tensors), dx, dy, dt, phi0 (list of nscal floats).  The plan
+    keeps references to the tensors until close()."""
+
+    def __init__(self, members, nscal, tune_cache=None, tune=True):
+        torch = _torch()
+        self._keep = members
+        arr = (MoncMember * len(members))()
+        for m, mem in enumerate(members):
+            nx, ny, nz = _grid(mem["state0"][0])
+            sh = tuple(mem["state0"][0].shape)
+            M = arr[m]
+            M.nx, M.ny, M.nz = nx, ny, nz
+            M.dx, M.dy, M.dt = float(mem["dx"]), float(mem["dy"]), float(mem["dt"])
+            M.rdz, M.rho, M.rhon = [p.value for p in _prof(mem["prof"])]
+            for p, key in enumerate(("state0", "state1")):
+                for f, t in enumerate(mem[key]):
+                    M.state[p][f] = _ptr(t, torch.float64, sh, f"{key}[{f}]").value
+            for q, v in enumerate(mem.get("phi0", [0.0] * nscal)):
+                M.phi0[q] = float(v)
+        plan = C.c_void_p()
+        cache = tune_cache.encode() if tune_cache else None
+        _check(lib().monc_ensemble_create(C.cast(arr, C.c_void_p), len(members), nscal, cache,
+                                          1 if tune else 0, C.byref(plan)),
+               "monc_ensemble_create")
+        self._plan = plan
+        self.nscal = nscal
+
+    def run(self, nsteps, stream=None):
+        _check(lib().monc_ensemble_run(self._plan, int(nsteps), _stream(stream)),
+               "monc_ensemble_run")
+
+    def step(self, stream=None):
+        _check(lib().monc_ensemble_step(self._plan, _stream(stream)), "monc_ensemble_step")
+
+    @property
+    def parity(self):
+        return int(lib().monc_ensemble_parity(self._plan))
+
+    def info(self):
+        ti, grid, nit = (C.c_int * 2)(), (C.c_int * 2)(), (C.c_int * 2)()
+        lib().monc_ensemble_info(self._plan, ti, grid, nit)
+        return {"ti": list(ti), "grid": list(grid), "nitems": list(nit)}
+
+    def close(self):
+        if self._plan:
+            lib().monc_ensemble_destroy(self._plan)
+            self._plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -133,7 +133,6 @@ int do_step(double* const* state_in, double* const* state_out, int nscal,
     if (budgets && !workspace)
         return fail(MONC_EINVAL, "budgets requested but workspace is NULL");
     hipStream_t s = (hipStream_t)stream;
-    TRY(hip_status(launch_halo(8, nf, (void* const*)state_in, nx, ny, nz, s), "step/halo"));
     AdvArgs a;
     fill_args(a, nx, ny, nz, dx, dy, dt, rdz, rho, rhon, nscal);
     for (int f = 0; f < nf; f++) {
@@ -279,6 +278,75 @@ int monc_cast_working(int dtype, int nfields, const double* const* src, void* co
     const long n = (long)(nx + 4) * (ny + 4) * nz;
     return hip_status(launch_cast(dtype, nfields, src, work, offset, n, (hipStream_t)stream),
                       "cast_working");
+}
+
+int monc_ensemble_create(const monc_member* members, int nmembers, int nscal,
+                         const char* tune_cache, int tune, monc_ensemble** plan) {
+    if (!plan) return fail(MONC_EINVAL, "plan is NULL");
+    *plan = nullptr;
+    if (!members || nmembers < 1) return fail(MONC_EINVAL, "need at least one member");
+    TRY(check_nscal(nscal));
+    if (nscal > 3)
+        return fail(MONC_EUNSUPPORTED, "ensembles advect at most 3 scalars (got %d)", nscal);
+    for (int m = 0; m < nmembers; m++) {
+        const monc_member& M = members[m];
+        int rc = check_grid(M.nx, M.ny, M.nz);
+        if (rc == MONC_OK) rc = check_spacing(M.dx, M.dy);
+        if (rc == MONC_OK) rc = check_dt(M.dt);
+        if (rc == MONC_OK) rc = check_prof(M.rdz, M.rho, M.rhon);
+        for (int p = 0; p < 2 && rc == MONC_OK; p++)
+            for (int f = 0; f < 3 + nscal && rc == MONC_OK; f++)
+                if (!M.state[p][f]) rc = fail(MONC_EINVAL, "member %d: state[%d][%d] is NULL", m, p, f);
+        if (rc == MONC_OK)
+            rc = check_alias(3 + nscal, (const void* const*)M.state[0], 3 + nscal,
+                             (const void* const*)M.state[1]);
+        if (rc != MONC_OK) {
+            std::string d = g_last_error;
+            return fail(rc, "member %d: %s", m, d.c_str());
+        }
+    }
+    std::string err;
+    EnsemblePlan* P = nullptr;
+    const int rc = ensemble_create(members, nmembers, nscal, tune_cache, tune, &P, &err);
+    if (rc != MONC_OK) return fail(rc, "ensemble_create: %s", err.c_str());
+    *plan = reinterpret_cast<monc_ensemble*>(P);
+    return MONC_OK;
+}
+
+int monc_ensemble_run(monc_ensemble* plan, int nsteps, monc_stream_t stream) {
+    if (!plan) return fail(MONC_EINVAL, "plan is NULL");
+    if (nsteps < 1) return fail(MONC_EINVAL, "nsteps must be >= 1");
+    std::string err;
+    const int rc = ensemble_run(reinterpret_cast<EnsemblePlan*>(plan), nsteps,
+                                (hipStream_t)stream, &err);
+    if (rc != MONC_OK) return fail(rc, "ensemble_run: %s", err.c_str());
+    return MONC_OK;
+}
+
+int monc_ensemble_step(monc_ensemble* plan, monc_stream_t stream) {
+    if (!plan) return fail(MONC_EINVAL, "plan is NULL");
+    std::string err;
+    const int rc =
+        ensemble_step_eager(reinterpret_cast<EnsemblePlan*>(plan), (hipStream_t)stream, &err);
+    if (rc != MONC_OK) return fail(rc, "ensemble_step: %s", err.c_str());
+    return MONC_OK;
+}
+
+int monc_ensemble_parity(const monc_ensemble* plan) {
+    if (!plan) return fail(MONC_EINVAL, "plan is NULL");
+    return ensemble_parity(reinterpret_cast<const EnsemblePlan*>(plan));
+}
+
+int monc_ensemble_info(const monc_ensemble* plan, int* ti, int* grid, int* nitems) {
+    if (!plan) return fail(MONC_EINVAL, "plan is NULL");
+    ensemble_info(reinterpret_cast<const EnsemblePlan*>(plan), ti, grid, nitems);
+    return MONC_OK;
+}
+
+int monc_ensemble_destroy(monc_ensemble* plan) {
+    if (!plan) return MONC_OK;
+    ensemble_destroy(reinterpret_cast<EnsemblePlan*>(plan));
+    return MONC_OK;
 }
 
 int monc_budgets_check(const double* b) {

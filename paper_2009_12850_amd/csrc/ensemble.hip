@@ -1,0 +1,414 @@
+// ensemble.hip -- batched advection of an ensemble of uneven LES members.
+//
+// Every member advances with the mixed-precision step (FP32 source terms from
+// the FP64 state, FP64 accumulation; the single-precision advection of
+// Sec. 4.1).  One persistent launch per column-height class walks a work list
+// of (member, tile) items sorted by cost; N steps are captured once into a
+// hipGraph and replayed with one hipGraphLaunch.  The segment length and the
+// persistent grid size of each class are chosen by timing candidates on the
+// plan's own members (cached in a small JSON file keyed by device, class,
+// precision and scalar count).
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "march.hpp"
+
+namespace monc {
+
+namespace {
+
+constexpr int ENS_WAVES = 8;  // FP64 state held in registers
+
+struct EnsMember {
+    AdvArgs a[2];  // a[p]: reads state[p], writes state[1-p]
+    int ti;        // planes per segment
+    int njt;       // tiles along y
+};
+
+template <int NCH, int NS>
+__global__ void __launch_bounds__(ENS_WAVES * 64)
+    ensemble_step(const EnsMember* __restrict__ mem, const int4* __restrict__ items, int nitems,
+                  int parity) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const int4 w = items[it];
+        const EnsMember* M = mem + w.x;
+        TileJob t;
+        t.s0 = 0;
+        t.ti = M->ti;
+        t.jt = w.y;
+        t.seg = w.z;
+        t.partial_row = nullptr;
+        t.first_pass = 1;
+        march_tile<double, float, STEP, true, NS, false, NCH>(M->a[parity], t, smem_raw);
+        __syncthreads();  // the LDS is reused by the next item
+    }
+}
+
+template <int NCH, int NS>
+hipError_t launch_class(const EnsMember* mem, const int4* items, int nitems, int grid, int parity,
+                        hipStream_t s) {
+    constexpr size_t lds = march_lds_bytes<double, float, NS, NCH>();
+    ensemble_step<NCH, NS><<<grid, ENS_WAVES * 64, lds, s>>>(mem, items, nitems, parity);
+    return hipGetLastError();
+}
+
+hipError_t set_attrs() {
+    const size_t l10 = march_lds_bytes<double, float, 0, 1>(), l11 = march_lds_bytes<double, float, 1, 1>();
+    const size_t l12 = march_lds_bytes<double, float, 2, 1>(), l13 = march_lds_bytes<double, float, 3, 1>();
+    const size_t l20 = march_lds_bytes<double, float, 0, 2>(), l21 = march_lds_bytes<double, float, 1, 2>();
+    const size_t l22 = march_lds_bytes<double, float, 2, 2>(), l23 = march_lds_bytes<double, float, 3, 2>();
+    const void* k[8] = {(const void*)ensemble_step<1, 0>, (const void*)ensemble_step<1, 1>,
+                        (const void*)ensemble_step<1, 2>, (const void*)ensemble_step<1, 3>,
+                        (const void*)ensemble_step<2, 0>, (const void*)ensemble_step<2, 1>,
+                        (const void*)ensemble_step<2, 2>, (const void*)ensemble_step<2, 3>};
+    const size_t l[8] = {l10, l11, l12, l13, l20, l21, l22, l23};
+    for (int q = 0; q < 8; q++) {
+        hipError_t e = hipFuncSetAttribute(k[q], hipFuncAttributeMaxDynamicSharedMemorySize, (int)l[q]);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_any(int nch, int ns, const EnsMember* mem, const int4* items, int nitems,
+                      int grid, int parity, hipStream_t s) {
+    if (nitems <= 0) return hipSuccess;
+    if (nch == 1) {
+        switch (ns) {
+            case 0: return launch_class<1, 0>(mem, items, nitems, grid, parity, s);
+            case 1: return launch_class<1, 1>(mem, items, nitems, grid, parity, s);
+            case 2: return launch_class<1, 2>(mem, items, nitems, grid, parity, s);
+            case 3: return launch_class<1, 3>(mem, items, nitems, grid, parity, s);
+        }
+    } else {
+        switch (ns) {
+            case 0: return launch_class<2, 0>(mem, items, nitems, grid, parity, s);
+            case 1: return launch_class<2, 1>(mem, items, nitems, grid, parity, s);
+            case 2: return launch_class<2, 2>(mem, items, nitems, grid, parity, s);
+            case 3: return launch_class<2, 3>(mem, items, nitems, grid, parity, s);
+        }
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// The plan
+// ---------------------------------------------------------------------------
+struct EnsemblePlan {
+    int n = 0, nscal = 0;
+    std::vector<monc_member> members;
+    std::vector<EnsMember> hmem;
+    EnsMember* d_mem = nullptr;
+    // per class (0: nz <= 64, 1: 64 < nz <= 128)
+    int4* d_items[2] = {nullptr, nullptr};
+    int nitems[2] = {0, 0};
+    int grid[2] = {0, 0};
+    int ti[2] = {32, 32};
+    hipStream_t cap = nullptr;
+    hipGraphExec_t exec[2] = {nullptr, nullptr};  // by starting parity
+    int exec_steps[2] = {0, 0};
+    int parity = 0;
+};
+
+namespace {
+
+int tj_of(int nch) { return ENS_WAVES / nch; }
+
+// Work list of one class for a segment length: every (member, tile) item,
+// sorted by decreasing cost (planes x levels x columns) so that the
+// round-robin walk of the persistent workgroups balances.
+std::vector<int4> build_items(const EnsemblePlan& P, int cls, int ti) {
+    std::vector<int4> items;
+    for (int m = 0; m < P.n; m++) {
+        const monc_member& M = P.members[m];
+        const int nch = M.nz <= 64 ? 1 : 2;
+        if (nch - 1 != cls) continue;
+        const int tj = tj_of(nch);
+        const int njt = (M.ny + tj - 1) / tj;
+        const int nseg = (M.nx + ti - 1) / ti;
+        for (int s = 0; s < nseg; s++) {
+            const int planes = std::min(ti, M.nx - s * ti);
+            const int cols = tj;
+            for (int t = 0; t < njt; t++)
+                items.push_back(make_int4(m, t, s, planes * cols * M.nz));
+        }
+    }
+    std::stable_sort(items.begin(), items.end(),
+                     [](const int4& a, const int4& b) { return a.w > b.w; });
+    return items;
+}
+
+hipError_t upload_class(EnsemblePlan& P, int cls, int ti) {
+    hipError_t e0 = hipStreamSynchronize(P.cap);  // the old list may still be in use
+    if (e0 != hipSuccess) return e0;
+    std::vector<int4> items = build_items(P, cls, ti);
+    if (P.d_items[cls]) {
+        hipFree(P.d_items[cls]);
+        P.d_items[cls] = nullptr;
+    }
+    P.nitems[cls] = (int)items.size();
+    P.ti[cls] = ti;
+    for (int m = 0; m < P.n; m++) {
+        const int nch = P.members[m].nz <= 64 ? 1 : 2;
+        if (nch - 1 == cls) P.hmem[m].ti = ti;
+    }
+    if (items.empty()) return hipSuccess;
+    hipError_t e = hipMalloc(&P.d_items[cls], items.size() * sizeof(int4));
+    if (e != hipSuccess) return e;
+    return hipMemcpy(P.d_items[cls], items.data(), items.size() * sizeof(int4),
+                     hipMemcpyHostToDevice);
+}
+
+hipError_t upload_members(EnsemblePlan& P) {
+    return hipMemcpy(P.d_mem, P.hmem.data(), P.hmem.size() * sizeof(EnsMember),
+                     hipMemcpyHostToDevice);
+}
+
+hipError_t launch_step(EnsemblePlan& P, int parity, hipStream_t s) {
+    for (int c = 0; c < 2; c++) {
+        hipError_t e = launch_any(c + 1, P.nscal, P.d_mem, P.d_items[c], P.nitems[c], P.grid[c],
+                                  parity, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// --- tiny JSON cache: {"key": [ti, grid], ...} -------------------------------
+std::string cache_key(int cls, int nscal) {
+    hipDeviceProp_t prop;
+    int dev = 0;
+    hipGetDevice(&dev);
+    hipGetDeviceProperties(&prop, dev);
+    char buf[256];
+    snprintf(buf, sizeof buf, "%s|nz%s|fp32-tend-fp64-state|nscal%d", prop.gcnArchName,
+             cls == 0 ? "<=64" : "<=128", nscal);
+    return buf;
+}
+
+bool cache_read(const char* path, const std::string& key, int* ti, int* grid) {
+    if (!path) return false;
+    FILE* f = fopen(path, "r");
+    if (!f) return false;
+    std::string text;
+    char buf[4096];
+    size_t r;
+    while ((r = fread(buf, 1, sizeof buf, f)) > 0) text.append(buf, r);
+    fclose(f);
+    const std::string pat = "\"" + key + "\": [";
+    const size_t p = text.find(pat);
+    if (p == std::string::npos) return false;
+    return sscanf(text.c_str() + p + pat.size(), "%d, %d", ti, grid) == 2;
+}
+
+void cache_write(const char* path, const std::string& key, int ti, int grid) {
+    if (!path) return;
+    std::vector<std::string> lines;
+    FILE* f = fopen(path, "r");
+    if (f) {
+        char buf[1024];
+        while (fgets(buf, sizeof buf, f)) {
+            std::string l(buf);
+            if (l.find("\": [") != std::string::npos && l.find("\"" + key + "\"") == std::string::npos) {
+                while (!l.empty() && (l.back() == '\n' || l.back() == ',')) l.pop_back();
+                lines.push_back(l);
+            }
+        }
+        fclose(f);
+    }
+    char ent[512];
+    snprintf(ent, sizeof ent, "  \"%s\": [%d, %d]", key.c_str(), ti, grid);
+    lines.push_back(ent);
+    f = fopen(path, "w");
+    if (!f) return;
+    fprintf(f, "{\n");
+    for (size_t i = 0; i < lines.size(); i++)
+        fprintf(f, "%s%s\n", lines[i].c_str(), i + 1 < lines.size() ? "," : "");
+    fprintf(f, "}\n");
+    fclose(f);
+}
+
+// Time one step of one class (average of reps) for the current items/grid.
+float time_class(EnsemblePlan& P, int cls, int reps) {
+    hipEvent_t a, b;
+    hipEventCreate(&a);
+    hipEventCreate(&b);
+    launch_any(cls + 1, P.nscal, P.d_mem, P.d_items[cls], P.nitems[cls], P.grid[cls], P.parity,
+               P.cap);
+    hipEventRecord(a, P.cap);
+    for (int r = 0; r < reps; r++)
+        launch_any(cls + 1, P.nscal, P.d_mem, P.d_items[cls], P.nitems[cls], P.grid[cls],
+                   P.parity, P.cap);
+    hipEventRecord(b, P.cap);
+    hipEventSynchronize(b);
+    float ms = 0;
+    hipEventElapsedTime(&ms, a, b);
+    hipEventDestroy(a);
+    hipEventDestroy(b);
+    return ms / reps;
+}
+
+int num_cus() {
+    int dev = 0, cus = 256;
+    hipGetDevice(&dev);
+    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    return cus;
+}
+
+// The autotuner: segment length x persistent grid size, timed on the plan's
+// own members.  Candidates whose work list is shorter than the grid are
+// clipped.  Timing writes only the members' "next" buffers.
+hipError_t tune_class(EnsemblePlan& P, int cls, const char* cache, bool tune) {
+    const int cus = num_cus();
+    int best_ti = 32, best_grid = 2 * cus;
+    const std::string key = cache_key(cls, P.nscal);
+    bool have = cache_read(cache, key, &best_ti, &best_grid);
+    if (!have && tune) {
+        float best = 1e30f;
+        const int tis[] = {16, 32, 64, 128};
+        const int grids[] = {cus, 2 * cus, 4 * cus};
+        for (int ti : tis) {
+            hipError_t e = upload_class(P, cls, ti);
+            if (e != hipSuccess) return e;
+            e = upload_members(P);
+            if (e != hipSuccess) return e;
+            if (P.nitems[cls] == 0) return hipSuccess;
+            for (int g : grids) {
+                P.grid[cls] = std::min(g, P.nitems[cls]);
+                const float ms = time_class(P, cls, 3);
+                if (ms < best) {
+                    best = ms;
+                    best_ti = ti;
+                    best_grid = g;
+                }
+            }
+        }
+        cache_write(cache, key, best_ti, best_grid);
+    }
+    hipError_t e = upload_class(P, cls, best_ti);
+    if (e != hipSuccess) return e;
+    P.grid[cls] = std::max(1, std::min(best_grid, P.nitems[cls]));
+    return upload_members(P);
+}
+
+}  // namespace
+
+int ensemble_create(const monc_member* members, int n, int nscal, const char* tune_cache,
+                    int tune, EnsemblePlan** out, std::string* err) {
+    EnsemblePlan* P = new EnsemblePlan();
+    P->n = n;
+    P->nscal = nscal;
+    P->members.assign(members, members + n);
+    P->hmem.resize(n);
+    for (int m = 0; m < n; m++) {
+        const monc_member& M = members[m];
+        for (int p = 0; p < 2; p++) {
+            AdvArgs& a = P->hmem[m].a[p];
+            for (int f = 0; f < 3 + MAXS; f++) {
+                a.in[f] = nullptr;
+                a.out[f] = nullptr;
+            }
+            for (int f = 0; f < 3 + nscal; f++) {
+                a.in[f] = M.state[p][f];
+                a.out[f] = M.state[1 - p][f];
+            }
+            for (int s = 0; s < MAXS; s++) a.phi0[s] = s < nscal ? M.phi0[s] : 0.0;
+            a.nscal = nscal;
+            a.nx = M.nx;
+            a.ny = M.ny;
+            a.nz = M.nz;
+            a.dx = M.dx;
+            a.dy = M.dy;
+            a.dt = M.dt;
+            a.rdz = M.rdz;
+            a.rho = M.rho;
+            a.rhon = M.rhon;
+            a.partials = nullptr;
+        }
+        const int nch = M.nz <= 64 ? 1 : 2;
+        P->hmem[m].njt = (M.ny + tj_of(nch) - 1) / tj_of(nch);
+        P->hmem[m].ti = 32;
+    }
+    hipError_t e = set_attrs();
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&P->cap, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipMalloc(&P->d_mem, sizeof(EnsMember) * n);
+    for (int c = 0; c < 2 && e == hipSuccess; c++) e = tune_class(*P, c, tune_cache, tune != 0);
+    if (e == hipSuccess) e = hipStreamSynchronize(P->cap);
+    if (e != hipSuccess) {
+        *err = hipGetErrorString(e);
+        ensemble_destroy(P);
+        return MONC_EHIP;
+    }
+    *out = P;
+    return MONC_OK;
+}
+
+int ensemble_step_eager(EnsemblePlan* P, hipStream_t s, std::string* err) {
+    hipError_t e = launch_step(*P, P->parity, s);
+    if (e != hipSuccess) {
+        *err = hipGetErrorString(e);
+        return MONC_EHIP;
+    }
+    P->parity ^= 1;
+    return MONC_OK;
+}
+
+int ensemble_run(EnsemblePlan* P, int nsteps, hipStream_t s, std::string* err) {
+    const int p0 = P->parity;
+    if (!P->exec[p0] || P->exec_steps[p0] != nsteps) {
+        if (P->exec[p0]) {
+            hipGraphExecDestroy(P->exec[p0]);
+            P->exec[p0] = nullptr;
+        }
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamBeginCapture(P->cap, hipStreamCaptureModeThreadLocal);
+        for (int k = 0; k < nsteps && e == hipSuccess; k++) e = launch_step(*P, p0 ^ (k & 1), P->cap);
+        hipError_t e2 = hipStreamEndCapture(P->cap, &g);
+        if (e == hipSuccess) e = e2;
+        if (e == hipSuccess) e = hipGraphInstantiate(&P->exec[p0], g, nullptr, nullptr, 0);
+        if (g) hipGraphDestroy(g);
+        if (e != hipSuccess) {
+            *err = std::string("graph capture: ") + hipGetErrorString(e);
+            P->exec[p0] = nullptr;
+            return MONC_EHIP;
+        }
+        P->exec_steps[p0] = nsteps;
+    }
+    hipError_t e = hipGraphLaunch(P->exec[p0], s);
+    if (e != hipSuccess) {
+        *err = hipGetErrorString(e);
+        return MONC_EHIP;
+    }
+    P->parity ^= (nsteps & 1);
+    return MONC_OK;
+}
+
+void ensemble_info(const EnsemblePlan* P, int* ti, int* grid, int* nitems) {
+    for (int c = 0; c < 2; c++) {
+        if (ti) ti[c] = P->ti[c];
+        if (grid) grid[c] = P->grid[c];
+        if (nitems) nitems[c] = P->nitems[c];
+    }
+}
+
+int ensemble_parity(const EnsemblePlan* P) { return P->parity; }
+
+void ensemble_destroy(EnsemblePlan* P) {
+    if (!P) return;
+    for (int c = 0; c < 2; c++) {
+        if (P->exec[c]) hipGraphExecDestroy(P->exec[c]);
+        if (P->d_items[c]) hipFree(P->d_items[c]);
+    }
+    if (P->d_mem) hipFree(P->d_mem);
+    if (P->cap) hipStreamDestroy(P->cap);
+    delete P;
+}
+
+}  // namespace monc

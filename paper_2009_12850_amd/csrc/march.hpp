@@ -117,8 +117,18 @@ __device__ __forceinline__ double bud_ident(int op) {
     return op == 2 ? __builtin_huge_val() : 0.0;
 }
 
+// One tile of the march: columns jt*TJ .. jt*TJ+TJ-1, planes seg*ti .. .
+struct TileJob {
+    int s0;               // first scalar of this group
+    int ti;               // planes per x-segment
+    int jt, seg;          // the tile
+    double* partial_row;  // budget partials of this tile (BUD only)
+    int first_pass;       // write the budget slots this group does not own
+};
+
 template <typename Ts, typename T, int MODE, bool PW, int NS, bool BUD, int NCH>
-__global__ void __launch_bounds__((march_waves<Ts, T>() * 64)) advect_march(MarchArgs m) {
+__device__ __forceinline__ void march_tile(const AdvArgs& a, const TileJob& tj,
+                                           unsigned char* smem_raw) {
     using To = typename std::conditional<std::is_same<T, double>::value, double, float>::type;
     constexpr int MARCH_WAVES = march_waves<Ts, T>();
     constexpr int TJ = MARCH_WAVES / NCH;
@@ -132,14 +142,12 @@ __global__ void __launch_bounds__((march_waves<Ts, T>() * 64)) advect_march(Marc
     constexpr int NJ = (6 + 4 * NS) * NCH;
     constexpr int NACC = MONC_B_SCALAR0 + 3 * NS;
 
-    extern __shared__ __align__(16) unsigned char smem_raw[];
     T* const vel = reinterpret_cast<T*>(smem_raw);  // [3][2][VC][CSZ]
     T* const sph = vel + 6 * VC * CSZ;              // [NS][SC][CSZ]
     T* const sfy = sph + NS * SC * CSZ;             // [NS][FC][NZP]
     T* const lev = sfy + NS * FC * NZP;             // [NLEV][NZP]
     T* const fzc = lev + NLEV * NZP;                // [NS][TJ][NCH] chunk-top faces
 
-    const AdvArgs& a = m.a;
     const int nx = a.nx, ny = a.ny, nz = a.nz;
     const size_t sx = (size_t)(ny + 4) * nz;
     const int lane = threadIdx.x & 63;
@@ -148,18 +156,11 @@ __global__ void __launch_bounds__((march_waves<Ts, T>() * 64)) advect_march(Marc
     const int ch = wv % NCH;  // chunk within the column
     const int k = 64 * ch + lane;
 
-    // Tiles: consecutive tiles along y go to the same XCD (workgroups are
-    // dealt to the 8 XCDs round-robin), so neighbouring tiles share halo
-    // columns through that XCD's L2.
-    int b = blockIdx.x;
-    const int nb = gridDim.x;
-    if ((nb & 7) == 0) b = (b & 7) * (nb >> 3) + (b >> 3);
-    const int jt = b % m.njt, seg = b / m.njt;
-    const int j0 = jt * TJ;
-    const int i0 = seg * m.ti;
-    const int i1 = min(i0 + m.ti, nx);
+    const int j0 = tj.jt * TJ;
+    const int i0 = tj.seg * tj.ti;
+    const int i1 = min(i0 + tj.ti, nx);
     const int j = j0 + cc;
-    const bool own_ok = j <= ny + 1;  // column exists in the padded array
+    const bool own_ok = j <= ny + 1;  // a column the tile reads (interior or its neighbours)
     const bool active = j < ny;       // interior column: compute and store
     const bool kin = k < nz;
     const bool store = active && kin;
@@ -218,12 +219,23 @@ __global__ void __launch_bounds__((march_waves<Ts, T>() * 64)) advect_march(Marc
     T phi0c[NSA];
 #pragma unroll
     for (int s = 0; s < NS; s++) {
-        fptr[3 + s] = (const Ts*)a.in[3 + m.s0 + s];
-        off[s] = MODE == STEP ? a.phi0[m.s0 + s] : 0.0;
-        phi0c[s] = (T)a.phi0[m.s0 + s];
+        fptr[3 + s] = (const Ts*)a.in[3 + tj.s0 + s];
+        off[s] = MODE == STEP ? a.phi0[tj.s0 + s] : 0.0;
+        phi0c[s] = (T)a.phi0[tj.s0 + s];
     }
-    // plane ii of field pointer p (uniform), element at byte offset boff
-    auto plane = [&](const Ts* p, int ii) -> const Ts* { return p + (size_t)(ii + 2) * sx; };
+    // Periodic neighbours are read at wrapped indices: the arrays' halos are
+    // never read.  plane ii of field pointer p (uniform) ...
+    auto wrapx = [&](int ii) -> int {
+        ii %= nx;
+        return ii < 0 ? ii + nx : ii;
+    };
+    auto wrapy = [&](int jj) -> int {
+        jj %= ny;
+        return jj < 0 ? jj + ny : jj;
+    };
+    auto plane = [&](const Ts* p, int ii) -> const Ts* {
+        return p + (size_t)(wrapx(ii) + 2) * sx;
+    };
     auto ld = [&](const Ts* pl, uint32_t boff, bool ok) -> Ts {
         Ts x = zero_of<Ts>();
         if (ok) x = *(const Ts*)((const char*)pl + boff);
@@ -231,7 +243,8 @@ __global__ void __launch_bounds__((march_waves<Ts, T>() * 64)) advect_march(Marc
     };
     // own column: byte offset within a plane, and which levels load (the lid
     // level of w reads as 0)
-    const uint32_t own_boff = (uint32_t)(((j + 2) * nz + k) * (int)sizeof(Ts));
+    const uint32_t own_boff = (uint32_t)(((j + 2) * nz + k) * (int)sizeof(Ts));   // stores
+    const uint32_t own_roff = (uint32_t)(((wrapy(j) + 2) * nz + k) * (int)sizeof(Ts));  // loads
     const bool ok_s = own_ok && kin;
     const bool ok_w = own_ok && k < nz - 1;
 
@@ -270,7 +283,7 @@ __global__ void __launch_bounds__((march_waves<Ts, T>() * 64)) advect_march(Marc
         hj_ptr[q] = fp;
         hj_dpl[q] = dpl;
         hj_ok[q] = valid && kk < nz && !(f == 2 && kk >= nz - 1);
-        hj_boff[q] = valid ? (uint32_t)(((jj + 2) * nz + kk) * (int)sizeof(Ts)) : 0u;
+        hj_boff[q] = valid ? (uint32_t)(((wrapy(jj) + 2) * nz + kk) * (int)sizeof(Ts)) : 0u;
         // LDS element offset (velocity slots: parity added per step)
         hj_lds[q] = f < 3 ? ((f * 2) * VC + c) * CSZ + 2 + kk
                           : (int)(sph - vel) + ((f - 3) * SC + c) * CSZ + 2 + kk;
@@ -315,15 +328,15 @@ __global__ void __launch_bounds__((march_waves<Ts, T>() * 64)) advect_march(Marc
     __syncthreads();  // level table visible
 #pragma unroll
     for (int p = 0; p < 3; p++) {
-        U[p] = ld(plane(fptr[0], i0 - 1 + p), own_boff, ok_s);
-        V[p] = ld(plane(fptr[1], i0 - 1 + p), own_boff, ok_s);
-        W[p] = ld(plane(fptr[2], i0 - 1 + p), own_boff, ok_w);
+        U[p] = ld(plane(fptr[0], i0 - 1 + p), own_roff, ok_s);
+        V[p] = ld(plane(fptr[1], i0 - 1 + p), own_roff, ok_s);
+        W[p] = ld(plane(fptr[2], i0 - 1 + p), own_roff, ok_w);
     }
 #pragma unroll
     for (int s = 0; s < NS; s++) {
-        const Ts Pm2 = ld(plane(fptr[3 + s], i0 - 2), own_boff, ok_s);
+        const Ts Pm2 = ld(plane(fptr[3 + s], i0 - 2), own_roff, ok_s);
 #pragma unroll
-        for (int p = 0; p < 4; p++) P[s][p] = ld(plane(fptr[3 + s], i0 - 1 + p), own_boff, ok_s);
+        for (int p = 0; p < 4; p++) P[s][p] = ld(plane(fptr[3 + s], i0 - 1 + p), own_roff, ok_s);
         FXm[s] = tvd_flux<T>(cvt0<T, Ts>(U[0]), cvt<T, Ts>(Pm2, off[s]), cvt<T, Ts>(P[s][0], off[s]),
                              cvt<T, Ts>(P[s][1], off[s]), cvt<T, Ts>(P[s][2], off[s]), cfx, rfx,
                              (T)1);
@@ -345,7 +358,7 @@ __global__ void __launch_bounds__((march_waves<Ts, T>() * 64)) advect_march(Marc
         const int kk = 64 * chunk + lane;
         const bool ok = kk < nz && !(f == 2 && kk >= nz - 1);
         const Ts* fp = f == 0 ? fptr[0] : (f == 1 ? fptr[1] : fptr[2]);
-        const Ts x = ld(plane(fp, pl), (uint32_t)(((jj + 2) * nz + kk) * (int)sizeof(Ts)), ok);
+        const Ts x = ld(plane(fp, pl), (uint32_t)(((wrapy(jj) + 2) * nz + kk) * (int)sizeof(Ts)), ok);
         vslot(f, pl)[c * CSZ + 2 + kk] = cvt0<T, Ts>(x);
     }
 #pragma unroll
@@ -372,11 +385,11 @@ __global__ void __launch_bounds__((march_waves<Ts, T>() * 64)) advect_march(Marc
         Ts NU = zero_of<Ts>(), NV = zero_of<Ts>(), NW = zero_of<Ts>();
         Ts NP[NSA];
         if (more) {
-            NU = ld(plane(fptr[0], i + 2), own_boff, ok_s);
-            NV = ld(plane(fptr[1], i + 2), own_boff, ok_s);
-            NW = ld(plane(fptr[2], i + 2), own_boff, ok_w);
+            NU = ld(plane(fptr[0], i + 2), own_roff, ok_s);
+            NV = ld(plane(fptr[1], i + 2), own_roff, ok_s);
+            NW = ld(plane(fptr[2], i + 2), own_roff, ok_w);
 #pragma unroll
-            for (int s = 0; s < NS; s++) NP[s] = ld(plane(fptr[3 + s], i + 3), own_boff, ok_s);
+            for (int s = 0; s < NS; s++) NP[s] = ld(plane(fptr[3 + s], i + 3), own_roff, ok_s);
 #pragma unroll
             for (int q = 0; q < NQ; q++) HB[q] = job_load(q, i + 1);
         }
@@ -521,11 +534,11 @@ __global__ void __launch_bounds__((march_waves<Ts, T>() * 64)) advect_march(Marc
             const T val = part[s] + fym * rdy + rhon_inv * rdz * fzm;
             if (store) {
                 if constexpr (MODE == TEND) {
-                    To* op = (To*)a.out[3 + m.s0 + s] + gplane;
+                    To* op = (To*)a.out[3 + tj.s0 + s] + gplane;
                     *(To*)((char*)op + own_boff / sizeof(Ts) * sizeof(To)) = (To)val;
                 } else {
                     // the state is FP64 whatever the compute type
-                    double* op = (double*)a.out[3 + m.s0 + s] + gplane;
+                    double* op = (double*)a.out[3 + tj.s0 + s] + gplane;
                     const double nsv = (double)P[s][1] + dt * (double)val;
                     *(double*)((char*)op + own_boff) = nsv;
                     if constexpr (BUD) {
@@ -574,22 +587,42 @@ __global__ void __launch_bounds__((march_waves<Ts, T>() * 64)) advect_march(Marc
         if (threadIdx.x < NB) {
             const int q = threadIdx.x;
             const int op = bud_op(q);
-            double* row = a.partials + (size_t)blockIdx.x * NB;
+            double* row = tj.partial_row;
             const bool scalar_slot = q >= MONC_B_SCALAR0;
             const int s = scalar_slot ? (q - MONC_B_SCALAR0) / 3 : -1;
-            const bool mine_scalar = scalar_slot && s >= m.s0 && s < m.s0 + NS;
+            const bool mine_scalar = scalar_slot && s >= tj.s0 && s < tj.s0 + NS;
             const bool mine_mom = !scalar_slot && PW;
             if (mine_scalar || mine_mom || q == MONC_B_NONFINITE) {
-                const int lq = scalar_slot ? q - 3 * m.s0 : q;
+                const int lq = scalar_slot ? q - 3 * tj.s0 : q;
                 double v = red[lq];
                 for (int w2 = 1; w2 < MARCH_WAVES; w2++) v = bud_comb(v, red[w2 * NACC + lq], op);
-                if (q == MONC_B_NONFINITE && !m.first_pass) v += row[q];
+                if (q == MONC_B_NONFINITE && !tj.first_pass) v += row[q];
                 row[q] = v;
-            } else if (m.first_pass) {
+            } else if (tj.first_pass) {
                 row[q] = bud_ident(op);
             }
         }
     }
+}
+
+// One workgroup per tile.
+template <typename Ts, typename T, int MODE, bool PW, int NS, bool BUD, int NCH>
+__global__ void __launch_bounds__((march_waves<Ts, T>() * 64)) advect_march(MarchArgs m) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    // Consecutive tiles along y go to the same XCD (workgroups are dealt to
+    // the 8 XCDs round-robin), so neighbouring tiles share halo columns
+    // through that XCD's L2.
+    int b = blockIdx.x;
+    const int nb = gridDim.x;
+    if ((nb & 7) == 0) b = (b & 7) * (nb >> 3) + (b >> 3);
+    TileJob t;
+    t.s0 = m.s0;
+    t.ti = m.ti;
+    t.jt = b % m.njt;
+    t.seg = b / m.njt;
+    t.partial_row = BUD ? m.a.partials + (size_t)blockIdx.x * NB : nullptr;
+    t.first_pass = m.first_pass;
+    march_tile<Ts, T, MODE, PW, NS, BUD, NCH>(m.a, t, smem_raw);
 }
 
 }  // namespace monc

@@ -5,6 +5,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <string>
+
 #include "../../include/monc_adv.h"
 
 namespace monc {
@@ -45,5 +47,15 @@ hipError_t launch_budget_final(const double* partials, int nblocks,
 hipError_t launch_cast(int dtype, int nfields, const double* const* src,
                        void* const* dst, const double* offset, long n,
                        hipStream_t s);
+
+// Ensemble plans (ensemble.hip).
+struct EnsemblePlan;
+int ensemble_create(const monc_member* members, int n, int nscal, const char* tune_cache,
+                    int tune, EnsemblePlan** out, std::string* err);
+int ensemble_step_eager(EnsemblePlan* P, hipStream_t s, std::string* err);
+int ensemble_run(EnsemblePlan* P, int nsteps, hipStream_t s, std::string* err);
+void ensemble_info(const EnsemblePlan* P, int* ti, int* grid, int* nitems);
+int ensemble_parity(const EnsemblePlan* P);
+void ensemble_destroy(EnsemblePlan* P);
 
 }  // namespace monc

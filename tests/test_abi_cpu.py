@@ -122,3 +122,32 @@ def test_strerror_and_workspace():
     assert L.monc_strerror(12345) == b"unknown error"
     assert M.monc_step_workspace_bytes(1024, 1024, 128, 2) > 0
     assert M.monc_step_workspace_bytes(0, 4, 4, 2) == 0
+
+
+def test_ensemble_create_validates_members():
+    L = M.lib()
+    arr = (M.MoncMember * 1)()
+    m = arr[0]
+    m.nx, m.ny, m.nz = 8, 8, 8
+    m.dx = m.dy = 50.0
+    m.dt = 0.5
+    m.rdz = m.rho = m.rhon = 0x1000
+    for p in range(2):
+        for f in range(5):
+            m.state[p][f] = 0x2000 + 0x100 * (5 * p + f)
+    plan = C.c_void_p()
+    m.dt = 0.0
+    assert L.monc_ensemble_create(C.cast(arr, C.c_void_p), 1, 2, None, 0,
+                                  C.byref(plan)) == M.MONC_EINVAL
+    m.dt = 0.5
+    m.state[1][3] = 0
+    assert L.monc_ensemble_create(C.cast(arr, C.c_void_p), 1, 2, None, 0,
+                                  C.byref(plan)) == M.MONC_EINVAL
+    m.state[1][3] = 0x2000
+    assert L.monc_ensemble_create(C.cast(arr, C.c_void_p), 1, 2, None, 0,
+                                  C.byref(plan)) == M.MONC_EINVAL  # aliases state[0][0]
+    assert L.monc_ensemble_create(C.cast(arr, C.c_void_p), 0, 2, None, 0,
+                                  C.byref(plan)) == M.MONC_EINVAL
+    assert L.monc_ensemble_create(C.cast(arr, C.c_void_p), 1, 4, None, 0,
+                                  C.byref(plan)) == M.MONC_EUNSUPPORTED
+    assert L.monc_ensemble_run(None, 5, None) == M.MONC_EINVAL

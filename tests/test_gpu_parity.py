@@ -236,3 +236,25 @@ def test_big1024_subdomains_match_oracle():
             exp = ref[n][i0 + 2:i1 + 2, j0 + 2:j1 + 2]
             e = np.abs(got - exp).max() / np.abs(exp).max()
             assert e <= TOL64, f"region {(i0, i1, j0, j1)} field {n}: {e:.3e}"
+
+
+def test_halos_are_never_read():
+    """Inputs with NaN halos (never filled) give the oracle's result: periodic
+    neighbours are read at wrapped interior indices."""
+    say("unfilled halos")
+    g, host = case(20, 14, 40, 2, seed=530)
+    dt = 0.5
+    ref = oracle_tendencies(host, g, dt)
+    poisoned = [I.pad(I.interior(h)) for h in host]  # NaN halos
+    T = torch()
+    d = to_dev(poisoned)
+    out = [T.zeros_like(x) for x in d]
+    M.monc_advect(M.MONC_F64, d, out, g.dx, g.dy, prof_dev(g), dt)
+    T.cuda.synchronize()
+    for n, (a, b) in enumerate(zip(out, ref)):
+        assert rel_err(a.cpu().numpy(), b) <= TOL64, n
+    step_ref = O.step([h.copy() for h in host], g, dt)
+    o, b = run_step(to_dev(poisoned), g, dt)
+    for n in range(5):
+        assert rel_err(o[n].cpu().numpy() - host[n], step_ref[n] - host[n]) <= TOL64, n
+    assert b[M.B_NONFINITE] == 0
