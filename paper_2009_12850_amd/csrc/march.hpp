@@ -225,13 +225,21 @@ __device__ __forceinline__ void march_tile(const AdvArgs& a, const TileJob& tj,
     }
     // Periodic neighbours are read at wrapped indices: the arrays' halos are
     // never read.  plane ii of field pointer p (uniform) ...
+    // indices reach at most two periods outside [0, n): wrap by adds, not
+    // by an integer division
     auto wrapx = [&](int ii) -> int {
-        ii %= nx;
-        return ii < 0 ? ii + nx : ii;
+        if (ii < 0) ii += nx;
+        if (ii < 0) ii += nx;
+        if (ii >= nx) ii -= nx;
+        if (ii >= nx) ii -= nx;
+        return ii;
     };
     auto wrapy = [&](int jj) -> int {
-        jj %= ny;
-        return jj < 0 ? jj + ny : jj;
+        if (jj < 0) jj += ny;
+        if (jj < 0) jj += ny;
+        if (jj >= ny) jj -= ny;
+        if (jj >= ny) jj -= ny;
+        return jj;
     };
     auto plane = [&](const Ts* p, int ii) -> const Ts* {
         return p + (size_t)(wrapx(ii) + 2) * sx;
