@@ -574,3 +574,72 @@ double oracle_max_courant(const double *u, const double *v, const double *w,
     vgeom_free(&vg);
     return cmax;
 }
+
+/* ---------------------------------------------------------------------------
+ * 4x restriction of a fine state to a coarse grid (the coarse-graining used to
+ * build training targets for the learned flux correction).  nx, ny, nz must be
+ * multiples of 4.  Coarse cell (I,J,K) covers fine cells 4I..4I+3 etc.
+ *   dZ_K   = sum of dz over the 4 fine cells
+ *   RHON_K = sum rhon dz / dZ_K          (mass-weighted centre density)
+ *   RHO_K  = rho of the fine top face 4K+3
+ *   scalar = sum rhon dz phi / (16 sum rhon dz)       (mass-weighted mean)
+ *   U      = sum_{j,k} rhon dz u(4I+3) / (4 RHON_K dZ_K) (mass-flux mean on the face)
+ *   V      likewise on the fine face 4J+3
+ *   W      = mean of w over the 16 fine faces at level 4K+3
+ * With these, the coarse mass flux through a coarse face is the sum of the fine
+ * mass fluxes through it, so the coarse mass divergence is the volume-weighted
+ * mean of the fine ones.  Outputs: coarse fields (interior), rdz_c, rho_c,
+ * rhon_c [nz/4].
+ * ------------------------------------------------------------------------- */
+int oracle_restrict4(double *const *fine, double *const *coarse, int nscal, int nx,
+                     int ny, int nz, const double *rdz, const double *rho,
+                     const double *rhon, double *rdz_c, double *rho_c,
+                     double *rhon_c) {
+    if (nx % 4 || ny % 4 || nz % 4 || nx < 4 || ny < 4 || nz < 4) return OR_EINVAL;
+    grid_t gf = {nx, ny, nz};
+    grid_t gc = {nx / 4, ny / 4, nz / 4};
+    int NX = nx / 4, NY = ny / 4, NZ = nz / 4;
+    double *dZ = (double *)malloc(sizeof(double) * NZ);
+    double *mZ = (double *)malloc(sizeof(double) * NZ); /* sum rhon dz */
+    for (int K = 0; K < NZ; K++) {
+        dZ[K] = 0.0;
+        mZ[K] = 0.0;
+        for (int k = 4 * K; k < 4 * K + 4; k++) {
+            double dz = 1.0 / rdz[k];
+            dZ[K] += dz;
+            mZ[K] += rhon[k] * dz;
+        }
+        rdz_c[K] = 1.0 / dZ[K];
+        rhon_c[K] = mZ[K] / dZ[K];
+        rho_c[K] = rho[4 * K + 3];
+    }
+    for (int I = 0; I < NX; I++)
+        for (int J = 0; J < NY; J++)
+            for (int K = 0; K < NZ; K++) {
+                long c = at(&gc, I, J, K);
+                double su = 0.0, sv = 0.0, sw = 0.0;
+                for (int j = 4 * J; j < 4 * J + 4; j++)
+                    for (int k = 4 * K; k < 4 * K + 4; k++)
+                        su += rhon[k] / rdz[k] * fine[0][at(&gf, 4 * I + 3, j, k)];
+                for (int i = 4 * I; i < 4 * I + 4; i++)
+                    for (int k = 4 * K; k < 4 * K + 4; k++)
+                        sv += rhon[k] / rdz[k] * fine[1][at(&gf, i, 4 * J + 3, k)];
+                for (int i = 4 * I; i < 4 * I + 4; i++)
+                    for (int j = 4 * J; j < 4 * J + 4; j++)
+                        sw += fine[2][at(&gf, i, j, 4 * K + 3)];
+                coarse[0][c] = su / (4.0 * mZ[K]);
+                coarse[1][c] = sv / (4.0 * mZ[K]);
+                coarse[2][c] = (K == NZ - 1) ? 0.0 : sw / 16.0;
+                for (int s = 0; s < nscal; s++) {
+                    double sp = 0.0;
+                    for (int i = 4 * I; i < 4 * I + 4; i++)
+                        for (int j = 4 * J; j < 4 * J + 4; j++)
+                            for (int k = 4 * K; k < 4 * K + 4; k++)
+                                sp += rhon[k] / rdz[k] * fine[3 + s][at(&gf, i, j, k)];
+                    coarse[3 + s][c] = sp / (16.0 * mZ[K]);
+                }
+            }
+    free(dZ);
+    free(mZ);
+    return OR_OK;
+}

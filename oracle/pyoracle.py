@@ -62,6 +62,8 @@ def lib():
                                      dp]
         L.oracle_max_courant.argtypes = [dp, dp, dp, i, i, i, d, d, dp, d]
         L.oracle_max_courant.restype = d
+        L.oracle_restrict4.argtypes = [C.POINTER(dp), C.POINTER(dp), i, i, i, i, dp, dp, dp,
+                                       dp, dp, dp]
         _lib = L
     return _lib
 
@@ -183,3 +185,24 @@ def max_courant(u, v, w, g, dt):
     rdz = np.ascontiguousarray(g.rdz, np.float64)
     return lib().oracle_max_courant(_p(u), _p(v), _p(w), nx, ny, nz, g.dx, g.dy,
                                     _p(rdz), float(dt))
+
+
+def restrict4(state, g):
+    """4x restriction; returns (coarse padded arrays with NaN halos, coarse Geometry)."""
+    from paper_2009_12850_amd import inputs as I
+    nx, ny, nz = _shape(state[0])
+    NX, NY, NZ = nx // 4, ny // 4, nz // 4
+    nscal = len(state) - 3
+    out = [np.full((NX + 4, NY + 4, NZ), np.nan) for _ in state]
+    rdz_c, rho_c, rhon_c = np.zeros(NZ), np.zeros(NZ), np.zeros(NZ)
+    P = C.POINTER(C.c_double)
+    a_in = (P * len(state))(*[_p(s) for s in state])
+    a_out = (P * len(state))(*[_p(s) for s in out])
+    rdz, rho, rhon = _prof(g)
+    rc = lib().oracle_restrict4(a_in, a_out, nscal, nx, ny, nz, _p(rdz), _p(rho), _p(rhon),
+                                _p(rdz_c), _p(rho_c), _p(rhon_c))
+    _check(rc, "restrict4")
+    zf = np.cumsum(1.0 / rdz_c)
+    gc = I.Geometry(NX, NY, NZ, 4 * g.dx, 4 * g.dy, rdz_c, rho_c, rhon_c, zf,
+                    zf - 0.5 / rdz_c)
+    return out, gc

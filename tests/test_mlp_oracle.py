@@ -1,0 +1,154 @@
+"""Pins of the FP64 oracle of the learned flux correction (CPU only)."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import mlp_ref as R
+from oracle import pyoracle as O
+from paper_2009_12850_amd import inputs as I
+
+
+def test_bf16_rounding_matches_torch_conversion():
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(0)
+    x = np.concatenate([rng.standard_normal(20000) * 10.0 ** rng.integers(-6, 6, 20000),
+                        [1.0, 1.0 + 2 ** -8, 1.0 + 3 * 2 ** -9, -0.0, 65504.0]])
+    ref = torch.from_numpy(x.astype(np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
+    np.testing.assert_array_equal(R.bf16(x), ref)
+    assert R.bf16(1.0 + 2 ** -8) == 1.0          # tie goes to even
+    assert R.bf16(1.0 + 3 * 2 ** -8) == 1.0 + 2 ** -6
+
+
+def test_gelu_derivative_is_the_derivative():
+    z = np.linspace(-6, 6, 241)
+    h = 1e-6
+    num = (R.gelu(z + h) - R.gelu(z - h)) / (2 * h)
+    np.testing.assert_allclose(R.gelu_grad(z), num, atol=1e-9)
+    # the Gaussian CDF form: gelu(z) = z * Phi(z)
+    assert abs(R.gelu(1.0) - 0.8413447460685429) < 1e-15
+
+
+def small_problem(seed=0, B=6):
+    rng = np.random.default_rng(seed)
+    p = R.init_params(seed)
+    X = rng.standard_normal((4 * B, R.K))
+    X[:, R.NIN:] = 0.0
+    target = rng.standard_normal((B, 4))
+    rhohat = rng.uniform(0.7, 1.0, (B, 4))
+    mask = np.ones((B, 4))
+    mask[0, 2] = 0.0
+    return p, X, target, rhohat, mask
+
+
+def loss_of(p, X, target, rhohat, mask):
+    Y, _ = R.forward(X, p, emulate=False)
+    return R.loss_and_grad(Y, target, rhohat, mask)[0]
+
+
+def test_backward_matches_finite_differences_fp64():
+    p, X, target, rhohat, mask = small_problem()
+    Y, cache = R.forward(X, p, emulate=False)
+    loss, dY = R.loss_and_grad(Y, target, rhohat, mask)
+    g = R.backward(dY, cache, emulate=False)
+    rng = np.random.default_rng(1)
+    W1cols = [j * R.K + k for j in range(R.H) for k in range(R.NIN)]
+    idx = list(rng.choice(W1cols, 40, replace=False)) + list(
+        rng.choice(np.arange(R.H * R.K, R.NPARAM), 60, replace=False))
+    for n in idx:
+        h = 1e-6
+        pp, pm = p.copy(), p.copy()
+        pp[n] += h
+        pm[n] -= h
+        num = (loss_of(pp, X, target, rhohat, mask) - loss_of(pm, X, target, rhohat, mask)) / (2 * h)
+        assert abs(num - g[n]) <= 1e-5 * (abs(num) + 1e-3), (n, num, g[n])
+    # padded input columns get no gradient
+    W1g = g[:R.H * R.K].reshape(R.H, R.K)
+    assert np.all(W1g[:, R.NIN:] == 0.0)
+
+
+def test_emulated_rounding_is_close_to_fp64():
+    p, X, target, rhohat, mask = small_problem(3)
+    Y64, _ = R.forward(X, p, emulate=False)
+    Yb, _ = R.forward(X, p, emulate=True)
+    assert np.abs(Yb - Y64).max() <= 0.05 * np.abs(Y64).max()
+
+
+def test_features_linear_field_and_wrap():
+    NX, NY, NZ = 7, 5, 4
+    ii, jj, kk = np.meshgrid(np.arange(NX), np.arange(NY), np.arange(NZ), indexing="ij")
+    state = [ii * 1.0, jj * 10.0, kk * 100.0, ii + 2.0 * jj]
+    norm = [0.0, 1.0, 0.0, 2.0, 1.0, 1.0, 0.0, 1.0]
+    cell = (0 * NY + 4) * NZ + 0  # i = 0, j = 4, k = 0
+    X = R.features(state, norm, 0, [cell])[0]
+    for a in range(5):
+        assert X[((0 * 5 + a) * 5 + 2) * 3 + 1] == (a - 2) % NX          # u along x, wrapped
+        assert X[((1 * 5 + 2) * 5 + a) * 3 + 1] == 10.0 * ((4 + a - 2) % NY) / 2.0  # v along y
+    for c in range(3):
+        assert X[((2 * 5 + 2) * 5 + 2) * 3 + c] == 100.0 * max(c - 1, 0) - 1.0  # clamped z
+    assert np.all(X[R.NIN:] == 0.0)
+
+
+def test_y_features_are_x_features_of_the_transposed_state():
+    rng = np.random.default_rng(4)
+    NX, NY, NZ = 6, 8, 5
+    state = [rng.standard_normal((NX, NY, NZ)) for _ in range(4)]
+    norm = [0.1, 2.0, -0.3, 1.5, 0.0, 0.5, 300.0, 2.0]
+    T = lambda a: np.transpose(a, (1, 0, 2))
+    tstate = [T(state[1]), T(state[0]), T(state[2]), T(state[3])]
+    tnorm = [norm[2], norm[3], norm[0], norm[1]] + norm[4:]
+    cells = np.arange(NX * NY * NZ)
+    i, j, k = cells // (NY * NZ), (cells // NZ) % NY, cells % NZ
+    Xy = R.features(state, norm, 1, cells)
+    Xt = R.features(tstate, tnorm, 0, (j * NX + i) * NZ + k)
+    np.testing.assert_array_equal(Xy, Xt)
+
+
+def test_correction_is_conservative_on_a_periodic_grid():
+    rng = np.random.default_rng(5)
+    NX, NY, NZ = 6, 5, 3
+    Gx = rng.standard_normal((NX, NY, NZ, 4))
+    Gy = rng.standard_normal((NX, NY, NZ, 4))
+    rh = rng.uniform(0.5, 1.0, NZ)
+    c = R.correction(Gx.reshape(-1, 4), np.roll(Gx, 1, axis=0).reshape(-1, 4),
+                     Gy[..., R.SWAP].reshape(-1, 4), np.roll(Gy, 1, axis=1)[..., R.SWAP].reshape(-1, 4),
+                     np.broadcast_to(rh[None, None, :, None], (NX, NY, NZ, 4)).reshape(-1, 4))
+    total = (c.reshape(NX, NY, NZ, 4) * rh[None, None, :, None]).sum(axis=(0, 1, 2))
+    assert np.abs(total).max() <= 1e-12
+
+
+def test_adam_first_step_closed_form():
+    g = np.array([0.5, -2.0, 1e-3, 0.0])
+    p = np.array([1.0, 1.0, 1.0, 1.0])
+    p1, m, v = R.adam(p, np.zeros(4), np.zeros(4), g, 1, lr=1e-3)
+    np.testing.assert_allclose(p1, p - 1e-3 * g / (np.abs(g) + 1e-8), rtol=1e-12)
+
+
+def test_restriction_pins():
+    """Constant fields restrict to themselves; coarse scalar mass equals fine
+    mass; coarse mass divergence is the volume-weighted mean of the fine one."""
+    O.build(force=False)
+    g = I.make_geometry(16, 12, 16, dx=50.0, dy=50.0)
+    f = I.make_fields(g, 1, 5)
+    st = [O.halo_fill(I.pad(f[n])) for n in ["u", "v", "w", "th"]]
+    cs, gc = O.restrict4(st, g)
+    cs = [O.halo_fill(c) for c in cs]
+    D = I.interior(O.divergence(*st[:3], g))
+    Dc = I.interior(O.divergence(*cs[:3], gc))
+    agg = (D / g.rdz).reshape(4, 4, 3, 4, 4, 4).sum(axis=(1, 3, 5)) / (16.0 / gc.rdz)
+    assert np.abs(Dc - agg).max() <= 1e-15 * np.abs(D).max() * 10
+    m_f = np.sum(I.interior(st[3]) * (g.rhon / g.rdz)[None, None, :])
+    m_c = 16 * np.sum(I.interior(cs[3]) * (gc.rhon / gc.rdz)[None, None, :])
+    assert abs(m_f - m_c) <= 1e-13 * abs(m_f)
+    const = [O.halo_fill(I.pad(np.full((16, 12, 16), v))) for v in (3.0, -2.0, 0.5, 300.0)]
+    const[2][:, :, -1] = 0.0
+    cc, _ = O.restrict4(const, g)
+    for n, v in enumerate((3.0, -2.0, 0.5, 300.0)):
+        inner = I.interior(cc[n])
+        if n == 2:
+            inner = inner[:, :, :-1]
+        np.testing.assert_allclose(inner, v, rtol=1e-14)
+    assert np.all(I.interior(cc[2])[:, :, -1] == 0.0)
+    # coarse profiles: thickness adds up, density at the coarse top face
+    np.testing.assert_allclose(1.0 / gc.rdz, (1.0 / g.rdz).reshape(4, 4).sum(axis=1), rtol=1e-15)
+    np.testing.assert_array_equal(gc.rho, g.rho[3::4])
