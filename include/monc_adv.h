@@ -208,6 +208,92 @@ int monc_ensemble_parity(const monc_ensemble *plan);
 int monc_ensemble_info(const monc_ensemble *plan, int *ti, int *grid, int *nitems);
 int monc_ensemble_destroy(monc_ensemble *plan);
 
+/* ---------------------------------------------------------------------------
+ * a9. Learned coarse-grid flux correction.  A fine run is restricted to a
+ * grid 4x coarser in x, y and z; a small MLP (300 inputs = the 5x5x3
+ * neighbourhood of u, v, w, theta around a cell, standardised; two 64-unit
+ * GELU layers; 4 outputs = correction fluxes of u, v, w, theta through one face)
+ * is trained on the difference between the restricted fine evolution and the
+ * plain coarse PW/TVD step, and its flux divergence corrects the coarse step.
+ * Evaluation and training use BF16 MFMA with FP32 accumulation; FP32 master
+ * weights; Adam.  The plain step is the fallback.
+ *
+ * Feature order: index ((f*5 + a)*5 + b)*3 + c for field f in (u, v, w,
+ * theta), a = offset along the face normal + 2, b = tangential offset + 2, c =
+ * vertical offset + 1; periodic in x and y, edge-replicated in z; orient 1
+ * (y-faces) exchanges x and y and swaps u and v; entries 300..319 are 0.
+ * Parameter vector (FP32, MONC_MLP_NPARAM): W1[64][320] | b1[64] |
+ * W2[64][64] (W2[out][in]) | b2[64] | W3[4][64] | b3[4].
+ * BF16 weight pack (MONC_MLP_WPACK uint16): W1 | W2 | W3 padded to [32][64].
+ * ------------------------------------------------------------------------- */
+#define MONC_MLP_NIN 300
+#define MONC_MLP_K 320
+#define MONC_MLP_H 64
+#define MONC_MLP_NOUT 4
+#define MONC_MLP_NPARAM (MONC_MLP_H * MONC_MLP_K + MONC_MLP_H + MONC_MLP_H * MONC_MLP_H + \
+                         MONC_MLP_H + MONC_MLP_NOUT * MONC_MLP_H + MONC_MLP_NOUT)
+#define MONC_MLP_WPACK (MONC_MLP_H * MONC_MLP_K + MONC_MLP_H * MONC_MLP_H + 32 * MONC_MLP_H)
+
+/* Fine -> coarse restriction (nx, ny, nz multiples of 4): scalars are
+ * mass-weighted means over 4x4x4 blocks, u and v mass-flux-weighted means over
+ * the coarse face, w the mean over the coarse top face; coarse profiles
+ * rdz_c, rho_c, rhon_c [nz/4] (thickness sum, top-face density, mass-weighted
+ * centre density).  The coarse mass divergence is the volume-weighted mean of
+ * the fine one.  fine/coarse: host arrays of 3+nscal device pointers. */
+int monc_restrict4(int nscal, const double *const *fine, double *const *coarse, int nx,
+                   int ny, int nz, const double *rdz, const double *rho,
+                   const double *rhon, double *rdz_c, double *rho_c, double *rhon_c,
+                   monc_stream_t stream);
+/* Gather BF16 features (rows [ncells][320]) of cells (device linear indices
+ * (i*ny + j)*nz + k, or NULL for all cells in that order).  state: host array
+ * of 4 device pointers (u, v, w, theta); norm: host [8] = mean, std per field. */
+int monc_mlp_features(const double *const *state, int nx, int ny, int nz,
+                      const double *norm, int orient, const int *cells, int ncells,
+                      uint16_t *X, monc_stream_t stream);
+/* BF16 weight pack from the FP32 parameters. */
+int monc_mlp_pack(const float *params, uint16_t *wpack, monc_stream_t stream);
+/* Y[m][4] = MLP(X[m][320]).  H1, H2 (BF16 [m][64]) and Z1, Z2 (FP32 [m][64],
+ * pre-activations) are saved for training when non-NULL. */
+int monc_mlp_forward(const uint16_t *X, int m, const float *params, const uint16_t *wpack,
+                     float *Y, uint16_t *H1, uint16_t *H2, float *Z1, float *Z2,
+                     monc_stream_t stream);
+/* Parameter gradient grad[MONC_MLP_NPARAM] from dY[m][4] and the saved forward
+ * activations; deterministic.  workspace >= monc_mlp_backward_workspace_bytes(m). */
+size_t monc_mlp_backward_workspace_bytes(int m);
+int monc_mlp_backward(const uint16_t *X, const uint16_t *H1, const uint16_t *H2,
+                      const float *Z1, const float *Z2, const float *dY, int m,
+                      const uint16_t *wpack, float *grad, void *workspace,
+                      monc_stream_t stream);
+/* Loss of the flux-divergence correction on b sampled cells (device linear
+ * indices `cells`).  Y4 = MLP outputs of the rows x(i), x(i-1), y(j), y(j-1)
+ * of those cells (b rows each, y outputs in the exchanged frame).  Correction
+ * c_q = -(gx(i) - gx(i-1) + gy(j) - gy(j-1)) / rhohat_q(k); target r_q / scale_q
+ * with the residual r_q = (c1_q - c0_q)/dt - tend_q of the coarse fields
+ * (c0, c1: the restricted state at t and t+dt; tend: the plain coarse source
+ * terms at c0; host arrays of 4 device pointers, u v w theta); w on the lid
+ * is masked.  loss[0] = inv_count * sum (c - target)^2; dY4 = its gradient.
+ * workspace >= monc_mlp_loss_workspace_bytes(b). */
+size_t monc_mlp_loss_workspace_bytes(int b);
+int monc_mlp_loss(const float *Y4, int b, const int *cells, const double *const *c0,
+                  const double *const *c1, const double *const *tend, int nx, int ny, int nz,
+                  double dt, const double *scale, const double *rho, const double *rhon,
+                  double inv_count, float *dY4, float *loss, void *workspace,
+                  monc_stream_t stream);
+/* One Adam step (t >= 1) on the FP32 parameters, then the BF16 pack. */
+int monc_mlp_adam(float *params, float *m1, float *m2, const float *grad, int t, double lr,
+                  double beta1, double beta2, double eps, uint16_t *wpack,
+                  monc_stream_t stream);
+/* Corrected coarse step for u, v, w, theta: out = in + dt (tend + scale_q c_q),
+ * c_q = -(gx_q(i) - gx_q(i-1) + gy_q(j) - gy_q(j-1)) / rhohat_q(k) with gx, gy
+ * [nx*ny*nz][4] face outputs (gy in the exchanged frame), rhohat = rho(k)/rho(0)
+ * for w and rhon(k)/rhon(0) otherwise.  If any face output is not finite the
+ * step is the plain one and flags[1] (device int) counts it; flags[0] is
+ * scratch.  tend: the plain source terms (monc_advect). */
+int monc_correct_step(double *const *state_in, double *const *tend, const float *gx,
+                      const float *gy, double *const *state_out, int nx, int ny, int nz,
+                      const double *scale, const double *rho, const double *rhon,
+                      double dt, int *flags, monc_stream_t stream);
+
 /* Map a budgets array (HOST copy, after synchronising) to a status:
  * MONC_ENONFINITE if any non-finite value was written, MONC_ECFL if the
  * largest Courant number exceeds 1, else MONC_OK. */

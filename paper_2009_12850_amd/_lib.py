@@ -52,6 +52,17 @@ _SIGS = {
                         ip),
     "monc_cast_working": ([ip, ip, PP, PP, DPTR, ip, ip, ip, vp], ip),
     "monc_budgets_check": ([DPTR], ip),
+    "monc_restrict4": ([ip, PP, PP, ip, ip, ip, vp, vp, vp, vp, vp, vp, vp], ip),
+    "monc_mlp_features": ([PP, ip, ip, ip, DPTR, ip, vp, ip, vp, vp], ip),
+    "monc_mlp_pack": ([vp, vp, vp], ip),
+    "monc_mlp_forward": ([vp, ip, vp, vp, vp, vp, vp, vp, vp, vp], ip),
+    "monc_mlp_backward_workspace_bytes": ([ip], C.c_size_t),
+    "monc_mlp_backward": ([vp, vp, vp, vp, vp, vp, ip, vp, vp, vp, vp], ip),
+    "monc_mlp_loss_workspace_bytes": ([ip], C.c_size_t),
+    "monc_mlp_loss": ([vp, ip, vp, PP, PP, PP, ip, ip, ip, dp, DPTR, vp, vp, dp, vp, vp, vp,
+                       vp], ip),
+    "monc_mlp_adam": ([vp, vp, vp, vp, ip, dp, dp, dp, dp, vp, vp], ip),
+    "monc_correct_step": ([PP, PP, vp, vp, PP, ip, ip, ip, DPTR, vp, vp, dp, vp, vp], ip),
     "monc_ensemble_create": ([vp, ip, ip, C.c_char_p, ip, C.POINTER(vp)], ip),
     "monc_ensemble_run": ([vp, ip, vp], ip),
     "monc_ensemble_step": ([vp, vp], ip),
@@ -347,3 +358,98 @@ class Ensemble:
             self.close()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------------------
+# Learned coarse-grid correction
+# ---------------------------------------------------------------------------
+MONC_MLP_NIN, MONC_MLP_K, MONC_MLP_H, MONC_MLP_NOUT = 300, 320, 64, 4
+MONC_MLP_NPARAM = (MONC_MLP_H * MONC_MLP_K + MONC_MLP_H + MONC_MLP_H * MONC_MLP_H + MONC_MLP_H
+                   + MONC_MLP_NOUT * MONC_MLP_H + MONC_MLP_NOUT)
+MONC_MLP_WPACK = MONC_MLP_H * MONC_MLP_K + MONC_MLP_H * MONC_MLP_H + 32 * MONC_MLP_H
+
+
+def _dbl(vals):
+    vals = [float(x) for x in vals]
+    return (C.c_double * len(vals))(*vals)
+
+
+def _opt(t):
+    return None if t is None else _ptr(t)
+
+
+def monc_restrict4(fine, coarse, prof, prof_c, stream=None):
+    torch = _torch()
+    nx, ny, nz = _grid(fine[0])
+    fa = _ptrs(fine, torch.float64, tuple(fine[0].shape), "fine")
+    ca = _ptrs(coarse, torch.float64, tuple(coarse[0].shape), "coarse")
+    nz_c = nz // 4
+    pc = [_ptr(p, torch.float64, (nz_c,), n) for p, n in zip(prof_c, ("rdz_c", "rho_c", "rhon_c"))]
+    _check(lib().monc_restrict4(len(fine) - 3, fa, ca, nx, ny, nz, *_prof(prof), *pc,
+                                _stream(stream)), "monc_restrict4")
+
+
+def monc_mlp_features(state, norm, orient, cells, X, stream=None):
+    torch = _torch()
+    nx, ny, nz = _grid(state[0])
+    sa = _ptrs(state, torch.float64, tuple(state[0].shape), "state")
+    n = nx * ny * nz if cells is None else cells.numel()
+    cp = None if cells is None else _ptr(cells, torch.int32, None, "cells")
+    _check(lib().monc_mlp_features(sa, nx, ny, nz, _dbl(norm), int(orient), cp, n,
+                                   _ptr(X, None, None, "X"), _stream(stream)), "monc_mlp_features")
+
+
+def monc_mlp_pack(params, wpack, stream=None):
+    _check(lib().monc_mlp_pack(_ptr(params), _ptr(wpack), _stream(stream)), "monc_mlp_pack")
+
+
+def monc_mlp_forward(X, m, params, wpack, Y, H1=None, H2=None, Z1=None, Z2=None, stream=None):
+    _check(lib().monc_mlp_forward(_ptr(X), int(m), _ptr(params), _ptr(wpack), _ptr(Y), _opt(H1),
+                                  _opt(H2), _opt(Z1), _opt(Z2), _stream(stream)),
+           "monc_mlp_forward")
+
+
+def monc_mlp_backward_workspace_bytes(m):
+    return int(lib().monc_mlp_backward_workspace_bytes(int(m)))
+
+
+def monc_mlp_backward(X, H1, H2, Z1, Z2, dY, m, wpack, grad, workspace, stream=None):
+    _check(lib().monc_mlp_backward(_ptr(X), _ptr(H1), _ptr(H2), _ptr(Z1), _ptr(Z2), _ptr(dY),
+                                   int(m), _ptr(wpack), _ptr(grad), _ptr(workspace),
+                                   _stream(stream)), "monc_mlp_backward")
+
+
+def monc_mlp_loss_workspace_bytes(b):
+    return int(lib().monc_mlp_loss_workspace_bytes(int(b)))
+
+
+def monc_mlp_loss(Y4, b, cells, c0, c1, tend, dt, scale, prof_c, inv_count, dY4, loss,
+                  workspace, stream=None):
+    torch = _torch()
+    nx, ny, nz = _grid(c0[0])
+    sh = tuple(c0[0].shape)
+    a0, a1, at = (_ptrs(x, torch.float64, sh, n) for x, n in ((c0, "c0"), (c1, "c1"), (tend, "tend")))
+    rdz, rho, rhon = prof_c
+    _check(lib().monc_mlp_loss(_ptr(Y4), int(b), _ptr(cells, torch.int32), a0, a1, at, nx, ny, nz,
+                               float(dt), _dbl(scale), _ptr(rho), _ptr(rhon), float(inv_count),
+                               _ptr(dY4), _ptr(loss), _ptr(workspace), _stream(stream)),
+           "monc_mlp_loss")
+
+
+def monc_mlp_adam(params, m1, m2, grad, t, lr, b1, b2, eps, wpack, stream=None):
+    _check(lib().monc_mlp_adam(_ptr(params), _ptr(m1), _ptr(m2), _ptr(grad), int(t), float(lr),
+                               float(b1), float(b2), float(eps), _ptr(wpack), _stream(stream)),
+           "monc_mlp_adam")
+
+
+def monc_correct_step(state_in, tend, gx, gy, state_out, scale, prof_c, dt, flags, stream=None):
+    torch = _torch()
+    nx, ny, nz = _grid(state_in[0])
+    sh = tuple(state_in[0].shape)
+    ia = _ptrs(state_in, torch.float64, sh, "state_in")
+    ta = _ptrs(tend, torch.float64, sh, "tend")
+    oa = _ptrs(state_out, torch.float64, sh, "state_out")
+    rdz, rho, rhon = prof_c
+    _check(lib().monc_correct_step(ia, ta, _ptr(gx), _ptr(gy), oa, nx, ny, nz, _dbl(scale),
+                                   _ptr(rho), _ptr(rhon), float(dt), _ptr(flags, torch.int32),
+                                   _stream(stream)), "monc_correct_step")

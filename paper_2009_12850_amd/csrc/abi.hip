@@ -349,6 +349,119 @@ int monc_ensemble_destroy(monc_ensemble* plan) {
     return MONC_OK;
 }
 
+int monc_restrict4(int nscal, const double* const* fine, double* const* coarse, int nx, int ny,
+                   int nz, const double* rdz, const double* rho, const double* rhon,
+                   double* rdz_c, double* rho_c, double* rhon_c, monc_stream_t stream) {
+    TRY(check_grid(nx, ny, nz));
+    TRY(check_nscal(nscal));
+    if (nx % 4 || ny % 4 || nz % 4 || nz < 8)
+        return fail(MONC_EINVAL, "restriction needs nx, ny, nz multiples of 4 (nz >= 8)");
+    TRY(check_prof(rdz, rho, rhon));
+    if (!rdz_c || !rho_c || !rhon_c) return fail(MONC_EINVAL, "coarse profile pointer is NULL");
+    TRY(check_ptrs(3 + nscal, fine, "fine"));
+    TRY(check_ptrs(3 + nscal, coarse, "coarse"));
+    TRY(check_alias(3 + nscal, (const void* const*)fine, 3 + nscal, (const void* const*)coarse));
+    return hip_status(launch_restrict4(nscal, fine, coarse, nx, ny, nz, rdz, rho, rhon, rdz_c,
+                                       rho_c, rhon_c, (hipStream_t)stream),
+                      "restrict4");
+}
+
+int monc_mlp_features(const double* const* state, int nx, int ny, int nz, const double* norm,
+                      int orient, const int* cells, int ncells, uint16_t* X,
+                      monc_stream_t stream) {
+    TRY(check_grid(nx, ny, nz));
+    TRY(check_ptrs(4, state, "state"));
+    if (!norm || !X) return fail(MONC_EINVAL, "norm or X is NULL");
+    if (orient != 0 && orient != 1) return fail(MONC_EINVAL, "orient must be 0 or 1");
+    if (ncells < 1) return fail(MONC_EINVAL, "ncells must be >= 1");
+    if (!cells && (long)ncells != (long)nx * ny * nz)
+        return fail(MONC_EINVAL, "without a cell list ncells must be nx*ny*nz");
+    for (int f = 0; f < 4; f++)
+        if (!(norm[2 * f + 1] > 0)) return fail(MONC_EINVAL, "norm std %d must be > 0", f);
+    return hip_status(launch_features(state, nx, ny, nz, norm, orient, cells, ncells, X,
+                                      (hipStream_t)stream),
+                      "mlp_features");
+}
+
+int monc_mlp_pack(const float* params, uint16_t* wpack, monc_stream_t stream) {
+    if (!params || !wpack) return fail(MONC_EINVAL, "NULL pointer");
+    return hip_status(launch_mlp_pack(params, wpack, (hipStream_t)stream), "mlp_pack");
+}
+
+int monc_mlp_forward(const uint16_t* X, int m, const float* params, const uint16_t* wpack,
+                     float* Y, uint16_t* H1, uint16_t* H2, float* Z1, float* Z2,
+                     monc_stream_t stream) {
+    if (!X || !params || !wpack || !Y) return fail(MONC_EINVAL, "NULL pointer");
+    if (m < 1) return fail(MONC_EINVAL, "m must be >= 1");
+    if (((uintptr_t)X | (uintptr_t)wpack) & 15) return fail(MONC_EINVAL, "X, wpack must be 16-byte aligned");
+    return hip_status(launch_mlp_forward(X, m, params, wpack, Y, H1, H2, Z1, Z2,
+                                         (hipStream_t)stream),
+                      "mlp_forward");
+}
+
+size_t monc_mlp_backward_workspace_bytes(int m) { return m < 1 ? 0 : mlp_backward_workspace(m); }
+
+int monc_mlp_backward(const uint16_t* X, const uint16_t* H1, const uint16_t* H2, const float* Z1,
+                      const float* Z2, const float* dY, int m, const uint16_t* wpack,
+                      float* grad, void* workspace, monc_stream_t stream) {
+    if (!X || !H1 || !H2 || !Z1 || !Z2 || !dY || !wpack || !grad || !workspace)
+        return fail(MONC_EINVAL, "NULL pointer");
+    if (m < 1) return fail(MONC_EINVAL, "m must be >= 1");
+    if (((uintptr_t)X | (uintptr_t)wpack) & 15) return fail(MONC_EINVAL, "X, wpack must be 16-byte aligned");
+    return hip_status(launch_mlp_backward(X, H1, H2, Z1, Z2, dY, m, wpack, grad, workspace,
+                                          (hipStream_t)stream),
+                      "mlp_backward");
+}
+
+size_t monc_mlp_loss_workspace_bytes(int b) { return b < 1 ? 0 : mlp_loss_workspace(b); }
+
+int monc_mlp_loss(const float* Y4, int b, const int* cells, const double* const* c0,
+                  const double* const* c1, const double* const* tend, int nx, int ny, int nz,
+                  double dt, const double* scale, const double* rho, const double* rhon,
+                  double inv_count, float* dY4, float* loss, void* workspace,
+                  monc_stream_t stream) {
+    TRY(check_grid(nx, ny, nz));
+    TRY(check_dt(dt));
+    if (!Y4 || !cells || !dY4 || !loss || !workspace || !scale || !rho || !rhon)
+        return fail(MONC_EINVAL, "NULL pointer");
+    TRY(check_ptrs(4, c0, "c0"));
+    TRY(check_ptrs(4, c1, "c1"));
+    TRY(check_ptrs(4, tend, "tend"));
+    if (b < 1) return fail(MONC_EINVAL, "b must be >= 1");
+    for (int q = 0; q < 4; q++)
+        if (!(scale[q] > 0)) return fail(MONC_EINVAL, "scale %d must be > 0", q);
+    return hip_status(launch_mlp_loss(Y4, b, cells, c0, c1, tend, nx, ny, nz, dt, scale, rho,
+                                      rhon, inv_count, dY4, loss, workspace, (hipStream_t)stream),
+                      "mlp_loss");
+}
+
+int monc_mlp_adam(float* params, float* m1, float* m2, const float* grad, int t, double lr,
+                  double beta1, double beta2, double eps, uint16_t* wpack, monc_stream_t stream) {
+    if (!params || !m1 || !m2 || !grad || !wpack) return fail(MONC_EINVAL, "NULL pointer");
+    if (t < 1) return fail(MONC_EINVAL, "t must be >= 1");
+    if (!(lr > 0) || !(beta1 >= 0 && beta1 < 1) || !(beta2 >= 0 && beta2 < 1) || !(eps > 0))
+        return fail(MONC_EINVAL, "bad Adam hyper-parameters");
+    return hip_status(launch_mlp_adam(params, m1, m2, grad, t, lr, beta1, beta2, eps, wpack,
+                                      (hipStream_t)stream),
+                      "mlp_adam");
+}
+
+int monc_correct_step(double* const* state_in, double* const* tend, const float* gx,
+                      const float* gy, double* const* state_out, int nx, int ny, int nz,
+                      const double* scale, const double* rho, const double* rhon, double dt,
+                      int* flags, monc_stream_t stream) {
+    TRY(check_grid(nx, ny, nz));
+    TRY(check_dt(dt));
+    TRY(check_ptrs(4, state_in, "state_in"));
+    TRY(check_ptrs(4, tend, "tend"));
+    TRY(check_ptrs(4, state_out, "state_out"));
+    TRY(check_alias(4, (const void* const*)state_in, 4, (const void* const*)state_out));
+    if (!gx || !gy || !scale || !rho || !rhon || !flags) return fail(MONC_EINVAL, "NULL pointer");
+    return hip_status(launch_correct_step(state_in, tend, gx, gy, state_out, nx, ny, nz, scale,
+                                          rho, rhon, dt, flags, (hipStream_t)stream),
+                      "correct_step");
+}
+
 int monc_budgets_check(const double* b) {
     if (!b) return fail(MONC_EINVAL, "budgets is NULL");
     if (b[MONC_B_NONFINITE] > 0)

@@ -1,0 +1,740 @@
+// learned.hip -- the learned coarse-grid flux correction on gfx950.
+//
+// Restriction of fine states to a 4x coarser grid, the feature gather, a
+// 300 -> 64 -> 64 -> 4 GELU MLP evaluated and trained with BF16 MFMA
+// (v_mfma_f32_32x32x16_bf16, FP32 accumulation, FP32 master weights + Adam),
+// the flux-divergence loss, and the corrected coarse step with its fallback to
+// the plain PW/TVD step.
+#include <math.h>
+
+#include "monc_internal.hpp"
+#include "monc_scheme.hpp"
+
+namespace monc {
+
+namespace {
+
+constexpr int NIN = MONC_MLP_NIN, KP = MONC_MLP_K, HID = MONC_MLP_H, NO = MONC_MLP_NOUT;
+constexpr int OFF_W1 = 0, OFF_B1 = HID * KP, OFF_W2 = OFF_B1 + HID, OFF_B2 = OFF_W2 + HID * HID,
+              OFF_W3 = OFF_B2 + HID, OFF_B3 = OFF_W3 + NO * HID;
+constexpr int NPARAM = OFF_B3 + NO;
+static_assert(NPARAM == MONC_MLP_NPARAM, "parameter layout");
+// bf16 weight pack: W1 [64][320] | W2 [64][64] | W3 padded to [32][64]
+constexpr int PK_W1 = 0, PK_W2 = HID * KP, PK_W3 = PK_W2 + HID * HID;
+constexpr int PK_SIZE = PK_W3 + 32 * HID;
+static_assert(PK_SIZE == MONC_MLP_WPACK, "pack layout");
+
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x16_t __attribute__((ext_vector_type(16)));
+struct u16x8 {
+    uint16_t v[8];
+};
+
+__device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
+__device__ __forceinline__ uint16_t f2bf(float f) { return f32_to_bf16_rne(f); }
+
+__device__ __forceinline__ bf16x8_t ld8(const uint16_t* p) {  // 16-byte aligned
+    const uint4 v = *reinterpret_cast<const uint4*>(p);
+    return __builtin_bit_cast(bf16x8_t, v);
+}
+__device__ __forceinline__ bf16x8_t gather8(const uint16_t* p, int stride) {
+    u16x8 t;
+#pragma unroll
+    for (int v = 0; v < 8; v++) t.v[v] = p[v * stride];
+    return __builtin_bit_cast(bf16x8_t, t);
+}
+__device__ __forceinline__ bf16x8_t zero8() {
+    u16x8 t;
+#pragma unroll
+    for (int v = 0; v < 8; v++) t.v[v] = 0;
+    return __builtin_bit_cast(bf16x8_t, t);
+}
+__device__ __forceinline__ f32x16_t mfma(bf16x8_t a, bf16x8_t b, f32x16_t c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
+// Accumulator element r of lane l holds row 8(r/4) + 4(l/32) + r%4, column l%32
+// of the 32x32 tile.  Operand fragments: lane l supplies row (A) / column (B)
+// l%32 and the 8 k-values 8(l/32) .. 8(l/32)+7 of each 16-wide k block (the
+// same k assignment for A and B, which is all the product needs).
+__device__ __forceinline__ int acc_row(int r, int lane) { return 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3); }
+
+__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu_grad(float z) {
+    return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) +
+           z * expf(-0.5f * z * z) * 0.39894228040143268f;
+}
+
+// ---------------------------------------------------------------------------
+// 4x restriction: mass-weighted scalars, mass-flux-weighted face means for u,
+// v, plain means for w on the coarse top faces; coarse profiles.
+// ---------------------------------------------------------------------------
+struct RestrictArgs {
+    const double* fine[3 + MAXS];
+    double* coarse[3 + MAXS];
+    int nscal, nx, ny, nz;
+    const double *rdz, *rho, *rhon;
+    double *rdz_c, *rho_c, *rhon_c;
+};
+
+__global__ void __launch_bounds__(256) restrict_profiles(RestrictArgs a) {
+    const int K = blockIdx.x * blockDim.x + threadIdx.x;
+    if (K >= a.nz / 4) return;
+    double dZ = 0.0, mZ = 0.0;
+    for (int k = 4 * K; k < 4 * K + 4; k++) {
+        const double dz = 1.0 / a.rdz[k];
+        dZ += dz;
+        mZ += a.rhon[k] * dz;
+    }
+    a.rdz_c[K] = 1.0 / dZ;
+    a.rhon_c[K] = mZ / dZ;
+    a.rho_c[K] = a.rho[4 * K + 3];
+}
+
+__global__ void __launch_bounds__(256) restrict_fields(RestrictArgs a) {
+    const int NX = a.nx / 4, NY = a.ny / 4, NZ = a.nz / 4;
+    const long n = (long)NX * NY * NZ;
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const int K = (int)(t % NZ), J = (int)((t / NZ) % NY), I = (int)(t / ((long)NZ * NY));
+    const long fsx = (long)(a.ny + 4) * a.nz;
+    auto F = [&](int f, int i, int j, int k) -> double {
+        return a.fine[f][(long)(i + 2) * fsx + (long)(j + 2) * a.nz + k];
+    };
+    double mZ = 0.0;
+    for (int k = 4 * K; k < 4 * K + 4; k++) mZ += a.rhon[k] / a.rdz[k];
+    double su = 0.0, sv = 0.0, sw = 0.0;
+    for (int j = 4 * J; j < 4 * J + 4; j++)
+        for (int k = 4 * K; k < 4 * K + 4; k++) su += a.rhon[k] / a.rdz[k] * F(0, 4 * I + 3, j, k);
+    for (int i = 4 * I; i < 4 * I + 4; i++)
+        for (int k = 4 * K; k < 4 * K + 4; k++) sv += a.rhon[k] / a.rdz[k] * F(1, i, 4 * J + 3, k);
+    for (int i = 4 * I; i < 4 * I + 4; i++)
+        for (int j = 4 * J; j < 4 * J + 4; j++) sw += F(2, i, j, 4 * K + 3);
+    const long c = (long)(I + 2) * (NY + 4) * NZ + (long)(J + 2) * NZ + K;
+    a.coarse[0][c] = su / (4.0 * mZ);
+    a.coarse[1][c] = sv / (4.0 * mZ);
+    a.coarse[2][c] = K == NZ - 1 ? 0.0 : sw / 16.0;
+    for (int s = 0; s < a.nscal; s++) {
+        double sp = 0.0;
+        for (int i = 4 * I; i < 4 * I + 4; i++)
+            for (int j = 4 * J; j < 4 * J + 4; j++)
+                for (int k = 4 * K; k < 4 * K + 4; k++) sp += a.rhon[k] / a.rdz[k] * F(3 + s, i, j, k);
+        a.coarse[3 + s][c] = sp / (16.0 * mZ);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Feature gather: row c of X = the 5x5x3 neighbourhood of (u, v, w, theta)
+// around cell cells[c] (or c), standardised, in BF16; orient 1 exchanges x and
+// y (and u, v).  One thread per (row, feature).
+// ---------------------------------------------------------------------------
+struct FeatArgs {
+    const double* f[4];
+    double mean[4], inv_std[4];
+    int nx, ny, nz, orient;
+    const int* cells;
+    long ncells;
+    uint16_t* X;
+};
+
+__global__ void __launch_bounds__(256) features_kernel(FeatArgs a) {
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= a.ncells * KP) return;
+    const long row = t / KP;
+    const int n = (int)(t - row * KP);
+    uint16_t out = 0;
+    if (n < NIN) {
+        const int f = n / 75, a5 = (n / 15) % 5, b5 = (n / 3) % 5, c3 = n % 3;
+        const int cell = a.cells ? a.cells[row] : (int)row;
+        const int k = cell % a.nz, j = (cell / a.nz) % a.ny, i = cell / (a.nz * a.ny);
+        const int src = a.orient ? (f == 0 ? 1 : (f == 1 ? 0 : f)) : f;
+        const int di = a.orient ? b5 - 2 : a5 - 2;
+        const int dj = a.orient ? a5 - 2 : b5 - 2;
+        int ii = (i + di) % a.nx;
+        if (ii < 0) ii += a.nx;
+        int jj = (j + dj) % a.ny;
+        if (jj < 0) jj += a.ny;
+        int kk = k + c3 - 1;
+        kk = kk < 0 ? 0 : (kk > a.nz - 1 ? a.nz - 1 : kk);
+        const double v = a.f[src][((long)(ii + 2) * (a.ny + 4) + (jj + 2)) * a.nz + kk];
+        out = f2bf((float)((v - a.mean[src]) * a.inv_std[src]));
+    }
+    a.X[t] = out;
+}
+
+// ---------------------------------------------------------------------------
+// Weight pack (FP32 master -> BF16 MFMA operands)
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) pack_kernel(const float* __restrict__ p, uint16_t* __restrict__ w) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= PK_SIZE) return;
+    float v = 0.0f;
+    if (t < PK_W2) {
+        v = p[OFF_W1 + t];
+    } else if (t < PK_W3) {
+        v = p[OFF_W2 + (t - PK_W2)];
+    } else {
+        const int r = (t - PK_W3) / HID, c = (t - PK_W3) % HID;
+        v = r < NO ? p[OFF_W3 + r * HID + c] : 0.0f;
+    }
+    w[t] = f2bf(v);
+}
+
+// ---------------------------------------------------------------------------
+// Forward: 4 waves x 32 rows.  H = GELU(X W1^T + b1), H2 = GELU(H W2^T + b2),
+// Y = H2 W3^T + b3, with BF16 operands (X, W, H, H2) and FP32 accumulation.
+// ---------------------------------------------------------------------------
+constexpr int FWD_ROWS = 128;
+constexpr size_t FWD_LDS = (size_t)PK_SIZE * 2 + 4 * 32 * HID * 2 + (2 * HID + NO) * 4;
+
+__global__ void __launch_bounds__(256) mlp_forward(const uint16_t* __restrict__ X, int m,
+                                                   const float* __restrict__ params,
+                                                   const uint16_t* __restrict__ wpack,
+                                                   float* __restrict__ Y, uint16_t* H1o,
+                                                   uint16_t* H2o, float* Z1o, float* Z2o) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    uint16_t* sw = reinterpret_cast<uint16_t*>(smem);  // pack
+    uint16_t* sH = sw + PK_SIZE;                          // [4][32][64]
+    float* sb = reinterpret_cast<float*>(sH + 4 * 32 * HID);
+    for (int t = threadIdx.x; t < PK_SIZE / 8; t += 256)
+        reinterpret_cast<uint4*>(sw)[t] = reinterpret_cast<const uint4*>(wpack)[t];
+    for (int t = threadIdx.x; t < 2 * HID + NO; t += 256)
+        sb[t] = t < HID ? params[OFF_B1 + t] : (t < 2 * HID ? params[OFF_B2 + t - HID] : params[OFF_B3 + t - 2 * HID]);
+    __syncthreads();
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int row0 = blockIdx.x * FWD_ROWS + 32 * w;
+    const int ar = row0 + (lane & 31);  // A-operand row of this lane
+    const int kh = 8 * (lane >> 5);
+    uint16_t* H = sH + w * 32 * HID;
+
+    // layer 1
+#pragma unroll
+    for (int nt = 0; nt < 2; nt++) {
+        f32x16_t acc = {};
+        for (int kk = 0; kk < KP / 16; kk++) {
+            const bf16x8_t av = ar < m ? ld8(X + (size_t)ar * KP + 16 * kk + kh) : zero8();
+            const bf16x8_t bv = ld8(sw + PK_W1 + (32 * nt + (lane & 31)) * KP + 16 * kk + kh);
+            acc = mfma(av, bv, acc);
+        }
+#pragma unroll
+        for (int r = 0; r < 16; r++) {
+            const int lr = acc_row(r, lane), col = 32 * nt + (lane & 31);
+            const int row = row0 + lr;
+            const float z = acc[r] + sb[col];
+            const uint16_t h = f2bf(gelu(z));
+            H[lr * HID + col] = h;
+            if (row < m) {
+                if (Z1o) Z1o[(size_t)row * HID + col] = z;
+                if (H1o) H1o[(size_t)row * HID + col] = h;
+            }
+        }
+    }
+    __syncthreads();
+    // layer 2
+    f32x16_t acc2[2];
+#pragma unroll
+    for (int nt = 0; nt < 2; nt++) {
+        f32x16_t acc = {};
+#pragma unroll
+        for (int kk = 0; kk < HID / 16; kk++) {
+            const bf16x8_t av = ld8(H + (lane & 31) * HID + 16 * kk + kh);
+            const bf16x8_t bv = ld8(sw + PK_W2 + (32 * nt + (lane & 31)) * HID + 16 * kk + kh);
+            acc = mfma(av, bv, acc);
+        }
+        acc2[nt] = acc;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int nt = 0; nt < 2; nt++) {
+#pragma unroll
+        for (int r = 0; r < 16; r++) {
+            const int lr = acc_row(r, lane), col = 32 * nt + (lane & 31);
+            const int row = row0 + lr;
+            const float z = acc2[nt][r] + sb[HID + col];
+            const uint16_t h = f2bf(gelu(z));
+            H[lr * HID + col] = h;
+            if (row < m) {
+                if (Z2o) Z2o[(size_t)row * HID + col] = z;
+                if (H2o) H2o[(size_t)row * HID + col] = h;
+            }
+        }
+    }
+    __syncthreads();
+    // layer 3 (4 outputs, padded to a 32-wide tile)
+    f32x16_t acc = {};
+#pragma unroll
+    for (int kk = 0; kk < HID / 16; kk++) {
+        const bf16x8_t av = ld8(H + (lane & 31) * HID + 16 * kk + kh);
+        const bf16x8_t bv = ld8(sw + PK_W3 + (lane & 31) * HID + 16 * kk + kh);
+        acc = mfma(av, bv, acc);
+    }
+    const int col = lane & 31;
+    if (col < NO) {
+#pragma unroll
+        for (int r = 0; r < 16; r++) {
+            const int row = row0 + acc_row(r, lane);
+            if (row < m) Y[(size_t)row * NO + col] = acc[r] + sb[2 * HID + col];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Backward: 64 rows per workgroup (4 waves); per-workgroup partial gradients
+// of every parameter, reduced afterwards in a fixed order.
+// ---------------------------------------------------------------------------
+constexpr int BWD_ROWS = 64;
+constexpr size_t BWD_LDS = (size_t)BWD_ROWS * KP * 2 + 4 * (size_t)BWD_ROWS * HID * 2 +
+                           (size_t)HID * HID * 2 + (size_t)BWD_ROWS * NO * 4 + NO * HID * 4 +
+                           2 * 256 * 4;
+
+__global__ void __launch_bounds__(256) mlp_backward(const uint16_t* __restrict__ X,
+                                                    const uint16_t* __restrict__ H1,
+                                                    const uint16_t* __restrict__ H2,
+                                                    const float* __restrict__ Z1,
+                                                    const float* __restrict__ Z2,
+                                                    const float* __restrict__ dY, int m,
+                                                    const uint16_t* __restrict__ wpack,
+                                                    float* __restrict__ partials) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    uint16_t* sX = reinterpret_cast<uint16_t*>(smem);  // [64][320]
+    uint16_t* sH1 = sX + BWD_ROWS * KP;                   // [64][64]
+    uint16_t* sH2 = sH1 + BWD_ROWS * HID;
+    uint16_t* sdZ2 = sH2 + BWD_ROWS * HID;
+    uint16_t* sdZ1 = sdZ2 + BWD_ROWS * HID;
+    uint16_t* sW2 = sdZ1 + BWD_ROWS * HID;               // W2[j2][j1]
+    float* sdY = reinterpret_cast<float*>(sW2 + HID * HID);  // [64][4]
+    float* sW3 = sdY + BWD_ROWS * NO;                    // [4][64] (bf16 values)
+    float* red = sW3 + NO * HID;                          // [2][256]
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int row0 = blockIdx.x * BWD_ROWS;
+    float* part = partials + (size_t)blockIdx.x * NPARAM;
+
+    for (int t = tid; t < BWD_ROWS * KP / 8; t += 256) {
+        const int r = t / (KP / 8);
+        uint4 v = make_uint4(0, 0, 0, 0);
+        if (row0 + r < m) v = reinterpret_cast<const uint4*>(X + (size_t)(row0 + r) * KP)[t % (KP / 8)];
+        reinterpret_cast<uint4*>(sX)[t] = v;
+    }
+    for (int t = tid; t < BWD_ROWS * HID; t += 256) {
+        const int r = t / HID;
+        const bool ok = row0 + r < m;
+        sH1[t] = ok ? H1[(size_t)row0 * HID + t] : (uint16_t)0;
+        sH2[t] = ok ? H2[(size_t)row0 * HID + t] : (uint16_t)0;
+    }
+    for (int t = tid; t < HID * HID; t += 256) sW2[t] = wpack[PK_W2 + t];
+    for (int t = tid; t < NO * HID; t += 256) sW3[t] = bf2f(wpack[PK_W3 + t]);
+    for (int t = tid; t < BWD_ROWS * NO; t += 256)
+        sdY[t] = (row0 + t / NO < m) ? dY[(size_t)row0 * NO + t] : 0.0f;
+    __syncthreads();
+
+    // dZ2 = (dY W3) * gelu'(Z2); bias gradient b2
+    float db2 = 0.0f;  // thread handles column tid % 64, rows tid/64 + 4q
+    {
+        const int col = tid & 63;
+        for (int r = tid >> 6; r < BWD_ROWS; r += 4) {
+            float dz = 0.0f;
+            if (row0 + r < m) {
+                float dh = 0.0f;
+#pragma unroll
+                for (int q = 0; q < NO; q++) dh += sdY[r * NO + q] * sW3[q * HID + col];
+                dz = dh * gelu_grad(Z2[(size_t)(row0 + r) * HID + col]);
+            }
+            db2 += dz;
+            sdZ2[r * HID + col] = f2bf(dz);
+        }
+    }
+    red[tid] = db2;
+    __syncthreads();
+    if (tid < HID) part[OFF_B2 + tid] = red[tid] + red[tid + 64] + red[tid + 128] + red[tid + 192];
+
+    // dH1 = dZ2 W2 (MFMA), dZ1 = dH1 * gelu'(Z1): one 32x32 tile per wave.
+    // The bias gradient b1 sums the FP32 dZ1 values: each lane sums its 16
+    // rows, then the 4 (row tile, lane half) partials of a column are added in
+    // a fixed order.
+    const int kh = 8 * (lane >> 5);
+    {
+        const int rt = w >> 1, ct = w & 1;
+        f32x16_t acc = {};
+#pragma unroll
+        for (int kk = 0; kk < HID / 16; kk++) {
+            const bf16x8_t av = ld8(sdZ2 + (32 * rt + (lane & 31)) * HID + 16 * kk + kh);
+            const bf16x8_t bv = gather8(sW2 + (16 * kk + kh) * HID + 32 * ct + (lane & 31), HID);
+            acc = mfma(av, bv, acc);
+        }
+        float colsum = 0.0f;
+#pragma unroll
+        for (int r = 0; r < 16; r++) {
+            const int lr = 32 * rt + acc_row(r, lane), col = 32 * ct + (lane & 31);
+            float dz = 0.0f;
+            if (row0 + lr < m) dz = acc[r] * gelu_grad(Z1[(size_t)(row0 + lr) * HID + col]);
+            sdZ1[lr * HID + col] = f2bf(dz);
+            colsum += dz;
+        }
+        red[256 + (2 * rt + (lane >> 5)) * HID + 32 * ct + (lane & 31)] = colsum;
+    }
+    __syncthreads();
+    if (tid < HID)
+        part[OFF_B1 + tid] = red[256 + tid] + red[256 + HID + tid] + red[256 + 2 * HID + tid] +
+                             red[256 + 3 * HID + tid];
+    // dW2[j2][j1] = sum_rows dZ2[row][j2] H1[row][j1]: one tile per wave
+    {
+        const int it = w >> 1, jt = w & 1;
+        f32x16_t acc = {};
+#pragma unroll
+        for (int kk = 0; kk < BWD_ROWS / 16; kk++) {
+            const bf16x8_t av = gather8(sdZ2 + (16 * kk + kh) * HID + 32 * it + (lane & 31), HID);
+            const bf16x8_t bv = gather8(sH1 + (16 * kk + kh) * HID + 32 * jt + (lane & 31), HID);
+            acc = mfma(av, bv, acc);
+        }
+#pragma unroll
+        for (int r = 0; r < 16; r++) {
+            const int j2 = 32 * it + acc_row(r, lane), j1 = 32 * jt + (lane & 31);
+            part[OFF_W2 + j2 * HID + j1] = acc[r];
+        }
+    }
+    // dW1[j][k] = sum_rows dZ1[row][j] X[row][k]: 2 x 10 tiles, 5 per wave
+    for (int tt = w; tt < 20; tt += 4) {
+        const int it = tt / 10, kt = tt % 10;
+        f32x16_t acc = {};
+#pragma unroll
+        for (int kk = 0; kk < BWD_ROWS / 16; kk++) {
+            const bf16x8_t av = gather8(sdZ1 + (16 * kk + kh) * HID + 32 * it + (lane & 31), HID);
+            const bf16x8_t bv = gather8(sX + (16 * kk + kh) * KP + 32 * kt + (lane & 31), KP);
+            acc = mfma(av, bv, acc);
+        }
+#pragma unroll
+        for (int r = 0; r < 16; r++) {
+            const int j = 32 * it + acc_row(r, lane), k = 32 * kt + (lane & 31);
+            part[OFF_W1 + j * KP + k] = acc[r];
+        }
+    }
+    // dW3[q][j2] = sum_rows dY[row][q] H2[row][j2]; db3
+    {
+        const int q = tid / HID, j2 = tid % HID;  // 256 = 4 x 64
+        float s = 0.0f;
+        for (int r = 0; r < BWD_ROWS; r++) s += sdY[r * NO + q] * bf2f(sH2[r * HID + j2]);
+        part[OFF_W3 + q * HID + j2] = s;
+        if (tid < NO) {
+            float sb = 0.0f;
+            for (int r = 0; r < BWD_ROWS; r++) sb += sdY[r * NO + tid];
+            part[OFF_B3 + tid] = sb;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256) reduce_partials(const float* __restrict__ partials, int nb,
+                                                       int n, float* __restrict__ out) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    float s = 0.0f;
+    for (int b = 0; b < nb; b++) s += partials[(size_t)b * n + p];
+    out[p] = s;
+}
+
+// ---------------------------------------------------------------------------
+// Flux-divergence loss over B sampled cells; Y4 rows: x(i) | x(i-1) | y(j) |
+// y(j-1), B each; the y outputs are in the exchanged frame (u, v swapped).
+// The target of field q at a cell is the coarse residual
+//   r_q = (c1_q - c0_q)/dt - tend_q   (restricted fine evolution minus the
+// plain coarse source term), divided by scale_q; w on the lid is masked out.
+// ---------------------------------------------------------------------------
+struct LossArgs {
+    const float* Y4;
+    int B;
+    const int* cells;
+    const double* c0[4];
+    const double* c1[4];
+    const double* tend[4];
+    int nx, ny, nz;
+    double inv_dt;
+    double inv_scale[4];
+    const double *rho, *rhon;
+    double inv_n;
+    float* dY4;
+    double* partial;
+};
+
+__global__ void __launch_bounds__(256) loss_kernel(LossArgs a) {
+    __shared__ double red[256];
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    const int B = a.B;
+    double l = 0.0;
+    if (b < B) {
+        const int sw[4] = {1, 0, 2, 3};
+        const int cell = a.cells[b];
+        const int k = cell % a.nz, j = (cell / a.nz) % a.ny, i = cell / (a.nz * a.ny);
+        const long g = ((long)(i + 2) * (a.ny + 4) + (j + 2)) * a.nz + k;
+        for (int q = 0; q < 4; q++) {
+            const float yxp = a.Y4[(size_t)b * 4 + q], yxm = a.Y4[(size_t)(B + b) * 4 + q];
+            const float yyp = a.Y4[(size_t)(2 * B + b) * 4 + sw[q]],
+                        yym = a.Y4[(size_t)(3 * B + b) * 4 + sw[q]];
+            const float rh = (float)(q == 2 ? a.rho[k] / a.rho[0] : a.rhon[k] / a.rhon[0]);
+            const float tgt = (float)(((a.c1[q][g] - a.c0[q][g]) * a.inv_dt - a.tend[q][g]) *
+                                      a.inv_scale[q]);
+            const float msk = (q == 2 && k == a.nz - 1) ? 0.0f : 1.0f;
+            const float c = -(yxp - yxm + yyp - yym) / rh;
+            const float err = (c - tgt) * msk;
+            l += (double)err * (double)err;
+            const float gr = (float)(2.0 * (double)err * a.inv_n) / rh;
+            a.dY4[(size_t)b * 4 + q] = -gr;
+            a.dY4[(size_t)(B + b) * 4 + q] = gr;
+            a.dY4[(size_t)(2 * B + b) * 4 + sw[q]] = -gr;
+            a.dY4[(size_t)(3 * B + b) * 4 + sw[q]] = gr;
+        }
+    }
+    red[threadIdx.x] = l;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) a.partial[blockIdx.x] = red[0] * a.inv_n;
+}
+
+__global__ void __launch_bounds__(256) loss_final(const double* __restrict__ partial, int nb,
+                                                  float* __restrict__ loss) {
+    __shared__ double red[256];
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nb; b += 256) s += partial[b];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int q = 128; q > 0; q >>= 1) {
+        if (threadIdx.x < q) red[threadIdx.x] += red[threadIdx.x + q];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) loss[0] = (float)red[0];
+}
+
+// ---------------------------------------------------------------------------
+// Adam on the FP32 master weights, then the BF16 pack
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) adam_kernel(float* __restrict__ p, float* __restrict__ m1,
+                                                   float* __restrict__ m2,
+                                                   const float* __restrict__ g, float lr,
+                                                   float b1, float b2, float eps, float c1,
+                                                   float c2) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= NPARAM) return;
+    const float gt = g[t];
+    const float a = b1 * m1[t] + (1.0f - b1) * gt;
+    const float v = b2 * m2[t] + (1.0f - b2) * gt * gt;
+    m1[t] = a;
+    m2[t] = v;
+    p[t] -= lr * (a / c1) / (sqrtf(v / c2) + eps);
+}
+
+// ---------------------------------------------------------------------------
+// Corrected coarse step: state_out = state_in + dt (tend + S c), with c the
+// flux divergence of the network's face fluxes; falls back to the plain step
+// (c = 0) when any face flux is not finite, and counts the fallbacks.
+// ---------------------------------------------------------------------------
+struct CorrArgs {
+    const double* in[4];
+    const double* tend[4];
+    double* out[4];
+    const float* gx;
+    const float* gy;
+    int nx, ny, nz;
+    double scale[4];
+    const double *rho, *rhon;
+    double dt;
+    int* flags;
+};
+
+__global__ void __launch_bounds__(256) corr_clear(int* flags) {
+    if (threadIdx.x == 0) flags[0] = 0;
+}
+
+__global__ void __launch_bounds__(256) corr_check(const float* __restrict__ gx,
+                                                  const float* __restrict__ gy, long n,
+                                                  int* flags) {
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    if (!isfinite(gx[t]) || !isfinite(gy[t])) atomicOr(flags, 1);
+}
+
+__global__ void __launch_bounds__(256) corr_step(CorrArgs a) {
+    const long n = (long)a.nx * a.ny * a.nz;
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool plain = a.flags[0] != 0;
+    if (t == 0 && plain) a.flags[1] += 1;
+    if (t >= n) return;
+    const int k = (int)(t % a.nz), j = (int)((t / a.nz) % a.ny), i = (int)(t / ((long)a.nz * a.ny));
+    const int im = i == 0 ? a.nx - 1 : i - 1, jm = j == 0 ? a.ny - 1 : j - 1;
+    const long cm_x = ((long)im * a.ny + j) * a.nz + k, cm_y = ((long)i * a.ny + jm) * a.nz + k;
+    const long g = ((long)(i + 2) * (a.ny + 4) + (j + 2)) * a.nz + k;
+    const int sw[4] = {1, 0, 2, 3};
+    for (int q = 0; q < 4; q++) {
+        double c = 0.0;
+        if (!plain) {
+            const double rh = q == 2 ? a.rho[k] / a.rho[0] : a.rhon[k] / a.rhon[0];
+            const double div = (double)a.gx[t * 4 + q] - (double)a.gx[cm_x * 4 + q] +
+                               (double)a.gy[t * 4 + sw[q]] - (double)a.gy[cm_y * 4 + sw[q]];
+            c = -a.scale[q] * div / rh;
+        }
+        double v = a.in[q][g] + a.dt * (a.tend[q][g] + c);
+        if (q == 2 && k == a.nz - 1) v = 0.0;
+        a.out[q][g] = v;
+    }
+}
+
+int blocks_for(long n) { return (int)((n + 255) / 256); }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_restrict4(int nscal, const double* const* fine, double* const* coarse, int nx,
+                            int ny, int nz, const double* rdz, const double* rho,
+                            const double* rhon, double* rdz_c, double* rho_c, double* rhon_c,
+                            hipStream_t s) {
+    RestrictArgs a;
+    for (int f = 0; f < 3 + nscal; f++) {
+        a.fine[f] = fine[f];
+        a.coarse[f] = coarse[f];
+    }
+    a.nscal = nscal;
+    a.nx = nx;
+    a.ny = ny;
+    a.nz = nz;
+    a.rdz = rdz;
+    a.rho = rho;
+    a.rhon = rhon;
+    a.rdz_c = rdz_c;
+    a.rho_c = rho_c;
+    a.rhon_c = rhon_c;
+    restrict_profiles<<<1, 256, 0, s>>>(a);
+    restrict_fields<<<blocks_for((long)(nx / 4) * (ny / 4) * (nz / 4)), 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_features(const double* const* state, int nx, int ny, int nz, const double* norm,
+                           int orient, const int* cells, long ncells, uint16_t* X, hipStream_t s) {
+    FeatArgs a;
+    for (int f = 0; f < 4; f++) {
+        a.f[f] = state[f];
+        a.mean[f] = norm[2 * f];
+        a.inv_std[f] = 1.0 / norm[2 * f + 1];
+    }
+    a.nx = nx;
+    a.ny = ny;
+    a.nz = nz;
+    a.orient = orient;
+    a.cells = cells;
+    a.ncells = ncells;
+    a.X = X;
+    features_kernel<<<blocks_for(ncells * KP), 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_pack(const float* params, uint16_t* wpack, hipStream_t s) {
+    pack_kernel<<<blocks_for(PK_SIZE), 256, 0, s>>>(params, wpack);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_forward(const uint16_t* X, int m, const float* params,
+                              const uint16_t* wpack, float* Y, uint16_t* H1, uint16_t* H2,
+                              float* Z1, float* Z2, hipStream_t s) {
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void*)mlp_forward,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)FWD_LDS);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    mlp_forward<<<(m + FWD_ROWS - 1) / FWD_ROWS, 256, FWD_LDS, s>>>(X, m, params, wpack, Y, H1, H2,
+                                                                    Z1, Z2);
+    return hipGetLastError();
+}
+
+size_t mlp_backward_workspace(int m) {
+    return (size_t)((m + BWD_ROWS - 1) / BWD_ROWS) * NPARAM * sizeof(float);
+}
+
+hipError_t launch_mlp_backward(const uint16_t* X, const uint16_t* H1, const uint16_t* H2,
+                               const float* Z1, const float* Z2, const float* dY, int m,
+                               const uint16_t* wpack, float* grad, void* ws, hipStream_t s) {
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void*)mlp_backward,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)BWD_LDS);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    const int nb = (m + BWD_ROWS - 1) / BWD_ROWS;
+    mlp_backward<<<nb, 256, BWD_LDS, s>>>(X, H1, H2, Z1, Z2, dY, m, wpack, (float*)ws);
+    reduce_partials<<<blocks_for(NPARAM), 256, 0, s>>>((const float*)ws, nb, NPARAM, grad);
+    return hipGetLastError();
+}
+
+size_t mlp_loss_workspace(int b) { return (size_t)((b + 255) / 256) * sizeof(double); }
+
+hipError_t launch_mlp_loss(const float* Y4, int b, const int* cells, const double* const* c0,
+                           const double* const* c1, const double* const* tend, int nx, int ny,
+                           int nz, double dt, const double* scale, const double* rho,
+                           const double* rhon, double inv_n, float* dY4, float* loss, void* ws,
+                           hipStream_t s) {
+    LossArgs a;
+    a.Y4 = Y4;
+    a.B = b;
+    a.cells = cells;
+    for (int q = 0; q < 4; q++) {
+        a.c0[q] = c0[q];
+        a.c1[q] = c1[q];
+        a.tend[q] = tend[q];
+        a.inv_scale[q] = 1.0 / scale[q];
+    }
+    a.nx = nx;
+    a.ny = ny;
+    a.nz = nz;
+    a.inv_dt = 1.0 / dt;
+    a.rho = rho;
+    a.rhon = rhon;
+    a.inv_n = inv_n;
+    a.dY4 = dY4;
+    a.partial = (double*)ws;
+    const int nb = (b + 255) / 256;
+    loss_kernel<<<nb, 256, 0, s>>>(a);
+    loss_final<<<1, 256, 0, s>>>((const double*)ws, nb, loss);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_adam(float* params, float* m1, float* m2, const float* grad, int t,
+                           double lr, double b1, double b2, double eps, uint16_t* wpack,
+                           hipStream_t s) {
+    const float c1 = (float)(1.0 - pow(b1, t)), c2 = (float)(1.0 - pow(b2, t));
+    adam_kernel<<<blocks_for(NPARAM), 256, 0, s>>>(params, m1, m2, grad, (float)lr, (float)b1,
+                                                  (float)b2, (float)eps, c1, c2);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_mlp_pack(params, wpack, s);
+}
+
+hipError_t launch_correct_step(double* const* in, double* const* tend, const float* gx,
+                               const float* gy, double* const* out, int nx, int ny, int nz,
+                               const double* scale, const double* rho, const double* rhon,
+                               double dt, int* flags, hipStream_t s) {
+    CorrArgs a;
+    for (int q = 0; q < 4; q++) {
+        a.in[q] = in[q];
+        a.tend[q] = tend[q];
+        a.out[q] = out[q];
+        a.scale[q] = scale[q];
+    }
+    a.gx = gx;
+    a.gy = gy;
+    a.nx = nx;
+    a.ny = ny;
+    a.nz = nz;
+    a.rho = rho;
+    a.rhon = rhon;
+    a.dt = dt;
+    a.flags = flags;
+    const long n = (long)nx * ny * nz;
+    corr_clear<<<1, 64, 0, s>>>(flags);
+    corr_check<<<blocks_for(n * 4), 256, 0, s>>>(gx, gy, n * 4, flags);
+    corr_step<<<blocks_for(n), 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+}  // namespace monc

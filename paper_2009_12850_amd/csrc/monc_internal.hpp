@@ -48,6 +48,35 @@ hipError_t launch_cast(int dtype, int nfields, const double* const* src,
                        void* const* dst, const double* offset, long n,
                        hipStream_t s);
 
+// Learned correction (learned.hip).
+hipError_t launch_restrict4(int nscal, const double* const* fine, double* const* coarse, int nx,
+                            int ny, int nz, const double* rdz, const double* rho,
+                            const double* rhon, double* rdz_c, double* rho_c, double* rhon_c,
+                            hipStream_t s);
+hipError_t launch_features(const double* const* state, int nx, int ny, int nz, const double* norm,
+                           int orient, const int* cells, long ncells, uint16_t* X, hipStream_t s);
+hipError_t launch_mlp_pack(const float* params, uint16_t* wpack, hipStream_t s);
+hipError_t launch_mlp_forward(const uint16_t* X, int m, const float* params,
+                              const uint16_t* wpack, float* Y, uint16_t* H1, uint16_t* H2,
+                              float* Z1, float* Z2, hipStream_t s);
+size_t mlp_backward_workspace(int m);
+hipError_t launch_mlp_backward(const uint16_t* X, const uint16_t* H1, const uint16_t* H2,
+                               const float* Z1, const float* Z2, const float* dY, int m,
+                               const uint16_t* wpack, float* grad, void* ws, hipStream_t s);
+size_t mlp_loss_workspace(int b);
+hipError_t launch_mlp_loss(const float* Y4, int b, const int* cells, const double* const* c0,
+                           const double* const* c1, const double* const* tend, int nx, int ny,
+                           int nz, double dt, const double* scale, const double* rho,
+                           const double* rhon, double inv_n, float* dY4, float* loss, void* ws,
+                           hipStream_t s);
+hipError_t launch_mlp_adam(float* params, float* m1, float* m2, const float* grad, int t,
+                           double lr, double b1, double b2, double eps, uint16_t* wpack,
+                           hipStream_t s);
+hipError_t launch_correct_step(double* const* in, double* const* tend, const float* gx,
+                               const float* gy, double* const* out, int nx, int ny, int nz,
+                               const double* scale, const double* rho, const double* rhon,
+                               double dt, int* flags, hipStream_t s);
+
 // Ensemble plans (ensemble.hip).
 struct EnsemblePlan;
 int ensemble_create(const monc_member* members, int n, int nscal, const char* tune_cache,

@@ -1,0 +1,268 @@
+"""Learned coarse-grid flux correction: data, training and coarse runs.
+
+Fine runs of the plain scheme (monc_step, FP64) are restricted every
+`every` steps to a grid 4x coarser (monc_restrict4).  A coarse step of
+dt_c = every * dt is then corrected by the flux divergence of a small MLP,
+trained so that the corrected coarse source terms reproduce the restricted
+fine evolution.  All arithmetic on the fields and the network runs in the
+library's kernels; this module only orchestrates the calls, samples training
+cells (seeded, on the host) and computes normalisation statistics from a few
+host copies.
+"""
+from __future__ import annotations
+
+import dataclasses
+import time
+
+import numpy as np
+
+from . import _lib as M
+from . import inputs as I
+
+FIELDS = ["u", "v", "w", "th"]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+@dataclasses.dataclass
+class CoarseSeries:
+    snaps: list          # coarse states (4 padded FP64 device tensors each)
+    tend: list           # plain coarse source terms of snaps[:-1]
+    prof_c: list         # rdz_c, rho_c, rhon_c device tensors
+    dxc: float
+    dtc: float
+
+
+def fine_series(seed, nx, ny, nz, steps, every, dt, dx, device, amp=5.0, timing=None):
+    """Run the plain fine scheme and keep the restricted state every `every`
+    steps (including the initial state)."""
+    torch = _torch()
+    g = I.make_geometry(nx, ny, nz, dx, dx)
+    f = I.make_fields(g, 1, seed, amp=amp, padded=True)
+    A = [torch.from_numpy(f.pop(n)).to(device) for n in FIELDS]
+    B = [torch.empty_like(x) for x in A]
+    prof = [torch.from_numpy(np.ascontiguousarray(a)).to(device) for a in (g.rdz, g.rho, g.rhon)]
+    nzc = nz // 4
+    prof_c = [torch.empty(nzc, dtype=torch.float64, device=device) for _ in range(3)]
+    shape_c = (nx // 4 + 4, ny // 4 + 4, nzc)
+    snaps = []
+
+    def snap(state):
+        c = [torch.zeros(shape_c, dtype=torch.float64, device=device) for _ in range(4)]
+        M.monc_restrict4(state, c, prof, prof_c)
+        snaps.append(c)
+
+    snap(A)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(1, steps + 1):
+        M.monc_step(A, B, dx, dx, prof, dt)
+        A, B = B, A
+        if s % every == 0:
+            snap(A)
+    torch.cuda.synchronize()
+    if timing is not None:
+        timing.append(time.perf_counter() - t0)
+    dtc = every * dt
+    tend = []
+    for c in snaps[:-1]:
+        t = [torch.zeros_like(x) for x in c]
+        M.monc_advect(M.MONC_F64, c, t, 4 * dx, 4 * dx, prof_c, dtc)
+        tend.append(t)
+    return CoarseSeries(snaps, tend, prof_c, 4 * dx, dtc)
+
+
+def _coarse_dims(ser):
+    sh = ser.snaps[0][0].shape
+    return sh[0] - 4, sh[1] - 4, sh[2]
+
+
+def _interior(t):
+    return t[2:-2, 2:-2, :]
+
+
+def statistics(series_list, nsample=4):
+    """Input means/stds per field and residual scales per field, from a few
+    host copies of the coarse data."""
+    vals = [[] for _ in range(4)]
+    res = [[] for _ in range(4)]
+    for ser in series_list:
+        idx = np.linspace(0, len(ser.tend) - 1, min(nsample, len(ser.tend))).astype(int)
+        for n in idx:
+            c0 = [_interior(x).cpu().numpy() for x in ser.snaps[n]]
+            c1 = [_interior(x).cpu().numpy() for x in ser.snaps[n + 1]]
+            td = [_interior(x).cpu().numpy() for x in ser.tend[n]]
+            for q in range(4):
+                vals[q].append(c0[q].ravel())
+                r = (c1[q] - c0[q]) / ser.dtc - td[q]
+                if q == 2:
+                    r = r[:, :, :-1]
+                res[q].append(r.ravel())
+    norm = []
+    for q in range(4):
+        v = np.concatenate(vals[q])
+        norm += [float(v.mean()), float(max(v.std(), 1e-12))]
+    scale = [float(max(np.concatenate(res[q]).std(), 1e-30)) for q in range(4)]
+    return norm, scale
+
+
+class Correction:
+    """The MLP, its FP32 master weights, Adam moments and training buffers."""
+
+    def __init__(self, device, seed, norm, scale, batch=8192):
+        torch = _torch()
+        from_np = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a)).to(device=device, dtype=dt)
+        self.device = device
+        self.norm, self.scale = list(norm), list(scale)
+        self.params = from_np(init_params(seed), torch.float32)
+        self.m1 = torch.zeros_like(self.params)
+        self.m2 = torch.zeros_like(self.params)
+        self.grad = torch.zeros_like(self.params)
+        self.wpack = torch.zeros(M.MONC_MLP_WPACK, dtype=torch.int16, device=device)
+        M.monc_mlp_pack(self.params, self.wpack)
+        self.t = 0
+        self.B = batch
+        R = 4 * batch
+        self.X = torch.zeros((R, M.MONC_MLP_K), dtype=torch.int16, device=device)
+        self.Y = torch.zeros((R, 4), dtype=torch.float32, device=device)
+        self.H1 = torch.zeros((R, 64), dtype=torch.int16, device=device)
+        self.H2 = torch.zeros_like(self.H1)
+        self.Z1 = torch.zeros((R, 64), dtype=torch.float32, device=device)
+        self.Z2 = torch.zeros_like(self.Z1)
+        self.dY = torch.zeros_like(self.Y)
+        self.ws_b = torch.zeros(M.monc_mlp_backward_workspace_bytes(R), dtype=torch.uint8,
+                                device=device)
+        self.ws_l = torch.zeros(M.monc_mlp_loss_workspace_bytes(batch), dtype=torch.uint8,
+                                device=device)
+        self.loss = torch.zeros(1, dtype=torch.float32, device=device)
+        self.cells = torch.zeros(batch, dtype=torch.int32, device=device)
+        self.cx = torch.zeros(2 * batch, dtype=torch.int32, device=device)
+        self.cy = torch.zeros(2 * batch, dtype=torch.int32, device=device)
+
+    def sample(self, rng, NX, NY, NZ):
+        B = self.B
+        i = rng.integers(0, NX, B)
+        j = rng.integers(0, NY, B)
+        k = rng.integers(0, NZ, B)
+        c = (i * NY + j) * NZ + k
+        xm = (((i - 1) % NX) * NY + j) * NZ + k
+        ym = (i * NY + (j - 1) % NY) * NZ + k
+        n_terms = 4 * B - int(np.sum(k == NZ - 1))  # w on the lid is masked
+        return c, xm, ym, n_terms
+
+    def _forward_loss(self, ser, n, rng, save):
+        """Features, forward pass and loss on B seeded random cells of snapshot
+        pair n of a series."""
+        torch = _torch()
+        NX, NY, NZ = _coarse_dims(ser)
+        c, xm, ym, nterm = self.sample(rng, NX, NY, NZ)
+        B = self.B
+        host = np.concatenate([c, xm, c, ym, c]).astype(np.int32)
+        dev = torch.from_numpy(host).to(self.device)
+        self.cx.copy_(dev[:2 * B])
+        self.cy.copy_(dev[2 * B:4 * B])
+        self.cells.copy_(dev[4 * B:])
+        c0, c1, td = ser.snaps[n], ser.snaps[n + 1], ser.tend[n]
+        M.monc_mlp_features(c0, self.norm, 0, self.cx, self.X.narrow(0, 0, 2 * B))
+        M.monc_mlp_features(c0, self.norm, 1, self.cy, self.X.narrow(0, 2 * B, 2 * B))
+        saved = (self.H1, self.H2, self.Z1, self.Z2) if save else (None,) * 4
+        M.monc_mlp_forward(self.X, 4 * B, self.params, self.wpack, self.Y, *saved)
+        M.monc_mlp_loss(self.Y, B, self.cells, c0, c1, td, ser.dtc, self.scale, ser.prof_c,
+                        1.0 / nterm, self.dY, self.loss, self.ws_l)
+
+    def train_step(self, ser, n, rng, lr=1e-3):
+        """One Adam step; returns the (device) loss before the update."""
+        self._forward_loss(ser, n, rng, save=True)
+        M.monc_mlp_backward(self.X, self.H1, self.H2, self.Z1, self.Z2, self.dY, 4 * self.B,
+                            self.wpack, self.grad, self.ws_b)
+        self.t += 1
+        M.monc_mlp_adam(self.params, self.m1, self.m2, self.grad, self.t, lr, 0.9, 0.999, 1e-8,
+                        self.wpack)
+        return self.loss
+
+    def evaluate_loss(self, ser, n, rng):
+        """Loss on B cells without updating the weights."""
+        self._forward_loss(ser, n, rng, save=False)
+        return float(self.loss.item())
+
+
+def init_params(seed):
+    """FP32 master weights ~ N(0, 1/fan_in), biases 0, padded inputs 0 (drawn
+    on the host from a seeded generator)."""
+    rng = np.random.default_rng(seed)
+    H, K, NIN = M.MONC_MLP_H, M.MONC_MLP_K, M.MONC_MLP_NIN
+    W1 = rng.standard_normal((H, K)) / np.sqrt(NIN)
+    W1[:, NIN:] = 0.0
+    W2 = rng.standard_normal((H, H)) / np.sqrt(H)
+    W3 = rng.standard_normal((4, H)) / np.sqrt(H) * 0.1
+    return np.concatenate([W1.ravel(), np.zeros(H), W2.ravel(), np.zeros(H), W3.ravel(),
+                           np.zeros(4)]).astype(np.float32)
+
+
+def train(model, series_list, steps, seed=0, lr=1e-3, log=None, every=100):
+    rng = np.random.default_rng(seed)
+    hist = []
+    for it in range(steps):
+        ser = series_list[rng.integers(0, len(series_list))]
+        n = int(rng.integers(0, len(ser.tend)))
+        loss = model.train_step(ser, n, rng, lr=lr)
+        if (it + 1) % every == 0 or it == 0:
+            hist.append((it + 1, float(loss.item())))
+            if log:
+                log(f"  train step {it + 1}: loss {hist[-1][1]:.4f}")
+    return hist
+
+
+class CoarseRunner:
+    """Coarse steps, plain or corrected, on one coarse grid."""
+
+    def __init__(self, ser, model=None):
+        torch = _torch()
+        self.ser = ser
+        self.model = model
+        shape = ser.snaps[0][0].shape
+        dev = ser.snaps[0][0].device
+        self.tend = [torch.zeros(shape, dtype=torch.float64, device=dev) for _ in range(4)]
+        NX, NY, NZ = shape[0] - 4, shape[1] - 4, shape[2]
+        self.N = NX * NY * NZ
+        if model is not None:
+            self.X = torch.zeros((2 * self.N, M.MONC_MLP_K), dtype=torch.int16, device=dev)
+            self.G = torch.zeros((2 * self.N, 4), dtype=torch.float32, device=dev)
+            self.flags = torch.zeros(2, dtype=torch.int32, device=dev)
+
+    def step(self, A, B):
+        s = self.ser
+        if self.model is None:
+            M.monc_step(A, B, s.dxc, s.dxc, s.prof_c, s.dtc)
+            return
+        mdl, N = self.model, self.N
+        M.monc_advect(M.MONC_F64, A, self.tend, s.dxc, s.dxc, s.prof_c, s.dtc)
+        M.monc_mlp_features(A, mdl.norm, 0, None, self.X.narrow(0, 0, N))
+        M.monc_mlp_features(A, mdl.norm, 1, None, self.X.narrow(0, N, N))
+        M.monc_mlp_forward(self.X, 2 * N, mdl.params, mdl.wpack, self.G)
+        M.monc_correct_step(A, self.tend, self.G.narrow(0, 0, N), self.G.narrow(0, N, N), B,
+                            mdl.scale, s.prof_c, s.dtc, self.flags)
+
+    def run(self, state0, nsteps):
+        torch = _torch()
+        A = [x.clone() for x in state0]
+        B = [torch.zeros_like(x) for x in A]
+        for _ in range(nsteps):
+            self.step(A, B)
+            A, B = B, A
+        return A
+
+
+def errors(state, ref, ref0):
+    """Per field: RMS(state - ref) / RMS(ref - ref0) over the interior (the
+    error relative to the change of the restricted fine solution)."""
+    out = []
+    for q in range(4):
+        a, r, r0 = _interior(state[q]), _interior(ref[q]), _interior(ref0[q])
+        num = float(((a - r) ** 2).mean().sqrt())
+        den = float(((r - r0) ** 2).mean().sqrt())
+        out.append(num / max(den, 1e-300))
+    return out

@@ -1,0 +1,347 @@
+"""GPU parity of the learned coarse-grid flux correction against the FP64 oracle.
+
+Every kernel of the learned form is checked through the C ABI: the 4x
+restriction against the C oracle, the BF16 features, each MLP layer (given the
+GPU's own inputs to that layer, so the bound is FP32 accumulation, not
+accumulated BF16 rounding), the parameter gradient, the loss and its gradient,
+Adam, and the corrected step with its plain-step fallback.  A short training
+run must lower the loss on held-out data.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from gpu_util import dev, to_dev, torch
+from oracle import mlp_ref as R
+from oracle import pyoracle as O
+from paper_2009_12850_amd import _lib as M
+from paper_2009_12850_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _setup():
+    O.build(force=False)
+    M.lib()
+
+
+def bf16_bits_to_f64(t):
+    T = torch()
+    return t.view(T.bfloat16).double().cpu().numpy()
+
+
+def fine_case(nx, ny, nz, seed, nscal=1):
+    g = I.make_geometry(nx, ny, nz, dx=50.0, dy=50.0)
+    f = I.make_fields(g, nscal, seed, amp=5.0)
+    names = ["u", "v", "w"] + I.scalar_names(nscal)
+    return g, [O.halo_fill(I.pad(f[n])) for n in names]
+
+
+def coarse_state(NX, NY, NZ, seed):
+    """A random coarse state (padded, halos unused) with realistic magnitudes."""
+    rng = np.random.default_rng(seed)
+    s = [rng.standard_normal((NX + 4, NY + 4, NZ)) * a + b
+         for a, b in ((3.0, 1.0), (2.0, -0.5), (0.7, 0.0), (0.5, 300.0))]
+    s[2][:, :, -1] = 0.0
+    return s
+
+
+@pytest.mark.parametrize("shape,nscal", [((32, 32, 32), 1), ((16, 24, 8), 2), ((8, 4, 128), 1)])
+def test_restriction_matches_oracle(shape, nscal):
+    nx, ny, nz = shape
+    say(f"restrict4 {shape} nscal={nscal}")
+    g, host = fine_case(nx, ny, nz, 900 + nx + nscal, nscal)
+    ref, gc = O.restrict4(host, g)
+    T = torch()
+    fine = to_dev(host)
+    shc = (nx // 4 + 4, ny // 4 + 4, nz // 4)
+    coarse = [T.zeros(shc, dtype=T.float64, device=dev()) for _ in host]
+    prof_c = [T.zeros(nz // 4, dtype=T.float64, device=dev()) for _ in range(3)]
+    M.monc_restrict4(fine, coarse, to_dev([g.rdz, g.rho, g.rhon]), prof_c)
+    T.cuda.synchronize()
+    for n, (a, b) in enumerate(zip(coarse, ref)):
+        a, b = I.interior(a.cpu().numpy()), I.interior(b)
+        err = np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+        assert err <= 1e-14, (n, err)
+    for a, b in zip(prof_c, (gc.rdz, gc.rho, gc.rhon)):
+        np.testing.assert_allclose(a.cpu().numpy(), b, rtol=1e-15, atol=0)
+
+
+@pytest.mark.parametrize("orient", [0, 1])
+def test_features_match_oracle(orient):
+    NX, NY, NZ = 12, 10, 7
+    say(f"features orient={orient}")
+    s = coarse_state(NX, NY, NZ, 31 + orient)
+    norm = [1.0, 3.0, -0.5, 2.0, 0.0, 0.7, 300.0, 0.5]
+    T = torch()
+    ds = to_dev(s)
+    inner = [I.interior(a) for a in s]
+    n = NX * NY * NZ
+    X = T.zeros((n, R.K), dtype=T.int16, device=dev())
+    M.monc_mlp_features(ds, norm, orient, None, X)
+    rng = np.random.default_rng(5)
+    cells = rng.integers(0, n, 300).astype(np.int32)
+    Xs = T.zeros((300, R.K), dtype=T.int16, device=dev())
+    M.monc_mlp_features(ds, norm, orient, to_dev([cells])[0], Xs)
+    T.cuda.synchronize()
+    for got, idx in ((X, np.arange(n)), (Xs, cells)):
+        ref = R.bf16(R.features(inner, norm, orient, idx))
+        g = bf16_bits_to_f64(got)
+        bad = g != ref
+        # (x - mean) * (1/std) on the GPU vs (x - mean) / std: equal after
+        # rounding to BF16 unless a value sits on a rounding boundary.
+        assert bad.sum() <= 2, bad.sum()
+        if bad.any():
+            assert np.all(np.abs(g[bad] - ref[bad]) <= 2.0 ** -7 * np.abs(ref[bad]))
+
+
+def run_forward(X_host_bf16, params, m):
+    T = torch()
+    Xd = T.from_numpy(X_host_bf16.astype(np.float32)).to(dev()).to(T.bfloat16).view(T.int16)
+    pd = T.from_numpy(params.astype(np.float32)).to(dev())
+    wp = T.zeros(M.MONC_MLP_WPACK, dtype=T.int16, device=dev())
+    M.monc_mlp_pack(pd, wp)
+    Y = T.zeros((m, 4), dtype=T.float32, device=dev())
+    H1 = T.zeros((m, 64), dtype=T.int16, device=dev())
+    H2 = T.zeros_like(H1)
+    Z1 = T.zeros((m, 64), dtype=T.float32, device=dev())
+    Z2 = T.zeros_like(Z1)
+    M.monc_mlp_forward(Xd, m, pd, wp, Y, H1, H2, Z1, Z2)
+    T.cuda.synchronize()
+    return Xd, pd, wp, Y, H1, H2, Z1, Z2
+
+
+def layer_tol(A, W):
+    """FP32-accumulation bound for rows of A @ W.T: a few ulps of sum |a w|."""
+    return 64 * np.finfo(np.float32).eps * (np.abs(A) @ np.abs(W).T) + 1e-30
+
+
+@pytest.mark.parametrize("m", [1, 127, 128, 1000])
+def test_forward_layers_match_oracle(m):
+    say(f"forward m={m}")
+    rng = np.random.default_rng(100 + m)
+    p = R.init_params(7).astype(np.float32).astype(np.float64)
+    p[R.H * R.K:R.H * R.K + R.H] = rng.standard_normal(R.H) * 0.1        # nonzero b1
+    X = rng.standard_normal((m, R.K))
+    X[:, R.NIN:] = 0.0
+    Xb = R.bf16(X)
+    _, _, _, Y, H1, H2, Z1, Z2 = run_forward(Xb, p, m)
+    W1, b1, W2, b2, W3, b3 = R.unpack(p)
+    W1b, W2b, W3b = R.bf16(W1), R.bf16(W2), R.bf16(W3)
+    z1, h1 = Z1.double().cpu().numpy(), bf16_bits_to_f64(H1)
+    z2, h2 = Z2.double().cpu().numpy(), bf16_bits_to_f64(H2)
+    y = Y.double().cpu().numpy()
+    # each layer from the GPU's own input to that layer
+    assert np.all(np.abs(z1 - (Xb @ W1b.T + b1)) <= layer_tol(Xb, W1b))
+    assert np.all(np.abs(z2 - (h1 @ W2b.T + b2)) <= layer_tol(h1, W2b))
+    assert np.all(np.abs(y - (h2 @ W3b.T + b3)) <= layer_tol(h2, W3b))
+    # activations: BF16(GELU(z)) of the GPU's z, to one BF16 ulp (FP32 erf)
+    for z, h in ((z1, h1), (z2, h2)):
+        ref = R.bf16(R.gelu(z))
+        assert np.all(np.abs(h - ref) <= 2.0 ** -8 * np.abs(ref) + 1e-30)
+        assert (h != ref).mean() <= 0.01
+    # end to end against the emulated oracle
+    Yr, _ = R.forward(Xb, p, emulate=True)
+    assert np.abs(y - Yr).max() <= 0.02 * np.abs(Yr).max()
+
+
+@pytest.mark.parametrize("m", [64, 200, 4096])
+def test_backward_matches_oracle(m):
+    say(f"backward m={m}")
+    T = torch()
+    rng = np.random.default_rng(200 + m)
+    p = R.init_params(11).astype(np.float32).astype(np.float64)
+    X = rng.standard_normal((m, R.K))
+    X[:, R.NIN:] = 0.0
+    Xd, pd, wp, Y, H1, H2, Z1, Z2 = run_forward(R.bf16(X), p, m)
+    dY = (rng.standard_normal((m, 4)) / m).astype(np.float32)
+    ws = T.zeros(M.monc_mlp_backward_workspace_bytes(m), dtype=T.uint8, device=dev())
+    grad = T.zeros(R.NPARAM, dtype=T.float32, device=dev())
+    dYd = T.from_numpy(dY).to(dev())
+    M.monc_mlp_backward(Xd, H1, H2, Z1, Z2, dYd, m, wp, grad, ws)
+    g1 = grad.double().cpu().numpy()
+    grad2 = T.full_like(grad, np.nan)
+    M.monc_mlp_backward(Xd, H1, H2, Z1, Z2, dYd, m, wp, grad2, ws)
+    T.cuda.synchronize()
+    assert T.equal(grad, grad2), "backward is not deterministic"
+    _, b1, W2, b2, W3, b3 = R.unpack(p)
+    cache = dict(Xb=bf16_bits_to_f64(Xd), Z1=Z1.double().cpu().numpy(), H1=bf16_bits_to_f64(H1),
+                 Z2=Z2.double().cpu().numpy(), H2=bf16_bits_to_f64(H2), W2b=R.bf16(W2),
+                 W3b=R.bf16(W3))
+    ref = R.backward(dY.astype(np.float64), cache, emulate=True)
+    gb, rb = R.unpack(g1), R.unpack(ref)
+    names = ["W1", "b1", "W2", "b2", "W3", "b3"]
+    for name, a, b in zip(names, gb, rb):
+        err = np.abs(a - b).max() / max(np.abs(b).max(), 1e-30)
+        say(f"  {name}: rel err {err:.2e}")
+        # dZ rounded to BF16 on both sides; a flipped rounding moves single
+        # entries by one BF16 ulp, which bounds the block-wise error.
+        assert err <= 4e-3, (name, err)
+    assert np.all(gb[0][:, R.NIN:] == 0.0)
+
+
+def test_loss_matches_oracle():
+    NX, NY, NZ, B = 10, 9, 6, 300
+    say("loss")
+    T = torch()
+    rng = np.random.default_rng(41)
+    c0 = coarse_state(NX, NY, NZ, 1)
+    c1 = [a + 0.5 * rng.standard_normal(a.shape) for a in c0]
+    c1[2][:, :, -1] = 0.0
+    tend = [0.1 * rng.standard_normal(a.shape) for a in c0]
+    dt, scale = 2.0, [0.3, 0.2, 0.05, 0.01]
+    rho = np.exp(-np.arange(NZ) / 5.0) * 1.2
+    rhon = np.exp(-(np.arange(NZ) + 0.5) / 5.0) * 1.2
+    cells = rng.integers(0, NX * NY * NZ, B).astype(np.int32)
+    cells[:3] = [NZ - 1, 2 * NZ - 1, NX * NY * NZ - 1]          # lid cells
+    Y4 = rng.standard_normal((4 * B, 4)).astype(np.float32)
+    k = cells % NZ
+    j = (cells // NZ) % NY
+    i = cells // (NZ * NY)
+    tgt = np.stack([((c1[q] - c0[q]) / dt - tend[q])[i + 2, j + 2, k] / scale[q]
+                    for q in range(4)], axis=1)
+    rh = np.stack([rhon[k] / rhon[0], rhon[k] / rhon[0], rho[k] / rho[0], rhon[k] / rhon[0]],
+                  axis=1)
+    mask = np.ones((B, 4))
+    mask[k == NZ - 1, 2] = 0.0
+    loss_ref, dY_ref = R.loss_and_grad(Y4.astype(np.float64), tgt, rh, mask)
+    dY = T.zeros((4 * B, 4), dtype=T.float32, device=dev())
+    loss = T.zeros(1, dtype=T.float32, device=dev())
+    ws = T.zeros(M.monc_mlp_loss_workspace_bytes(B), dtype=T.uint8, device=dev())
+    M.monc_mlp_loss(T.from_numpy(Y4).to(dev()), B, to_dev([cells])[0], to_dev(c0), to_dev(c1),
+                    to_dev(tend), dt, scale, to_dev([np.zeros(NZ), rho, rhon]),
+                    1.0 / mask.sum(), dY, loss, ws)
+    T.cuda.synchronize()
+    assert abs(loss.item() - loss_ref) <= 1e-5 * loss_ref
+    d = dY.double().cpu().numpy()
+    assert np.abs(d - dY_ref).max() <= 1e-5 * np.abs(dY_ref).max()
+
+
+def test_adam_and_pack_match_oracle():
+    say("adam")
+    T = torch()
+    rng = np.random.default_rng(77)
+    p = rng.standard_normal(R.NPARAM).astype(np.float32)
+    m1 = (0.01 * rng.standard_normal(R.NPARAM)).astype(np.float32)
+    m2 = (1e-4 * rng.random(R.NPARAM)).astype(np.float32)
+    g = (0.1 * rng.standard_normal(R.NPARAM)).astype(np.float32)
+    pd, m1d, m2d, gd = (T.from_numpy(a.copy()).to(dev()) for a in (p, m1, m2, g))
+    wp = T.zeros(M.MONC_MLP_WPACK, dtype=T.int16, device=dev())
+    M.monc_mlp_adam(pd, m1d, m2d, gd, 3, 1e-3, 0.9, 0.999, 1e-8, wp)
+    T.cuda.synchronize()
+    pr, mr, vr = R.adam(p.astype(np.float64), m1.astype(np.float64), m2.astype(np.float64),
+                        g.astype(np.float64), 3, lr=1e-3)
+    got = pd.double().cpu().numpy()
+    # an FP32 update: the step is lr-sized, computed to FP32 relative accuracy
+    assert np.abs(got - pr).max() <= 1e-6 * np.abs(pr).max()
+    np.testing.assert_allclose(m1d.double().cpu().numpy(), mr, rtol=1e-6, atol=1e-12)
+    np.testing.assert_allclose(m2d.double().cpu().numpy(), vr, rtol=1e-6, atol=1e-14)
+    W1, _, W2, _, W3, _ = R.unpack(pd.double().cpu().numpy())
+    packed = bf16_bits_to_f64(wp)
+    n1, n2 = R.H * R.K, R.H * R.H
+    np.testing.assert_array_equal(packed[:n1], R.bf16(W1).ravel())
+    np.testing.assert_array_equal(packed[n1:n1 + n2], R.bf16(W2).ravel())
+    w3 = packed[n1 + n2:].reshape(32, R.H)
+    np.testing.assert_array_equal(w3[:4], R.bf16(W3))
+    assert np.all(w3[4:] == 0.0)
+
+
+def corrected_case(NX, NY, NZ, seed):
+    rng = np.random.default_rng(seed)
+    s = coarse_state(NX, NY, NZ, seed)
+    tend = [0.1 * rng.standard_normal(a.shape) for a in s]
+    gx = rng.standard_normal((NX * NY * NZ, 4)).astype(np.float32)
+    gy = rng.standard_normal((NX * NY * NZ, 4)).astype(np.float32)
+    rho = 1.2 * np.exp(-np.arange(NZ) / 7.0)
+    rhon = 1.2 * np.exp(-(np.arange(NZ) + 0.5) / 7.0)
+    return s, tend, gx, gy, rho, rhon
+
+
+def run_correct(s, tend, gx, gy, rho, rhon, scale, dt):
+    T = torch()
+    out = [T.full(a.shape, np.nan, dtype=T.float64, device=dev()) for a in s]
+    flags = T.zeros(2, dtype=T.int32, device=dev())
+    M.monc_correct_step(to_dev(s), to_dev(tend), T.from_numpy(gx).to(dev()),
+                        T.from_numpy(gy).to(dev()), out, scale,
+                        to_dev([np.zeros_like(rho), rho, rhon]), dt, flags)
+    T.cuda.synchronize()
+    return [o.cpu().numpy() for o in out], flags.cpu().numpy()
+
+
+def test_corrected_step_matches_oracle_and_conserves():
+    NX, NY, NZ = 9, 7, 5
+    say("correct_step")
+    s, tend, gx, gy, rho, rhon = corrected_case(NX, NY, NZ, 3)
+    scale, dt = [0.3, 0.2, 0.05, 0.01], 2.0
+    out, flags = run_correct(s, tend, gx, gy, rho, rhon, scale, dt)
+    assert flags[1] == 0
+    G = gx.astype(np.float64).reshape(NX, NY, NZ, 4)
+    Gy = gy.astype(np.float64).reshape(NX, NY, NZ, 4)
+    rh = np.stack([rhon / rhon[0], rhon / rhon[0], rho / rho[0], rhon / rhon[0]], axis=1)
+    rhb = np.broadcast_to(rh[None, None], (NX, NY, NZ, 4)).reshape(-1, 4)
+    c = R.correction(G.reshape(-1, 4), np.roll(G, 1, axis=0).reshape(-1, 4),
+                     Gy.reshape(-1, 4), np.roll(Gy, 1, axis=1).reshape(-1, 4), rhb)
+    c = c.reshape(NX, NY, NZ, 4)
+    for q in range(4):
+        ref = I.interior(s[q]) + dt * (I.interior(tend[q]) + scale[q] * c[..., q])
+        if q == 2:
+            ref[:, :, -1] = 0.0
+        err = np.abs(I.interior(out[q]) - ref).max() / np.abs(ref).max()
+        assert err <= 1e-14, (q, err)
+        # the correction adds no mass: sum of rhohat * (out - plain) vanishes
+        plain = I.interior(s[q]) + dt * I.interior(tend[q])
+        dm = ((I.interior(out[q]) - plain) * rh[None, None, :, q])
+        if q == 2:
+            dm = dm[:, :, :-1]
+        assert abs(dm.sum()) <= 1e-11 * np.abs(dm).sum()
+
+
+def test_corrected_step_falls_back_on_nonfinite_fluxes():
+    NX, NY, NZ = 8, 8, 4
+    say("correct_step fallback")
+    s, tend, gx, gy, rho, rhon = corrected_case(NX, NY, NZ, 4)
+    gx[17, 2] = np.nan
+    out, flags = run_correct(s, tend, gx, gy, rho, rhon, [1.0] * 4, 2.0)
+    assert flags[1] == 1
+    for q in range(4):
+        ref = I.interior(s[q]) + 2.0 * I.interior(tend[q])
+        if q == 2:
+            ref[:, :, -1] = 0.0
+        np.testing.assert_array_equal(I.interior(out[q]), ref)
+
+
+def test_training_lowers_held_out_loss():
+    """A short training run on restricted fine runs lowers the loss on a
+    held-out run below that of the untrained network and of no correction."""
+    from paper_2009_12850_amd import learned as L
+    say("training")
+    d = dev()
+    train = [L.fine_series(s, 64, 64, 32, steps=24, every=4, dt=0.5, dx=50.0, device=d)
+             for s in (11, 12)]
+    held = L.fine_series(13, 64, 64, 32, steps=24, every=4, dt=0.5, dx=50.0, device=d)
+    norm, scale = L.statistics(train)
+    model = L.Correction(d, seed=3, norm=norm, scale=scale, batch=2048)
+    T = torch()
+
+    def held_loss(mdl):
+        rng = np.random.default_rng(99)
+        return np.mean([mdl.evaluate_loss(held, n, rng) for n in range(len(held.tend))])
+
+    zero = L.Correction(d, seed=3, norm=norm, scale=scale, batch=2048)
+    zero.params.zero_()
+    M.monc_mlp_pack(zero.params, zero.wpack)
+    base = held_loss(zero)
+    before = held_loss(model)
+    hist = L.train(model, train, steps=300, seed=1, lr=1e-3, log=say)
+    after = held_loss(model)
+    T.cuda.synchronize()
+    say(f"  held-out loss: zero {base:.4f}, untrained {before:.4f}, trained {after:.4f}")
+    assert np.isfinite(after)
+    assert after < 0.9 * base and after < before
