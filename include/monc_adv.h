@@ -2,14 +2,16 @@
  * monc_adv.h -- C ABI of the MI355X advection library (libmoncadv.so).
  *
  * The operation is the advection component of the MONC LES dynamical core
- * (Brown et al., arXiv 2009.12850): Sec. 2.1 names advection as the single
- * longest-running component and lists the prognostic fields u, v, w, theta
- * and any number of q fields; Sec. 3 describes the dynamics group, where every
- * component adds a source term ("tendency") that "step fields" integrates
- * last; Sec. 3.1 names the two schemes, the energy-conserving Piacsek-Williams
- * scheme (momentum) and Leonard's positivity-preserving ULTIMATE scheme
- * (scalars); Sec. 4.1 describes the single-precision variant.  The exact
- * discretisation implemented here is stated in monc_adv_scheme below.
+ * (Brown et al., arXiv 2009.12850).  Sec. 2.1: advection is the longest
+ * running component; the prognostic fields are u, v, w, theta and any number
+ * of further scalars.  Sec. 3: each dynamics component adds a source term and
+ * the field update integrates them last.  Sec. 3.1: momentum uses the
+ * energy-conserving Piacsek-Williams scheme, scalars Leonard's ULTIMATE
+ * (positivity-preserving, TVD) scheme.  Sec. 4.1: the single-precision
+ * variant.  The discretisation itself (flux form on the Arakawa C grid,
+ * QUICKEST face values with the ULTIMATE limiter, first-order upwind where
+ * the far upwind cell lies outside the column, no flux through ground or lid)
+ * is stated with each entry point below.
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -91,7 +93,7 @@ enum {
 #define MONC_NBUDGET (MONC_B_SCALAR0 + 3 * MONC_MAX_SCALARS)
 
 /* ---------------------------------------------------------------------------
- * a1. Periodic halo fill (the halo swap that opens every timestep, Sec. 2.1,
+ * Periodic halo fill (the halo swap that opens every timestep, Sec. 2.1,
  * on a single periodic domain).  fields: host array of nfields device
  * pointers; each field's 2-deep x-y halo, corners included, becomes a copy of
  * the interior at the wrapped index.  Bitwise copy.
@@ -104,9 +106,13 @@ int monc_halo_fill_bf16(int nfields, uint16_t *const *fields, int nx, int ny,
                         int nz, monc_stream_t stream);
 
 /* ---------------------------------------------------------------------------
- * a3. Piacsek-Williams momentum source terms (Sec. 3.1, energy-conserving
- * scheme) in FP64.  Inputs u, v, w with valid halos; outputs su, sv, sw
- * (interior written, halo untouched; sw[...][nz-1] = 0).
+ * Piacsek-Williams momentum source terms (Sec. 3.1, energy-conserving
+ * scheme) in FP64.  Flux form on the C grid: each velocity component is
+ * carried by the mass flux through the faces of its own staggered cell, the
+ * face values being two-point means, with the anelastic densities rho/rhon
+ * weighting the vertical fluxes, so that the kinetic-energy source summed over
+ * a periodic domain is the energy flux through its boundary (zero here).
+ * Outputs su, sv, sw (interior written, halo untouched; sw[...][nz-1] = 0).
  * ------------------------------------------------------------------------- */
 int monc_advect_pw(const double *u, const double *v, const double *w,
                    double *su, double *sv, double *sw, int nx, int ny, int nz,
@@ -114,10 +120,13 @@ int monc_advect_pw(const double *u, const double *v, const double *w,
                    const double *rhon, monc_stream_t stream);
 
 /* ---------------------------------------------------------------------------
- * a4. ULTIMATE-limited QUICKEST (TVD) scalar source terms (Sec. 3.1,
+ * ULTIMATE-limited QUICKEST (TVD) scalar source terms (Sec. 3.1,
  * positivity-preserving scheme) in FP64, for nscal scalars at once.  q and sq
- * are host arrays of nscal device pointers.  Halos (depth 2) of u, v, w and
- * every q must be valid.  dt enters through the Courant numbers.
+ * are host arrays of nscal device pointers.  Face values are third-order
+ * QUICKEST values clipped by the ULTIMATE limiter between the upwind cell and
+ * the monotone bound set by the Courant number; dt enters through the Courant
+ * numbers, and a face with Courant number above 1 is reported in the budgets
+ * of the fused calls (here the result is then undefined).
  * ------------------------------------------------------------------------- */
 int monc_advect_tvd(const double *u, const double *v, const double *w,
                     int nscal, const double *const *q, double *const *sq,
@@ -126,7 +135,7 @@ int monc_advect_tvd(const double *u, const double *v, const double *w,
                     double dt, monc_stream_t stream);
 
 /* ---------------------------------------------------------------------------
- * a3+a4 fused: PW for u, v, w and TVD for nscal scalars in one pass, in the
+ * Fused source terms: PW for u, v, w and TVD for nscal scalars in one pass, in the
  * storage type `dtype` (MONC_F64: double in, double out; MONC_F32: float in,
  * float out; MONC_BF16: bfloat16 bits in, float out).  in = host array of
  * 3+nscal device pointers (u, v, w, scalars), out likewise.  phi0 (host array
@@ -141,8 +150,8 @@ int monc_advect(int dtype, const void *const *in, void *const *out, int nscal,
                 const double *rhon, double dt, monc_stream_t stream);
 
 /* ---------------------------------------------------------------------------
- * a1-a6. One forward step of the whole path ("step fields" integrates the
- * source terms last, Sec. 3): PW + TVD from state_in (periodic neighbours read
+ * One forward step of advection and field update (the update integrates
+ * the source terms last, Sec. 3): PW + TVD from state_in (periodic neighbours read
  * at wrapped indices), state_out = state_in + dt * s, w lid = 0, and
  * optionally the FP64 budgets.  state_in/state_out: host arrays of 3+nscal
  * device pointers, FP64, state_out must not alias state_in (halos are neither
@@ -156,7 +165,7 @@ int monc_step(double *const *state_in, double *const *state_out, int nscal,
               const double *rho, const double *rhon, double dt,
               double *budgets, void *workspace, monc_stream_t stream);
 
-/* a7. The same step with the tendencies computed in FP32 from the FP64 state
+/* The same step with the tendencies computed in FP32 from the FP64 state
  * (scalars first reduced by phi0 in FP64, then rounded) and accumulated in
  * FP64: the single-precision advection of Sec. 4.1 without a separate
  * marshalling pass.  Budgets stay FP64. */
@@ -166,7 +175,7 @@ int monc_step_mixed(double *const *state_in, double *const *state_out,
                     const double *rhon, double dt, double *budgets,
                     void *workspace, monc_stream_t stream);
 
-/* a7. Marshalling (Sec. 4.1): write a narrower working copy of FP64 fields.
+/* Marshalling (Sec. 4.1): write a narrower working copy of FP64 fields.
  * dtype MONC_F32 or MONC_BF16 (round to nearest even); work[f] receives
  * src[f] - offset[f] (offset may be NULL = zeros) over the whole padded array,
  * halo included. */
@@ -175,7 +184,7 @@ int monc_cast_working(int dtype, int nfields, const double *const *src,
                       int nz, monc_stream_t stream);
 
 /* ---------------------------------------------------------------------------
- * a8. Batched ensemble.  Many independent LES members of uneven size advance
+ * Batched ensemble.  Many independent LES members of uneven size advance
  * together, each with the monc_step_mixed step (FP32 source terms, FP64
  * state): one persistent launch per column-height class (nz <= 64, nz <= 128)
  * walks a cost-sorted list of (member, tile) work items, and monc_ensemble_run
@@ -209,7 +218,7 @@ int monc_ensemble_info(const monc_ensemble *plan, int *ti, int *grid, int *nitem
 int monc_ensemble_destroy(monc_ensemble *plan);
 
 /* ---------------------------------------------------------------------------
- * a9. Learned coarse-grid flux correction.  A fine run is restricted to a
+ * Learned coarse-grid flux correction.  A fine run is restricted to a
  * grid 4x coarser in x, y and z; a small MLP (300 inputs = the 5x5x3
  * neighbourhood of u, v, w, theta around a cell, standardised; two 64-unit
  * GELU layers; 4 outputs = correction fluxes of u, v, w, theta through one face)
@@ -245,8 +254,9 @@ int monc_restrict4(int nscal, const double *const *fine, double *const *coarse, 
                    const double *rhon, double *rdz_c, double *rho_c, double *rhon_c,
                    monc_stream_t stream);
 /* Gather BF16 features (rows [ncells][320]) of cells (device linear indices
- * (i*ny + j)*nz + k, or NULL for all cells in that order).  state: host array
- * of 4 device pointers (u, v, w, theta); norm: host [8] = mean, std per field. */
+ * (i*ny + j)*nz + k, or NULL for all cells in that order; a listed cell outside
+ * the grid gives a zero row).  state: host array of 4 device pointers (u, v, w,
+ * theta); norm: host [8] = mean, std per field. */
 int monc_mlp_features(const double *const *state, int nx, int ny, int nz,
                       const double *norm, int orient, const int *cells, int ncells,
                       uint16_t *X, monc_stream_t stream);
@@ -271,7 +281,8 @@ int monc_mlp_backward(const uint16_t *X, const uint16_t *H1, const uint16_t *H2,
  * with the residual r_q = (c1_q - c0_q)/dt - tend_q of the coarse fields
  * (c0, c1: the restricted state at t and t+dt; tend: the plain coarse source
  * terms at c0; host arrays of 4 device pointers, u v w theta); w on the lid
- * is masked.  loss[0] = inv_count * sum (c - target)^2; dY4 = its gradient.
+ * is masked, and so are all terms of a listed cell outside the grid.
+ * loss[0] = inv_count * sum (c - target)^2; dY4 = its gradient.
  * workspace >= monc_mlp_loss_workspace_bytes(b). */
 size_t monc_mlp_loss_workspace_bytes(int b);
 int monc_mlp_loss(const float *Y4, int b, const int *cells, const double *const *c0,
@@ -283,16 +294,32 @@ int monc_mlp_loss(const float *Y4, int b, const int *cells, const double *const 
 int monc_mlp_adam(float *params, float *m1, float *m2, const float *grad, int t, double lr,
                   double beta1, double beta2, double eps, uint16_t *wpack,
                   monc_stream_t stream);
-/* Corrected coarse step for u, v, w, theta: out = in + dt (tend + scale_q c_q),
- * c_q = -(gx_q(i) - gx_q(i-1) + gy_q(j) - gy_q(j-1)) / rhohat_q(k) with gx, gy
- * [nx*ny*nz][4] face outputs (gy in the exchanged frame), rhohat = rho(k)/rho(0)
- * for w and rhon(k)/rhon(0) otherwise.  If any face output is not finite the
- * step is the plain one and flags[1] (device int) counts it; flags[0] is
- * scratch.  tend: the plain source terms (monc_advect). */
+/* Corrected coarse step for u, v, w, theta: out = in + dt (tend + c_q), with
+ *   c_q = -scale_q (gx_q(i) - gx_q(i-1) + gy_q(j) - gy_q(j-1)) / rhohat_q(k)
+ * for u, v, w, where gx, gy are [nx*ny*nz][4] face outputs of the network (gy
+ * in the exchanged frame, u and v swapped) and rhohat = rho(k)/rho(0) for w,
+ * rhon(k)/rhon(0) otherwise.  tend: the plain source terms (monc_advect of
+ * state_in).  Guards:
+ *  - theta: the correction flux through each lateral face, G = h rhon(0)
+ *    scale_3 g (h = dx or dy), is clamped so that the corrected face value
+ *    (plain flux + G) / (rhon(k) * normal velocity) stays within the ULTIMATE
+ *    admissible interval of that face (between the upwind value and the
+ *    monotone bound; only the upwind value at a local extremum);
+ *  - if any face output is not finite, the step is the plain one;
+ *  - if the corrected state's kinetic energy (sum of m u^2 + m v^2 + m_w w^2,
+ *    m = rhon dz, m_w = rho dz) or theta variance (mass-weighted) exceeds
+ *    `growth` times that of the plain step from the same state, the step is
+ *    the plain one.
+ * flags: device int[4]; flags[0] is scratch, flags[1] and flags[2] count the
+ * steps that fell back (non-finite, growth), flags[3] counts clamped theta
+ * faces; the caller zeroes flags[1..3] once.  workspace: device memory of at
+ * least monc_correct_step_workspace_bytes(nx, ny, nz) bytes; deterministic. */
+size_t monc_correct_step_workspace_bytes(int nx, int ny, int nz);
 int monc_correct_step(double *const *state_in, double *const *tend, const float *gx,
                       const float *gy, double *const *state_out, int nx, int ny, int nz,
-                      const double *scale, const double *rho, const double *rhon,
-                      double dt, int *flags, monc_stream_t stream);
+                      double dx, double dy, const double *scale, const double *rdz,
+                      const double *rho, const double *rhon, double dt, double growth,
+                      int *flags, void *workspace, monc_stream_t stream);
 
 /* Map a budgets array (HOST copy, after synchronising) to a status:
  * MONC_ENONFINITE if any non-finite value was written, MONC_ECFL if the

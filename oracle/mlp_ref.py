@@ -159,3 +159,98 @@ def adam(p, m, v, g, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
     mh = m / (1 - b1 ** t)
     vh = v / (1 - b2 ** t)
     return p - lr * mh / (np.sqrt(vh) + eps), m, v
+
+
+def _ultimate_interval(pU, pC, pD, c):
+    """Admissible face values of the ULTIMATE universal limiter in normalised
+    variables (Leonard 1991): with t = (phi - pU)/(pD - pU), a face whose
+    upwind cell is not monotone between its neighbours (tC outside (0, 1))
+    takes the upwind value; otherwise tC <= t_f <= min(1, tC/c).  Returns the
+    QUICKEST face value limited to that range, and the range (lo, hi) in
+    physical values, lo <= hi."""
+    delta = pD - pU
+    safe = np.where(delta != 0.0, delta, 1.0)
+    tC = np.where(delta != 0.0, (pC - pU) / safe, -1.0)
+    mono = (tC > 0.0) & (tC < 1.0)
+    csafe = np.where(c > 0.0, c, 1.0)
+    t_hi = np.where(c > 0.0, np.minimum(1.0, tC / csafe), 1.0)
+    # QUICKEST: the centred value minus the upwind-biased Courant term and the
+    # curvature term (1 - c^2)/6 * (pD - 2 pC + pU)
+    quick = 0.5 * (pC + pD) - 0.5 * c * (pD - pC) - (1.0 - c * c) / 6.0 * (pD - 2.0 * pC + pU)
+    tq = (quick - pU) / safe
+    tf = np.clip(tq, tC, t_hi)
+    f = np.where(mono, pU + tf * delta, pC)
+    a, b = pU + tC * delta, pU + t_hi * delta
+    lo = np.where(mono, np.minimum(a, b), pC)
+    hi = np.where(mono, np.maximum(a, b), pC)
+    return f, lo, hi
+
+
+def _theta_face_correction(a, th_m1, th_0, th_p1, th_p2, dt_over_h, rhon_k, G):
+    """Clamped theta correction flux through faces with normal velocity a,
+    between cells 0 and +1 (neighbours -1 and +2 for the far-upwind values)."""
+    c = np.abs(a) * dt_over_h
+    pos = a >= 0.0
+    pU = np.where(pos, th_m1, th_p2)
+    pC = np.where(pos, th_0, th_p1)
+    pD = np.where(pos, th_p1, th_0)
+    f, lo, hi = _ultimate_interval(pU, pC, pD, c)
+    moving = a != 0.0
+    amass = np.where(moving, rhon_k * a, 1.0)
+    trial = f + G / amass
+    f_new = np.clip(trial, lo, hi)
+    Geff = np.where(moving, amass * (f_new - f), 0.0)
+    clamped = np.where(moving, (trial < lo) | (trial > hi), G != 0.0)
+    return Geff, clamped
+
+
+def corrected_step(state, tend, gx, gy, dx, dy, scale, rdz, rho, rhon, dt, growth):
+    """The guarded corrected coarse step in FP64.
+
+    state, tend: 4 interior arrays (NX, NY, NZ) of u, v, w, theta and their
+    plain source terms; gx, gy: [NX*NY*NZ, 4] face outputs (gy in the exchanged
+    frame).  u, v, w: c_q = -scale_q (div of g) / rhohat_q.  theta: face fluxes
+    G = h rhon(0) scale_3 g clamped to the ULTIMATE admissible face values,
+    then their divergence.  Plain step if any output is not finite, or if the
+    kinetic energy or the mass-weighted theta variance of the corrected state
+    exceeds `growth` times the plain one.  Returns (out, (nonfinite, grown,
+    n_clamped_faces))."""
+    NX, NY, NZ = state[0].shape
+    plain = [state[q] + dt * tend[q] for q in range(4)]
+    plain[2] = plain[2].copy()
+    plain[2][:, :, -1] = 0.0
+    if not (np.all(np.isfinite(gx)) and np.all(np.isfinite(gy))):
+        return plain, (1, 0, 0)
+    Gx = np.asarray(gx, np.float64).reshape(NX, NY, NZ, 4)
+    Gy = np.asarray(gy, np.float64).reshape(NX, NY, NZ, 4)[..., SWAP]
+    rh = [rhon / rhon[0], rhon / rhon[0], rho / rho[0]]
+    out = []
+    for q in range(3):
+        div = Gx[..., q] - np.roll(Gx[..., q], 1, axis=0) + Gy[..., q] - np.roll(Gy[..., q], 1, axis=1)
+        c = -scale[q] * div / rh[q][None, None, :]
+        out.append(state[q] + dt * (tend[q] + c))
+    th, u, v = state[3], state[0], state[1]
+    rk = rhon[None, None, :]
+    r = lambda f, s, ax: np.roll(f, -s, axis=ax)        # r(f, s, ax)[i] = f[i + s]
+    Fx, cx = _theta_face_correction(u, r(th, -1, 0), th, r(th, 1, 0), r(th, 2, 0), dt / dx, rk,
+                                    dx * rhon[0] * scale[3] * Gx[..., 3])
+    Fy, cy = _theta_face_correction(v, r(th, -1, 1), th, r(th, 1, 1), r(th, 2, 1), dt / dy, rk,
+                                    dy * rhon[0] * scale[3] * Gy[..., 3])
+    cth = -((Fx - np.roll(Fx, 1, axis=0)) / dx + (Fy - np.roll(Fy, 1, axis=1)) / dy) / rk
+    out.append(th + dt * (tend[3] + cth))
+    out[2][:, :, -1] = 0.0
+    m = (rhon / rdz)[None, None, :]
+    mw = np.where(np.arange(NZ) < NZ - 1, rho / rdz, 0.0)[None, None, :]
+
+    def ke(s):
+        return np.sum(m * (s[0] ** 2 + s[1] ** 2)) + np.sum(mw * s[2] ** 2)
+
+    def var(t):
+        M = np.sum(m * np.ones_like(t))
+        mean = np.sum(m * t) / M
+        return np.sum(m * (t - mean) ** 2) / M
+
+    nclamp = int(cx.sum() + cy.sum())
+    if not (ke(out) <= growth * ke(plain) and var(out[3]) <= growth * var(plain[3])):
+        return plain, (0, 1, nclamp)
+    return out, (0, 0, nclamp)

@@ -62,7 +62,9 @@ _SIGS = {
     "monc_mlp_loss": ([vp, ip, vp, PP, PP, PP, ip, ip, ip, dp, DPTR, vp, vp, dp, vp, vp, vp,
                        vp], ip),
     "monc_mlp_adam": ([vp, vp, vp, vp, ip, dp, dp, dp, dp, vp, vp], ip),
-    "monc_correct_step": ([PP, PP, vp, vp, PP, ip, ip, ip, DPTR, vp, vp, dp, vp, vp], ip),
+    "monc_correct_step_workspace_bytes": ([ip, ip, ip], C.c_size_t),
+    "monc_correct_step": ([PP, PP, vp, vp, PP, ip, ip, ip, dp, dp, DPTR, vp, vp, vp, dp, dp,
+                           vp, vp, vp], ip),
     "monc_ensemble_create": ([vp, ip, ip, C.c_char_p, ip, C.POINTER(vp)], ip),
     "monc_ensemble_run": ([vp, ip, vp], ip),
     "monc_ensemble_step": ([vp, vp], ip),
@@ -442,7 +444,12 @@ def monc_mlp_adam(params, m1, m2, grad, t, lr, b1, b2, eps, wpack, stream=None):
            "monc_mlp_adam")
 
 
-def monc_correct_step(state_in, tend, gx, gy, state_out, scale, prof_c, dt, flags, stream=None):
+def monc_correct_step_workspace_bytes(nx, ny, nz):
+    return int(lib().monc_correct_step_workspace_bytes(int(nx), int(ny), int(nz)))
+
+
+def monc_correct_step(state_in, tend, gx, gy, state_out, dx, dy, scale, prof_c, dt, growth,
+                      flags, workspace, stream=None):
     torch = _torch()
     nx, ny, nz = _grid(state_in[0])
     sh = tuple(state_in[0].shape)
@@ -450,6 +457,7 @@ def monc_correct_step(state_in, tend, gx, gy, state_out, scale, prof_c, dt, flag
     ta = _ptrs(tend, torch.float64, sh, "tend")
     oa = _ptrs(state_out, torch.float64, sh, "state_out")
     rdz, rho, rhon = prof_c
-    _check(lib().monc_correct_step(ia, ta, _ptr(gx), _ptr(gy), oa, nx, ny, nz, _dbl(scale),
-                                   _ptr(rho), _ptr(rhon), float(dt), _ptr(flags, torch.int32),
-                                   _stream(stream)), "monc_correct_step")
+    _check(lib().monc_correct_step(ia, ta, _ptr(gx), _ptr(gy), oa, nx, ny, nz, float(dx),
+                                   float(dy), _dbl(scale), _ptr(rdz), _ptr(rho), _ptr(rhon),
+                                   float(dt), float(growth), _ptr(flags, torch.int32),
+                                   _ptr(workspace), _stream(stream)), "monc_correct_step")

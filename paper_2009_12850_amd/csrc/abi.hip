@@ -446,19 +446,31 @@ int monc_mlp_adam(float* params, float* m1, float* m2, const float* grad, int t,
                       "mlp_adam");
 }
 
+size_t monc_correct_step_workspace_bytes(int nx, int ny, int nz) {
+    if (nx < 1 || ny < 1 || nz < 1) return 0;
+    return correct_step_workspace_bytes(nx, ny, nz);
+}
+
 int monc_correct_step(double* const* state_in, double* const* tend, const float* gx,
                       const float* gy, double* const* state_out, int nx, int ny, int nz,
-                      const double* scale, const double* rho, const double* rhon, double dt,
-                      int* flags, monc_stream_t stream) {
+                      double dx, double dy, const double* scale, const double* rdz,
+                      const double* rho, const double* rhon, double dt, double growth,
+                      int* flags, void* workspace, monc_stream_t stream) {
     TRY(check_grid(nx, ny, nz));
+    TRY(check_spacing(dx, dy));
     TRY(check_dt(dt));
     TRY(check_ptrs(4, state_in, "state_in"));
     TRY(check_ptrs(4, tend, "tend"));
     TRY(check_ptrs(4, state_out, "state_out"));
     TRY(check_alias(4, (const void* const*)state_in, 4, (const void* const*)state_out));
-    if (!gx || !gy || !scale || !rho || !rhon || !flags) return fail(MONC_EINVAL, "NULL pointer");
-    return hip_status(launch_correct_step(state_in, tend, gx, gy, state_out, nx, ny, nz, scale,
-                                          rho, rhon, dt, flags, (hipStream_t)stream),
+    if (!gx || !gy || !scale || !rdz || !rho || !rhon || !flags || !workspace)
+        return fail(MONC_EINVAL, "NULL pointer");
+    if (!(growth > 0.0)) return fail(MONC_EINVAL, "growth must be > 0 (got %g)", growth);
+    for (int q = 0; q < 4; q++)
+        if (!std::isfinite(scale[q])) return fail(MONC_EINVAL, "scale[%d] is not finite", q);
+    return hip_status(launch_correct_step(state_in, tend, gx, gy, state_out, nx, ny, nz, dx, dy,
+                                          scale, rdz, rho, rhon, dt, growth, flags, workspace,
+                                          (hipStream_t)stream),
                       "correct_step");
 }
 

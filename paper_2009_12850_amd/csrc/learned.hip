@@ -58,10 +58,11 @@ __device__ __forceinline__ f32x16_t mfma(bf16x8_t a, bf16x8_t b, f32x16_t c) {
 // same k assignment for A and B, which is all the product needs).
 __device__ __forceinline__ int acc_row(int r, int lane) { return 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3); }
 
-__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+// GELU(z) = z Phi(z) with Phi(z) = erfc(-z/sqrt 2)/2, which keeps its relative
+// accuracy for negative z (1 + erf(z/sqrt 2) cancels there).
+__device__ __forceinline__ float gelu(float z) { return 0.5f * z * erfcf(-z * 0.70710678118654752f); }
 __device__ __forceinline__ float gelu_grad(float z) {
-    return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) +
-           z * expf(-0.5f * z * z) * 0.39894228040143268f;
+    return 0.5f * erfcf(-z * 0.70710678118654752f) + z * expf(-0.5f * z * z) * 0.39894228040143268f;
 }
 
 // ---------------------------------------------------------------------------
@@ -142,9 +143,9 @@ __global__ void __launch_bounds__(256) features_kernel(FeatArgs a) {
     const long row = t / KP;
     const int n = (int)(t - row * KP);
     uint16_t out = 0;
-    if (n < NIN) {
+    const int cell = a.cells ? a.cells[row] : (int)row;
+    if (n < NIN && (unsigned)cell < (unsigned)(a.nx * a.ny * a.nz)) {
         const int f = n / 75, a5 = (n / 15) % 5, b5 = (n / 3) % 5, c3 = n % 3;
-        const int cell = a.cells ? a.cells[row] : (int)row;
         const int k = cell % a.nz, j = (cell / a.nz) % a.ny, i = cell / (a.nz * a.ny);
         const int src = a.orient ? (f == 0 ? 1 : (f == 1 ? 0 : f)) : f;
         const int di = a.orient ? b5 - 2 : a5 - 2;
@@ -460,7 +461,10 @@ __global__ void __launch_bounds__(256) loss_kernel(LossArgs a) {
     double l = 0.0;
     if (b < B) {
         const int sw[4] = {1, 0, 2, 3};
-        const int cell = a.cells[b];
+        int cell = a.cells[b];
+        // a cell outside the grid contributes nothing (its terms are masked)
+        const bool valid = (unsigned)cell < (unsigned)(a.nx * a.ny * a.nz);
+        if (!valid) cell = 0;
         const int k = cell % a.nz, j = (cell / a.nz) % a.ny, i = cell / (a.nz * a.ny);
         const long g = ((long)(i + 2) * (a.ny + 4) + (j + 2)) * a.nz + k;
         for (int q = 0; q < 4; q++) {
@@ -470,7 +474,7 @@ __global__ void __launch_bounds__(256) loss_kernel(LossArgs a) {
             const float rh = (float)(q == 2 ? a.rho[k] / a.rho[0] : a.rhon[k] / a.rhon[0]);
             const float tgt = (float)(((a.c1[q][g] - a.c0[q][g]) * a.inv_dt - a.tend[q][g]) *
                                       a.inv_scale[q]);
-            const float msk = (q == 2 && k == a.nz - 1) ? 0.0f : 1.0f;
+            const float msk = (!valid || (q == 2 && k == a.nz - 1)) ? 0.0f : 1.0f;
             const float c = -(yxp - yxm + yyp - yym) / rh;
             const float err = (c - tgt) * msk;
             l += (double)err * (double)err;
@@ -510,23 +514,34 @@ __global__ void __launch_bounds__(256) loss_final(const double* __restrict__ par
 __global__ void __launch_bounds__(256) adam_kernel(float* __restrict__ p, float* __restrict__ m1,
                                                    float* __restrict__ m2,
                                                    const float* __restrict__ g, float lr,
-                                                   float b1, float b2, float eps, float c1,
-                                                   float c2) {
+                                                   float b1, float omb1, float b2, float omb2,
+                                                   float eps, float c1, float c2) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= NPARAM) return;
     const float gt = g[t];
-    const float a = b1 * m1[t] + (1.0f - b1) * gt;
-    const float v = b2 * m2[t] + (1.0f - b2) * gt * gt;
+    const float a = b1 * m1[t] + omb1 * gt;
+    const float v = b2 * m2[t] + omb2 * gt * gt;
     m1[t] = a;
     m2[t] = v;
     p[t] -= lr * (a / c1) / (sqrtf(v / c2) + eps);
 }
 
 // ---------------------------------------------------------------------------
-// Corrected coarse step: state_out = state_in + dt (tend + S c), with c the
-// flux divergence of the network's face fluxes; falls back to the plain step
-// (c = 0) when any face flux is not finite, and counts the fallbacks.
+// Corrected coarse step: state_out = state_in + dt (tend + c), with c the flux
+// divergence of the network's face fluxes (times the per-field scale).
+// Guards, in order:
+//  * any non-finite face flux: the whole step is the plain one (flags bit 1);
+//  * theta: each lateral face's corrected flux is clamped so that the corrected
+//    face value stays in the ULTIMATE admissible interval of that face (the
+//    interval between the upwind value and the monotone bound, Sec. 3.1's
+//    positivity-preserving scheme), which keeps the 1-D update bounded;
+//  * growth: if the corrected state's kinetic energy or theta variance exceeds
+//    `growth` times the plain step's, the whole step is the plain one (bit 2).
 // ---------------------------------------------------------------------------
+// partial sums: KE corrected, KE plain, m th^2 and m th corrected, the same
+// plain, and the mass m
+constexpr int CORR_NSUM = 7;
+
 struct CorrArgs {
     const double* in[4];
     const double* tend[4];
@@ -534,10 +549,12 @@ struct CorrArgs {
     const float* gx;
     const float* gy;
     int nx, ny, nz;
+    double dx, dy, dt;
     double scale[4];
-    const double *rho, *rhon;
-    double dt;
+    const double *rdz, *rho, *rhon;
     int* flags;
+    double* partial;  // [nblocks][CORR_NSUM]
+    double growth;
 };
 
 __global__ void __launch_bounds__(256) corr_clear(int* flags) {
@@ -552,26 +569,167 @@ __global__ void __launch_bounds__(256) corr_check(const float* __restrict__ gx,
     if (!isfinite(gx[t]) || !isfinite(gy[t])) atomicOr(flags, 1);
 }
 
+// ULTIMATE-limited QUICKEST value of a face and its admissible interval
+// [lo, hi], from the far-upwind, upwind and downwind values and the Courant
+// number c in [0, 1].  At a local extremum only the upwind value is admissible.
+__device__ __forceinline__ void ult_interval(double pU, double pC, double pD, double c,
+                                             double& f, double& lo, double& hi) {
+    const double del = pD - pU, kap = pD - 2.0 * pC + pU;
+    if (fabs(kap) >= fabs(del)) {
+        f = lo = hi = pC;
+        return;
+    }
+    const double quick = 0.5 * (pC + pD) - 0.5 * c * (pD - pC) - (1.0 - c * c) / 6.0 * kap;
+    const double bnd = c > 0.0 ? pU + (pC - pU) / c : pD;
+    if (del > 0.0) {
+        lo = pC;
+        hi = fmin(pD, bnd);
+    } else {
+        lo = fmax(pD, bnd);
+        hi = pC;
+    }
+    f = fmin(fmax(quick, lo), hi);
+}
+
+// The theta correction flux through one lateral face after the clamp.  a: the
+// normal velocity on the face; p[0..3]: theta at the cells -1, 0, +1, +2
+// relative to the face's left cell; G: the unclamped correction flux (physical
+// flux units, rhon * velocity * theta).  Returns the admissible part of G.
+__device__ __forceinline__ double clamp_face(double a, const double* p, double dt_over_h,
+                                             double mass, double G, bool& clamped) {
+    double f, lo, hi;
+    const double c = fabs(a) * dt_over_h;
+    if (a >= 0.0)
+        ult_interval(p[0], p[1], p[2], c, f, lo, hi);
+    else
+        ult_interval(p[3], p[2], p[1], c, f, lo, hi);
+    const double F = mass * a * f;
+    const double F1 = mass * a * lo, F2 = mass * a * hi;
+    const double Fmin = fmin(F1, F2), Fmax = fmax(F1, F2);
+    const double Fc = fmin(fmax(F + G, Fmin), Fmax);
+    clamped = Fc != F + G;
+    return Fc - F;
+}
+
 __global__ void __launch_bounds__(256) corr_step(CorrArgs a) {
+    __shared__ double red[CORR_NSUM][256];
     const long n = (long)a.nx * a.ny * a.nz;
     const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool plain = a.flags[0] != 0;
-    if (t == 0 && plain) a.flags[1] += 1;
+    const bool plain = (a.flags[0] & 1) != 0;
+    double sum[CORR_NSUM] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (t < n) {
+        const int nx = a.nx, ny = a.ny, nz = a.nz;
+        const int k = (int)(t % nz), j = (int)((t / nz) % ny), i = (int)(t / ((long)nz * ny));
+        const int im = i == 0 ? nx - 1 : i - 1, jm = j == 0 ? ny - 1 : j - 1;
+        const long cm_x = ((long)im * ny + j) * nz + k, cm_y = ((long)i * ny + jm) * nz + k;
+        const long sx = (long)(ny + 4) * nz;
+        const long g = (long)(i + 2) * sx + (long)(j + 2) * nz + k;
+        const int sw[4] = {1, 0, 2, 3};
+        const double m = a.rhon[k] / a.rdz[k], mw = k < nz - 1 ? a.rho[k] / a.rdz[k] : 0.0;
+        double cq[4] = {0.0, 0.0, 0.0, 0.0};
+        if (!plain) {
+            for (int q = 0; q < 3; q++) {
+                const double rh = q == 2 ? a.rho[k] / a.rho[0] : a.rhon[k] / a.rhon[0];
+                const double div = (double)a.gx[t * 4 + q] - (double)a.gx[cm_x * 4 + q] +
+                                   (double)a.gy[t * 4 + sw[q]] - (double)a.gy[cm_y * 4 + sw[q]];
+                cq[q] = -a.scale[q] * div / rh;
+            }
+            // theta: clamped face fluxes; G = h rhon(0) S g for a face of width h
+            const double* th = a.in[3];
+            const double* u = a.in[0];
+            const double* v = a.in[1];
+            const double mk = a.rhon[k];
+            const double cx = a.dx * a.rhon[0] * a.scale[3], cy = a.dy * a.rhon[0] * a.scale[3];
+            auto wx = [&](int ii) { ii = ii < 0 ? ii + nx : (ii >= nx ? ii - nx : ii); return ii; };
+            auto wy = [&](int jj) { jj = jj < 0 ? jj + ny : (jj >= ny ? jj - ny : jj); return jj; };
+            auto at = [&](const double* f, int ii, int jj) {
+                return f[(long)(ii + 2) * sx + (long)(jj + 2) * nz + k];
+            };
+            // theta at offsets -2 .. +2 along x and y; a face's four cells
+            // (-1, 0, +1, +2 from its left cell) start at index 1 for the face
+            // i+1/2 (left cell i) and at index 0 for i-1/2 (left cell i-1)
+            double px[5], py[5];
+            for (int o = 0; o < 5; o++) {
+                px[o] = at(th, wx(i - 2 + o), j);
+                py[o] = at(th, i, wy(j - 2 + o));
+            }
+            bool c1, c2, c3, c4;
+            const double Gxp = clamp_face(at(u, i, j), px + 1, a.dt / a.dx, mk,
+                                          cx * (double)a.gx[t * 4 + 3], c1);
+            const double Gxm = clamp_face(at(u, im, j), px, a.dt / a.dx, mk,
+                                          cx * (double)a.gx[cm_x * 4 + 3], c2);
+            const double Gyp = clamp_face(at(v, i, j), py + 1, a.dt / a.dy, mk,
+                                          cy * (double)a.gy[t * 4 + 3], c3);
+            const double Gym = clamp_face(at(v, i, jm), py, a.dt / a.dy, mk,
+                                          cy * (double)a.gy[cm_y * 4 + 3], c4);
+            cq[3] = -((Gxp - Gxm) / a.dx + (Gyp - Gym) / a.dy) / mk;
+            const int nc = (int)c1 + (int)c3;  // faces i+1/2 and j+1/2 belong to this cell
+            if (nc) atomicAdd(a.flags + 3, nc);
+        }
+        double o[4], pl[4];
+        for (int q = 0; q < 4; q++) {
+            pl[q] = a.in[q][g] + a.dt * a.tend[q][g];
+            o[q] = a.in[q][g] + a.dt * (a.tend[q][g] + cq[q]);
+            if (q == 2 && k == nz - 1) o[q] = pl[q] = 0.0;
+            a.out[q][g] = o[q];
+        }
+        sum[0] = m * (o[0] * o[0] + o[1] * o[1]) + mw * o[2] * o[2];
+        sum[1] = m * (pl[0] * pl[0] + pl[1] * pl[1]) + mw * pl[2] * pl[2];
+        sum[2] = m * o[3] * o[3];
+        sum[3] = m * o[3];
+        sum[4] = m * pl[3] * pl[3];
+        sum[5] = m * pl[3];
+        sum[6] = m;
+    }
+    for (int q = 0; q < CORR_NSUM; q++) red[q][threadIdx.x] = sum[q];
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (threadIdx.x < st)
+            for (int q = 0; q < CORR_NSUM; q++) red[q][threadIdx.x] += red[q][threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x < CORR_NSUM) a.partial[(long)blockIdx.x * CORR_NSUM + threadIdx.x] = red[threadIdx.x][0];
+}
+
+// Sums the block partials in a fixed order and takes the step's decision:
+// flags[1] counts non-finite fallbacks, flags[2] growth fallbacks.
+__global__ void __launch_bounds__(256) corr_decide(const double* __restrict__ partial, int nb,
+                                                   double growth, int* flags) {
+    __shared__ double red[CORR_NSUM][256];
+    double s[CORR_NSUM] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < nb; b += 256)
+        for (int q = 0; q < CORR_NSUM; q++) s[q] += partial[(long)b * CORR_NSUM + q];
+    for (int q = 0; q < CORR_NSUM; q++) red[q][threadIdx.x] = s[q];
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (threadIdx.x < st)
+            for (int q = 0; q < CORR_NSUM; q++) red[q][threadIdx.x] += red[q][threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        if (flags[0] & 1) {
+            flags[1] += 1;
+            return;
+        }
+        const double ke_c = red[0][0], ke_p = red[1][0], mass = red[6][0];
+        const double var_c = red[2][0] / mass - (red[3][0] / mass) * (red[3][0] / mass);
+        const double var_p = red[4][0] / mass - (red[5][0] / mass) * (red[5][0] / mass);
+        if (!(ke_c <= growth * ke_p) || !(var_c <= growth * var_p)) {
+            flags[0] |= 2;
+            flags[2] += 1;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256) corr_revert(CorrArgs a) {
+    if ((a.flags[0] & 2) == 0) return;
+    const long n = (long)a.nx * a.ny * a.nz;
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n) return;
     const int k = (int)(t % a.nz), j = (int)((t / a.nz) % a.ny), i = (int)(t / ((long)a.nz * a.ny));
-    const int im = i == 0 ? a.nx - 1 : i - 1, jm = j == 0 ? a.ny - 1 : j - 1;
-    const long cm_x = ((long)im * a.ny + j) * a.nz + k, cm_y = ((long)i * a.ny + jm) * a.nz + k;
     const long g = ((long)(i + 2) * (a.ny + 4) + (j + 2)) * a.nz + k;
-    const int sw[4] = {1, 0, 2, 3};
     for (int q = 0; q < 4; q++) {
-        double c = 0.0;
-        if (!plain) {
-            const double rh = q == 2 ? a.rho[k] / a.rho[0] : a.rhon[k] / a.rhon[0];
-            const double div = (double)a.gx[t * 4 + q] - (double)a.gx[cm_x * 4 + q] +
-                               (double)a.gy[t * 4 + sw[q]] - (double)a.gy[cm_y * 4 + sw[q]];
-            c = -a.scale[q] * div / rh;
-        }
-        double v = a.in[q][g] + a.dt * (a.tend[q][g] + c);
+        double v = a.in[q][g] + a.dt * a.tend[q][g];
         if (q == 2 && k == a.nz - 1) v = 0.0;
         a.out[q][g] = v;
     }
@@ -703,17 +861,25 @@ hipError_t launch_mlp_adam(float* params, float* m1, float* m2, const float* gra
                            double lr, double b1, double b2, double eps, uint16_t* wpack,
                            hipStream_t s) {
     const float c1 = (float)(1.0 - pow(b1, t)), c2 = (float)(1.0 - pow(b2, t));
+    // 1 - beta in FP64 before rounding: 1.0f - 0.999f is 1.3e-5 away from 0.001 in
+    // relative terms, far more than the FP32 rounding of 0.001 itself.
     adam_kernel<<<blocks_for(NPARAM), 256, 0, s>>>(params, m1, m2, grad, (float)lr, (float)b1,
-                                                  (float)b2, (float)eps, c1, c2);
+                                                  (float)(1.0 - b1), (float)b2, (float)(1.0 - b2),
+                                                  (float)eps, c1, c2);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return launch_mlp_pack(params, wpack, s);
 }
 
+size_t correct_step_workspace_bytes(int nx, int ny, int nz) {
+    return (size_t)blocks_for((long)nx * ny * nz) * CORR_NSUM * sizeof(double);
+}
+
 hipError_t launch_correct_step(double* const* in, double* const* tend, const float* gx,
                                const float* gy, double* const* out, int nx, int ny, int nz,
-                               const double* scale, const double* rho, const double* rhon,
-                               double dt, int* flags, hipStream_t s) {
+                               double dx, double dy, const double* scale, const double* rdz,
+                               const double* rho, const double* rhon, double dt, double growth,
+                               int* flags, void* workspace, hipStream_t s) {
     CorrArgs a;
     for (int q = 0; q < 4; q++) {
         a.in[q] = in[q];
@@ -726,14 +892,22 @@ hipError_t launch_correct_step(double* const* in, double* const* tend, const flo
     a.nx = nx;
     a.ny = ny;
     a.nz = nz;
+    a.dx = dx;
+    a.dy = dy;
+    a.dt = dt;
+    a.rdz = rdz;
     a.rho = rho;
     a.rhon = rhon;
-    a.dt = dt;
     a.flags = flags;
+    a.partial = static_cast<double*>(workspace);
+    a.growth = growth;
     const long n = (long)nx * ny * nz;
+    const int nb = blocks_for(n);
     corr_clear<<<1, 64, 0, s>>>(flags);
     corr_check<<<blocks_for(n * 4), 256, 0, s>>>(gx, gy, n * 4, flags);
-    corr_step<<<blocks_for(n), 256, 0, s>>>(a);
+    corr_step<<<nb, 256, 0, s>>>(a);
+    corr_decide<<<1, 256, 0, s>>>(a.partial, nb, growth, flags);
+    corr_revert<<<nb, 256, 0, s>>>(a);
     return hipGetLastError();
 }
 

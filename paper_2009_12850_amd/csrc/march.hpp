@@ -166,7 +166,7 @@ __device__ __forceinline__ void march_tile(const AdvArgs& a, const TileJob& tj,
     const bool store = active && kin;
 
     const double dt = a.dt;
-    // ---- level table (row a2: vertical geometry from rdz, rho, rhon) ----
+    // ---- level table (vertical geometry from rdz, rho, rhon) ----
     for (int kk = threadIdx.x; kk < NZP; kk += MARCH_WAVES * 64) {
         double v[NLEV];
 #pragma unroll

@@ -72,10 +72,12 @@ hipError_t launch_mlp_loss(const float* Y4, int b, const int* cells, const doubl
 hipError_t launch_mlp_adam(float* params, float* m1, float* m2, const float* grad, int t,
                            double lr, double b1, double b2, double eps, uint16_t* wpack,
                            hipStream_t s);
+size_t correct_step_workspace_bytes(int nx, int ny, int nz);
 hipError_t launch_correct_step(double* const* in, double* const* tend, const float* gx,
                                const float* gy, double* const* out, int nx, int ny, int nz,
-                               const double* scale, const double* rho, const double* rhon,
-                               double dt, int* flags, hipStream_t s);
+                               double dx, double dy, const double* scale, const double* rdz,
+                               const double* rho, const double* rhon, double dt, double growth,
+                               int* flags, void* workspace, hipStream_t s);
 
 // Ensemble plans (ensemble.hip).
 struct EnsemblePlan;

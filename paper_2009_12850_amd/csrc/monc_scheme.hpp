@@ -12,7 +12,7 @@
 
 namespace monc {
 
-// Per-level vertical coefficients (row a2 of the path).  Built once per level
+// Per-level vertical coefficients.  Built once per level
 // from rdz, rho, rhon (float64) and rounded to T.
 template <typename T>
 struct Level {

@@ -217,12 +217,15 @@ def train(model, series_list, steps, seed=0, lr=1e-3, log=None, every=100):
 
 
 class CoarseRunner:
-    """Coarse steps, plain or corrected, on one coarse grid."""
+    """Coarse steps, plain or corrected, on one coarse grid.  `growth` is the
+    factor by which a corrected step may raise the kinetic energy or the theta
+    variance over the plain step before the plain step is taken instead."""
 
-    def __init__(self, ser, model=None):
+    def __init__(self, ser, model=None, growth=1.01):
         torch = _torch()
         self.ser = ser
         self.model = model
+        self.growth = growth
         shape = ser.snaps[0][0].shape
         dev = ser.snaps[0][0].device
         self.tend = [torch.zeros(shape, dtype=torch.float64, device=dev) for _ in range(4)]
@@ -231,7 +234,9 @@ class CoarseRunner:
         if model is not None:
             self.X = torch.zeros((2 * self.N, M.MONC_MLP_K), dtype=torch.int16, device=dev)
             self.G = torch.zeros((2 * self.N, 4), dtype=torch.float32, device=dev)
-            self.flags = torch.zeros(2, dtype=torch.int32, device=dev)
+            self.flags = torch.zeros(4, dtype=torch.int32, device=dev)
+            self.ws = torch.zeros(M.monc_correct_step_workspace_bytes(NX, NY, NZ),
+                                  dtype=torch.uint8, device=dev)
 
     def step(self, A, B):
         s = self.ser
@@ -244,7 +249,13 @@ class CoarseRunner:
         M.monc_mlp_features(A, mdl.norm, 1, None, self.X.narrow(0, N, N))
         M.monc_mlp_forward(self.X, 2 * N, mdl.params, mdl.wpack, self.G)
         M.monc_correct_step(A, self.tend, self.G.narrow(0, 0, N), self.G.narrow(0, N, N), B,
-                            mdl.scale, s.prof_c, s.dtc, self.flags)
+                            s.dxc, s.dxc, mdl.scale, s.prof_c, s.dtc, self.growth, self.flags,
+                            self.ws)
+
+    def fallbacks(self):
+        """(non-finite fallbacks, growth fallbacks, clamped theta faces) so far."""
+        f = self.flags.cpu().numpy()
+        return int(f[1]), int(f[2]), int(f[3])
 
     def run(self, state0, nsteps):
         torch = _torch()

@@ -142,10 +142,11 @@ def test_forward_layers_match_oracle(m):
     assert np.all(np.abs(z1 - (Xb @ W1b.T + b1)) <= layer_tol(Xb, W1b))
     assert np.all(np.abs(z2 - (h1 @ W2b.T + b2)) <= layer_tol(h1, W2b))
     assert np.all(np.abs(y - (h2 @ W3b.T + b3)) <= layer_tol(h2, W3b))
-    # activations: BF16(GELU(z)) of the GPU's z, to one BF16 ulp (FP32 erf)
+    # activations: BF16(GELU(z)) of the GPU's z, to one BF16 ulp (at most 2^-7
+    # relative); the FP32 GELU rarely moves a value across a rounding boundary
     for z, h in ((z1, h1), (z2, h2)):
         ref = R.bf16(R.gelu(z))
-        assert np.all(np.abs(h - ref) <= 2.0 ** -8 * np.abs(ref) + 1e-30)
+        assert np.all(np.abs(h - ref) <= 2.0 ** -7 * np.abs(ref) + 1e-30)
         assert (h != ref).mean() <= 0.01
     # end to end against the emulated oracle
     Yr, _ = R.forward(Xb, p, emulate=True)
@@ -241,8 +242,13 @@ def test_adam_and_pack_match_oracle():
     got = pd.double().cpu().numpy()
     # an FP32 update: the step is lr-sized, computed to FP32 relative accuracy
     assert np.abs(got - pr).max() <= 1e-6 * np.abs(pr).max()
-    np.testing.assert_allclose(m1d.double().cpu().numpy(), mr, rtol=1e-6, atol=1e-12)
-    np.testing.assert_allclose(m2d.double().cpu().numpy(), vr, rtol=1e-6, atol=1e-14)
+    # moments: FP32 sums of two terms, bounded by a few FP32 ulps of the terms
+    eps32 = np.finfo(np.float32).eps
+    g64 = g.astype(np.float64)
+    bound1 = 4 * eps32 * (0.9 * np.abs(m1) + 0.1 * np.abs(g64))
+    bound2 = 4 * eps32 * (0.999 * m2 + 0.001 * g64 * g64)
+    assert np.all(np.abs(m1d.double().cpu().numpy() - mr) <= bound1)
+    assert np.all(np.abs(m2d.double().cpu().numpy() - vr) <= bound2)
     W1, _, W2, _, W3, _ = R.unpack(pd.double().cpu().numpy())
     packed = bf16_bits_to_f64(wp)
     n1, n2 = R.H * R.K, R.H * R.H
@@ -253,68 +259,96 @@ def test_adam_and_pack_match_oracle():
     assert np.all(w3[4:] == 0.0)
 
 
-def corrected_case(NX, NY, NZ, seed):
+def corrected_case(NX, NY, NZ, seed, theta_scale=1.0):
     rng = np.random.default_rng(seed)
     s = coarse_state(NX, NY, NZ, seed)
+    # a smooth theta with small noise: both monotone faces (where the clamp
+    # can act) and local extrema
+    x = np.arange(NX + 4)[:, None, None]
+    y = np.arange(NY + 4)[None, :, None]
+    s[3] = 300.0 + np.sin(0.9 * x) * np.cos(0.7 * y) + 0.05 * rng.standard_normal(s[3].shape)
     tend = [0.1 * rng.standard_normal(a.shape) for a in s]
     gx = rng.standard_normal((NX * NY * NZ, 4)).astype(np.float32)
     gy = rng.standard_normal((NX * NY * NZ, 4)).astype(np.float32)
+    gx[:, 3] *= theta_scale
+    gy[:, 3] *= theta_scale
+    rdz = 1.0 / np.linspace(40.0, 80.0, NZ)
     rho = 1.2 * np.exp(-np.arange(NZ) / 7.0)
     rhon = 1.2 * np.exp(-(np.arange(NZ) + 0.5) / 7.0)
-    return s, tend, gx, gy, rho, rhon
+    return s, tend, gx, gy, rdz, rho, rhon
 
 
-def run_correct(s, tend, gx, gy, rho, rhon, scale, dt):
+def run_correct(s, tend, gx, gy, rdz, rho, rhon, scale, dt, growth, dx=200.0, dy=200.0):
     T = torch()
+    NX, NY, NZ = s[0].shape[0] - 4, s[0].shape[1] - 4, s[0].shape[2]
     out = [T.full(a.shape, np.nan, dtype=T.float64, device=dev()) for a in s]
-    flags = T.zeros(2, dtype=T.int32, device=dev())
+    flags = T.zeros(4, dtype=T.int32, device=dev())
+    ws = T.zeros(M.monc_correct_step_workspace_bytes(NX, NY, NZ), dtype=T.uint8, device=dev())
     M.monc_correct_step(to_dev(s), to_dev(tend), T.from_numpy(gx).to(dev()),
-                        T.from_numpy(gy).to(dev()), out, scale,
-                        to_dev([np.zeros_like(rho), rho, rhon]), dt, flags)
+                        T.from_numpy(gy).to(dev()), out, dx, dy, scale,
+                        to_dev([rdz, rho, rhon]), dt, growth, flags, ws)
     T.cuda.synchronize()
     return [o.cpu().numpy() for o in out], flags.cpu().numpy()
 
 
-def test_corrected_step_matches_oracle_and_conserves():
-    NX, NY, NZ = 9, 7, 5
-    say("correct_step")
-    s, tend, gx, gy, rho, rhon = corrected_case(NX, NY, NZ, 3)
+def oracle_correct(s, tend, gx, gy, rdz, rho, rhon, scale, dt, growth, dx=200.0, dy=200.0):
+    return R.corrected_step([I.interior(a) for a in s], [I.interior(a) for a in tend], gx, gy,
+                            dx, dy, scale, rdz, rho, rhon, dt, growth)
+
+
+@pytest.mark.parametrize("shape,theta_scale", [((9, 7, 5), 1.0), ((16, 12, 8), 0.05),
+                                               ((32, 32, 32), 0.3)])
+def test_corrected_step_matches_oracle_and_conserves(shape, theta_scale):
+    NX, NY, NZ = shape
+    say(f"correct_step {shape} theta_scale={theta_scale}")
+    s, tend, gx, gy, rdz, rho, rhon = corrected_case(NX, NY, NZ, 3 + NX, theta_scale)
     scale, dt = [0.3, 0.2, 0.05, 0.01], 2.0
-    out, flags = run_correct(s, tend, gx, gy, rho, rhon, scale, dt)
-    assert flags[1] == 0
-    G = gx.astype(np.float64).reshape(NX, NY, NZ, 4)
-    Gy = gy.astype(np.float64).reshape(NX, NY, NZ, 4)
-    rh = np.stack([rhon / rhon[0], rhon / rhon[0], rho / rho[0], rhon / rhon[0]], axis=1)
-    rhb = np.broadcast_to(rh[None, None], (NX, NY, NZ, 4)).reshape(-1, 4)
-    c = R.correction(G.reshape(-1, 4), np.roll(G, 1, axis=0).reshape(-1, 4),
-                     Gy.reshape(-1, 4), np.roll(Gy, 1, axis=1).reshape(-1, 4), rhb)
-    c = c.reshape(NX, NY, NZ, 4)
+    out, flags = run_correct(s, tend, gx, gy, rdz, rho, rhon, scale, dt, 1e300)
+    ref, (nonfin, grown, nclamp) = oracle_correct(s, tend, gx, gy, rdz, rho, rhon, scale, dt,
+                                                  1e300)
+    say(f"  clamped theta faces: gpu {flags[3]}, oracle {nclamp} of {2 * NX * NY * NZ}")
+    assert flags[1] == 0 and flags[2] == 0 and nonfin == 0 and grown == 0
+    assert abs(int(flags[3]) - nclamp) <= 2
+    assert 0 < nclamp < 2 * NX * NY * NZ
     for q in range(4):
-        ref = I.interior(s[q]) + dt * (I.interior(tend[q]) + scale[q] * c[..., q])
-        if q == 2:
-            ref[:, :, -1] = 0.0
-        err = np.abs(I.interior(out[q]) - ref).max() / np.abs(ref).max()
+        a = I.interior(out[q])
+        err = np.abs(a - ref[q]).max() / np.abs(ref[q]).max()
         assert err <= 1e-14, (q, err)
-        # the correction adds no mass: sum of rhohat * (out - plain) vanishes
+        # the correction adds no mass
         plain = I.interior(s[q]) + dt * I.interior(tend[q])
-        dm = ((I.interior(out[q]) - plain) * rh[None, None, :, q])
+        w = (rho if q == 2 else rhon) / rdz
+        dm = (a - plain) * w[None, None, :]
         if q == 2:
             dm = dm[:, :, :-1]
-        assert abs(dm.sum()) <= 1e-11 * np.abs(dm).sum()
+        assert abs(dm.sum()) <= 1e-12 * np.abs(dm).sum() + 1e-300
 
 
 def test_corrected_step_falls_back_on_nonfinite_fluxes():
     NX, NY, NZ = 8, 8, 4
-    say("correct_step fallback")
-    s, tend, gx, gy, rho, rhon = corrected_case(NX, NY, NZ, 4)
+    say("correct_step non-finite fallback")
+    s, tend, gx, gy, rdz, rho, rhon = corrected_case(NX, NY, NZ, 4)
     gx[17, 2] = np.nan
-    out, flags = run_correct(s, tend, gx, gy, rho, rhon, [1.0] * 4, 2.0)
-    assert flags[1] == 1
+    out, flags = run_correct(s, tend, gx, gy, rdz, rho, rhon, [1.0] * 4, 2.0, 1e300)
+    assert flags[1] == 1 and flags[2] == 0 and flags[3] == 0
     for q in range(4):
         ref = I.interior(s[q]) + 2.0 * I.interior(tend[q])
         if q == 2:
             ref[:, :, -1] = 0.0
         np.testing.assert_array_equal(I.interior(out[q]), ref)
+
+
+def test_corrected_step_growth_guard():
+    NX, NY, NZ = 12, 10, 6
+    say("correct_step growth guard")
+    s, tend, gx, gy, rdz, rho, rhon = corrected_case(NX, NY, NZ, 5)
+    scale = [0.3, 0.2, 0.05, 0.01]
+    for growth in (1e-6, 1e300):
+        out, flags = run_correct(s, tend, gx, gy, rdz, rho, rhon, scale, 2.0, growth)
+        ref, fl = oracle_correct(s, tend, gx, gy, rdz, rho, rhon, scale, 2.0, growth)
+        assert flags[2] == fl[1] == (1 if growth < 1 else 0)
+        for q in range(4):
+            a = I.interior(out[q])
+            assert np.abs(a - ref[q]).max() <= 1e-14 * np.abs(ref[q]).max()
 
 
 def test_training_lowers_held_out_loss():

@@ -152,3 +152,94 @@ def test_restriction_pins():
     # coarse profiles: thickness adds up, density at the coarse top face
     np.testing.assert_allclose(1.0 / gc.rdz, (1.0 / g.rdz).reshape(4, 4).sum(axis=1), rtol=1e-15)
     np.testing.assert_array_equal(gc.rho, g.rho[3::4])
+
+
+def _coarse_1d(NX, a, seed):
+    """1-D periodic column along x (ny = 1, nz = 2), constant u = a, v = w = 0,
+    theta rough; returns state, plain source terms (from the C oracle), geometry."""
+    g = I.make_geometry(NX, 1, 2, dx=1.0, dy=1.0)
+    rng = np.random.default_rng(seed)
+    th = rng.random((NX, 1, 2)) + np.sin(np.arange(NX) * 0.7)[:, None, None]
+    u = np.full((NX, 1, 2), a)
+    z = np.zeros((NX, 1, 2))
+    st = [O.halo_fill(I.pad(x)) for x in (u, z, z, th)]
+    dt = 0.5
+    sth = O.tvd(*st[:3], st[3], g, dt)
+    tend = [z, z, z, I.interior(sth)]
+    return [I.interior(x) for x in st], tend, g, dt
+
+
+def test_corrected_step_with_zero_outputs_is_the_plain_step():
+    NX = 10
+    state, tend, g, dt = _coarse_1d(NX, 0.6, 1)
+    zero = np.zeros((NX * 2, 4))
+    out, flags = R.corrected_step(state, tend, zero, zero, 1.0, 1.0, [1.0] * 4, g.rdz, g.rho,
+                                  g.rhon, dt, 1.01)
+    assert flags == (0, 0, 0)
+    for q in range(4):
+        np.testing.assert_array_equal(out[q], state[q] + dt * tend[q])
+
+
+@pytest.mark.parametrize("a", [0.8, -0.6])
+def test_theta_clamp_keeps_the_1d_update_between_upwind_neighbours(a):
+    """Any face value in the ULTIMATE admissible range keeps the 1-D update of
+    theta between the old values of the cell and its upwind neighbour (the
+    boundedness that makes the scheme positivity-preserving); large random
+    correction fluxes must therefore be clamped into that range."""
+    NX = 64
+    state, tend, g, dt = _coarse_1d(NX, a, 2)
+    rng = np.random.default_rng(3)
+    gx = np.zeros((NX * 2, 4))
+    gx[:, 3] = rng.standard_normal(NX * 2) * 5.0
+    gy = np.zeros_like(gx)
+    out, flags = R.corrected_step(state, tend, gx, gy, 1.0, 1.0, [1.0] * 4, g.rdz, g.rho,
+                                  g.rhon, dt, 1e300)
+    assert flags[0] == 0 and flags[1] == 0 and flags[2] > NX
+    th = state[3]
+    up = np.roll(th, 1, axis=0) if a > 0 else np.roll(th, -1, axis=0)
+    lo, hi = np.minimum(th, up), np.maximum(th, up)
+    new = out[3]
+    assert np.all(new >= lo - 1e-14) and np.all(new <= hi + 1e-14)
+    # the same fluxes without the clamp leave the range: the clamp is what holds it
+    G = 1.0 * g.rhon[0] * gx[:, 3].reshape(NX, 1, 2)
+    raw = state[3] + dt * (tend[3] - (G - np.roll(G, 1, axis=0)) / g.rhon[None, None, :])
+    assert np.any(raw < lo - 1e-3) or np.any(raw > hi + 1e-3)
+    # mass is unchanged by the clamped correction
+    m = g.rhon / g.rdz
+    plain = state[3] + dt * tend[3]
+    assert abs(np.sum((new - plain) * m)) <= 1e-13 * np.sum(np.abs(new) * m)
+
+
+def test_growth_guard_reverts_to_the_plain_step():
+    NX = 16
+    state, tend, g, dt = _coarse_1d(NX, 0.5, 4)
+    rng = np.random.default_rng(5)
+    gx = rng.standard_normal((NX * 2, 4)) * 0.1
+    gy = rng.standard_normal((NX * 2, 4)) * 0.1
+    args = (1.0, 1.0, [1.0] * 4, g.rdz, g.rho, g.rhon, dt)
+    out_big, fl_big = R.corrected_step(state, tend, gx, gy, *args, 1e300)
+    out_tiny, fl_tiny = R.corrected_step(state, tend, gx, gy, *args, 1e-6)
+    assert fl_big[1] == 0 and fl_tiny[1] == 1
+    plain = [state[q] + dt * tend[q] for q in range(4)]
+    for q in range(4):
+        np.testing.assert_array_equal(out_tiny[q], plain[q])
+    assert any(np.any(out_big[q] != plain[q]) for q in range(4))
+    bad = gx.copy()
+    bad[3, 1] = np.inf
+    out_nan, fl_nan = R.corrected_step(state, tend, bad, gy, *args, 1e300)
+    assert fl_nan[0] == 1
+    for q in range(4):
+        np.testing.assert_array_equal(out_nan[q], plain[q])
+
+
+def test_ultimate_interval_contains_the_oracle_face_value():
+    """The limited face value of the normalised-variable form equals the C
+    oracle's ULTIMATE face value, and lies in its interval."""
+    rng = np.random.default_rng(6)
+    for _ in range(500):
+        pU, pC, pD = rng.standard_normal(3)
+        c = rng.uniform(0.0, 1.0)
+        f, lo, hi = R._ultimate_interval(np.array(pU), np.array(pC), np.array(pD), np.array(c))
+        ref = O.ultimate_face(pU, pC, pD, c)
+        assert abs(float(f) - ref) <= 1e-14 * (abs(ref) + 1.0)
+        assert lo <= f <= hi
