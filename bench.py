@@ -1,14 +1,16 @@
 """Benchmark of the MONC advection step on one MI355X.
 
 One step = one call of monc_step on the 1024 x 1024 x 128 grid with u, v, w,
-theta, q1 in FP64: halo fill, Piacsek-Williams momentum + ULTIMATE/TVD scalar
-source terms, forward update into the second buffer, and the FP64 budgets.
-Inputs are seeded synthetic fields, resident in HBM before timing starts.
+theta, q1 in FP64: Piacsek-Williams momentum + ULTIMATE/TVD scalar source
+terms (periodic neighbours read at wrapped indices), forward update into the
+second buffer, and the FP64 budgets.  Inputs are seeded synthetic fields,
+resident in HBM before timing starts.
 
 Prints one JSON line: grid-point updates per second (nx*ny*nz per step),
 the roofline of the dominant kernel (HBM-bound stencil, algorithmic bytes =
 one read and one write of every field), the oracle timed on the host cores on
-a bounded sample, and the precision forms (FP32 / BF16 tendencies).
+a bounded sample, and the other forms: FP32 / BF16 tendencies, the mixed
+step, the batched ensemble, and the learned coarse-grid correction.
 """
 from __future__ import annotations
 
@@ -40,6 +42,11 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-forms", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=12.0)
+    p.add_argument("--no-learned", action="store_true",
+                   help="skip the learned-correction form (fine runs, training, coarse runs)")
+    p.add_argument("--learned-seeds", type=int, default=16,
+                   help="fine runs for the learned form; the last quarter is held out")
+    p.add_argument("--learned-train-steps", type=int, default=3000)
     p.add_argument("--calibrate-copy", action="store_true",
                    help="also run a plain 1 GiB device-to-device copy (reference for "
                         "the HBM byte counters)")
@@ -240,6 +247,14 @@ def main():
         state.clear()
         torch.cuda.empty_cache()
         forms["ensemble"] = bench_ensemble(torch, M, I, dev, 50, log)
+    if not args.no_forms and not args.no_learned:
+        from paper_2009_12850_amd import learned as L
+        log("learned correction: fine runs, training, coarse runs")
+        ns = args.learned_seeds
+        forms["learned"] = L.run_experiment(
+            seeds=range(2000, 2000 + ns), n_train=ns - max(1, ns // 4),
+            train_steps=args.learned_train_steps, device=dev, log=log)
+        torch.cuda.empty_cache()
 
     cpu = None
     if not args.no_cpu_baseline:

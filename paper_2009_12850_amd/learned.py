@@ -36,12 +36,20 @@ class CoarseSeries:
     dtc: float
 
 
-def fine_series(seed, nx, ny, nz, steps, every, dt, dx, device, amp=5.0, timing=None):
+def fine_fields(seed, nx, ny, nz, dx, amp=5.0):
+    """Seeded fine initial state (host, padded) of u, v, w, theta."""
+    g = I.make_geometry(nx, ny, nz, dx, dx)
+    return I.make_fields(g, 1, seed, amp=amp, padded=True)
+
+
+def fine_series(seed, nx, ny, nz, steps, every, dt, dx, device, amp=5.0, timing=None,
+                fields=None):
     """Run the plain fine scheme and keep the restricted state every `every`
-    steps (including the initial state)."""
+    steps (including the initial state).  `fields`: a prefetched
+    fine_fields(seed, ...) result, else it is generated here."""
     torch = _torch()
     g = I.make_geometry(nx, ny, nz, dx, dx)
-    f = I.make_fields(g, 1, seed, amp=amp, padded=True)
+    f = dict(fields) if fields is not None else fine_fields(seed, nx, ny, nz, dx, amp)
     A = [torch.from_numpy(f.pop(n)).to(device) for n in FIELDS]
     B = [torch.empty_like(x) for x in A]
     prof = [torch.from_numpy(np.ascontiguousarray(a)).to(device) for a in (g.rdz, g.rho, g.rhon)]
@@ -277,3 +285,127 @@ def errors(state, ref, ref0):
         den = float(((r - r0) ** 2).mean().sqrt())
         out.append(num / max(den, 1e-300))
     return out
+
+
+def _event_ms(fn, stream=None):
+    torch = _torch()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    fn()
+    e1.record()
+    e1.synchronize()
+    return e0.elapsed_time(e1)
+
+
+def time_fine_steps(fields, nx, ny, nz, dx, dt, steps, device):
+    """Milliseconds for `steps` plain fine steps (FP64, u v w theta)."""
+    torch = _torch()
+    g = I.make_geometry(nx, ny, nz, dx, dx)
+    A = [torch.from_numpy(fields[n]).to(device) for n in FIELDS]
+    B = [torch.empty_like(x) for x in A]
+    prof = [torch.from_numpy(np.ascontiguousarray(a)).to(device) for a in (g.rdz, g.rho, g.rhon)]
+    M.monc_step(A, B, dx, dx, prof, dt)         # warm-up
+    state = [A, B]
+
+    def run():
+        a, b = state
+        for _ in range(steps):
+            M.monc_step(a, b, dx, dx, prof, dt)
+            a, b = b, a
+
+    return _event_ms(run)
+
+
+def run_experiment(nx=512, ny=512, nz=128, seeds=range(2000, 2016), n_train=12, steps=200,
+                   every=4, dt=0.5, dx=50.0, train_steps=3000, batch=8192, lr=1e-3,
+                   coarse_steps=50, growth=1.01, device=None, log=None):
+    """Fine runs -> restricted data -> training -> coarse runs on held-out seeds.
+
+    Returns a dict with the one-step held-out loss (trained vs no correction),
+    the coarse-run errors after `coarse_steps` steps against the restricted
+    fine solution (plain and learned, per field), fallback counts, and the
+    timings behind the speedup T_fine(steps) / T_coarse+MLP(coarse_steps)."""
+    import concurrent.futures as cf
+    torch = _torch()
+    device = device or torch.device("cuda:0")
+    say = log or (lambda m: None)
+    seeds = list(seeds)
+    series = []
+    t_fine_runs = []
+    with cf.ThreadPoolExecutor(1) as ex:
+        nxt = ex.submit(fine_fields, seeds[0], nx, ny, nz, dx)
+        first = None
+        for n, sd in enumerate(seeds):
+            f = nxt.result()
+            if n + 1 < len(seeds):
+                nxt = ex.submit(fine_fields, seeds[n + 1], nx, ny, nz, dx)
+            if first is None:
+                first = f
+            series.append(fine_series(sd, nx, ny, nz, steps, every, dt, dx, device,
+                                      timing=t_fine_runs, fields=f))
+            say(f"  fine run seed {sd}: {t_fine_runs[-1]:.2f} s")
+    t_fine = time_fine_steps(first, nx, ny, nz, dx, dt, steps, device)
+    del first
+    train_set, held = series[:n_train], series[n_train:]
+    norm, scale = statistics(train_set)
+    model = Correction(device, seed=0, norm=norm, scale=scale, batch=batch)
+    zero = Correction(device, seed=0, norm=norm, scale=scale, batch=batch)
+    zero.params.zero_()
+    M.monc_mlp_pack(zero.params, zero.wpack)
+    t0 = time.perf_counter()
+    hist = train(model, train_set, int(train_steps * 2 / 3), seed=1, lr=lr, log=say, every=500)
+    hist += train(model, train_set, train_steps - int(train_steps * 2 / 3), seed=2, lr=lr * 0.3,
+                  log=say, every=500)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+
+    def held_loss(mdl):
+        rng = np.random.default_rng(99)
+        return float(np.mean([mdl.evaluate_loss(ser, n, rng) for ser in held
+                              for n in range(0, len(ser.tend), max(1, len(ser.tend) // 8))]))
+
+    loss_zero, loss_trained = held_loss(zero), held_loss(model)
+    nsteps = min(coarse_steps, len(held[0].tend))
+    err_plain, err_learned, fb = [], [], [0, 0, 0]
+    t_plain = t_learned = 0.0
+    for ser in held:
+        ref, ref0 = ser.snaps[nsteps], ser.snaps[0]
+        for mdl, errs in ((None, err_plain), (model, err_learned)):
+            runner = CoarseRunner(ser, mdl, growth=growth)
+            runner.run(ser.snaps[0], 1)            # warm-up
+            if mdl is not None:
+                runner.flags.zero_()
+            box = {}
+            ms = _event_ms(lambda: box.setdefault("out", runner.run(ser.snaps[0], nsteps)))
+            errs.append(errors(box["out"], ref, ref0))
+            if mdl is None:
+                t_plain += ms / len(held)
+            else:
+                t_learned += ms / len(held)
+                fb = [a + b for a, b in zip(fb, runner.fallbacks())]
+    # MLP forward alone on one coarse step's rows
+    runner = CoarseRunner(held[0], model, growth=growth)
+    N = runner.N
+    M.monc_mlp_features(held[0].snaps[0], model.norm, 0, None, runner.X.narrow(0, 0, N))
+    M.monc_mlp_features(held[0].snaps[0], model.norm, 1, None, runner.X.narrow(0, N, N))
+    M.monc_mlp_forward(runner.X, 2 * N, model.params, model.wpack, runner.G)
+    reps = 20
+    fwd_ms = _event_ms(lambda: [M.monc_mlp_forward(runner.X, 2 * N, model.params, model.wpack,
+                                                   runner.G) for _ in range(reps)]) / reps
+    flop = 2.0 * (M.MONC_MLP_NIN * M.MONC_MLP_H + M.MONC_MLP_H * M.MONC_MLP_H +
+                  M.MONC_MLP_H * M.MONC_MLP_NOUT)
+    mean = lambda errs: [float(np.mean([e[q] for e in errs])) for q in range(4)]
+    return {
+        "fine": [nx, ny, nz], "coarse": [nx // 4, ny // 4, nz // 4],
+        "seeds_train": seeds[:n_train], "seeds_held_out": seeds[n_train:],
+        "train_steps": train_steps, "batch_cells": batch, "train_s": t_train,
+        "loss_first": hist[0][1], "loss_last": hist[-1][1],
+        "held_out_loss_no_correction": loss_zero, "held_out_loss_trained": loss_trained,
+        "coarse_steps": nsteps, "fields": FIELDS,
+        "err_plain": mean(err_plain), "err_learned": mean(err_learned),
+        "fallback_nonfinite": fb[0], "fallback_growth": fb[1], "theta_faces_clamped": fb[2],
+        "t_fine_ms": t_fine, "t_coarse_plain_ms": t_plain, "t_coarse_learned_ms": t_learned,
+        "speedup_vs_fine": t_fine / t_learned,
+        "mlp_forward_ms": fwd_ms, "mlp_rows": 2 * N,
+        "mlp_tflops": 2 * N * flop / (fwd_ms * 1e-3) / 1e12,
+    }

@@ -379,3 +379,18 @@ def test_training_lowers_held_out_loss():
     say(f"  held-out loss: zero {base:.4f}, untrained {before:.4f}, trained {after:.4f}")
     assert np.isfinite(after)
     assert after < 0.9 * base and after < before
+
+
+def test_experiment_driver_small():
+    """The end-to-end driver (fine runs, restriction, training, held-out
+    coarse runs plain and learned, timings) on a small grid."""
+    from paper_2009_12850_amd import learned as L
+    say("experiment driver, 64x64x32")
+    r = L.run_experiment(nx=64, ny=64, nz=32, seeds=range(30, 34), n_train=3, steps=24,
+                         train_steps=150, batch=1024, coarse_steps=6, device=dev(), log=say)
+    say(f"  {r}")
+    assert r["coarse"] == [16, 16, 8] and r["coarse_steps"] == 6
+    assert all(np.isfinite(r["err_plain"])) and all(np.isfinite(r["err_learned"]))
+    assert r["held_out_loss_trained"] < r["held_out_loss_no_correction"]
+    assert r["fallback_nonfinite"] == 0
+    assert r["t_fine_ms"] > 0 and r["t_coarse_learned_ms"] > 0 and r["mlp_tflops"] > 0

@@ -238,6 +238,25 @@ def test_big1024_subdomains_match_oracle():
             assert e <= TOL64, f"region {(i0, i1, j0, j1)} field {n}: {e:.3e}"
 
 
+@pytest.mark.parametrize("nscal,nz,budgets", [(1, 128, False), (1, 128, True), (2, 128, False),
+                                             (3, 96, False), (4, 128, False), (1, 64, False)])
+def test_step_with_unfilled_halos_every_grouping(nscal, nz, budgets):
+    """NaN halos, every scalar grouping (passes of 2 or 3 scalars), one and two
+    z-chunks, with and without budgets: the step matches the oracle."""
+    say(f"unfilled halos step nscal={nscal} nz={nz} budgets={budgets}")
+    g, host = case(20, 14, nz, nscal, seed=540 + nscal + nz)
+    dt = 0.5
+    ref = O.step([h.copy() for h in host], g, dt)
+    poisoned = [I.pad(I.interior(h)) for h in host]
+    o, b = run_step(to_dev(poisoned), g, dt, with_budgets=budgets)
+    for n in range(3 + nscal):
+        got = o[n].cpu().numpy()
+        assert np.all(np.isfinite(I.interior(got))), n
+        assert rel_err(got - host[n], ref[n] - host[n]) <= TOL64, n
+    if budgets:
+        assert b[M.B_NONFINITE] == 0
+
+
 def test_halos_are_never_read():
     """Inputs with NaN halos (never filled) give the oracle's result: periodic
     neighbours are read at wrapped interior indices."""
