@@ -28,6 +28,46 @@ if ROOT not in sys.path:
 
 HBM_PEAK = 8.0e12  # B/s, MI355X HBM3E
 
+# Sources of the dominant kernel: a measured HBM traffic figure is reported
+# only while these files are unchanged since the counters were taken.
+KERNEL_SOURCES = ["paper_2009_12850_amd/csrc/march.hpp",
+                  "paper_2009_12850_amd/csrc/march_launch.hpp",
+                  "paper_2009_12850_amd/csrc/march_step64.hip",
+                  "paper_2009_12850_amd/csrc/monc_scheme.hpp",
+                  "paper_2009_12850_amd/csrc/advect.hip"]
+TRAFFIC_FILE = "profiles/advect_march_step_f64_big1024_traffic.txt"
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary (FETCH_SIZE and WRITE_SIZE, each scaled by what the counter reads
+    for a plain device copy of known size), or None if there is none for this
+    workload or the kernel sources have changed since."""
+    path = os.path.join(ROOT, TRAFFIC_FILE)
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("workload") != workload or kv.get("source_sha256") != kernel_source_hash():
+        return None
+    try:
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
@@ -205,8 +245,10 @@ def main():
     k_ms = event_time_ms(torch, stream, lambda: step(False), args.steps)
     bytes_alg = 16.0 * nf * npts  # read + write of every FP64 field
     achieved = bytes_alg / (k_ms * 1e-3)
+    traffic = measured_traffic(args.workload)
     roofline = {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9,
-                "unit": "GB/s", "frac": achieved / HBM_PEAK, "traffic": None,
+                "unit": "GB/s", "frac": achieved / HBM_PEAK,
+                "traffic": traffic / 1e9 if traffic else None, "traffic_unit": "GB per launch",
                 "kernel": "monc_step (fused PW+TVD+update, FP64)",
                 "bytes_per_launch": bytes_alg, "launch_ms": k_ms}
 

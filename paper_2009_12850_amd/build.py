@@ -19,9 +19,13 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
          "-Wall", "-Wno-unused-function", "-Wno-unknown-pragmas"]
 
 
+# Extra compile flags for build-time tuning, e.g. MONC_HIPCC_FLAGS=-DMONC_MARCH_WAVES64=4
+EXTRA = os.environ.get("MONC_HIPCC_FLAGS", "").split()
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj]
+    cmd = [HIPCC, *FLAGS, *EXTRA, "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed on {src}:\n{r.stdout}\n{r.stderr}")

@@ -35,10 +35,10 @@ Tiling march_tiling(int nx, int ny, int nz, int waves) {
     return t;
 }
 
-// Both step variants hold FP64 state, so they run 8-wave workgroups.
+// Both step variants hold FP64 state, so they run the FP64 workgroup size.
 int step_grid(int nx, int ny, int nz, bool mixed) {
     (void)mixed;
-    return march_tiling(nx, ny, nz, 8).nblocks;
+    return march_tiling(nx, ny, nz, march_waves<double, double>()).nblocks;
 }
 
 int step_blocks(int nx, int ny, int nz) { return step_grid(nx, ny, nz, false); }

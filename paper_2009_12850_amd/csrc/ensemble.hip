@@ -23,7 +23,7 @@ namespace monc {
 
 namespace {
 
-constexpr int ENS_WAVES = 8;  // FP64 state held in registers
+constexpr int ENS_WAVES = march_waves<double, float>();  // FP64 state held in registers
 
 struct EnsMember {
     AdvArgs a[2];  // a[p]: reads state[p], writes state[1-p]
@@ -32,7 +32,7 @@ struct EnsMember {
 };
 
 template <int NCH, int NS>
-__global__ void __launch_bounds__(ENS_WAVES * 64)
+__global__ void __launch_bounds__(ENS_WAVES * 64) __attribute__((amdgpu_waves_per_eu(2)))
     ensemble_step(const EnsMember* __restrict__ mem, const int4* __restrict__ items, int nitems,
                   int parity) {
     extern __shared__ __align__(16) unsigned char smem_raw[];

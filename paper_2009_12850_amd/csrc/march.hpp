@@ -81,10 +81,15 @@ __device__ __forceinline__ T cvt0(Ts x) {
 }
 
 // Waves per workgroup: 8 when FP64 values are held (a wave needs up to 256
-// registers), 16 when storage and compute are both 32-bit or narrower.
+// registers, so two waves share a SIMD), 16 when storage and compute are both
+// 32-bit or narrower.  MONC_MARCH_WAVES64 sets the FP64 count at build time
+// (4 gives two workgroups per CU, whose barriers then overlap).
+#ifndef MONC_MARCH_WAVES64
+#define MONC_MARCH_WAVES64 8
+#endif
 template <typename Ts, typename T>
 __host__ __device__ constexpr int march_waves() {
-    return (sizeof(T) == 8 || sizeof(Ts) == 8) ? 8 : 16;
+    return (sizeof(T) == 8 || sizeof(Ts) == 8) ? MONC_MARCH_WAVES64 : 16;
 }
 
 __host__ __device__ constexpr int march_nq(int ns, int nch, int wv) {
@@ -615,7 +620,8 @@ __device__ __forceinline__ void march_tile(const AdvArgs& a, const TileJob& tj,
 
 // One workgroup per tile.
 template <typename Ts, typename T, int MODE, bool PW, int NS, bool BUD, int NCH>
-__global__ void __launch_bounds__((march_waves<Ts, T>() * 64)) advect_march(MarchArgs m) {
+__global__ void __launch_bounds__((march_waves<Ts, T>() * 64))
+    __attribute__((amdgpu_waves_per_eu(2))) advect_march(MarchArgs m) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     // Consecutive tiles along y go to the same XCD (workgroups are dealt to
     // the 8 XCDs round-robin), so neighbouring tiles share halo columns
