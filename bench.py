@@ -106,6 +106,30 @@ def event_time_ms(torch, stream, fn, reps):
     return start.elapsed_time(end) / reps
 
 
+PW_FLOP = 92  # floating-point operations of one PW evaluation per grid point
+
+
+def bench_scaled(torch, M, vel64, g, prof, stream, npts, reps):
+    """Work-scaled PW (the PW arithmetic repeated 1..16 times on the same data)
+    in FP64 and FP32: time, effective FLOP rate and HBM fraction per factor."""
+    vel32 = [v.float() for v in vel64]
+    out = {}
+    for name, code, vel, eb in (("f64", M.MONC_F64, vel64, 8), ("f32", M.MONC_F32, vel32, 4)):
+        outs = [torch.empty_like(v) for v in vel]
+        M.monc_advect_pw_scaled(code, *vel, *outs, g.dx, g.dy, prof, 1, stream)  # warm-up
+        rows = {}
+        for work in (1, 2, 4, 8, 16):
+            ms = event_time_ms(torch, stream, lambda: M.monc_advect_pw_scaled(
+                code, *vel, *outs, g.dx, g.dy, prof, work, stream), reps)
+            rows[str(work)] = {"ms": ms,
+                               "tflops": PW_FLOP * work * npts / (ms * 1e-3) / 1e12,
+                               "hbm_frac": 6.0 * eb * npts / (ms * 1e-3) / HBM_PEAK}
+        out[name] = rows
+        del outs
+    del vel32
+    return out
+
+
 def cpu_baseline(seconds):
     """The FP64 oracle, unchanged, on a 256 x 256 x 128 slab of the same kind
     of input (5 fields), stepped until about `seconds` of CPU work is done."""
@@ -279,6 +303,8 @@ def main():
                 "hbm_frac": (eb + 4.0) * nf * npts / (t * 1e-3) / HBM_PEAK,
                 "speedup_vs_f64": t64 / t}
             del work, outs
+        forms["work_scaled_pw"] = bench_scaled(torch, M, state[0][:3], g, prof, stream, npts,
+                                               max(3, args.steps // 4))
         mixed = lambda: M.monc_step_mixed(state[0], state[1], phi0, g.dx, g.dy, prof, w.dt,
                                           None, None, stream)
         tm = event_time_ms(torch, stream, mixed, args.steps)

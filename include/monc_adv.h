@@ -120,6 +120,23 @@ int monc_advect_pw(const double *u, const double *v, const double *w,
                    const double *rhon, monc_stream_t stream);
 
 /* ---------------------------------------------------------------------------
+ * Work-scaled PW (the experiment of Sec. 4 that raises the PW arithmetic to
+ * that of the ULTIMATE scheme, about sixteen-fold): the PW source terms of
+ * monc_advect_pw evaluated `work` times per grid point (1 <= work <=
+ * MONC_MAX_WORK) on the same loaded values, each repetition chained to the
+ * previous one so that none is merged or dropped; the result does not depend
+ * on `work`.  dtype MONC_F64 (double in and out) or MONC_F32 (float in and
+ * out).  Bytes per point are fixed (one read of u, v, w, one write of su, sv,
+ * sw); arithmetic is 92 floating-point operations per point per repetition.
+ * Halos are not read.  A measurement kernel: one thread per grid point.
+ * ------------------------------------------------------------------------- */
+#define MONC_MAX_WORK 64
+int monc_advect_pw_scaled(int dtype, const void *u, const void *v, const void *w, void *su,
+                          void *sv, void *sw, int nx, int ny, int nz, double dx, double dy,
+                          const double *rdz, const double *rho, const double *rhon, int work,
+                          monc_stream_t stream);
+
+/* ---------------------------------------------------------------------------
  * ULTIMATE-limited QUICKEST (TVD) scalar source terms (Sec. 3.1,
  * positivity-preserving scheme) in FP64, for nscal scalars at once.  q and sq
  * are host arrays of nscal device pointers.  Face values are third-order

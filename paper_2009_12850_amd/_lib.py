@@ -20,6 +20,7 @@ MONC_OK, MONC_EINVAL, MONC_EHIP, MONC_ECFL, MONC_ENONFINITE, MONC_EUNSUPPORTED =
 MONC_F64, MONC_F32, MONC_BF16 = 0, 1, 2
 MONC_MAX_SCALARS = 8
 MONC_MAX_NZ = 128
+MONC_MAX_WORK = 64
 B_CU, B_CV, B_CW, B_PU, B_QU, B_PV, B_QV, B_PW, B_QW, B_COURANT, B_NONFINITE = range(11)
 B_SCALAR0 = 11
 MONC_NBUDGET = B_SCALAR0 + 3 * MONC_MAX_SCALARS
@@ -44,6 +45,8 @@ _SIGS = {
     "monc_halo_fill_f32": ([ip, PP, ip, ip, ip, vp], ip),
     "monc_halo_fill_bf16": ([ip, PP, ip, ip, ip, vp], ip),
     "monc_advect_pw": ([vp, vp, vp, vp, vp, vp, ip, ip, ip, dp, dp, vp, vp, vp, vp], ip),
+    "monc_advect_pw_scaled": ([ip, vp, vp, vp, vp, vp, vp, ip, ip, ip, dp, dp, vp, vp, vp, ip, vp],
+                              ip),
     "monc_advect_tvd": ([vp, vp, vp, ip, PP, PP, ip, ip, ip, dp, dp, vp, vp, vp, dp, vp], ip),
     "monc_advect": ([ip, PP, PP, ip, DPTR, ip, ip, ip, dp, dp, vp, vp, vp, dp, vp], ip),
     "monc_step_workspace_bytes": ([ip, ip, ip, ip], C.c_size_t),
@@ -193,6 +196,18 @@ def monc_advect_pw(u, v, w, su, sv, sw, dx, dy, prof, stream=None):
           zip((u, v, w, su, sv, sw), ("u", "v", "w", "su", "sv", "sw"))]
     _check(lib().monc_advect_pw(*ps, nx, ny, nz, float(dx), float(dy), *_prof(prof),
                                 _stream(stream)), "monc_advect_pw")
+
+
+def monc_advect_pw_scaled(dtype, u, v, w, su, sv, sw, dx, dy, prof, work, stream=None):
+    torch = _torch()
+    nx, ny, nz = _grid(u)
+    tdt = torch.float64 if dtype == MONC_F64 else torch.float32
+    sh = tuple(u.shape)
+    p = [_ptr(x, tdt, sh, n) for x, n in ((u, "u"), (v, "v"), (w, "w"), (su, "su"), (sv, "sv"),
+                                            (sw, "sw"))]
+    _check(lib().monc_advect_pw_scaled(int(dtype), *p, nx, ny, nz, float(dx), float(dy),
+                                       *_prof(prof), int(work), _stream(stream)),
+           "monc_advect_pw_scaled")
 
 
 def monc_advect_tvd(u, v, w, q, sq, dx, dy, prof, dt, stream=None):

@@ -191,6 +191,27 @@ int monc_advect_pw(const double* u, const double* v, const double* w, double* su
                       "advect_pw");
 }
 
+int monc_advect_pw_scaled(int dtype, const void* u, const void* v, const void* w, void* su,
+                          void* sv, void* sw, int nx, int ny, int nz, double dx, double dy,
+                          const double* rdz, const double* rho, const double* rhon, int work,
+                          monc_stream_t stream) {
+    TRY(check_grid(nx, ny, nz));
+    TRY(check_spacing(dx, dy));
+    TRY(check_prof(rdz, rho, rhon));
+    if (dtype != MONC_F64 && dtype != MONC_F32)
+        return fail(MONC_EINVAL, "dtype must be MONC_F64 or MONC_F32 (got %d)", dtype);
+    if (work < 1 || work > MONC_MAX_WORK)
+        return fail(MONC_EINVAL, "work must be in [1, %d] (got %d)", MONC_MAX_WORK, work);
+    const void* in[3] = {u, v, w};
+    const void* out[3] = {su, sv, sw};
+    TRY(check_ptrs(3, in, "velocity"));
+    TRY(check_ptrs(3, out, "tendency"));
+    TRY(check_alias(3, in, 3, out));
+    return hip_status(launch_pw_scaled(dtype, u, v, w, su, sv, sw, nx, ny, nz, dx, dy, rdz, rho,
+                                       rhon, work, (hipStream_t)stream),
+                      "advect_pw_scaled");
+}
+
 int monc_advect_tvd(const double* u, const double* v, const double* w, int nscal,
                     const double* const* q, double* const* sq, int nx, int ny, int nz,
                     double dx, double dy, const double* rdz, const double* rho,

@@ -72,6 +72,10 @@ hipError_t launch_mlp_loss(const float* Y4, int b, const int* cells, const doubl
 hipError_t launch_mlp_adam(float* params, float* m1, float* m2, const float* grad, int t,
                            double lr, double b1, double b2, double eps, uint16_t* wpack,
                            hipStream_t s);
+hipError_t launch_pw_scaled(int dtype, const void* u, const void* v, const void* w, void* su,
+                            void* sv, void* sw, int nx, int ny, int nz, double dx, double dy,
+                            const double* rdz, const double* rho, const double* rhon, int work,
+                            hipStream_t s);
 size_t correct_step_workspace_bytes(int nx, int ny, int nz);
 hipError_t launch_correct_step(double* const* in, double* const* tend, const float* gx,
                                const float* gy, double* const* out, int nx, int ny, int nz,

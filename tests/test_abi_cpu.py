@@ -151,3 +151,61 @@ def test_ensemble_create_validates_members():
     assert L.monc_ensemble_create(C.cast(arr, C.c_void_p), 1, 4, None, 0,
                                   C.byref(plan)) == M.MONC_EUNSUPPORTED
     assert L.monc_ensemble_run(None, 5, None) == M.MONC_EINVAL
+
+
+@pytest.mark.parametrize("dtype,work", [(M.MONC_F64, 0), (M.MONC_F64, M.MONC_MAX_WORK + 1),
+                                        (M.MONC_BF16, 1), (7, 1)])
+def test_pw_scaled_rejects_bad_work_and_dtype(dtype, work):
+    L = M.lib()
+    rc = L.monc_advect_pw_scaled(dtype, FAKE, C.c_void_p(0x5000), C.c_void_p(0x6000),
+                                 C.c_void_p(0x2000), C.c_void_p(0x3000), C.c_void_p(0x4000),
+                                 4, 4, 4, 50.0, 50.0, *_prof3(), work, None)
+    assert rc == M.MONC_EINVAL and L.monc_last_error()
+
+
+def _block(n, base):
+    return _arr([base + 0x100 * q for q in range(n)])
+
+
+def test_learned_entry_points_validate_before_launch():
+    L = M.lib()
+    d = C.c_double
+    prof = _prof3()
+    # restriction needs multiples of 4
+    rc = L.monc_restrict4(1, _block(4, 0x10000), _block(4, 0x20000), 6, 8, 8, *prof, FAKE, FAKE,
+                          FAKE, None)
+    assert rc == M.MONC_EINVAL and b"multiples of 4" in L.monc_last_error()
+    # features: orient, zero std, missing cell list with the wrong count
+    norm = (d * 8)(0, 1, 0, 1, 0, 1, 0, 1)
+    bad = (d * 8)(0, 1, 0, 0, 0, 1, 0, 1)
+    assert L.monc_mlp_features(_block(4, 0x10000), 4, 4, 4, norm, 2, None, 64, FAKE,
+                               None) == M.MONC_EINVAL
+    assert L.monc_mlp_features(_block(4, 0x10000), 4, 4, 4, bad, 0, None, 64, FAKE,
+                               None) == M.MONC_EINVAL
+    assert L.monc_mlp_features(_block(4, 0x10000), 4, 4, 4, norm, 0, None, 63, FAKE,
+                               None) == M.MONC_EINVAL
+    # forward: empty batch, misaligned rows
+    assert L.monc_mlp_forward(FAKE, 0, FAKE, FAKE, FAKE, None, None, None, None,
+                              None) == M.MONC_EINVAL
+    assert L.monc_mlp_forward(C.c_void_p(0x1008), 4, FAKE, FAKE, FAKE, None, None, None, None,
+                              None) == M.MONC_EINVAL
+    # Adam: t < 1 and a bad beta
+    assert L.monc_mlp_adam(FAKE, FAKE, FAKE, FAKE, 0, 1e-3, 0.9, 0.999, 1e-8, FAKE,
+                           None) == M.MONC_EINVAL
+    assert L.monc_mlp_adam(FAKE, FAKE, FAKE, FAKE, 1, 1e-3, 1.0, 0.999, 1e-8, FAKE,
+                           None) == M.MONC_EINVAL
+    # corrected step: growth must be positive, scales finite, state not aliased
+    scale = (d * 4)(1, 1, 1, 1)
+    nanscale = (d * 4)(1, float("nan"), 1, 1)
+    args = (_block(4, 0x10000), _block(4, 0x20000), FAKE, FAKE, _block(4, 0x30000), 4, 4, 4, 50.0,
+            50.0)
+    assert L.monc_correct_step(*args, scale, *prof, 2.0, 0.0, FAKE, FAKE,
+                               None) == M.MONC_EINVAL
+    assert L.monc_correct_step(*args, nanscale, *prof, 2.0, 1.01, FAKE, FAKE,
+                               None) == M.MONC_EINVAL
+    alias = (_block(4, 0x10000), _block(4, 0x20000), FAKE, FAKE, _block(4, 0x10000), 4, 4, 4, 50.0,
+             50.0)
+    assert L.monc_correct_step(*alias, scale, *prof, 2.0, 1.01, FAKE, FAKE,
+                               None) == M.MONC_EINVAL
+    assert M.monc_correct_step_workspace_bytes(8, 8, 8) > 0
+    assert M.monc_mlp_backward_workspace_bytes(0) == 0
