@@ -140,11 +140,17 @@ def _one_field(g: Geometry, name: str, n: int, seed: int, amp: float, noise: flo
 
 
 def make_fields(g: Geometry, nscal: int, seed: int, amp: float = 5.0,
-                noise: float = 0.01, padded: bool = False, threads: int = 8) -> dict:
+                noise: float = 0.01, padded: bool = False, threads: int = 8,
+                only=None) -> dict:
     """Fields u, v, w and nscal scalars (th, q1, ...), interior (nx, ny, nz)
-    arrays, or [(nx+4)][(ny+4)][nz] arrays with a NaN halo if padded."""
+    arrays, or [(nx+4)][(ny+4)][nz] arrays with a NaN halo if padded.  `only`
+    restricts the output to the named fields (each field's draws depend only
+    on the seed and its position in the full list, so a subset is the same)."""
     import concurrent.futures as cf
     names = ["u", "v", "w"] + scalar_names(nscal)
+    index = {name: n for n, name in enumerate(names)}
+    if only is not None:
+        names = [n for n in names if n in only]
     out = {}
     views = {}
     for name in names:
@@ -156,14 +162,15 @@ def make_fields(g: Geometry, nscal: int, seed: int, amp: float = 5.0,
             out[name] = np.empty((g.nx, g.ny, g.nz))
             views[name] = out[name]
     with cf.ThreadPoolExecutor(max_workers=max(1, min(threads, len(names)))) as ex:
-        futs = [ex.submit(_one_field, g, name, n, seed, amp, noise, views[name])
-                for n, name in enumerate(names)]
+        futs = [ex.submit(_one_field, g, name, index[name], seed, amp, noise, views[name])
+                for name in names]
         for f in futs:
             f.result()
     return out
 
 
-def make_divfree_velocity(g: Geometry, seed: int, amp: float = 5.0) -> dict:
+def make_divfree_velocity(g: Geometry, seed: int, amp: float = 5.0,
+                          padded: bool = False) -> dict:
     """u, v, w whose anelastic mass divergence vanishes to round-off.
 
     Built from three periodic potentials on the C-grid: A (x-z, at
@@ -172,39 +179,67 @@ def make_divfree_velocity(g: Geometry, seed: int, amp: float = 5.0) -> dict:
         rhon_k u = -rdz_k (A_k - A_{k-1}) + rhon_k (C_j - C_{j-1})/dy
         rhon_k v = -rdz_k (B_k - B_{k-1}) - rhon_k (C_i - C_{i-1})/dx
         rho_k  w =  (A_i - A_{i-1})/dx + (B_j - B_{j-1})/dy,   A_{-1} = B_{-1} = 0.
-    The result is scaled so that the largest speed component equals amp.
+    The result is scaled so that the largest speed component equals amp (the
+    divergence is linear in the potentials, so scaling keeps it zero).
+    Padded output: [(nx+4)][(ny+4)][nz] with a NaN halo.
     """
+    import concurrent.futures as cf
     rng = np.random.default_rng(seed)
     xf = (np.arange(g.nx) + 1.0) * g.dx
     yc = (np.arange(g.ny) + 0.5) * g.dy
     xc = (np.arange(g.nx) + 0.5) * g.dx
     yf = (np.arange(g.ny) + 1.0) * g.dy
-    pa = _mode_sum(g, _draw_modes(rng), xf, yc, g.z_face, True)
-    pb = _mode_sum(g, _draw_modes(rng), xc, yf, g.z_face, True)
-    pc = _mode_sum(g, _draw_modes(rng), xf, yf, g.z_centre, False)
+    modes = [_draw_modes(rng) for _ in range(3)]
+    with cf.ThreadPoolExecutor(3) as ex:
+        fa = ex.submit(_mode_sum, g, modes[0], xf, yc, g.z_face, True)
+        fb = ex.submit(_mode_sum, g, modes[1], xc, yf, g.z_face, True)
+        fc = ex.submit(_mode_sum, g, modes[2], xf, yf, g.z_centre, False)
+        pa, pb, pc = fa.result(), fb.result(), fc.result()
     pa[:, :, g.nz - 1] = 0.0
     pb[:, :, g.nz - 1] = 0.0
     pa *= g.dx * g.rhon.max()
     pb *= g.dy * g.rhon.max()
     pc *= g.dx
+    rdz = g.rdz[None, None, :]
+    rhon = g.rhon[None, None, :]
+    rho = g.rho[None, None, :]
 
-    def build(a, b, c):
-        zero = np.zeros((g.nx, g.ny, 1))
-        a_km = np.concatenate([zero, a[:, :, :-1]], axis=2)
-        b_km = np.concatenate([zero, b[:, :, :-1]], axis=2)
-        rdz = g.rdz[None, None, :]
-        rhon = g.rhon[None, None, :]
-        rho = g.rho[None, None, :]
-        u = (-rdz * (a - a_km) + rhon * (c - np.roll(c, 1, axis=1)) / g.dy) / rhon
-        v = (-rdz * (b - b_km) - rhon * (c - np.roll(c, 1, axis=0)) / g.dx) / rhon
-        w = ((a - np.roll(a, 1, axis=0)) / g.dx + (b - np.roll(b, 1, axis=1)) / g.dy) / rho
-        w[:, :, g.nz - 1] = 0.0
-        return u, v, w
+    def alloc():
+        if padded:
+            a = np.full((g.nx + 4, g.ny + 4, g.nz), np.nan)
+            return a, a[2:g.nx + 2, 2:g.ny + 2, :]
+        a = np.empty((g.nx, g.ny, g.nz))
+        return a, a
 
-    u, v, w = build(pa, pb, pc)
+    def vertical(a, out):
+        # -rdz_k (a_k - a_{k-1}) / rhon_k with a_{-1} = 0
+        out[:, :, 0] = a[:, :, 0]
+        np.subtract(a[:, :, 1:], a[:, :, :-1], out=out[:, :, 1:])
+        out *= -rdz / rhon
+
+    def u_part(out):
+        vertical(pa, out)
+        out += (pc - np.roll(pc, 1, axis=1)) / g.dy
+
+    def v_part(out):
+        vertical(pb, out)
+        out -= (pc - np.roll(pc, 1, axis=0)) / g.dx
+
+    def w_part(out):
+        np.subtract(pa, np.roll(pa, 1, axis=0), out=out)
+        out /= g.dx
+        out += (pb - np.roll(pb, 1, axis=1)) / g.dy
+        out /= rho
+        out[:, :, g.nz - 1] = 0.0
+
+    (U, u), (V, v), (W, w) = alloc(), alloc(), alloc()
+    with cf.ThreadPoolExecutor(3) as ex:
+        for f in [ex.submit(u_part, u), ex.submit(v_part, v), ex.submit(w_part, w)]:
+            f.result()
     scale = amp / max(np.abs(u).max(), np.abs(v).max(), np.abs(w).max())
-    u, v, w = build(pa * scale, pb * scale, pc * scale)
-    return {"u": u, "v": v, "w": w}
+    for x in (u, v, w):
+        x *= scale
+    return {"u": U, "v": V, "w": W}
 
 
 def pad(f: np.ndarray, fill: float = np.nan) -> np.ndarray:
@@ -236,13 +271,14 @@ class Workload:
     dt: float = 0.5
     steps: int = 1
     dx: float = 50.0
+    divfree: bool = False   # divergence-free velocity (for runs of many steps)
 
 
 WORKLOADS = {
     # one PW + TVD evaluation, 32^3, u v w th q1
     "tiny32": Workload("tiny32", 32, 32, 32, 2, seed=1),
     # 100 forward steps, 512x512x128, u v w th q1 q2 q3
-    "steps512": Workload("steps512", 512, 512, 128, 4, seed=2, steps=100),
+    "steps512": Workload("steps512", 512, 512, 128, 4, seed=2, steps=100, divfree=True),
     # headline throughput, 1024x1024x128, u v w th q1
     "big1024": Workload("big1024", 1024, 1024, 128, 2, seed=3),
 }
@@ -251,7 +287,10 @@ WORKLOADS = {
 def make_workload(name: str, padded: bool = False):
     w = WORKLOADS[name]
     g = make_geometry(w.nx, w.ny, w.nz, w.dx, w.dx)
-    f = make_fields(g, w.nscal, w.seed, padded=padded)
+    if not w.divfree:
+        return w, g, make_fields(g, w.nscal, w.seed, padded=padded)
+    f = make_divfree_velocity(g, w.seed, padded=padded)
+    f.update(make_fields(g, w.nscal, w.seed, padded=padded, only=scalar_names(w.nscal)))
     return w, g, f
 
 

@@ -37,9 +37,13 @@ class CoarseSeries:
 
 
 def fine_fields(seed, nx, ny, nz, dx, amp=5.0):
-    """Seeded fine initial state (host, padded) of u, v, w, theta."""
+    """Seeded fine initial state (host, padded) of u, v, w, theta.  The flow is
+    divergence-free, as an anelastic flow after its pressure solve: a flow with
+    convergence zones would pile theta up there over hundreds of steps."""
     g = I.make_geometry(nx, ny, nz, dx, dx)
-    return I.make_fields(g, 1, seed, amp=amp, padded=True)
+    f = I.make_divfree_velocity(g, seed, amp=amp, padded=True)
+    f.update(I.make_fields(g, 1, seed, amp=amp, padded=True, only=["th"]))
+    return f
 
 
 def fine_series(seed, nx, ny, nz, steps, every, dt, dx, device, amp=5.0, timing=None,
@@ -332,7 +336,7 @@ def run_experiment(nx=512, ny=512, nz=128, seeds=range(2000, 2016), n_train=12, 
     seeds = list(seeds)
     series = []
     t_fine_runs = []
-    with cf.ThreadPoolExecutor(1) as ex:
+    with cf.ThreadPoolExecutor(2) as ex:
         nxt = ex.submit(fine_fields, seeds[0], nx, ny, nz, dx)
         first = None
         for n, sd in enumerate(seeds):
