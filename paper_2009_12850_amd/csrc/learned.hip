@@ -616,7 +616,10 @@ __global__ void __launch_bounds__(256) corr_step(CorrArgs a) {
     const long n = (long)a.nx * a.ny * a.nz;
     const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
     const bool plain = (a.flags[0] & 1) != 0;
+    __shared__ int nclamp_block;
+    if (threadIdx.x == 0) nclamp_block = 0;
     double sum[CORR_NSUM] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    int nclamp = 0;
     if (t < n) {
         const int nx = a.nx, ny = a.ny, nz = a.nz;
         const int k = (int)(t % nz), j = (int)((t / nz) % ny), i = (int)(t / ((long)nz * ny));
@@ -663,8 +666,7 @@ __global__ void __launch_bounds__(256) corr_step(CorrArgs a) {
             const double Gym = clamp_face(at(v, i, jm), py, a.dt / a.dy, mk,
                                           cy * (double)a.gy[cm_y * 4 + 3], c4);
             cq[3] = -((Gxp - Gxm) / a.dx + (Gyp - Gym) / a.dy) / mk;
-            const int nc = (int)c1 + (int)c3;  // faces i+1/2 and j+1/2 belong to this cell
-            if (nc) atomicAdd(a.flags + 3, nc);
+            nclamp = (int)c1 + (int)c3;  // faces i+1/2 and j+1/2 belong to this cell
         }
         double o[4], pl[4];
         for (int q = 0; q < 4; q++) {
@@ -682,13 +684,16 @@ __global__ void __launch_bounds__(256) corr_step(CorrArgs a) {
         sum[6] = m;
     }
     for (int q = 0; q < CORR_NSUM; q++) red[q][threadIdx.x] = sum[q];
-    __syncthreads();
+    __syncthreads();  // also orders the zeroing of nclamp_block before the adds
+    if (nclamp) atomicAdd(&nclamp_block, nclamp);
     for (int st = 128; st > 0; st >>= 1) {
         if (threadIdx.x < st)
             for (int q = 0; q < CORR_NSUM; q++) red[q][threadIdx.x] += red[q][threadIdx.x + st];
         __syncthreads();
     }
     if (threadIdx.x < CORR_NSUM) a.partial[(long)blockIdx.x * CORR_NSUM + threadIdx.x] = red[threadIdx.x][0];
+    // one global add per workgroup for the clamp count
+    if (threadIdx.x == 0 && nclamp_block) atomicAdd(a.flags + 3, nclamp_block);
 }
 
 // Sums the block partials in a fixed order and takes the step's decision:
