@@ -60,6 +60,43 @@ __device__ __forceinline__ bf16 zero_of<bf16>() {
     return z;
 }
 
+// Raw buffer access.  A buffer resource covers one x-plane of one field; an
+// offset at or beyond its size reads as 0 and drops a store, so a lane that
+// must not load (beyond the column, beyond the tile, the lid level of w) or
+// must not store gets the offset MARCH_OOB instead of a branch around the
+// access: the loads issue without waiting on one another and need no
+// zero-initialised destination.
+typedef int march_v2i __attribute__((ext_vector_type(2)));
+constexpr uint32_t MARCH_OOB = 0xFFFFFFF0u;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void* base, uint32_t bytes) {
+    // descriptor word 3: 32-bit data format, raw (unswizzled) addressing
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes,
+                                             0x00020000);
+}
+template <typename Ts>
+__device__ __forceinline__ Ts bload(__amdgpu_buffer_rsrc_t r, uint32_t off);
+template <>
+__device__ __forceinline__ double bload<double>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+template <>
+__device__ __forceinline__ float bload<float>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+template <>
+__device__ __forceinline__ bf16 bload<bf16>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    bf16 x;
+    x.bits = (uint16_t)__builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0);
+    return x;
+}
+__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t off, double v) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(march_v2i, v), r, off, 0, 0);
+}
+__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t off, float v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(int, v), r, off, 0, 0);
+}
+
 // storage -> compute, subtracting `off` first when the storage is FP64
 template <typename T, typename Ts>
 __device__ __forceinline__ T cvt(Ts x, double off) {
@@ -246,25 +283,32 @@ __device__ __forceinline__ void march_tile(const AdvArgs& a, const TileJob& tj,
         if (jj >= ny) jj -= ny;
         return jj;
     };
-    auto plane = [&](const Ts* p, int ii) -> const Ts* {
-        return p + (size_t)(wrapx(ii) + 2) * sx;
+    const uint32_t pbytes = (uint32_t)(sx * sizeof(Ts));  // one x-plane of a field
+    // element offset of plane ii (wrapped) within a field
+    auto poff = [&](int ii) -> size_t { return (size_t)(wrapx(ii) + 2) * sx; };
+    // load from the plane at element offset po of field pointer p, at byte
+    // offset boff within the plane
+    auto ldo = [&](const Ts* p, size_t po, uint32_t boff) -> Ts {
+        return bload<Ts>(plane_rsrc(p + po, pbytes), boff);
     };
-    auto ld = [&](const Ts* pl, uint32_t boff, bool ok) -> Ts {
-        Ts x = zero_of<Ts>();
-        if (ok) x = *(const Ts*)((const char*)pl + boff);
-        return x;
-    };
-    // own column: byte offset within a plane, and which levels load (the lid
-    // level of w reads as 0)
-    const uint32_t own_boff = (uint32_t)(((j + 2) * nz + k) * (int)sizeof(Ts));   // stores
-    const uint32_t own_roff = (uint32_t)(((wrapy(j) + 2) * nz + k) * (int)sizeof(Ts));  // loads
+    auto ld = [&](const Ts* p, int ii, uint32_t boff) -> Ts { return ldo(p, poff(ii), boff); };
+    // own column: byte offsets within a plane; lanes that do not load (or
+    // store) get MARCH_OOB (the lid level of w reads as 0)
     const bool ok_s = own_ok && kin;
     const bool ok_w = own_ok && k < nz - 1;
+    const uint32_t col_off = (uint32_t)(((wrapy(j) + 2) * nz + k) * (int)sizeof(Ts));
+    const uint32_t roff_s = ok_s ? col_off : MARCH_OOB;  // loads of u, v, scalars
+    const uint32_t roff_w = ok_w ? col_off : MARCH_OOB;  // loads of w
+    const uint32_t woff = store ? (uint32_t)(((j + 2) * nz + k) * (int)sizeof(To)) : MARCH_OOB;
+    const uint32_t wbytes = (uint32_t)(sx * sizeof(To));
+    const uint32_t wbytes64 = (uint32_t)(sx * sizeof(double));
+    const uint32_t woff64 = store ? (uint32_t)(((j + 2) * nz + k) * (int)sizeof(double)) : MARCH_OOB;
 
     // Halo jobs of one plane step, for each chunk: velocities u(i), v(i+1),
     // w(i+1) at columns j0-1 and j0+TJ; scalar s at plane i, columns j0-2,
     // j0-1, j0+TJ, j0+TJ+1.  Job id = wv + 8 q; decoded once here.
     int hj_f[NQ], hj_dpl[NQ], hj_lds[NQ];
+    bool hj_valid[NQ];
     const Ts* hj_ptr[NQ];
     uint32_t hj_boff[NQ];
     bool hj_ok[NQ];
@@ -296,17 +340,19 @@ __device__ __forceinline__ void march_tile(const AdvArgs& a, const TileJob& tj,
         hj_ptr[q] = fp;
         hj_dpl[q] = dpl;
         hj_ok[q] = valid && kk < nz && !(f == 2 && kk >= nz - 1);
-        hj_boff[q] = valid ? (uint32_t)(((wrapy(jj) + 2) * nz + kk) * (int)sizeof(Ts)) : 0u;
+        hj_boff[q] = hj_ok[q] ? (uint32_t)(((wrapy(jj) + 2) * nz + kk) * (int)sizeof(Ts))
+                              : MARCH_OOB;
         // LDS element offset (velocity slots: parity added per step)
         hj_lds[q] = f < 3 ? ((f * 2) * VC + c) * CSZ + 2 + kk
                           : (int)(sph - vel) + ((f - 3) * SC + c) * CSZ + 2 + kk;
-        if (!valid) hj_lds[q] = -1;
+        hj_valid[q] = valid;  // wave-uniform
     }
-    auto job_load = [&](int q, int i) -> Ts {
-        return ld(plane(hj_ptr[q], i + hj_dpl[q]), hj_boff[q], hj_ok[q]);
+    // halo loads of plane step i + 1 (o1, o2: offsets of planes i + 1 and i + 2)
+    auto job_load = [&](int q, size_t o1, size_t o2) -> Ts {
+        return ldo(hj_ptr[q], hj_dpl[q] ? o2 : o1, hj_boff[q]);
     };
     auto job_store = [&](int q, int i, Ts x) {
-        if (hj_lds[q] < 0) return;
+        if (!hj_valid[q]) return;
         const int f = hj_f[q];
         int e = hj_lds[q];
         double o = 0.0;
@@ -341,15 +387,15 @@ __device__ __forceinline__ void march_tile(const AdvArgs& a, const TileJob& tj,
     __syncthreads();  // level table visible
 #pragma unroll
     for (int p = 0; p < 3; p++) {
-        U[p] = ld(plane(fptr[0], i0 - 1 + p), own_roff, ok_s);
-        V[p] = ld(plane(fptr[1], i0 - 1 + p), own_roff, ok_s);
-        W[p] = ld(plane(fptr[2], i0 - 1 + p), own_roff, ok_w);
+        U[p] = ld(fptr[0], i0 - 1 + p, roff_s);
+        V[p] = ld(fptr[1], i0 - 1 + p, roff_s);
+        W[p] = ld(fptr[2], i0 - 1 + p, roff_w);
     }
 #pragma unroll
     for (int s = 0; s < NS; s++) {
-        const Ts Pm2 = ld(plane(fptr[3 + s], i0 - 2), own_roff, ok_s);
+        const Ts Pm2 = ld(fptr[3 + s], i0 - 2, roff_s);
 #pragma unroll
-        for (int p = 0; p < 4; p++) P[s][p] = ld(plane(fptr[3 + s], i0 - 1 + p), own_roff, ok_s);
+        for (int p = 0; p < 4; p++) P[s][p] = ld(fptr[3 + s], i0 - 1 + p, roff_s);
         FXm[s] = tvd_flux<T>(cvt0<T, Ts>(U[0]), cvt<T, Ts>(Pm2, off[s]), cvt<T, Ts>(P[s][0], off[s]),
                              cvt<T, Ts>(P[s][1], off[s]), cvt<T, Ts>(P[s][2], off[s]), cfx, rfx,
                              (T)1);
@@ -371,11 +417,21 @@ __device__ __forceinline__ void march_tile(const AdvArgs& a, const TileJob& tj,
         const int kk = 64 * chunk + lane;
         const bool ok = kk < nz && !(f == 2 && kk >= nz - 1);
         const Ts* fp = f == 0 ? fptr[0] : (f == 1 ? fptr[1] : fptr[2]);
-        const Ts x = ld(plane(fp, pl), (uint32_t)(((wrapy(jj) + 2) * nz + kk) * (int)sizeof(Ts)), ok);
+        const Ts x =
+            ld(fp, pl, ok ? (uint32_t)(((wrapy(jj) + 2) * nz + kk) * (int)sizeof(Ts)) : MARCH_OOB);
         vslot(f, pl)[c * CSZ + 2 + kk] = cvt0<T, Ts>(x);
     }
+    // plane offsets carried through the march: i+1, i+2, i+3 (for i = i0 - 1
+    // here); each step shifts them and wraps the newest with one compare
+    size_t o1 = poff(i0), o2 = poff(i0 + 1), o3 = poff(i0 + 2);
+    const size_t o_end = (size_t)(nx + 2) * sx, o_span = (size_t)nx * sx;
 #pragma unroll
-    for (int q = 0; q < NQ; q++) HB[q] = job_load(q, i0);
+    for (int q = 0; q < NQ; q++) HB[q] = job_load(q, o1, o2);
+    // now for i = i0
+    o1 = o2;
+    o2 = o3;
+    o3 += sx;
+    if (o3 >= o_end) o3 -= o_span;
 
     // per-level constants of this lane
     const bool bottom = k == 0;           // the ground face is below
@@ -398,13 +454,13 @@ __device__ __forceinline__ void march_tile(const AdvArgs& a, const TileJob& tj,
         Ts NU = zero_of<Ts>(), NV = zero_of<Ts>(), NW = zero_of<Ts>();
         Ts NP[NSA];
         if (more) {
-            NU = ld(plane(fptr[0], i + 2), own_roff, ok_s);
-            NV = ld(plane(fptr[1], i + 2), own_roff, ok_s);
-            NW = ld(plane(fptr[2], i + 2), own_roff, ok_w);
+            NU = ldo(fptr[0], o2, roff_s);
+            NV = ldo(fptr[1], o2, roff_s);
+            NW = ldo(fptr[2], o2, roff_w);
 #pragma unroll
-            for (int s = 0; s < NS; s++) NP[s] = ld(plane(fptr[3 + s], i + 3), own_roff, ok_s);
+            for (int s = 0; s < NS; s++) NP[s] = ldo(fptr[3 + s], o3, roff_s);
 #pragma unroll
-            for (int q = 0; q < NQ; q++) HB[q] = job_load(q, i + 1);
+            for (int q = 0; q < NQ; q++) HB[q] = job_load(q, o1, o2);
         }
         __syncthreads();
 
@@ -467,18 +523,18 @@ __device__ __forceinline__ void march_tile(const AdvArgs& a, const TileJob& tj,
             const T swc = pw_sw<T>(uc, ut, um, u_wt, vc, vt, vs, v_st, wc, ww, we, ws, wn, wb, wt,
                                    L, r2dx, r2dy);
             const T sw = k < nz - 1 ? swc : (T)0;
-            if (store) {
-                if constexpr (MODE == TEND) {
-                    *(To*)((char*)((To*)a.out[0] + gplane) + own_boff / sizeof(Ts) * sizeof(To)) = (To)su;
-                    *(To*)((char*)((To*)a.out[1] + gplane) + own_boff / sizeof(Ts) * sizeof(To)) = (To)sv;
-                    *(To*)((char*)((To*)a.out[2] + gplane) + own_boff / sizeof(Ts) * sizeof(To)) = (To)sw;
-                } else {
-                    const double nu = (double)U[1] + dt * (double)su;
-                    const double nv = (double)V[1] + dt * (double)sv;
-                    const double nw = k < nz - 1 ? (double)W[1] + dt * (double)sw : 0.0;
-                    *(double*)((char*)((double*)a.out[0] + gplane) + own_boff) = nu;
-                    *(double*)((char*)((double*)a.out[1] + gplane) + own_boff) = nv;
-                    *(double*)((char*)((double*)a.out[2] + gplane) + own_boff) = nw;
+            if constexpr (MODE == TEND) {
+                bstore(plane_rsrc((To*)a.out[0] + gplane, wbytes), woff, (To)su);
+                bstore(plane_rsrc((To*)a.out[1] + gplane, wbytes), woff, (To)sv);
+                bstore(plane_rsrc((To*)a.out[2] + gplane, wbytes), woff, (To)sw);
+            } else {
+                const double nu = (double)U[1] + dt * (double)su;
+                const double nv = (double)V[1] + dt * (double)sv;
+                const double nw = k < nz - 1 ? (double)W[1] + dt * (double)sw : 0.0;
+                bstore(plane_rsrc((double*)a.out[0] + gplane, wbytes64), woff64, nu);
+                bstore(plane_rsrc((double*)a.out[1] + gplane, wbytes64), woff64, nv);
+                bstore(plane_rsrc((double*)a.out[2] + gplane, wbytes64), woff64, nw);
+                if (store) {
                     if constexpr (BUD) {
                         const double ucd = (double)U[1], umd = (double)U[0];
                         const double vcd = (double)V[1], vsd = (double)vs;
@@ -545,15 +601,13 @@ __device__ __forceinline__ void march_tile(const AdvArgs& a, const TileJob& tj,
             if (lane == 0) fzm = ch == 0 ? (T)0 : fzc[(s * TJ + cc) * NCH + ch - 1];
             const T fym = sfy[(s * FC + cc) * NZP + k];
             const T val = part[s] + fym * rdy + rhon_inv * rdz * fzm;
-            if (store) {
-                if constexpr (MODE == TEND) {
-                    To* op = (To*)a.out[3 + tj.s0 + s] + gplane;
-                    *(To*)((char*)op + own_boff / sizeof(Ts) * sizeof(To)) = (To)val;
-                } else {
-                    // the state is FP64 whatever the compute type
-                    double* op = (double*)a.out[3 + tj.s0 + s] + gplane;
-                    const double nsv = (double)P[s][1] + dt * (double)val;
-                    *(double*)((char*)op + own_boff) = nsv;
+            if constexpr (MODE == TEND) {
+                bstore(plane_rsrc((To*)a.out[3 + tj.s0 + s] + gplane, wbytes), woff, (To)val);
+            } else {
+                // the state is FP64 whatever the compute type
+                const double nsv = (double)P[s][1] + dt * (double)val;
+                bstore(plane_rsrc((double*)a.out[3 + tj.s0 + s] + gplane, wbytes64), woff64, nsv);
+                if (store) {
                     if constexpr (BUD) {
                         const double phd = (double)P[s][1];
                         const double mass = (double)lev[LV_MASS * NZP + k];
@@ -566,6 +620,11 @@ __device__ __forceinline__ void march_tile(const AdvArgs& a, const TileJob& tj,
             }
         }
 
+        // advance the plane offsets
+        o1 = o2;
+        o2 = o3;
+        o3 += sx;
+        if (o3 >= o_end) o3 -= o_span;
         // rotate the windows
         U[0] = U[1];
         U[1] = U[2];
