@@ -284,6 +284,14 @@ int monc_mlp_pack(const float *params, uint16_t *wpack, monc_stream_t stream);
 int monc_mlp_forward(const uint16_t *X, int m, const float *params, const uint16_t *wpack,
                      float *Y, uint16_t *H1, uint16_t *H2, float *Z1, float *Z2,
                      monc_stream_t stream);
+/* Inference over every cell, cell order (i*ny + j)*nz + k: Y[nx*ny*nz][4] is
+ * bitwise what monc_mlp_features (cells = NULL, same orient) followed by
+ * monc_mlp_forward gives, but the features are gathered from the fields into
+ * the matrix operands directly and never stored.  state: host array of 4
+ * device pointers (u, v, w, theta); norm: host [8]; wpack 16-byte aligned. */
+int monc_mlp_infer(const double *const *state, int nx, int ny, int nz, const double *norm,
+                   int orient, const float *params, const uint16_t *wpack, float *Y,
+                   monc_stream_t stream);
 /* Parameter gradient grad[MONC_MLP_NPARAM] from dY[m][4] and the saved forward
  * activations; deterministic.  workspace >= monc_mlp_backward_workspace_bytes(m). */
 size_t monc_mlp_backward_workspace_bytes(int m);

@@ -58,6 +58,7 @@ _SIGS = {
     "monc_restrict4": ([ip, PP, PP, ip, ip, ip, vp, vp, vp, vp, vp, vp, vp], ip),
     "monc_mlp_features": ([PP, ip, ip, ip, DPTR, ip, vp, ip, vp, vp], ip),
     "monc_mlp_pack": ([vp, vp, vp], ip),
+    "monc_mlp_infer": ([PP, ip, ip, ip, DPTR, ip, vp, vp, vp, vp], ip),
     "monc_mlp_forward": ([vp, ip, vp, vp, vp, vp, vp, vp, vp, vp], ip),
     "monc_mlp_backward_workspace_bytes": ([ip], C.c_size_t),
     "monc_mlp_backward": ([vp, vp, vp, vp, vp, vp, ip, vp, vp, vp, vp], ip),
@@ -418,6 +419,15 @@ def monc_mlp_features(state, norm, orient, cells, X, stream=None):
 
 def monc_mlp_pack(params, wpack, stream=None):
     _check(lib().monc_mlp_pack(_ptr(params), _ptr(wpack), _stream(stream)), "monc_mlp_pack")
+
+
+def monc_mlp_infer(state, norm, orient, params, wpack, Y, stream=None):
+    torch = _torch()
+    nx, ny, nz = _grid(state[0])
+    sa = _ptrs(state, torch.float64, tuple(state[0].shape), "state")
+    _ptr(Y, torch.float32, (nx * ny * nz, 4), "Y")
+    _check(lib().monc_mlp_infer(sa, nx, ny, nz, _dbl(norm), int(orient), _ptr(params),
+                                _ptr(wpack), _ptr(Y), _stream(stream)), "monc_mlp_infer")
 
 
 def monc_mlp_forward(X, m, params, wpack, Y, H1=None, H2=None, Z1=None, Z2=None, stream=None):

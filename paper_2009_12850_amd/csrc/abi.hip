@@ -409,6 +409,21 @@ int monc_mlp_pack(const float* params, uint16_t* wpack, monc_stream_t stream) {
     return hip_status(launch_mlp_pack(params, wpack, (hipStream_t)stream), "mlp_pack");
 }
 
+int monc_mlp_infer(const double* const* state, int nx, int ny, int nz, const double* norm,
+                   int orient, const float* params, const uint16_t* wpack, float* Y,
+                   monc_stream_t stream) {
+    TRY(check_grid(nx, ny, nz));
+    TRY(check_ptrs(4, state, "state"));
+    if (!norm || !params || !wpack || !Y) return fail(MONC_EINVAL, "NULL pointer");
+    if (orient != 0 && orient != 1) return fail(MONC_EINVAL, "orient must be 0 or 1");
+    for (int f = 0; f < 4; f++)
+        if (!(norm[2 * f + 1] > 0)) return fail(MONC_EINVAL, "norm std %d must be > 0", f);
+    if ((uintptr_t)wpack & 15) return fail(MONC_EINVAL, "wpack must be 16-byte aligned");
+    return hip_status(launch_mlp_infer(state, nx, ny, nz, norm, orient, params, wpack, Y,
+                                       (hipStream_t)stream),
+                      "mlp_infer");
+}
+
 int monc_mlp_forward(const uint16_t* X, int m, const float* params, const uint16_t* wpack,
                      float* Y, uint16_t* H1, uint16_t* H2, float* Z1, float* Z2,
                      monc_stream_t stream) {

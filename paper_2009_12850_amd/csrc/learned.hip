@@ -279,6 +279,161 @@ __global__ void __launch_bounds__(256) mlp_forward(const uint16_t* __restrict__ 
 }
 
 // ---------------------------------------------------------------------------
+// Inference over every cell with the feature gather fused in: each lane builds
+// its MFMA operand fragments straight from the fields (no feature matrix in
+// memory), then the three layers run as in mlp_forward.  Workgroups are
+// persistent, so the weight pack is loaded into LDS once per workgroup.  The
+// features, products and sums are the same operations in the same order as
+// mlp_features followed by mlp_forward, so the outputs are bitwise the same.
+// ---------------------------------------------------------------------------
+struct InferArgs {
+    const double* f[4];
+    double mean[4], inv_std[4];
+    int nx, ny, nz;
+    long m;  // nx * ny * nz rows
+    const float* params;
+    const uint16_t* wpack;
+    float* Y;
+};
+
+// Field and element offset of feature n of a cell (n < NIN), from the wrapped
+// plane offsets xo, column offsets yo and clamped levels ko of that cell.
+template <int ORIENT>
+__device__ __forceinline__ void feature_at(int n, const long* xo, const long* yo, const int* ko,
+                                           int& src, long& off) {
+    const int f = n / 75, a5 = (n / 15) % 5, b5 = (n / 3) % 5, c3 = n % 3;
+    src = ORIENT ? (f == 0 ? 1 : (f == 1 ? 0 : f)) : f;
+    off = (ORIENT ? xo[b5] + yo[a5] : xo[a5] + yo[b5]) + ko[c3];
+}
+
+// The 20 operand fragments of row `row`: lanes 0-31 hold features 16kk..16kk+7
+// of each 16-wide block, lanes 32-63 (hi) features 16kk+8..16kk+15.
+template <int ORIENT>
+__device__ __forceinline__ void gather_fragments(const InferArgs& a, long row, bool hi,
+                                                 bf16x8_t* A) {
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const int k = (int)(row % nz);
+    const long col = row / nz;
+    const int j = (int)(col % ny), i = (int)(col / ny);
+    long xo[5], yo[5];
+    int ko[3];
+#pragma unroll
+    for (int d = 0; d < 5; d++) {
+        const int ii = ((i + d - 2) % nx + nx) % nx, jj = ((j + d - 2) % ny + ny) % ny;
+        xo[d] = (long)(ii + 2) * (ny + 4) * nz;
+        yo[d] = (long)(jj + 2) * nz;
+    }
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        const int kk = k + c - 1;
+        ko[c] = kk < 0 ? 0 : (kk > nz - 1 ? nz - 1 : kk);
+    }
+#pragma unroll
+    for (int kk = 0; kk < KP / 16; kk++) {
+        u16x8 t;
+#pragma unroll
+        for (int e = 0; e < 8; e++) {
+            const int n0 = 16 * kk + e, n1 = n0 + 8;
+            int s0 = 0, s1 = 0;
+            long o0 = 0, o1 = 0;
+            if (n0 < NIN) feature_at<ORIENT>(n0, xo, yo, ko, s0, o0);
+            if (n1 < NIN) feature_at<ORIENT>(n1, xo, yo, ko, s1, o1);
+            const bool z = hi ? n1 >= NIN : n0 >= NIN;
+            const int src = hi ? s1 : s0;
+            const double v = a.f[src][hi ? o1 : o0];
+            const uint16_t b = f2bf((float)((v - a.mean[src]) * a.inv_std[src]));
+            t.v[e] = z ? (uint16_t)0 : b;
+        }
+        A[kk] = __builtin_bit_cast(bf16x8_t, t);
+    }
+}
+
+template <int ORIENT>
+__global__ void __launch_bounds__(256) mlp_infer(InferArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    uint16_t* sw = reinterpret_cast<uint16_t*>(smem);  // pack
+    uint16_t* sH = sw + PK_SIZE;                          // [4][32][64]
+    float* sb = reinterpret_cast<float*>(sH + 4 * 32 * HID);
+    for (int t = threadIdx.x; t < PK_SIZE / 8; t += 256)
+        reinterpret_cast<uint4*>(sw)[t] = reinterpret_cast<const uint4*>(a.wpack)[t];
+    for (int t = threadIdx.x; t < 2 * HID + NO; t += 256)
+        sb[t] = t < HID ? a.params[OFF_B1 + t]
+                        : (t < 2 * HID ? a.params[OFF_B2 + t - HID] : a.params[OFF_B3 + t - 2 * HID]);
+    __syncthreads();
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int kh = 8 * (lane >> 5);
+    const bool hi = lane >= 32;
+    uint16_t* H = sH + w * 32 * HID;
+    const long ntiles = (a.m + FWD_ROWS - 1) / FWD_ROWS;
+    for (long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const long row0 = tile * FWD_ROWS + 32 * w;
+        const long ar = row0 + (lane & 31);
+        bf16x8_t A1[KP / 16];
+        if (ar < a.m) {
+            gather_fragments<ORIENT>(a, ar, hi, A1);
+        } else {
+#pragma unroll
+            for (int kk = 0; kk < KP / 16; kk++) A1[kk] = zero8();
+        }
+        // layer 1
+#pragma unroll
+        for (int nt = 0; nt < 2; nt++) {
+            f32x16_t acc = {};
+            for (int kk = 0; kk < KP / 16; kk++) {
+                const bf16x8_t bv = ld8(sw + PK_W1 + (32 * nt + (lane & 31)) * KP + 16 * kk + kh);
+                acc = mfma(A1[kk], bv, acc);
+            }
+#pragma unroll
+            for (int r = 0; r < 16; r++) {
+                const int lr = acc_row(r, lane), col = 32 * nt + (lane & 31);
+                H[lr * HID + col] = f2bf(gelu(acc[r] + sb[col]));
+            }
+        }
+        __syncthreads();
+        // layer 2
+        f32x16_t acc2[2];
+#pragma unroll
+        for (int nt = 0; nt < 2; nt++) {
+            f32x16_t acc = {};
+#pragma unroll
+            for (int kk = 0; kk < HID / 16; kk++) {
+                const bf16x8_t av = ld8(H + (lane & 31) * HID + 16 * kk + kh);
+                const bf16x8_t bv = ld8(sw + PK_W2 + (32 * nt + (lane & 31)) * HID + 16 * kk + kh);
+                acc = mfma(av, bv, acc);
+            }
+            acc2[nt] = acc;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int nt = 0; nt < 2; nt++) {
+#pragma unroll
+            for (int r = 0; r < 16; r++) {
+                const int lr = acc_row(r, lane), col = 32 * nt + (lane & 31);
+                H[lr * HID + col] = f2bf(gelu(acc2[nt][r] + sb[HID + col]));
+            }
+        }
+        __syncthreads();
+        // layer 3
+        f32x16_t acc = {};
+#pragma unroll
+        for (int kk = 0; kk < HID / 16; kk++) {
+            const bf16x8_t av = ld8(H + (lane & 31) * HID + 16 * kk + kh);
+            const bf16x8_t bv = ld8(sw + PK_W3 + (lane & 31) * HID + 16 * kk + kh);
+            acc = mfma(av, bv, acc);
+        }
+        const int col = lane & 31;
+        if (col < NO) {
+#pragma unroll
+            for (int r = 0; r < 16; r++) {
+                const long row = row0 + acc_row(r, lane);
+                if (row < a.m) a.Y[(size_t)row * NO + col] = acc[r] + sb[2 * HID + col];
+            }
+        }
+        __syncthreads();  // H is rewritten by the next tile
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Backward: 64 rows per workgroup (4 waves); per-workgroup partial gradients
 // of every parameter, reduced afterwards in a fixed order.
 // ---------------------------------------------------------------------------
@@ -807,6 +962,46 @@ hipError_t launch_mlp_forward(const uint16_t* X, int m, const float* params,
     }
     mlp_forward<<<(m + FWD_ROWS - 1) / FWD_ROWS, 256, FWD_LDS, s>>>(X, m, params, wpack, Y, H1, H2,
                                                                     Z1, Z2);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_infer(const double* const* state, int nx, int ny, int nz,
+                           const double* norm, int orient, const float* params,
+                           const uint16_t* wpack, float* Y, hipStream_t s) {
+    static bool attr[2] = {false, false};
+    static int ncu = 0;
+    const void* kern = orient ? (const void*)mlp_infer<1> : (const void*)mlp_infer<0>;
+    if (!attr[orient]) {
+        hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)FWD_LDS);
+        if (e != hipSuccess) return e;
+        attr[orient] = true;
+    }
+    if (ncu == 0) {
+        int dev = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) return e;
+    }
+    InferArgs a;
+    for (int f = 0; f < 4; f++) {
+        a.f[f] = state[f];
+        a.mean[f] = norm[2 * f];
+        a.inv_std[f] = 1.0 / norm[2 * f + 1];
+    }
+    a.nx = nx;
+    a.ny = ny;
+    a.nz = nz;
+    a.m = (long)nx * ny * nz;
+    a.params = params;
+    a.wpack = wpack;
+    a.Y = Y;
+    const long ntiles = (a.m + FWD_ROWS - 1) / FWD_ROWS;
+    const int grid = (int)(ntiles < 2L * ncu ? ntiles : 2L * ncu);
+    if (orient)
+        mlp_infer<1><<<grid, 256, FWD_LDS, s>>>(a);
+    else
+        mlp_infer<0><<<grid, 256, FWD_LDS, s>>>(a);
     return hipGetLastError();
 }
 

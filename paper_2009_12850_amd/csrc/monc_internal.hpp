@@ -56,6 +56,9 @@ hipError_t launch_restrict4(int nscal, const double* const* fine, double* const*
 hipError_t launch_features(const double* const* state, int nx, int ny, int nz, const double* norm,
                            int orient, const int* cells, long ncells, uint16_t* X, hipStream_t s);
 hipError_t launch_mlp_pack(const float* params, uint16_t* wpack, hipStream_t s);
+hipError_t launch_mlp_infer(const double* const* state, int nx, int ny, int nz,
+                           const double* norm, int orient, const float* params,
+                           const uint16_t* wpack, float* Y, hipStream_t s);
 hipError_t launch_mlp_forward(const uint16_t* X, int m, const float* params,
                               const uint16_t* wpack, float* Y, uint16_t* H1, uint16_t* H2,
                               float* Z1, float* Z2, hipStream_t s);

@@ -31,6 +31,7 @@ from __future__ import annotations
 
 import dataclasses
 import math
+import threading
 
 import numpy as np
 
@@ -80,6 +81,13 @@ def _draw_modes(rng: np.random.Generator, nmodes: int = 8):
     return modes
 
 
+# The field generators run in threads; their one BLAS call (the matrix product
+# below) is made one at a time, since concurrent calls into a multithreaded
+# BLAS from several Python threads have returned corrupted products on hosts
+# with many cores, which made the generated fields depend on thread timing.
+_BLAS_LOCK = threading.Lock()
+
+
 def _mode_sum(g: Geometry, modes, xs: np.ndarray, ys: np.ndarray,
               zs: np.ndarray, vertical_sine: bool) -> np.ndarray:
     """Normalised sum of the modes at positions xs (nx), ys (ny), zs (nz)."""
@@ -97,7 +105,9 @@ def _mode_sum(g: Geometry, modes, xs: np.ndarray, ys: np.ndarray,
         else:
             vert[n] = np.cos(math.pi * m * zs / H_TOP)
     total_r = sum(md[4] for md in modes)
-    return (horiz @ vert).reshape(g.nx, g.ny, g.nz) / total_r
+    with _BLAS_LOCK:
+        prod = horiz @ vert
+    return prod.reshape(g.nx, g.ny, g.nz) / total_r
 
 
 def scalar_names(nscal: int):

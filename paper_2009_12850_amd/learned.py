@@ -271,7 +271,6 @@ class CoarseRunner:
         NX, NY, NZ = shape[0] - 4, shape[1] - 4, shape[2]
         self.N = NX * NY * NZ
         if model is not None:
-            self.X = torch.zeros((2 * self.N, M.MONC_MLP_K), dtype=torch.int16, device=dev)
             self.G = torch.zeros((2 * self.N, 4), dtype=torch.float32, device=dev)
             self.flags = torch.zeros(4, dtype=torch.int32, device=dev)
             self.ws = torch.zeros(M.monc_correct_step_workspace_bytes(NX, NY, NZ),
@@ -284,9 +283,8 @@ class CoarseRunner:
             return
         mdl, N = self.model, self.N
         M.monc_advect(M.MONC_F64, A, self.tend, s.dxc, s.dxc, s.prof_c, s.dtc)
-        M.monc_mlp_features(A, mdl.norm, 0, None, self.X.narrow(0, 0, N))
-        M.monc_mlp_features(A, mdl.norm, 1, None, self.X.narrow(0, N, N))
-        M.monc_mlp_forward(self.X, 2 * N, mdl.params, mdl.wpack, self.G)
+        M.monc_mlp_infer(A, mdl.norm, 0, mdl.params, mdl.wpack, self.G.narrow(0, 0, N))
+        M.monc_mlp_infer(A, mdl.norm, 1, mdl.params, mdl.wpack, self.G.narrow(0, N, N))
         M.monc_correct_step(A, self.tend, self.G.narrow(0, 0, N), self.G.narrow(0, N, N), B,
                             s.dxc, s.dxc, mdl.scale, s.prof_c, s.dtc, self.growth, self.flags,
                             self.ws)
@@ -417,15 +415,18 @@ def run_experiment(nx=512, ny=512, nz=128, seeds=range(2000, 2016), n_train=12, 
             else:
                 t_learned += ms / len(held)
                 fb = [a + b for a, b in zip(fb, runner.fallbacks())]
-    # MLP forward alone on one coarse step's rows
+    # the fused gather + MLP over one coarse step's rows (both face orientations)
     runner = CoarseRunner(held[0], model, growth=growth)
     N = runner.N
-    M.monc_mlp_features(held[0].snaps[0], model.norm, 0, None, runner.X.narrow(0, 0, N))
-    M.monc_mlp_features(held[0].snaps[0], model.norm, 1, None, runner.X.narrow(0, N, N))
-    M.monc_mlp_forward(runner.X, 2 * N, model.params, model.wpack, runner.G)
+    A0 = held[0].snaps[0]
+
+    def infer():
+        M.monc_mlp_infer(A0, model.norm, 0, model.params, model.wpack, runner.G.narrow(0, 0, N))
+        M.monc_mlp_infer(A0, model.norm, 1, model.params, model.wpack, runner.G.narrow(0, N, N))
+
+    infer()
     reps = 20
-    fwd_ms = _event_ms(lambda: [M.monc_mlp_forward(runner.X, 2 * N, model.params, model.wpack,
-                                                   runner.G) for _ in range(reps)]) / reps
+    fwd_ms = _event_ms(lambda: [infer() for _ in range(reps)]) / reps
     flop = 2.0 * (M.MONC_MLP_NIN * M.MONC_MLP_H + M.MONC_MLP_H * M.MONC_MLP_H +
                   M.MONC_MLP_H * M.MONC_MLP_NOUT)
     mean = lambda errs: [float(np.mean([e[q] for e in errs])) for q in range(4)]
@@ -441,6 +442,6 @@ def run_experiment(nx=512, ny=512, nz=128, seeds=range(2000, 2016), n_train=12, 
         "fallback_nonfinite": fb[0], "fallback_growth": fb[1], "theta_faces_clamped": fb[2],
         "t_fine_ms": t_fine, "t_coarse_plain_ms": t_plain, "t_coarse_learned_ms": t_learned,
         "speedup_vs_fine": t_fine / t_learned,
-        "mlp_forward_ms": fwd_ms, "mlp_rows": 2 * N,
+        "mlp_infer_ms": fwd_ms, "mlp_rows": 2 * N,
         "mlp_tflops": 2 * N * flop / (fwd_ms * 1e-3) / 1e12,
     }

@@ -394,3 +394,28 @@ def test_experiment_driver_small():
     assert r["held_out_loss_trained"] < r["held_out_loss_no_correction"]
     assert r["fallback_nonfinite"] == 0
     assert r["t_fine_ms"] > 0 and r["t_coarse_learned_ms"] > 0 and r["mlp_tflops"] > 0
+
+
+@pytest.mark.parametrize("shape", [(12, 10, 7), (16, 16, 8), (5, 3, 33)])
+@pytest.mark.parametrize("orient", [0, 1])
+def test_fused_inference_equals_features_then_forward(shape, orient):
+    """The fused gather + MLP kernel gives bitwise the outputs of the feature
+    gather followed by the forward pass, over every cell."""
+    NX, NY, NZ = shape
+    say(f"infer {shape} orient={orient}")
+    T = torch()
+    s = to_dev(coarse_state(NX, NY, NZ, 60 + NZ))
+    norm = [1.0, 3.0, -0.5, 2.0, 0.0, 0.7, 300.0, 0.5]
+    p = T.from_numpy(R.init_params(13).astype(np.float32)).to(dev())
+    p[R.H * R.K:R.H * R.K + R.H] = 0.05
+    wp = T.zeros(M.MONC_MLP_WPACK, dtype=T.int16, device=dev())
+    M.monc_mlp_pack(p, wp)
+    n = NX * NY * NZ
+    X = T.zeros((n, R.K), dtype=T.int16, device=dev())
+    M.monc_mlp_features(s, norm, orient, None, X)
+    Y1 = T.zeros((n, 4), dtype=T.float32, device=dev())
+    M.monc_mlp_forward(X, n, p, wp, Y1)
+    Y2 = T.full((n, 4), float("nan"), dtype=T.float32, device=dev())
+    M.monc_mlp_infer(s, norm, orient, p, wp, Y2)
+    T.cuda.synchronize()
+    assert T.equal(Y1, Y2)
