@@ -244,10 +244,11 @@ int monc_ensemble_destroy(monc_ensemble *plan);
  * Evaluation and training use BF16 MFMA with FP32 accumulation; FP32 master
  * weights; Adam.  The plain step is the fallback.
  *
- * Feature order: index ((f*5 + a)*5 + b)*3 + c for field f in (u, v, w,
+ * Feature order: index f*80 + (a*5 + b)*3 + c for field f in (u, v, w,
  * theta), a = offset along the face normal + 2, b = tangential offset + 2, c =
  * vertical offset + 1; periodic in x and y, edge-replicated in z; orient 1
- * (y-faces) exchanges x and y and swaps u and v; entries 300..319 are 0.
+ * (y-faces) exchanges x and y and swaps u and v; slots f*80 + 75..79 are 0
+ * (300 values in 320 slots; W1 columns follow the same order).
  * Parameter vector (FP32, MONC_MLP_NPARAM): W1[64][320] | b1[64] |
  * W2[64][64] (W2[out][in]) | b2[64] | W3[4][64] | b3[4].
  * BF16 weight pack (MONC_MLP_WPACK uint16): W1 | W2 | W3 padded to [32][64].

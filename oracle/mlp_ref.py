@@ -15,9 +15,10 @@ FP64 and, when `emulate` is set, rounds to BF16 exactly where the GPU kernels
 do: the input features, the weights, the hidden activations, and the
 back-propagated pre-activation gradients that feed matrix products.
 
-Feature order: index ((f*5 + a)*5 + b)*3 + c for field f (u, v, w, theta),
+Feature order: index f*80 + (a*5 + b)*3 + c for field f (u, v, w, theta),
 a = offset along the face normal + 2, b = tangential offset + 2, c = vertical
-offset + 1; periodic in x and y, edge-replicated in z; indices 300..319 are 0.
+offset + 1; periodic in x and y, edge-replicated in z; each field's slots
+75..79 are 0 (300 values in 320 slots).
 """
 from __future__ import annotations
 
@@ -27,8 +28,11 @@ import numpy as np
 from scipy.special import erf
 
 NIN, K, H, NOUT = 300, 320, 64, 4
+FSTRIDE = 80                      # slots per field; 75 used
 NPARAM = H * K + H + H * H + H + NOUT * H + NOUT
 SWAP = [1, 0, 2, 3]
+USED = np.array([f * FSTRIDE + p for f in range(4) for p in range(75)])
+PAD = np.array([f * FSTRIDE + p for f in range(4) for p in range(75, FSTRIDE)])
 
 
 def bf16(x):
@@ -66,10 +70,10 @@ def pack(W1, b1, W2, b2, W3, b3):
 
 
 def init_params(seed):
-    """Weights ~ N(0, 1/fan_in), biases 0; padded input columns 300..319 zero."""
+    """Weights ~ N(0, 1/fan_in), biases 0; padded input columns zero."""
     rng = np.random.default_rng(seed)
     W1 = rng.standard_normal((H, K)) / math.sqrt(NIN)
-    W1[:, NIN:] = 0.0
+    W1[:, PAD] = 0.0
     W2 = rng.standard_normal((H, H)) / math.sqrt(H)
     W3 = rng.standard_normal((NOUT, H)) / math.sqrt(H)
     return pack(W1, np.zeros(H), W2, np.zeros(H), W3, np.zeros(NOUT))
@@ -98,7 +102,7 @@ def features(state, norm, orient, cells):
                     ii = (i + di) % NX
                     jj = (j + dj) % NY
                     kk = np.clip(k + c - 1, 0, NZ - 1)
-                    X[:, ((f * 5 + a) * 5 + b) * 3 + c] = (src[ii, jj, kk] - mean) / std
+                    X[:, f * FSTRIDE + (a * 5 + b) * 3 + c] = (src[ii, jj, kk] - mean) / std
     return X
 
 

@@ -59,11 +59,38 @@ __device__ __forceinline__ f32x16_t mfma(bf16x8_t a, bf16x8_t b, f32x16_t c) {
 __device__ __forceinline__ int acc_row(int r, int lane) { return 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3); }
 
 // GELU(z) = z Phi(z) with Phi(z) = erfc(-z/sqrt 2)/2, which keeps its relative
-// accuracy for negative z (1 + erf(z/sqrt 2) cancels there).
-__device__ __forceinline__ float gelu(float z) { return 0.5f * z * erfcf(-z * 0.70710678118654752f); }
-__device__ __forceinline__ float gelu_grad(float z) {
-    return 0.5f * erfcf(-z * 0.70710678118654752f) + z * expf(-0.5f * z * z) * 0.39894228040143268f;
+// accuracy for negative z (1 + erf(z/sqrt 2) cancels there).  erfc is the
+// Chebyshev fit of Numerical Recipes (Press et al., 2nd ed., Sec. 6.2,
+// fractional error below 1.2e-7 for all x): branch-free, one exponential and
+// one reciprocal, far below the BF16 rounding that follows.
+__device__ __forceinline__ float erfc_cheb(float x) {
+    const float ax = fabsf(x);
+    const float t = __builtin_amdgcn_rcpf(1.0f + 0.5f * ax);  // v_rcp_f32, about 1 ulp
+    float p = 0.17087277f;
+    p = fmaf(p, t, -0.82215223f);
+    p = fmaf(p, t, 1.48851587f);
+    p = fmaf(p, t, -1.13520398f);
+    p = fmaf(p, t, 0.27886807f);
+    p = fmaf(p, t, -0.18628806f);
+    p = fmaf(p, t, 0.09678418f);
+    p = fmaf(p, t, 0.37409196f);
+    p = fmaf(p, t, 1.00002368f);
+    p = fmaf(p, t, -1.26551223f);
+    const float r = t * __expf(p - ax * ax);
+    return x >= 0.0f ? r : 2.0f - r;
 }
+__device__ __forceinline__ float gelu(float z) { return 0.5f * z * erfc_cheb(-z * 0.70710678118654752f); }
+__device__ __forceinline__ float gelu_grad(float z) {
+    return 0.5f * erfc_cheb(-z * 0.70710678118654752f) +
+           z * __expf(-0.5f * z * z) * 0.39894228040143268f;
+}
+
+// MFMA k-assignment of the first layer: in 16-wide block kk, lanes 0-31 take
+// 8 consecutive slots of one field and lanes 32-63 the same 8 slots of the
+// next field (fields u, v for kk < 10, w, theta after), so both halves of a
+// row share their neighbourhood offsets.  With 80 slots per field the 8
+// values are one aligned 16-byte chunk of a feature row or weight row.
+__device__ __forceinline__ int kslot(int kk, int h) { return (2 * (kk / 10) + h) * 80 + 8 * (kk % 10); }
 
 // ---------------------------------------------------------------------------
 // 4x restriction: mass-weighted scalars, mass-flux-weighted face means for u,
@@ -144,8 +171,9 @@ __global__ void __launch_bounds__(256) features_kernel(FeatArgs a) {
     const int n = (int)(t - row * KP);
     uint16_t out = 0;
     const int cell = a.cells ? a.cells[row] : (int)row;
-    if (n < NIN && (unsigned)cell < (unsigned)(a.nx * a.ny * a.nz)) {
-        const int f = n / 75, a5 = (n / 15) % 5, b5 = (n / 3) % 5, c3 = n % 3;
+    const int f = n / 80, pos = n % 80;
+    if (pos < 75 && (unsigned)cell < (unsigned)(a.nx * a.ny * a.nz)) {
+        const int a5 = pos / 15, b5 = (pos / 3) % 5, c3 = pos % 3;
         const int k = cell % a.nz, j = (cell / a.nz) % a.ny, i = cell / (a.nz * a.ny);
         const int src = a.orient ? (f == 0 ? 1 : (f == 1 ? 0 : f)) : f;
         const int di = a.orient ? b5 - 2 : a5 - 2;
@@ -185,7 +213,28 @@ __global__ void __launch_bounds__(256) pack_kernel(const float* __restrict__ p, 
 // Y = H2 W3^T + b3, with BF16 operands (X, W, H, H2) and FP32 accumulation.
 // ---------------------------------------------------------------------------
 constexpr int FWD_ROWS = 128;
-constexpr size_t FWD_LDS = (size_t)PK_SIZE * 2 + 4 * 32 * HID * 2 + (2 * HID + NO) * 4;
+// LDS copies of the weights and the hidden activations use row strides padded
+// by 8 elements (16 bytes): with the unpadded strides (640 and 128 bytes) all
+// 32 rows that a 16-byte fragment load touches fall on the same LDS banks.
+constexpr int LW1 = KP + 8, LWH = HID + 8;
+constexpr int S_W1 = 0, S_W2 = HID * LW1, S_W3 = S_W2 + HID * LWH, S_WEND = S_W3 + 32 * LWH;
+constexpr size_t FWD_LDS = (size_t)S_WEND * 2 + 4 * 32 * LWH * 2 + (2 * HID + NO) * 4;
+
+// Global weight pack -> padded LDS copy, 16 bytes per thread and step.
+__device__ __forceinline__ void load_pack_padded(const uint16_t* __restrict__ wpack, uint16_t* sw) {
+    for (int t = threadIdx.x; t < PK_SIZE / 8; t += blockDim.x) {
+        const int g = 8 * t;
+        int d;
+        if (g < PK_W2) {
+            d = S_W1 + (g / KP) * LW1 + g % KP;
+        } else if (g < PK_W3) {
+            d = S_W2 + ((g - PK_W2) / HID) * LWH + (g - PK_W2) % HID;
+        } else {
+            d = S_W3 + ((g - PK_W3) / HID) * LWH + (g - PK_W3) % HID;
+        }
+        *reinterpret_cast<uint4*>(sw + d) = reinterpret_cast<const uint4*>(wpack)[t];
+    }
+}
 
 __global__ void __launch_bounds__(256) mlp_forward(const uint16_t* __restrict__ X, int m,
                                                    const float* __restrict__ params,
@@ -194,10 +243,9 @@ __global__ void __launch_bounds__(256) mlp_forward(const uint16_t* __restrict__ 
                                                    uint16_t* H2o, float* Z1o, float* Z2o) {
     extern __shared__ __align__(16) unsigned char smem[];
     uint16_t* sw = reinterpret_cast<uint16_t*>(smem);  // pack
-    uint16_t* sH = sw + PK_SIZE;                          // [4][32][64]
-    float* sb = reinterpret_cast<float*>(sH + 4 * 32 * HID);
-    for (int t = threadIdx.x; t < PK_SIZE / 8; t += 256)
-        reinterpret_cast<uint4*>(sw)[t] = reinterpret_cast<const uint4*>(wpack)[t];
+    uint16_t* sH = sw + S_WEND;                           // [4][32][LWH]
+    float* sb = reinterpret_cast<float*>(sH + 4 * 32 * LWH);
+    load_pack_padded(wpack, sw);
     for (int t = threadIdx.x; t < 2 * HID + NO; t += 256)
         sb[t] = t < HID ? params[OFF_B1 + t] : (t < 2 * HID ? params[OFF_B2 + t - HID] : params[OFF_B3 + t - 2 * HID]);
     __syncthreads();
@@ -205,24 +253,28 @@ __global__ void __launch_bounds__(256) mlp_forward(const uint16_t* __restrict__ 
     const int row0 = blockIdx.x * FWD_ROWS + 32 * w;
     const int ar = row0 + (lane & 31);  // A-operand row of this lane
     const int kh = 8 * (lane >> 5);
-    uint16_t* H = sH + w * 32 * HID;
+    uint16_t* H = sH + w * 32 * LWH;
 
     // layer 1
+    const int h = lane >> 5;
+    f32x16_t acc1[2] = {{}, {}};
+    for (int kk = 0; kk < KP / 16; kk++) {
+        const int ks = kslot(kk, h);
+        const bf16x8_t av = ar < m ? ld8(X + (size_t)ar * KP + ks) : zero8();
+#pragma unroll
+        for (int nt = 0; nt < 2; nt++)
+            acc1[nt] = mfma(av, ld8(sw + S_W1 + (32 * nt + (lane & 31)) * LW1 + ks), acc1[nt]);
+    }
 #pragma unroll
     for (int nt = 0; nt < 2; nt++) {
-        f32x16_t acc = {};
-        for (int kk = 0; kk < KP / 16; kk++) {
-            const bf16x8_t av = ar < m ? ld8(X + (size_t)ar * KP + 16 * kk + kh) : zero8();
-            const bf16x8_t bv = ld8(sw + PK_W1 + (32 * nt + (lane & 31)) * KP + 16 * kk + kh);
-            acc = mfma(av, bv, acc);
-        }
+        const f32x16_t acc = acc1[nt];
 #pragma unroll
         for (int r = 0; r < 16; r++) {
             const int lr = acc_row(r, lane), col = 32 * nt + (lane & 31);
             const int row = row0 + lr;
             const float z = acc[r] + sb[col];
             const uint16_t h = f2bf(gelu(z));
-            H[lr * HID + col] = h;
+            H[lr * LWH + col] = h;
             if (row < m) {
                 if (Z1o) Z1o[(size_t)row * HID + col] = z;
                 if (H1o) H1o[(size_t)row * HID + col] = h;
@@ -237,8 +289,8 @@ __global__ void __launch_bounds__(256) mlp_forward(const uint16_t* __restrict__ 
         f32x16_t acc = {};
 #pragma unroll
         for (int kk = 0; kk < HID / 16; kk++) {
-            const bf16x8_t av = ld8(H + (lane & 31) * HID + 16 * kk + kh);
-            const bf16x8_t bv = ld8(sw + PK_W2 + (32 * nt + (lane & 31)) * HID + 16 * kk + kh);
+            const bf16x8_t av = ld8(H + (lane & 31) * LWH + 16 * kk + kh);
+            const bf16x8_t bv = ld8(sw + S_W2 + (32 * nt + (lane & 31)) * LWH + 16 * kk + kh);
             acc = mfma(av, bv, acc);
         }
         acc2[nt] = acc;
@@ -252,7 +304,7 @@ __global__ void __launch_bounds__(256) mlp_forward(const uint16_t* __restrict__ 
             const int row = row0 + lr;
             const float z = acc2[nt][r] + sb[HID + col];
             const uint16_t h = f2bf(gelu(z));
-            H[lr * HID + col] = h;
+            H[lr * LWH + col] = h;
             if (row < m) {
                 if (Z2o) Z2o[(size_t)row * HID + col] = z;
                 if (H2o) H2o[(size_t)row * HID + col] = h;
@@ -264,8 +316,8 @@ __global__ void __launch_bounds__(256) mlp_forward(const uint16_t* __restrict__ 
     f32x16_t acc = {};
 #pragma unroll
     for (int kk = 0; kk < HID / 16; kk++) {
-        const bf16x8_t av = ld8(H + (lane & 31) * HID + 16 * kk + kh);
-        const bf16x8_t bv = ld8(sw + PK_W3 + (lane & 31) * HID + 16 * kk + kh);
+        const bf16x8_t av = ld8(H + (lane & 31) * LWH + 16 * kk + kh);
+        const bf16x8_t bv = ld8(sw + S_W3 + (lane & 31) * LWH + 16 * kk + kh);
         acc = mfma(av, bv, acc);
     }
     const int col = lane & 31;
@@ -296,97 +348,104 @@ struct InferArgs {
     float* Y;
 };
 
-// Field and element offset of feature n of a cell (n < NIN), from the wrapped
-// plane offsets xo, column offsets yo and clamped levels ko of that cell.
-template <int ORIENT>
-__device__ __forceinline__ void feature_at(int n, const long* xo, const long* yo, const int* ko,
-                                           int& src, long& off) {
-    const int f = n / 75, a5 = (n / 15) % 5, b5 = (n / 3) % 5, c3 = n % 3;
-    src = ORIENT ? (f == 0 ? 1 : (f == 1 ? 0 : f)) : f;
-    off = (ORIENT ? xo[b5] + yo[a5] : xo[a5] + yo[b5]) + ko[c3];
-}
+// Per-row gather state: wrapped plane offsets xo, column offsets yo, clamped
+// levels ko of the row's cell, and this lane's field of each pair (lanes 0-31:
+// u then w; lanes 32-63: v then theta, exchanged with u/v for y-faces).
+struct RowGather {
+    long xo[5], yo[5];
+    int ko[3];
+    const double* f[2];
+    double mean[2], inv[2];
+};
 
-// The 20 operand fragments of row `row`: lanes 0-31 hold features 16kk..16kk+7
-// of each 16-wide block, lanes 32-63 (hi) features 16kk+8..16kk+15.
 template <int ORIENT>
-__device__ __forceinline__ void gather_fragments(const InferArgs& a, long row, bool hi,
-                                                 bf16x8_t* A) {
+__device__ __forceinline__ void row_setup(const InferArgs& a, long row, int h, RowGather& g) {
     const int nx = a.nx, ny = a.ny, nz = a.nz;
     const int k = (int)(row % nz);
     const long col = row / nz;
     const int j = (int)(col % ny), i = (int)(col / ny);
-    long xo[5], yo[5];
-    int ko[3];
 #pragma unroll
     for (int d = 0; d < 5; d++) {
         const int ii = ((i + d - 2) % nx + nx) % nx, jj = ((j + d - 2) % ny + ny) % ny;
-        xo[d] = (long)(ii + 2) * (ny + 4) * nz;
-        yo[d] = (long)(jj + 2) * nz;
+        // y-faces exchange the roles of x and y
+        const long xoff = (long)(ii + 2) * (ny + 4) * nz, yoff = (long)(jj + 2) * nz;
+        g.xo[d] = ORIENT ? yoff : xoff;
+        g.yo[d] = ORIENT ? xoff : yoff;
     }
 #pragma unroll
     for (int c = 0; c < 3; c++) {
         const int kk = k + c - 1;
-        ko[c] = kk < 0 ? 0 : (kk > nz - 1 ? nz - 1 : kk);
+        g.ko[c] = kk < 0 ? 0 : (kk > nz - 1 ? nz - 1 : kk);
     }
 #pragma unroll
-    for (int kk = 0; kk < KP / 16; kk++) {
-        u16x8 t;
+    for (int pr = 0; pr < 2; pr++) {
+        const int fi = 2 * pr + h;                                  // feature field
+        const int src = ORIENT ? (fi == 0 ? 1 : (fi == 1 ? 0 : fi)) : fi;  // stored field
+        g.f[pr] = a.f[src];
+        g.mean[pr] = a.mean[src];
+        g.inv[pr] = a.inv_std[src];
+    }
+}
+
+// Operand fragment of block kk: slots 8(kk%10) .. +7 of this lane's field of
+// pair kk/10; slot p < 75 is neighbour (a, b, c) = (p/15, (p/3)%5, p%3).
+__device__ __forceinline__ bf16x8_t row_fragment(const RowGather& g, int kk) {
+    const int pr = kk / 10, p0 = 8 * (kk % 10);
+    u16x8 t;
 #pragma unroll
-        for (int e = 0; e < 8; e++) {
-            const int n0 = 16 * kk + e, n1 = n0 + 8;
-            int s0 = 0, s1 = 0;
-            long o0 = 0, o1 = 0;
-            if (n0 < NIN) feature_at<ORIENT>(n0, xo, yo, ko, s0, o0);
-            if (n1 < NIN) feature_at<ORIENT>(n1, xo, yo, ko, s1, o1);
-            const bool z = hi ? n1 >= NIN : n0 >= NIN;
-            const int src = hi ? s1 : s0;
-            const double v = a.f[src][hi ? o1 : o0];
-            const uint16_t b = f2bf((float)((v - a.mean[src]) * a.inv_std[src]));
-            t.v[e] = z ? (uint16_t)0 : b;
+    for (int e = 0; e < 8; e++) {
+        const int pos = p0 + e;
+        if (pos < 75) {
+            const int a5 = pos / 15, b5 = (pos / 3) % 5, c3 = pos % 3;
+            const double v = g.f[pr][g.xo[a5] + g.yo[b5] + g.ko[c3]];
+            t.v[e] = f2bf((float)((v - g.mean[pr]) * g.inv[pr]));
+        } else {
+            t.v[e] = 0;
         }
-        A[kk] = __builtin_bit_cast(bf16x8_t, t);
     }
+    return __builtin_bit_cast(bf16x8_t, t);
 }
 
 template <int ORIENT>
 __global__ void __launch_bounds__(256) mlp_infer(InferArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     uint16_t* sw = reinterpret_cast<uint16_t*>(smem);  // pack
-    uint16_t* sH = sw + PK_SIZE;                          // [4][32][64]
-    float* sb = reinterpret_cast<float*>(sH + 4 * 32 * HID);
-    for (int t = threadIdx.x; t < PK_SIZE / 8; t += 256)
-        reinterpret_cast<uint4*>(sw)[t] = reinterpret_cast<const uint4*>(a.wpack)[t];
+    uint16_t* sH = sw + S_WEND;                           // [4][32][LWH]
+    float* sb = reinterpret_cast<float*>(sH + 4 * 32 * LWH);
+    load_pack_padded(a.wpack, sw);
     for (int t = threadIdx.x; t < 2 * HID + NO; t += 256)
         sb[t] = t < HID ? a.params[OFF_B1 + t]
                         : (t < 2 * HID ? a.params[OFF_B2 + t - HID] : a.params[OFF_B3 + t - 2 * HID]);
     __syncthreads();
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int kh = 8 * (lane >> 5);
-    const bool hi = lane >= 32;
-    uint16_t* H = sH + w * 32 * HID;
+    const int h = lane >> 5;
+    uint16_t* H = sH + w * 32 * LWH;
     const long ntiles = (a.m + FWD_ROWS - 1) / FWD_ROWS;
     for (long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const long row0 = tile * FWD_ROWS + 32 * w;
         const long ar = row0 + (lane & 31);
-        bf16x8_t A1[KP / 16];
-        if (ar < a.m) {
-            gather_fragments<ORIENT>(a, ar, hi, A1);
-        } else {
+        const bool live = ar < a.m;
+        RowGather g;
+        row_setup<ORIENT>(a, live ? ar : 0, h, g);
+        // layer 1: fragments built block by block straight from the fields
+        f32x16_t acc1[2] = {{}, {}};
+        // fully unrolled: every slot index is then a constant and the gather
+        // state stays in registers
 #pragma unroll
-            for (int kk = 0; kk < KP / 16; kk++) A1[kk] = zero8();
+        for (int kk = 0; kk < KP / 16; kk++) {
+            const int ks = kslot(kk, h);
+            const bf16x8_t av = live ? row_fragment(g, kk) : zero8();
+#pragma unroll
+            for (int nt = 0; nt < 2; nt++)
+                acc1[nt] = mfma(av, ld8(sw + S_W1 + (32 * nt + (lane & 31)) * LW1 + ks), acc1[nt]);
         }
-        // layer 1
 #pragma unroll
         for (int nt = 0; nt < 2; nt++) {
-            f32x16_t acc = {};
-            for (int kk = 0; kk < KP / 16; kk++) {
-                const bf16x8_t bv = ld8(sw + PK_W1 + (32 * nt + (lane & 31)) * KP + 16 * kk + kh);
-                acc = mfma(A1[kk], bv, acc);
-            }
 #pragma unroll
             for (int r = 0; r < 16; r++) {
                 const int lr = acc_row(r, lane), col = 32 * nt + (lane & 31);
-                H[lr * HID + col] = f2bf(gelu(acc[r] + sb[col]));
+                H[lr * LWH + col] = f2bf(gelu(acc1[nt][r] + sb[col]));
             }
         }
         __syncthreads();
@@ -397,8 +456,8 @@ __global__ void __launch_bounds__(256) mlp_infer(InferArgs a) {
             f32x16_t acc = {};
 #pragma unroll
             for (int kk = 0; kk < HID / 16; kk++) {
-                const bf16x8_t av = ld8(H + (lane & 31) * HID + 16 * kk + kh);
-                const bf16x8_t bv = ld8(sw + PK_W2 + (32 * nt + (lane & 31)) * HID + 16 * kk + kh);
+                const bf16x8_t av = ld8(H + (lane & 31) * LWH + 16 * kk + kh);
+                const bf16x8_t bv = ld8(sw + S_W2 + (32 * nt + (lane & 31)) * LWH + 16 * kk + kh);
                 acc = mfma(av, bv, acc);
             }
             acc2[nt] = acc;
@@ -409,7 +468,7 @@ __global__ void __launch_bounds__(256) mlp_infer(InferArgs a) {
 #pragma unroll
             for (int r = 0; r < 16; r++) {
                 const int lr = acc_row(r, lane), col = 32 * nt + (lane & 31);
-                H[lr * HID + col] = f2bf(gelu(acc2[nt][r] + sb[HID + col]));
+                H[lr * LWH + col] = f2bf(gelu(acc2[nt][r] + sb[HID + col]));
             }
         }
         __syncthreads();
@@ -417,8 +476,8 @@ __global__ void __launch_bounds__(256) mlp_infer(InferArgs a) {
         f32x16_t acc = {};
 #pragma unroll
         for (int kk = 0; kk < HID / 16; kk++) {
-            const bf16x8_t av = ld8(H + (lane & 31) * HID + 16 * kk + kh);
-            const bf16x8_t bv = ld8(sw + PK_W3 + (lane & 31) * HID + 16 * kk + kh);
+            const bf16x8_t av = ld8(H + (lane & 31) * LWH + 16 * kk + kh);
+            const bf16x8_t bv = ld8(sw + S_W3 + (lane & 31) * LWH + 16 * kk + kh);
             acc = mfma(av, bv, acc);
         }
         const int col = lane & 31;

@@ -184,13 +184,11 @@ __device__ __forceinline__ float to_compute<bf16, float>(bf16 x) {
 }
 
 __device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
-    uint32_t b = __float_as_uint(f);
-    if ((b & 0x7f800000u) == 0x7f800000u) {  // inf / nan: keep, force quiet nan
-        return (uint16_t)((b >> 16) | ((b & 0xffffu) ? 0x40u : 0u));
-    }
-    uint32_t lsb = (b >> 16) & 1u;
-    b += 0x7fffu + lsb;
-    return (uint16_t)(b >> 16);
+    const uint32_t b = __float_as_uint(f);
+    const uint32_t rounded = (b + 0x7fffu + ((b >> 16) & 1u)) >> 16;
+    // inf and nan keep their class (a nan stays a quiet nan); a select, not a branch
+    const uint32_t special = (b >> 16) | ((b & 0xffffu) ? 0x40u : 0u);
+    return (uint16_t)(((b & 0x7f800000u) == 0x7f800000u) ? special : rounded);
 }
 
 }  // namespace monc

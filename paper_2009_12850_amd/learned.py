@@ -234,7 +234,7 @@ def init_params(seed):
     rng = np.random.default_rng(seed)
     H, K, NIN = M.MONC_MLP_H, M.MONC_MLP_K, M.MONC_MLP_NIN
     W1 = rng.standard_normal((H, K)) / np.sqrt(NIN)
-    W1[:, NIN:] = 0.0
+    W1.reshape(H, 4, K // 4)[:, :, 75:] = 0.0  # each field's 5 padding slots
     W2 = rng.standard_normal((H, H)) / np.sqrt(H)
     W3 = rng.standard_normal((4, H)) / np.sqrt(H) * 0.1
     return np.concatenate([W1.ravel(), np.zeros(H), W2.ravel(), np.zeros(H), W3.ravel(),

@@ -130,7 +130,7 @@ def test_forward_layers_match_oracle(m):
     p = R.init_params(7).astype(np.float32).astype(np.float64)
     p[R.H * R.K:R.H * R.K + R.H] = rng.standard_normal(R.H) * 0.1        # nonzero b1
     X = rng.standard_normal((m, R.K))
-    X[:, R.NIN:] = 0.0
+    X[:, R.PAD] = 0.0
     Xb = R.bf16(X)
     _, _, _, Y, H1, H2, Z1, Z2 = run_forward(Xb, p, m)
     W1, b1, W2, b2, W3, b3 = R.unpack(p)
@@ -160,7 +160,7 @@ def test_backward_matches_oracle(m):
     rng = np.random.default_rng(200 + m)
     p = R.init_params(11).astype(np.float32).astype(np.float64)
     X = rng.standard_normal((m, R.K))
-    X[:, R.NIN:] = 0.0
+    X[:, R.PAD] = 0.0
     Xd, pd, wp, Y, H1, H2, Z1, Z2 = run_forward(R.bf16(X), p, m)
     dY = (rng.standard_normal((m, 4)) / m).astype(np.float32)
     ws = T.zeros(M.monc_mlp_backward_workspace_bytes(m), dtype=T.uint8, device=dev())
@@ -185,7 +185,7 @@ def test_backward_matches_oracle(m):
         # dZ rounded to BF16 on both sides; a flipped rounding moves single
         # entries by one BF16 ulp, which bounds the block-wise error.
         assert err <= 4e-3, (name, err)
-    assert np.all(gb[0][:, R.NIN:] == 0.0)
+    assert np.all(gb[0][:, R.PAD] == 0.0)
 
 
 def test_loss_matches_oracle():

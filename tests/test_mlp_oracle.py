@@ -33,7 +33,7 @@ def small_problem(seed=0, B=6):
     rng = np.random.default_rng(seed)
     p = R.init_params(seed)
     X = rng.standard_normal((4 * B, R.K))
-    X[:, R.NIN:] = 0.0
+    X[:, R.PAD] = 0.0
     target = rng.standard_normal((B, 4))
     rhohat = rng.uniform(0.7, 1.0, (B, 4))
     mask = np.ones((B, 4))
@@ -52,7 +52,7 @@ def test_backward_matches_finite_differences_fp64():
     loss, dY = R.loss_and_grad(Y, target, rhohat, mask)
     g = R.backward(dY, cache, emulate=False)
     rng = np.random.default_rng(1)
-    W1cols = [j * R.K + k for j in range(R.H) for k in range(R.NIN)]
+    W1cols = [j * R.K + k for j in range(R.H) for k in R.USED]
     idx = list(rng.choice(W1cols, 40, replace=False)) + list(
         rng.choice(np.arange(R.H * R.K, R.NPARAM), 60, replace=False))
     for n in idx:
@@ -64,7 +64,7 @@ def test_backward_matches_finite_differences_fp64():
         assert abs(num - g[n]) <= 1e-5 * (abs(num) + 1e-3), (n, num, g[n])
     # padded input columns get no gradient
     W1g = g[:R.H * R.K].reshape(R.H, R.K)
-    assert np.all(W1g[:, R.NIN:] == 0.0)
+    assert np.all(W1g[:, R.PAD] == 0.0)
 
 
 def test_emulated_rounding_is_close_to_fp64():
@@ -81,12 +81,14 @@ def test_features_linear_field_and_wrap():
     norm = [0.0, 1.0, 0.0, 2.0, 1.0, 1.0, 0.0, 1.0]
     cell = (0 * NY + 4) * NZ + 0  # i = 0, j = 4, k = 0
     X = R.features(state, norm, 0, [cell])[0]
+    F = R.FSTRIDE
     for a in range(5):
-        assert X[((0 * 5 + a) * 5 + 2) * 3 + 1] == (a - 2) % NX          # u along x, wrapped
-        assert X[((1 * 5 + 2) * 5 + a) * 3 + 1] == 10.0 * ((4 + a - 2) % NY) / 2.0  # v along y
+        assert X[0 * F + (a * 5 + 2) * 3 + 1] == (a - 2) % NX          # u along x, wrapped
+        assert X[1 * F + (2 * 5 + a) * 3 + 1] == 10.0 * ((4 + a - 2) % NY) / 2.0  # v along y
     for c in range(3):
-        assert X[((2 * 5 + 2) * 5 + 2) * 3 + c] == 100.0 * max(c - 1, 0) - 1.0  # clamped z
-    assert np.all(X[R.NIN:] == 0.0)
+        assert X[2 * F + (2 * 5 + 2) * 3 + c] == 100.0 * max(c - 1, 0) - 1.0  # clamped z
+    assert np.all(X[R.PAD] == 0.0)
+    assert len(R.USED) == R.NIN and len(set(R.USED) | set(R.PAD)) == R.K
 
 
 def test_y_features_are_x_features_of_the_transposed_state():
