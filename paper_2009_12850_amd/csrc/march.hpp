@@ -582,7 +582,11 @@ __device__ __forceinline__ void march_tile(const AdvArgs& a, const TileJob& tj,
             const T pb = ph[owns - 1], pt = ph[owns + 1], ptt = ph[owns + 2];
             const T fz = tvd_flux<T>(wc, bottom ? pc : pb, pc, pt, top2 ? pt : ptt, cfz, rfz, rho);
             fzk[s] = fz;
-            if (NCH > 1 && lane == 63) fzc[(s * TJ + cc) * NCH + ch] = fz;
+            // the chunk's top face, for the chunk above (one lane stores: 64
+            // lanes writing one address would serialise in the LDS)
+            if constexpr (NCH > 1) {
+                if (lane == 63) fzc[(s * TJ + cc) * NCH + ch] = fz;
+            }
             // everything but the faces shared with the neighbours (j-1/2,
             // k-1/2); stored values are anomalies from phi0: add the term of
             // the constant
@@ -598,7 +602,12 @@ __device__ __forceinline__ void march_tile(const AdvArgs& a, const TileJob& tj,
         for (int s = 0; s < NS; s++) {
             const T up1 = __shfl_up(fzk[s], 1, 64);
             T fzm = up1;
-            if (lane == 0) fzm = ch == 0 ? (T)0 : fzc[(s * TJ + cc) * NCH + ch - 1];
+            if constexpr (NCH > 1) {
+                const T below = ch == 0 ? (T)0 : fzc[(s * TJ + cc) * NCH + (ch > 0 ? ch - 1 : 0)];
+                fzm = lane == 0 ? below : fzm;
+            } else {
+                fzm = lane == 0 ? (T)0 : fzm;
+            }
             const T fym = sfy[(s * FC + cc) * NZP + k];
             const T val = part[s] + fym * rdy + rhon_inv * rdz * fzm;
             if constexpr (MODE == TEND) {

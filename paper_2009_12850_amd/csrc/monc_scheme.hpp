@@ -152,10 +152,18 @@ __device__ __forceinline__ T tvd_flux(T a, T pm, T p0, T p1, T p2, T cfac, T rfa
     const T AD = A * D;
     const T Ab = A * U + (C - U) * rfac;  // |a| * (U + (C-U)/c)
     T lim;
-    if (delta > (T)0)
-        lim = fmin(fmax(Aphi, AC), fmin(AD, Ab));
-    else
-        lim = fmax(fmin(Aphi, AC), fmax(AD, Ab));
+    if constexpr (sizeof(T) == 4) {
+        // where the limiter applies, C lies strictly between U and D, so the
+        // clamp is the median of C, phi* and the median of C, D and the bound
+        // (v_med3_f32 twice, no compare)
+        lim = __builtin_amdgcn_fmed3f(AC, Aphi, __builtin_amdgcn_fmed3f(AC, AD, Ab));
+    } else {
+        // both clamps evaluated and one selected: a branch here would split the
+        // face into divergent blocks that the scheduler cannot interleave
+        const T lim_up = fmin(fmax(Aphi, AC), fmin(AD, Ab));
+        const T lim_dn = fmax(fmin(Aphi, AC), fmax(AD, Ab));
+        lim = delta > (T)0 ? lim_up : lim_dn;
+    }
     const T Af = (fabs(kappa) >= fabs(delta)) ? AC : lim;
     return mass * (pos ? Af : -Af);
 }
