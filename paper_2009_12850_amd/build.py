@@ -14,7 +14,11 @@ LIB = os.path.join(HERE, "libmoncadv.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # Packed FP32 instructions are disabled for every HIP translation unit.
-FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
+# Multiply-adds are fused only within one source expression (-ffp-contract=on),
+# so a formula gives the same bits wherever the compiler inlines it (the march
+# is unrolled by two; with fusion across statements the two copies rounded
+# differently and the result depended on the parity of the plane).
+FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-ffp-contract=on",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-function", "-Wno-unknown-pragmas"]
 

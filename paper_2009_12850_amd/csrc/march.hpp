@@ -376,7 +376,16 @@ __device__ __forceinline__ void march_tile(const AdvArgs& a, const TileJob& tj,
     Ts U[3], V[3], W[3];  // planes i-1, i, i+1 of the own column
     Ts P[NSA][4];         // planes i-1 .. i+2
     T FXm[NSA];           // flux through the x-face i-1/2 (rhon factored out)
-    Ts HB[NQ];            // halo columns of the next plane step
+    // Data of a later step t, loaded two steps ahead into one of two sets that
+    // alternate (the march is unrolled by two, so no register is copied while
+    // its load is in flight): velocities of plane t+1, scalars of plane t+2,
+    // halo columns of step t.
+    struct Ahead {
+        Ts u, v, w;
+        Ts p[NSA];
+        Ts h[NQ];
+    };
+    Ahead X, Y;
     double acc[BUD ? NACC : 1];
     if constexpr (BUD) {
 #pragma unroll
@@ -421,24 +430,31 @@ __device__ __forceinline__ void march_tile(const AdvArgs& a, const TileJob& tj,
             ld(fp, pl, ok ? (uint32_t)(((wrapy(jj) + 2) * nz + kk) * (int)sizeof(Ts)) : MARCH_OOB);
         vslot(f, pl)[c * CSZ + 2 + kk] = cvt0<T, Ts>(x);
     }
-    // plane offsets carried through the march: i+1, i+2, i+3 (for i = i0 - 1
-    // here); each step shifts them and wraps the newest with one compare
-    size_t o1 = poff(i0), o2 = poff(i0 + 1), o3 = poff(i0 + 2);
-    const size_t o_end = (size_t)(nx + 2) * sx, o_span = (size_t)nx * sx;
+    // step i0's halo columns into X; step i0+1's data into Y
 #pragma unroll
-    for (int q = 0; q < NQ; q++) HB[q] = job_load(q, o1, o2);
-    // now for i = i0
-    o1 = o2;
-    o2 = o3;
-    o3 += sx;
-    if (o3 >= o_end) o3 -= o_span;
+    for (int q = 0; q < NQ; q++) X.h[q] = job_load(q, poff(i0), poff(i0 + 1));
+    {
+        const size_t p1 = poff(i0 + 1), p2 = poff(i0 + 2), p3 = poff(i0 + 3);
+        Y.u = ldo(fptr[0], p2, roff_s);
+        Y.v = ldo(fptr[1], p2, roff_s);
+        Y.w = ldo(fptr[2], p2, roff_w);
+#pragma unroll
+        for (int s = 0; s < NS; s++) Y.p[s] = ldo(fptr[3 + s], p3, roff_s);
+#pragma unroll
+        for (int q = 0; q < NQ; q++) Y.h[q] = job_load(q, p1, p2);
+    }
+    // plane offsets carried through the march: planes i+2, i+3, i+4 of step
+    // i; each step shifts them and wraps the newest with one compare
+    size_t o2 = poff(i0 + 2), o3 = poff(i0 + 3), o4 = poff(i0 + 4);
+    const size_t o_end = (size_t)(nx + 2) * sx, o_span = (size_t)nx * sx;
 
     // per-level constants of this lane
     const bool bottom = k == 0;           // the ground face is below
     const bool top2 = k + 2 >= nz;        // no far-upwind cell above the top face
 
-    // ---- the march ----
-    for (int i = i0; i < i1; i++) {
+    // ---- the march: one step; Xs holds step i's halo columns and receives
+    // step i+2's data, Ys holds step i+1's data ----
+    auto march_step = [&](int i, Ahead& Xs, Ahead& Ys) __attribute__((always_inline)) {
         // slices of step i
         if (own_ok) {
             vslot(0, i)[ownv] = cvt0<T, Ts>(U[1]);
@@ -448,20 +464,16 @@ __device__ __forceinline__ void march_tile(const AdvArgs& a, const TileJob& tj,
             for (int s = 0; s < NS; s++) sph[s * SC * CSZ + owns] = cvt<T, Ts>(P[s][1], off[s]);
         }
 #pragma unroll
-        for (int q = 0; q < NQ; q++) job_store(q, i, HB[q]);
-        // prefetch of step i+1: own column and halo columns
-        const bool more = i + 1 < i1;
-        Ts NU = zero_of<Ts>(), NV = zero_of<Ts>(), NW = zero_of<Ts>();
-        Ts NP[NSA];
-        if (more) {
-            NU = ldo(fptr[0], o2, roff_s);
-            NV = ldo(fptr[1], o2, roff_s);
-            NW = ldo(fptr[2], o2, roff_w);
+        for (int q = 0; q < NQ; q++) job_store(q, i, Xs.h[q]);
+        // prefetch of step i+2 (planes stay in bounds past the segment end:
+        // they wrap, and the extra data is not used)
+        Xs.u = ldo(fptr[0], o3, roff_s);
+        Xs.v = ldo(fptr[1], o3, roff_s);
+        Xs.w = ldo(fptr[2], o3, roff_w);
 #pragma unroll
-            for (int s = 0; s < NS; s++) NP[s] = ldo(fptr[3 + s], o3, roff_s);
+        for (int s = 0; s < NS; s++) Xs.p[s] = ldo(fptr[3 + s], o4, roff_s);
 #pragma unroll
-            for (int q = 0; q < NQ; q++) HB[q] = job_load(q, o1, o2);
-        }
+        for (int q = 0; q < NQ; q++) Xs.h[q] = job_load(q, o2, o3);
         __syncthreads();
 
         const T* u_i = vslot(0, i);
@@ -630,27 +642,31 @@ __device__ __forceinline__ void march_tile(const AdvArgs& a, const TileJob& tj,
         }
 
         // advance the plane offsets
-        o1 = o2;
         o2 = o3;
-        o3 += sx;
-        if (o3 >= o_end) o3 -= o_span;
-        // rotate the windows
+        o3 = o4;
+        o4 += sx;
+        if (o4 >= o_end) o4 -= o_span;
+        // rotate the windows in step i+1's data
         U[0] = U[1];
         U[1] = U[2];
-        U[2] = NU;
+        U[2] = Ys.u;
         V[0] = V[1];
         V[1] = V[2];
-        V[2] = NV;
+        V[2] = Ys.v;
         W[0] = W[1];
         W[1] = W[2];
-        W[2] = NW;
+        W[2] = Ys.w;
 #pragma unroll
         for (int s = 0; s < NS; s++) {
             P[s][0] = P[s][1];
             P[s][1] = P[s][2];
             P[s][2] = P[s][3];
-            P[s][3] = more ? NP[s] : zero_of<Ts>();
+            P[s][3] = Ys.p[s];
         }
+    };
+    for (int i = i0; i < i1; i += 2) {
+        march_step(i, X, Y);
+        if (i + 1 < i1) march_step(i + 1, Y, X);
     }
 
     if constexpr (BUD) {
