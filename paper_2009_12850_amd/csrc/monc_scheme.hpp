@@ -128,44 +128,48 @@ __device__ __forceinline__ T pw_sw(T u_c, T u_ct, T u_w, T u_wt, T v_c, T v_ct, 
 //   mass   density factor of the face (rhon_k for lateral faces, rho_k for
 //          vertical ones)
 // For a >= 0 the upwind triple is (U,C,D) = (pm,p0,p1), else (p2,p1,p0).
-// The ULTIMATE bound U + (C-U)/c is multiplied through by |a|, using
-// |a|/c = spacing/dt, so the face flux needs no division; since |a| >= 0 and
-// rounding is monotone, clamping |a|*phi* between |a|*bounds equals |a| times
-// the clamped face value up to the rounding of the bound itself.
+//
+// The limited face value is written as C plus an offset, and everything is
+// multiplied by a, so that no division and no choice of the upwind triple
+// beyond C and one difference remains.  With s = sign(a), d1 = p1 - p0 and
+// e = C - U times s (p0 - pm for a >= 0, p2 - p1 otherwise):
+//   a (D - C)        = |a| d1
+//   a (phi* - C)     = |a| [ (1-c)/2 d1 - (1-c^2)/6 (d1 - e) ]     (QUICKEST)
+//   a (bound - C)    = e (spacing/dt - |a|)      bound = U + (C-U)/c
+// The profile is monotone exactly where d1 and e have the same sign.  Taking
+// all three offsets into the frame where d1 >= 0 (multiplying by sign(d1)),
+// the ULTIMATE clamp of phi* between C and the nearer of D and the bound is
+// max(0, min of the three), and where the profile is not monotone the third
+// offset is <= 0, so the same expression returns C.  This needs Courant
+// numbers c = |a| dt / spacing <= 1 (the stability limit of the scheme).
 // ---------------------------------------------------------------------------
+// x with its sign flipped where s has its sign bit set
+__device__ __forceinline__ double flip_sign_by(double x, double s) {
+    return __hiloint2double(__double2hiint(x) ^ (__double2hiint(s) & (int)0x80000000),
+                            __double2loint(x));
+}
+__device__ __forceinline__ float flip_sign_by(float x, float s) {
+    return __uint_as_float(__float_as_uint(x) ^ (__float_as_uint(s) & 0x80000000u));
+}
+
 template <typename T>
 __device__ __forceinline__ T tvd_flux(T a, T pm, T p0, T p1, T p2, T cfac, T rfac,
                                       T mass) {
     const bool pos = a >= (T)0;
-    const T U = pos ? pm : p2;
+    const T d1 = p1 - p0;
+    const T e = pos ? p0 - pm : p2 - p1;
     const T C = pos ? p0 : p1;
-    const T D = pos ? p1 : p0;
     const T A = fabs(a);
     const T c = A * cfac;
-    const T delta = D - U;
-    const T kappa = (D + U) - (T)2 * C;
-    // QUICKEST face value
-    const T phistar = (T)0.5 * (C + D) - (T)0.5 * c * (D - C) -
-                      ((T)1 - c * c) * ((T)1 / (T)6) * kappa;
-    const T Aphi = A * phistar;
-    const T AC = A * C;
-    const T AD = A * D;
-    const T Ab = A * U + (C - U) * rfac;  // |a| * (U + (C-U)/c)
-    T lim;
-    if constexpr (sizeof(T) == 4) {
-        // where the limiter applies, C lies strictly between U and D, so the
-        // clamp is the median of C, phi* and the median of C, D and the bound
-        // (v_med3_f32 twice, no compare)
-        lim = __builtin_amdgcn_fmed3f(AC, Aphi, __builtin_amdgcn_fmed3f(AC, AD, Ab));
-    } else {
-        // both clamps evaluated and one selected: a branch here would split the
-        // face into divergent blocks that the scheduler cannot interleave
-        const T lim_up = fmin(fmax(Aphi, AC), fmin(AD, Ab));
-        const T lim_dn = fmax(fmin(Aphi, AC), fmax(AD, Ab));
-        lim = delta > (T)0 ? lim_up : lim_dn;
-    }
-    const T Af = (fabs(kappa) >= fabs(delta)) ? AC : lim;
-    return mass * (pos ? Af : -Af);
+    const T se = flip_sign_by(e, d1);  // e in the frame d1 >= 0
+    const T ad1 = fabs(d1);
+    const T x_down = A * ad1;           // toward D
+    const T x_bound = se * (rfac - A);  // toward the ULTIMATE bound
+    const T h = fma((T)-0.5, c, (T)0.5);
+    const T q6 = fma(-c, c * (T)(1.0 / 6.0), (T)(1.0 / 6.0));
+    const T x_star = A * fma(h, ad1, -(q6 * (ad1 - se)));  // toward phi*
+    const T lim = fmax(fmin(fmin(x_star, x_down), x_bound), (T)0);
+    return mass * fma(a, C, copysign(lim, d1));
 }
 
 // First-order upwind flux (used where the far-upwind cell lies outside the
