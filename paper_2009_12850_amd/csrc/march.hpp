@@ -117,6 +117,38 @@ __device__ __forceinline__ T cvt0(Ts x) {
     }
 }
 
+// A copy the register allocator cannot fold into a renaming: the prefetch
+// registers then keep one physical register each through the march, instead
+// of rotating with the windows (a rotation that the unrolled loop does not
+// close costs copies at its back-edge, and those wait for the newest loads).
+template <typename Ts>
+__device__ __forceinline__ Ts pinned_copy(Ts x) {
+    if constexpr (sizeof(Ts) == 8) {
+        double r;
+        asm("v_mov_b64 %0, %1" : "=&v"(r) : "v"(x));
+        return r;
+    } else if constexpr (std::is_same<Ts, float>::value) {
+        float r;
+        asm("v_mov_b32 %0, %1" : "=&v"(r) : "v"(x));
+        return r;
+    } else {
+        uint32_t r;
+        asm("v_mov_b32 %0, %1" : "=&v"(r) : "v"((uint32_t)x.bits));
+        return Ts{(uint16_t)r};
+    }
+}
+
+// A value that is the same in every lane, moved to scalar registers.  The
+// read that produces it then runs in every lane (the compiler would otherwise
+// fold a read used by one lane into a branch on that lane).
+__device__ __forceinline__ double wave_uniform(double x) {
+    return __hiloint2double(__builtin_amdgcn_readfirstlane(__double2hiint(x)),
+                            __builtin_amdgcn_readfirstlane(__double2loint(x)));
+}
+__device__ __forceinline__ float wave_uniform(float x) {
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
+}
+
 // Waves per workgroup: 8 when FP64 values are held (a wave needs up to 256
 // registers, so two waves share a SIMD), 16 when storage and compute are both
 // 32-bit or narrower.  MONC_MARCH_WAVES64 sets the FP64 count at build time
@@ -144,7 +176,7 @@ __host__ __device__ constexpr size_t march_lds_bytes() {
     constexpr int TJ = MARCH_WAVES / NCH;
     return (size_t)(6 * (TJ + 2) + NS * (TJ + 4)) * march_csz<NCH>() * sizeof(T) +
            (size_t)(NS * (TJ + 1) + NLEV) * (64 * NCH) * sizeof(T) +
-           (size_t)(NS > 0 ? NS : 1) * MARCH_WAVES * sizeof(T);
+           (size_t)(NS > 0 ? NS : 1) * MARCH_WAVES * sizeof(T) + 64 * sizeof(T);
 }
 
 __device__ __forceinline__ int bud_op(int q) {
@@ -189,6 +221,7 @@ __device__ __forceinline__ void march_tile(const AdvArgs& a, const TileJob& tj,
     T* const sfy = sph + NS * SC * CSZ;             // [NS][FC][NZP]
     T* const lev = sfy + NS * FC * NZP;             // [NLEV][NZP]
     T* const fzc = lev + NLEV * NZP;                // [NS][TJ][NCH] chunk-top faces
+    T* const sink = fzc + NSA * MARCH_WAVES;         // [64] stores of unused halo jobs
 
     const int nx = a.nx, ny = a.ny, nz = a.nz;
     const size_t sx = (size_t)(ny + 4) * nz;
@@ -307,8 +340,8 @@ __device__ __forceinline__ void march_tile(const AdvArgs& a, const TileJob& tj,
     // Halo jobs of one plane step, for each chunk: velocities u(i), v(i+1),
     // w(i+1) at columns j0-1 and j0+TJ; scalar s at plane i, columns j0-2,
     // j0-1, j0+TJ, j0+TJ+1.  Job id = wv + 8 q; decoded once here.
-    int hj_f[NQ], hj_dpl[NQ], hj_lds[NQ];
-    bool hj_valid[NQ];
+    int hj_f[NQ], hj_dpl[NQ], hj_lds[NQ], hj_par[NQ];
+    double hj_o[NQ];
     const Ts* hj_ptr[NQ];
     uint32_t hj_boff[NQ];
     bool hj_ok[NQ];
@@ -342,28 +375,25 @@ __device__ __forceinline__ void march_tile(const AdvArgs& a, const TileJob& tj,
         hj_ok[q] = valid && kk < nz && !(f == 2 && kk >= nz - 1);
         hj_boff[q] = hj_ok[q] ? (uint32_t)(((wrapy(jj) + 2) * nz + kk) * (int)sizeof(Ts))
                               : MARCH_OOB;
-        // LDS element offset (velocity slots: parity added per step)
-        hj_lds[q] = f < 3 ? ((f * 2) * VC + c) * CSZ + 2 + kk
-                          : (int)(sph - vel) + ((f - 3) * SC + c) * CSZ + 2 + kk;
-        hj_valid[q] = valid;  // wave-uniform
+        // LDS element offset (velocity slots: the parity term hj_par is added
+        // on odd planes); a job without a column stores into the sink
+        hj_lds[q] = !valid ? (int)(sink - vel) + lane
+                    : f < 3 ? ((f * 2) * VC + c) * CSZ + 2 + kk
+                            : (int)(sph - vel) + ((f - 3) * SC + c) * CSZ + 2 + kk;
+        hj_par[q] = valid && f < 3 ? VC * CSZ : 0;
+        double o = 0.0;
+#pragma unroll
+        for (int s = 0; s < NS; s++)
+            if (valid && f == 3 + s) o = off[s];
+        hj_o[q] = o;
     }
     // halo loads of plane step i + 1 (o1, o2: offsets of planes i + 1 and i + 2)
     auto job_load = [&](int q, size_t o1, size_t o2) -> Ts {
         return ldo(hj_ptr[q], hj_dpl[q] ? o2 : o1, hj_boff[q]);
     };
+    // no branch: every job stores, unused ones into the sink
     auto job_store = [&](int q, int i, Ts x) {
-        if (!hj_valid[q]) return;
-        const int f = hj_f[q];
-        int e = hj_lds[q];
-        double o = 0.0;
-        if (f < 3) {
-            e += ((i + hj_dpl[q]) & 1) * VC * CSZ;
-        } else {
-#pragma unroll
-            for (int s = 0; s < NS; s++)
-                if (f == 3 + s) o = off[s];
-        }
-        vel[e] = cvt<T, Ts>(x, o);
+        vel[hj_lds[q] + (((i + hj_dpl[q]) & 1) ? hj_par[q] : 0)] = cvt<T, Ts>(x, hj_o[q]);
     };
     // own column slot addresses
     auto vslot = [&](int f, int plane_i) -> T* {
@@ -376,44 +406,48 @@ __device__ __forceinline__ void march_tile(const AdvArgs& a, const TileJob& tj,
     Ts U[3], V[3], W[3];  // planes i-1, i, i+1 of the own column
     Ts P[NSA][4];         // planes i-1 .. i+2
     T FXm[NSA];           // flux through the x-face i-1/2 (rhon factored out)
-    // Data of a later step t, loaded two steps ahead into one of two sets that
-    // alternate (the march is unrolled by two, so no register is copied while
-    // its load is in flight): velocities of plane t+1, scalars of plane t+2,
-    // halo columns of step t.
+    // Data of a later step t, loaded DEPTH steps ahead into one of DEPTH sets
+    // used in turn (the march is unrolled by DEPTH): velocities of plane t+1,
+    // scalars of plane t+2, halo columns of step t.  Step t shifts its set
+    // into the windows before the set is reloaded, so a load has DEPTH steps
+    // to arrive before anything waits for it.  (Three sets measured no
+    // faster than two for FP64 on 1024 x 1024 x 128.)
     struct Ahead {
         Ts u, v, w;
         Ts p[NSA];
         Ts h[NQ];
     };
-    Ahead X, Y;
+    constexpr int DEPTH = 2;
+    Ahead S[DEPTH];
     double acc[BUD ? NACC : 1];
     if constexpr (BUD) {
 #pragma unroll
         for (int q = 0; q < NACC; q++) acc[q] = bud_ident(bud_op(q));
     }
 
-    // ---- prologue: windows at i0, the carried x-face, the first slices ----
+    // ---- prologue: windows one plane behind i0 (step i0 shifts in its own
+    // data), the carried x-face, the first slices ----
     __syncthreads();  // level table visible
 #pragma unroll
     for (int p = 0; p < 3; p++) {
-        U[p] = ld(fptr[0], i0 - 1 + p, roff_s);
-        V[p] = ld(fptr[1], i0 - 1 + p, roff_s);
-        W[p] = ld(fptr[2], i0 - 1 + p, roff_w);
+        U[p] = ld(fptr[0], i0 - 2 + p, roff_s);
+        V[p] = ld(fptr[1], i0 - 2 + p, roff_s);
+        W[p] = ld(fptr[2], i0 - 2 + p, roff_w);
     }
 #pragma unroll
     for (int s = 0; s < NS; s++) {
-        const Ts Pm2 = ld(fptr[3 + s], i0 - 2, roff_s);
 #pragma unroll
-        for (int p = 0; p < 4; p++) P[s][p] = ld(fptr[3 + s], i0 - 1 + p, roff_s);
-        FXm[s] = tvd_flux<T>(cvt0<T, Ts>(U[0]), cvt<T, Ts>(Pm2, off[s]), cvt<T, Ts>(P[s][0], off[s]),
-                             cvt<T, Ts>(P[s][1], off[s]), cvt<T, Ts>(P[s][2], off[s]), cfx, rfx,
-                             (T)1);
+        for (int p = 0; p < 4; p++) P[s][p] = ld(fptr[3 + s], i0 - 2 + p, roff_s);
+        // x-face i0-1/2: u of plane i0-1, scalars of planes i0-2 .. i0+1
+        FXm[s] = tvd_flux<T>(cvt0<T, Ts>(U[1]), cvt<T, Ts>(P[s][0], off[s]),
+                             cvt<T, Ts>(P[s][1], off[s]), cvt<T, Ts>(P[s][2], off[s]),
+                             cvt<T, Ts>(P[s][3], off[s]), cfx, rfx, (T)1);
     }
-    if (own_ok) {
-        vslot(0, i0 - 1)[ownv] = cvt0<T, Ts>(U[0]);
-        vslot(1, i0)[ownv] = cvt0<T, Ts>(V[1]);
-        vslot(2, i0)[ownv] = cvt0<T, Ts>(W[1]);
-    }
+    // own slots of u(i0-1), v(i0), w(i0) (a column past ny+1 stores zeros
+    // that nothing reads)
+    vslot(0, i0 - 1)[ownv] = cvt0<T, Ts>(U[1]);
+    vslot(1, i0)[ownv] = cvt0<T, Ts>(V[2]);
+    vslot(2, i0)[ownv] = cvt0<T, Ts>(W[2]);
     // halo columns of u(i0-1), v(i0), w(i0)
     for (int id = wv; id < 6 * NCH; id += MARCH_WAVES) {
         const int chunk = id % NCH, h = id / NCH;
@@ -430,50 +464,68 @@ __device__ __forceinline__ void march_tile(const AdvArgs& a, const TileJob& tj,
             ld(fp, pl, ok ? (uint32_t)(((wrapy(jj) + 2) * nz + kk) * (int)sizeof(Ts)) : MARCH_OOB);
         vslot(f, pl)[c * CSZ + 2 + kk] = cvt0<T, Ts>(x);
     }
-    // step i0's halo columns into X; step i0+1's data into Y
+    // the data of steps i0 .. i0+DEPTH-1, set by set in this order (the
+    // scheduler may not interleave them: the loop's waits count on it)
 #pragma unroll
-    for (int q = 0; q < NQ; q++) X.h[q] = job_load(q, poff(i0), poff(i0 + 1));
-    {
-        const size_t p1 = poff(i0 + 1), p2 = poff(i0 + 2), p3 = poff(i0 + 3);
-        Y.u = ldo(fptr[0], p2, roff_s);
-        Y.v = ldo(fptr[1], p2, roff_s);
-        Y.w = ldo(fptr[2], p2, roff_w);
+    for (int d = 0; d < DEPTH; d++) {
+        const size_t p0 = poff(i0 + d), p1 = poff(i0 + d + 1), p2 = poff(i0 + d + 2);
+        S[d].u = ldo(fptr[0], p1, roff_s);
+        S[d].v = ldo(fptr[1], p1, roff_s);
+        S[d].w = ldo(fptr[2], p1, roff_w);
 #pragma unroll
-        for (int s = 0; s < NS; s++) Y.p[s] = ldo(fptr[3 + s], p3, roff_s);
+        for (int s = 0; s < NS; s++) S[d].p[s] = ldo(fptr[3 + s], p2, roff_s);
 #pragma unroll
-        for (int q = 0; q < NQ; q++) Y.h[q] = job_load(q, p1, p2);
+        for (int q = 0; q < NQ; q++) S[d].h[q] = job_load(q, p0, p1);
+        __builtin_amdgcn_sched_barrier(0);
     }
-    // plane offsets carried through the march: planes i+2, i+3, i+4 of step
-    // i; each step shifts them and wraps the newest with one compare
-    size_t o2 = poff(i0 + 2), o3 = poff(i0 + 3), o4 = poff(i0 + 4);
+    // plane offsets carried through the march: at step i, planes i+DEPTH
+    // (halo columns), i+DEPTH+1 (velocities), i+DEPTH+2 (scalars) of the data
+    // it prefetches; each step shifts them and wraps the newest with one
+    // compare
+    size_t o_h = poff(i0 + DEPTH), o_v = poff(i0 + DEPTH + 1), o_s = poff(i0 + DEPTH + 2);
     const size_t o_end = (size_t)(nx + 2) * sx, o_span = (size_t)nx * sx;
 
     // per-level constants of this lane
     const bool bottom = k == 0;           // the ground face is below
     const bool top2 = k + 2 >= nz;        // no far-upwind cell above the top face
 
-    // ---- the march: one step; Xs holds step i's halo columns and receives
-    // step i+2's data, Ys holds step i+1's data ----
-    auto march_step = [&](int i, Ahead& Xs, Ahead& Ys) __attribute__((always_inline)) {
-        // slices of step i
-        if (own_ok) {
-            vslot(0, i)[ownv] = cvt0<T, Ts>(U[1]);
-            vslot(1, i + 1)[ownv] = cvt0<T, Ts>(V[2]);
-            vslot(2, i + 1)[ownv] = cvt0<T, Ts>(W[2]);
+    // ---- the march: one step; Xs holds step i's data and receives step
+    // i+DEPTH's ----
+    auto march_step = [&](int i, Ahead& Xs) __attribute__((always_inline)) {
+        // shift step i's planes into the windows
+        U[0] = U[1];
+        U[1] = U[2];
+        U[2] = pinned_copy(Xs.u);
+        V[0] = V[1];
+        V[1] = V[2];
+        V[2] = pinned_copy(Xs.v);
+        W[0] = W[1];
+        W[1] = W[2];
+        W[2] = pinned_copy(Xs.w);
 #pragma unroll
-            for (int s = 0; s < NS; s++) sph[s * SC * CSZ + owns] = cvt<T, Ts>(P[s][1], off[s]);
+        for (int s = 0; s < NS; s++) {
+            P[s][0] = P[s][1];
+            P[s][1] = P[s][2];
+            P[s][2] = P[s][3];
+            P[s][3] = pinned_copy(Xs.p[s]);
         }
+        // slices of step i (a column past ny+1 stores zeros that nothing reads)
+        vslot(0, i)[ownv] = cvt0<T, Ts>(U[1]);
+        vslot(1, i + 1)[ownv] = cvt0<T, Ts>(V[2]);
+        vslot(2, i + 1)[ownv] = cvt0<T, Ts>(W[2]);
+#pragma unroll
+        for (int s = 0; s < NS; s++) sph[s * SC * CSZ + owns] = cvt<T, Ts>(P[s][1], off[s]);
 #pragma unroll
         for (int q = 0; q < NQ; q++) job_store(q, i, Xs.h[q]);
-        // prefetch of step i+2 (planes stay in bounds past the segment end:
+        // prefetch of step i+DEPTH (planes stay in bounds past the segment end:
         // they wrap, and the extra data is not used)
-        Xs.u = ldo(fptr[0], o3, roff_s);
-        Xs.v = ldo(fptr[1], o3, roff_s);
-        Xs.w = ldo(fptr[2], o3, roff_w);
+        Xs.u = ldo(fptr[0], o_v, roff_s);
+        Xs.v = ldo(fptr[1], o_v, roff_s);
+        Xs.w = ldo(fptr[2], o_v, roff_w);
 #pragma unroll
-        for (int s = 0; s < NS; s++) Xs.p[s] = ldo(fptr[3 + s], o4, roff_s);
+        for (int s = 0; s < NS; s++) Xs.p[s] = ldo(fptr[3 + s], o_s, roff_s);
 #pragma unroll
-        for (int q = 0; q < NQ; q++) Xs.h[q] = job_load(q, o2, o3);
+        for (int q = 0; q < NQ; q++) Xs.h[q] = job_load(q, o_h, o_v);
         __syncthreads();
 
         const T* u_i = vslot(0, i);
@@ -584,20 +636,18 @@ __device__ __forceinline__ void march_tile(const AdvArgs& a, const TileJob& tj,
             const T ps = ph[owns - CSZ], pn = ph[owns + CSZ], pnn = ph[owns + 2 * CSZ];
             const T fyp = tvd_flux<T>(vc, ps, pc, pn, pnn, cfy, rfy, (T)1);
             sfy[(s * FC + cc + 1) * NZP + k] = fyp;
-            if (cc == 0) {
-                sfy[(s * FC) * NZP + k] =
-                    tvd_flux<T>(vs, ph[owns - 2 * CSZ], ps, pc, pn, cfy, rfy, (T)1);
-            }
             // top face k+1/2.  Where the far-upwind cell is outside the column
             // it is replaced by the upwind cell, which makes the limiter return
             // the upwind value (first-order upwind); on the lid w is zero.
             const T pb = ph[owns - 1], pt = ph[owns + 1], ptt = ph[owns + 2];
             const T fz = tvd_flux<T>(wc, bottom ? pc : pb, pc, pt, top2 ? pt : ptt, cfz, rfz, rho);
             fzk[s] = fz;
-            // the chunk's top face, for the chunk above (one lane stores: 64
-            // lanes writing one address would serialise in the LDS)
+            // the chunk's top face, for the chunk above: lane 63 stores it, the
+            // other lanes store into the sink (no branch; 64 lanes writing one
+            // address would serialise in the LDS)
             if constexpr (NCH > 1) {
-                if (lane == 63) fzc[(s * TJ + cc) * NCH + ch] = fz;
+                T* const dst = lane == 63 ? fzc + (s * TJ + cc) * NCH + ch : sink + lane;
+                *dst = fz;
             }
             // everything but the faces shared with the neighbours (j-1/2,
             // k-1/2); stored values are anomalies from phi0: add the term of
@@ -605,6 +655,15 @@ __device__ __forceinline__ void march_tile(const AdvArgs& a, const TileJob& tj,
             part[s] = -((fxp[s] - FXm[s]) * rdx + fyp * rdy) - rhon_inv * rdz * fz -
                       phi0c[s] * D * rhon_inv;
             FXm[s] = fxp[s];
+        }
+        // the tile's y-faces j0-1/2: one (scalar, chunk) job per wave from
+        // wave 0 up, so that the extra work lands on different SIMDs
+        for (int jb = wv; jb < NS * NCH; jb += MARCH_WAVES) {
+            const int s = jb / NCH;
+            const int kb = 64 * (jb % NCH) + lane;
+            const T* ph = sph + s * SC * CSZ + 2 * CSZ + 2 + kb;  // column j0
+            sfy[(s * FC) * NZP + kb] = tvd_flux<T>(v_i[2 + kb], ph[-2 * CSZ], ph[-CSZ], ph[0],
+                                                   ph[CSZ], cfy, rfy, (T)1);
         }
         __syncthreads();
 
@@ -615,8 +674,9 @@ __device__ __forceinline__ void march_tile(const AdvArgs& a, const TileJob& tj,
             const T up1 = __shfl_up(fzk[s], 1, 64);
             T fzm = up1;
             if constexpr (NCH > 1) {
-                const T below = ch == 0 ? (T)0 : fzc[(s * TJ + cc) * NCH + (ch > 0 ? ch - 1 : 0)];
-                fzm = lane == 0 ? below : fzm;
+                // read unconditionally (one address: a broadcast), then select
+                const T below = wave_uniform(fzc[(s * TJ + cc) * NCH + (ch > 0 ? ch - 1 : 0)]);
+                fzm = lane == 0 ? (ch == 0 ? (T)0 : below) : fzm;
             } else {
                 fzm = lane == 0 ? (T)0 : fzm;
             }
@@ -642,31 +702,16 @@ __device__ __forceinline__ void march_tile(const AdvArgs& a, const TileJob& tj,
         }
 
         // advance the plane offsets
-        o2 = o3;
-        o3 = o4;
-        o4 += sx;
-        if (o4 >= o_end) o4 -= o_span;
-        // rotate the windows in step i+1's data
-        U[0] = U[1];
-        U[1] = U[2];
-        U[2] = Ys.u;
-        V[0] = V[1];
-        V[1] = V[2];
-        V[2] = Ys.v;
-        W[0] = W[1];
-        W[1] = W[2];
-        W[2] = Ys.w;
-#pragma unroll
-        for (int s = 0; s < NS; s++) {
-            P[s][0] = P[s][1];
-            P[s][1] = P[s][2];
-            P[s][2] = P[s][3];
-            P[s][3] = Ys.p[s];
-        }
+        o_h = o_v;
+        o_v = o_s;
+        o_s += sx;
+        if (o_s >= o_end) o_s -= o_span;
     };
-    for (int i = i0; i < i1; i += 2) {
-        march_step(i, X, Y);
-        if (i + 1 < i1) march_step(i + 1, Y, X);
+    for (int i = i0; i < i1; i += DEPTH) {
+        march_step(i, S[0]);
+#pragma unroll
+        for (int d = 1; d < DEPTH; d++)
+            if (i + d < i1) march_step(i + d, S[d]);
     }
 
     if constexpr (BUD) {

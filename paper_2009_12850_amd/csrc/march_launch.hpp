@@ -35,7 +35,9 @@ hipError_t launch_ns(const MarchArgs& m, const Tiling& t, hipStream_t s) {
             break;
         case 1: return launch_one<Ts, T, MODE, PW, 1, BUD, R>(m, t, s);
         case 2: return launch_one<Ts, T, MODE, PW, 2, BUD, R>(m, t, s);
-        case 3: return launch_one<Ts, T, MODE, PW, 3, BUD, R>(m, t, s);
+        case 3:  // groups of three only without budgets
+            if constexpr (!BUD) return launch_one<Ts, T, MODE, PW, 3, BUD, R>(m, t, s);
+            break;
     }
     return hipErrorInvalidValue;
 }
