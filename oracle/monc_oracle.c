@@ -643,3 +643,54 @@ int oracle_restrict4(double *const *fine, double *const *coarse, int nscal, int 
     free(mZ);
     return OR_OK;
 }
+
+/* ---------------------------------------------------------------------------
+ * Other source terms of the dynamics group (Sec. 3 and its hybrid-structure
+ * figure: the CPU computes the non-advection components of the group while
+ * the GPU computes advection, then the source terms are combined before the
+ * fields are stepped).  The paper does not name or define these components;
+ * the two taken here are standard members of an LES dynamics group:
+ *
+ *   Coriolis on an f-plane, relaxing toward a geostrophic wind (ug, vg):
+ *     su(i,j,k) =  fcor * (vbar - vg),  vbar = mean of v at (i,j), (i+1,j),
+ *                                              (i,j-1), (i+1,j-1)
+ *     sv(i,j,k) = -fcor * (ubar - ug),  ubar = mean of u at (i,j), (i-1,j),
+ *                                              (i,j+1), (i-1,j+1)
+ *   (the four C-grid neighbours around the u point and the v point)
+ *
+ *   Buoyancy of theta on the w faces (Boussinesq, constant reference th0):
+ *     sw(i,j,k) = grav * ((th(k) + th(k+1))/2 - th0) / th0   for k < nz-1,
+ *     sw(i,j,nz-1) = 0 (the lid)
+ *
+ * Neighbours are read at wrapped periodic indices (halos are not used).
+ * ------------------------------------------------------------------------- */
+int oracle_dyn(const double *u, const double *v, const double *th, double *su,
+               double *sv, double *sw, int nx, int ny, int nz, double fcor,
+               double ug, double vg, double grav, double th0) {
+    if (!u || !v || !th || !su || !sv || !sw || nx < 1 || ny < 1 || nz < 1) return OR_EINVAL;
+    if (!(th0 > 0.0)) return OR_EINVAL;
+    grid_t g = {nx, ny, nz};
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < nx; i++) {
+        int im = posmod(i - 1, nx), ip = posmod(i + 1, nx);
+        for (int j = 0; j < ny; j++) {
+            int jm = posmod(j - 1, ny), jp = posmod(j + 1, ny);
+            for (int k = 0; k < nz; k++) {
+                long c = at(&g, i, j, k);
+                double vbar = (v[at(&g, i, j, k)] + v[at(&g, ip, j, k)] +
+                               v[at(&g, i, jm, k)] + v[at(&g, ip, jm, k)]) / 4.0;
+                double ubar = (u[at(&g, i, j, k)] + u[at(&g, im, j, k)] +
+                               u[at(&g, i, jp, k)] + u[at(&g, im, jp, k)]) / 4.0;
+                su[c] = fcor * (vbar - vg);
+                sv[c] = -fcor * (ubar - ug);
+                if (k < nz - 1) {
+                    double thf = (th[c] + th[at(&g, i, j, k + 1)]) / 2.0;
+                    sw[c] = grav * (thf - th0) / th0;
+                } else {
+                    sw[c] = 0.0;
+                }
+            }
+        }
+    }
+    return OR_OK;
+}

@@ -64,6 +64,7 @@ def lib():
         L.oracle_max_courant.restype = d
         L.oracle_restrict4.argtypes = [C.POINTER(dp), C.POINTER(dp), i, i, i, i, dp, dp, dp,
                                        dp, dp, dp]
+        L.oracle_dyn.argtypes = [dp, dp, dp, dp, dp, dp, i, i, i, d, d, d, d, d]
         _lib = L
     return _lib
 
@@ -206,3 +207,35 @@ def restrict4(state, g):
     gc = I.Geometry(NX, NY, NZ, 4 * g.dx, 4 * g.dy, rdz_c, rho_c, rhon_c, zf,
                     zf - 0.5 / rdz_c)
     return out, gc
+
+
+def dyn(u, v, th, fcor, ug, vg, grav, th0):
+    """Coriolis and buoyancy source terms (su, sv, sw) of the other dynamics
+    components (wrapped periodic neighbours; halos are not read)."""
+    nx, ny, nz = _shape(u)
+    su, sv, sw = (np.zeros_like(u) for _ in range(3))
+    _check(lib().oracle_dyn(_p(u), _p(v), _p(th), _p(su), _p(sv), _p(sw), nx, ny, nz,
+                            float(fcor), float(ug), float(vg), float(grav), float(th0)),
+           "dyn")
+    return su, sv, sw
+
+
+def step_dyn(state, g, dt, fcor, ug, vg, grav, th0, allow_cfl=False):
+    """One forward step with the advection source terms and the other dynamics
+    source terms combined before the update (the hybrid structure of Sec. 3):
+    f_out = f_in + dt (s_adv + s_dyn), s_dyn = 0 for the scalars, w = 0 on the
+    lid.  state = [u, v, w, theta, scalars...]; theta (state[3]) drives the
+    buoyancy.  The inputs are not modified (halo-filled copies are used)."""
+    nx, ny, nz = _shape(state[0])
+    state = [halo_fill(f) for f in state]
+    su, sv, sw = pw(state[0], state[1], state[2], g)
+    du, dv, dw = dyn(state[0], state[1], state[3], fcor, ug, vg, grav, th0)
+    out = [np.full_like(f, np.nan) for f in state]
+    sl = (slice(2, nx + 2), slice(2, ny + 2), slice(None))
+    for f, (sa, sd) in enumerate(((su, du), (sv, dv), (sw, dw))):
+        out[f][sl] = state[f][sl] + dt * (sa[sl] + sd[sl])
+    out[2][2:nx + 2, 2:ny + 2, nz - 1] = 0.0
+    for s in range(len(state) - 3):
+        st = tvd(state[0], state[1], state[2], state[3 + s], g, dt, allow_cfl=allow_cfl)
+        out[3 + s][sl] = state[3 + s][sl] + dt * st[sl]
+    return out
