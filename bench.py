@@ -162,6 +162,45 @@ def cpu_baseline(seconds):
                       f"(u v w th q1), {el:.1f} s"}
 
 
+DYN_PARAMS = (1.0e-4, 5.0, 0.0, 9.81, 300.0)  # fcor, ug, vg, grav, th0
+
+
+def bench_dynamics(torch, M, state, g, prof, w, stream, npts, nf, reps):
+    """The step with the other dynamics source terms (Coriolis, buoyancy):
+    the paper's hybrid structure (other components beside the advection,
+    source terms combined before the step) on one stream and on two, against
+    the same terms fused into the advection pass."""
+    tend = [torch.empty_like(a) for a in state[0]]
+    dyn = [torch.empty_like(a) for a in state[0][:3]]
+    side = torch.cuda.Stream()
+    out = {}
+    runs = {
+        "plain_step": lambda: M.monc_step(state[0], state[1], g.dx, g.dy, prof, w.dt,
+                                          None, None, stream),
+        "sequential": lambda: M.monc_hybrid_step(state[0], state[1], tend, dyn, g.dx, g.dy,
+                                                 prof, w.dt, DYN_PARAMS, stream),
+        "two_streams": lambda: M.monc_hybrid_step(state[0], state[1], tend, dyn, g.dx,
+                                                  g.dy, prof, w.dt, DYN_PARAMS, stream,
+                                                  side_stream=side),
+        "fused": lambda: M.monc_step_dyn(state[0], state[1], g.dx, g.dy, prof, w.dt,
+                                         DYN_PARAMS, stream),
+    }
+    for name, fn in runs.items():
+        fn()
+        torch.cuda.synchronize()
+        ms = event_time_ms(torch, stream, fn, reps)
+        torch.cuda.synchronize()
+        out[name] = {"ms": ms, "gpups": npts / (ms * 1e-3)}
+    # bytes: the hybrid path writes and re-reads every source term
+    out["fused"]["bytes_per_point"] = 16.0 * nf
+    # advection source terms 16 nf, Coriolis + buoyancy 48, combine 8 (3 nf + 3)
+    out["two_streams"]["bytes_per_point"] = 16.0 * nf + 48.0 + 8.0 * (3 * nf + 3)
+    out["fused_speedup_vs_two_streams"] = out["two_streams"]["ms"] / out["fused"]["ms"]
+    out["fused_cost_vs_plain_step"] = out["fused"]["ms"] / out["plain_step"]["ms"]
+    del tend, dyn
+    return out
+
+
 def bench_ensemble(torch, M, I, dev, steps, log):
     """64 uneven members (nx, ny in {64..256}, nz in {64, 96}), FP32 source
     terms from the FP64 state, `steps` steps in one captured graph launch,
@@ -309,6 +348,8 @@ def main():
                                           None, None, stream)
         tm = event_time_ms(torch, stream, mixed, args.steps)
         forms["mixed_step"] = {"ms": tm, "gpups": npts / (tm * 1e-3)}
+        forms["dynamics"] = bench_dynamics(torch, M, state, g, prof, w, stream, npts, nf,
+                                           args.steps)
 
     if not args.no_forms:
         del B

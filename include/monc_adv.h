@@ -347,6 +347,69 @@ int monc_correct_step(double *const *state_in, double *const *tend, const float 
                       const double *rho, const double *rhon, double dt, double growth,
                       int *flags, void *workspace, monc_stream_t stream);
 
+/* ---------------------------------------------------------------------------
+ * Other source terms of the dynamics group and the combined step (the hybrid
+ * structure of Sec. 3 and its hybrid-dynamics figure: the other components of
+ * the dynamics group run beside the advection, then every source term is
+ * combined before the fields are stepped).  The paper names no such
+ * component; the two provided are the f-plane Coriolis force toward a
+ * geostrophic wind and the buoyancy of theta:
+ *   su = fcor (vbar - vg), vbar = mean of v at (i,j), (i+1,j), (i,j-1), (i+1,j-1)
+ *   sv = -fcor (ubar - ug), ubar = mean of u at (i,j), (i-1,j), (i,j+1), (i-1,j+1)
+ *   sw = grav ((th_k + th_{k+1})/2 - th0) / th0 for k < nz-1, 0 on the lid.
+ * Periodic neighbours are read at wrapped indices; halos are neither read nor
+ * written.  All fields are device FP64 arrays in the usual padded layout.
+ * Errors: MONC_EINVAL for NULL pointers, bad sizes, non-finite parameters,
+ * th0 <= 0, or aliasing outputs.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    double fcor;     /* Coriolis parameter (1/s) */
+    double ug, vg;   /* geostrophic wind (m/s) */
+    double grav;     /* gravitational acceleration (m/s^2) */
+    double th0;      /* reference potential temperature (K), > 0 */
+} monc_dyn_params;
+
+/* The other dynamics source terms alone: su, sv, sw from u, v and theta. */
+int monc_dyn_tend(const double *u, const double *v, const double *theta, double *su,
+                  double *sv, double *sw, int nx, int ny, int nz,
+                  const monc_dyn_params *p, monc_stream_t stream);
+
+/* Combine source terms and step: out[f] = in[f] + dt (ta[f] + tb[f]) for f
+ * in 0..nfields-1 (fields ordered u, v, w, scalars; w = 0 on the lid).  tb may
+ * be NULL, and so may any tb[f]: that field then steps with ta alone.  in, ta,
+ * tb, out: host arrays of device pointers; out must not alias an input. */
+int monc_combine_step(int nfields, const double *const *in, const double *const *ta,
+                      const double *const *tb, double *const *out, int nx, int ny,
+                      int nz, double dt, monc_stream_t stream);
+
+/* The hybrid step on two streams: the other dynamics source terms on
+ * side_stream (into dyn_tend[0..2], device buffers of the caller) while the
+ * advection source terms of all 3+nscal fields run on `stream` (into
+ * tend[0..2+nscal]); `stream` then waits for the side stream and the combine
+ * pass steps the fields: state_out = state_in + dt (s_adv + s_dyn), s_dyn = 0
+ * for the scalars.  theta is scalar 0 (nscal >= 1); halos are neither read
+ * nor written.  tend and dyn_tend must not alias the states or each other.
+ * side_stream may equal stream (then the passes run one after another).  On
+ * return every pass is enqueued; the side stream also waits for `stream` at
+ * entry, so both streams see state_in as it is when the call is made.
+ * Results are bitwise those of monc_step_dyn. */
+int monc_hybrid_step(double *const *state_in, double *const *state_out,
+                     double *const *tend, double *const *dyn_tend, int nscal, int nx,
+                     int ny, int nz, double dx, double dy, const double *rdz,
+                     const double *rho, const double *rhon, double dt,
+                     const monc_dyn_params *p, monc_stream_t stream,
+                     monc_stream_t side_stream);
+
+/* The same step in one pass: the Coriolis and buoyancy terms are added to the
+ * PW source terms inside the advection march, so no source term goes through
+ * HBM (the paper's further-work idea of combining source terms on the device
+ * before they leave it, Sec. 5).  Arguments as monc_step without budgets;
+ * nscal >= 1 (theta = scalar 0). */
+int monc_step_dyn(double *const *state_in, double *const *state_out, int nscal, int nx,
+                  int ny, int nz, double dx, double dy, const double *rdz,
+                  const double *rho, const double *rhon, double dt,
+                  const monc_dyn_params *p, monc_stream_t stream);
+
 /* Map a budgets array (HOST copy, after synchronising) to a status:
  * MONC_ENONFINITE if any non-finite value was written, MONC_ECFL if the
  * largest Courant number exceeds 1, else MONC_OK. */

@@ -54,6 +54,11 @@ _SIGS = {
     "monc_step_mixed": ([PP, PP, ip, DPTR, ip, ip, ip, dp, dp, vp, vp, vp, dp, vp, vp, vp],
                         ip),
     "monc_cast_working": ([ip, ip, PP, PP, DPTR, ip, ip, ip, vp], ip),
+    "monc_dyn_tend": ([vp, vp, vp, vp, vp, vp, ip, ip, ip, vp, vp], ip),
+    "monc_combine_step": ([ip, PP, PP, PP, PP, ip, ip, ip, dp, vp], ip),
+    "monc_hybrid_step": ([PP, PP, PP, PP, ip, ip, ip, ip, dp, dp, vp, vp, vp, dp, vp, vp, vp],
+                         ip),
+    "monc_step_dyn": ([PP, PP, ip, ip, ip, ip, dp, dp, vp, vp, vp, dp, vp, vp], ip),
     "monc_budgets_check": ([DPTR], ip),
     "monc_restrict4": ([ip, PP, PP, ip, ip, ip, vp, vp, vp, vp, vp, vp, vp], ip),
     "monc_mlp_features": ([PP, ip, ip, ip, DPTR, ip, vp, ip, vp, vp], ip),
@@ -269,6 +274,79 @@ def monc_step(state_in, state_out, dx, dy, prof, dt, budgets=None, workspace=Non
         rc = lib().monc_step(ia, oa, nscal, nx, ny, nz, float(dx), float(dy), *_prof(prof),
                              float(dt), b, ws, _stream(stream))
         _check(rc, "monc_step")
+
+
+class DynParams(C.Structure):
+    """monc_dyn_params: Coriolis parameter, geostrophic wind, gravity, theta reference."""
+    _fields_ = [("fcor", C.c_double), ("ug", C.c_double), ("vg", C.c_double),
+                ("grav", C.c_double), ("th0", C.c_double)]
+
+
+def _dyn(p):
+    if isinstance(p, DynParams):
+        return C.byref(p)
+    return C.byref(DynParams(*[float(x) for x in p]))
+
+
+def monc_dyn_tend(u, v, theta, su, sv, sw, params, stream=None):
+    """Coriolis and buoyancy source terms; params = (fcor, ug, vg, grav, th0)."""
+    torch = _torch()
+    nx, ny, nz = _grid(u)
+    sh = tuple(u.shape)
+    args = [_ptr(t, torch.float64, sh, n) for t, n in
+            zip((u, v, theta, su, sv, sw), ("u", "v", "theta", "su", "sv", "sw"))]
+    rc = lib().monc_dyn_tend(*args, nx, ny, nz, _dyn(params), _stream(stream))
+    _check(rc, "monc_dyn_tend")
+
+
+def monc_combine_step(state_in, ta, tb, state_out, dt, stream=None):
+    """state_out[f] = state_in[f] + dt (ta[f] + tb[f]); tb may be None or hold None."""
+    torch = _torch()
+    nx, ny, nz = _grid(state_in[0])
+    sh = tuple(state_in[0].shape)
+    n = len(state_in)
+    ia = _ptrs(state_in, torch.float64, sh, "state_in")
+    aa = _ptrs(ta, torch.float64, sh, "ta")
+    oa = _ptrs(state_out, torch.float64, sh, "state_out")
+    ba = None
+    if tb is not None:
+        ba = (C.c_void_p * n)()
+        for f, t in enumerate(tb):
+            ba[f] = None if t is None else _ptr(t, torch.float64, sh, f"tb[{f}]").value
+    rc = lib().monc_combine_step(n, ia, aa, ba, oa, nx, ny, nz, float(dt), _stream(stream))
+    _check(rc, "monc_combine_step")
+
+
+def monc_hybrid_step(state_in, state_out, tend, dyn_tend, dx, dy, prof, dt, params,
+                     stream=None, side_stream=None):
+    """Advection source terms on `stream`, Coriolis and buoyancy on `side_stream`,
+    then one combine pass (state_out = state_in + dt (s_adv + s_dyn))."""
+    torch = _torch()
+    nx, ny, nz = _grid(state_in[0])
+    sh = tuple(state_in[0].shape)
+    nscal = len(state_in) - 3
+    ia = _ptrs(state_in, torch.float64, sh, "state_in")
+    oa = _ptrs(state_out, torch.float64, sh, "state_out")
+    ta = _ptrs(tend, torch.float64, sh, "tend")
+    da = _ptrs(dyn_tend, torch.float64, sh, "dyn_tend")
+    s_main = _stream(stream)
+    s_side = s_main if side_stream is None else _stream(side_stream)
+    rc = lib().monc_hybrid_step(ia, oa, ta, da, nscal, nx, ny, nz, float(dx), float(dy),
+                                *_prof(prof), float(dt), _dyn(params), s_main, s_side)
+    _check(rc, "monc_hybrid_step")
+
+
+def monc_step_dyn(state_in, state_out, dx, dy, prof, dt, params, stream=None):
+    """One pass: PW + TVD + Coriolis + buoyancy, then the step."""
+    torch = _torch()
+    nx, ny, nz = _grid(state_in[0])
+    sh = tuple(state_in[0].shape)
+    nscal = len(state_in) - 3
+    ia = _ptrs(state_in, torch.float64, sh, "state_in")
+    oa = _ptrs(state_out, torch.float64, sh, "state_out")
+    rc = lib().monc_step_dyn(ia, oa, nscal, nx, ny, nz, float(dx), float(dy), *_prof(prof),
+                             float(dt), _dyn(params), _stream(stream))
+    _check(rc, "monc_step_dyn")
 
 
 def monc_step_mixed(state_in, state_out, phi0, dx, dy, prof, dt, budgets=None,

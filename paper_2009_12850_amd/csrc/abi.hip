@@ -105,6 +105,8 @@ void fill_args(AdvArgs& a, int nx, int ny, int nz, double dx, double dy, double 
     a.rho = rho;
     a.rhon = rhon;
     a.partials = nullptr;
+    a.dyn = 0;
+    a.fcor = a.ug = a.vg = a.gth = a.th0 = 0.0;
 }
 
 int do_halo(int bytes, int nfields, void* const* fields, int nx, int ny, int nz,
@@ -148,6 +150,44 @@ int do_step(double* const* state_in, double* const* state_out, int nscal,
                                            step_grid(nx, ny, nz, mixed), budgets, s),
                        "step/budgets"));
     return MONC_OK;
+}
+
+int check_dyn(const monc_dyn_params* p) {
+    if (!p) return fail(MONC_EINVAL, "dynamics parameters are NULL");
+    if (!isfinite(p->fcor) || !isfinite(p->ug) || !isfinite(p->vg) ||
+        !isfinite(p->grav) || !isfinite(p->th0))
+        return fail(MONC_EINVAL, "dynamics parameters must be finite");
+    if (!(p->th0 > 0.0)) return fail(MONC_EINVAL, "th0 must be > 0 (got %g)", p->th0);
+    return MONC_OK;
+}
+
+void set_dyn(AdvArgs& a, const monc_dyn_params* p) {
+    a.dyn = 1;
+    a.fcor = p->fcor;
+    a.ug = p->ug;
+    a.vg = p->vg;
+    a.gth = p->grav / p->th0;
+    a.th0 = p->th0;
+}
+
+DynArgs dyn_args(const double* u, const double* v, const double* th, double* su, double* sv,
+                 double* sw, int nx, int ny, int nz, const monc_dyn_params* p) {
+    DynArgs d;
+    d.u = u;
+    d.v = v;
+    d.th = th;
+    d.su = su;
+    d.sv = sv;
+    d.sw = sw;
+    d.nx = nx;
+    d.ny = ny;
+    d.nz = nz;
+    d.fcor = p->fcor;
+    d.ug = p->ug;
+    d.vg = p->vg;
+    d.gth = p->grav / p->th0;
+    d.th0 = p->th0;
+    return d;
 }
 
 }  // namespace
@@ -285,6 +325,135 @@ int monc_step_mixed(double* const* state_in, double* const* state_out, int nscal
                     double* budgets, void* workspace, monc_stream_t stream) {
     return do_step(state_in, state_out, nscal, phi0, nx, ny, nz, dx, dy, rdz, rho, rhon,
                    dt, budgets, workspace, stream, true);
+}
+
+int monc_dyn_tend(const double* u, const double* v, const double* theta, double* su,
+                  double* sv, double* sw, int nx, int ny, int nz, const monc_dyn_params* p,
+                  monc_stream_t stream) {
+    TRY(check_grid(nx, ny, nz));
+    TRY(check_dyn(p));
+    const void* in[3] = {u, v, theta};
+    const void* out[3] = {su, sv, sw};
+    TRY(check_ptrs(3, in, "inputs"));
+    TRY(check_ptrs(3, out, "outputs"));
+    TRY(check_alias(3, in, 3, out));
+    return hip_status(
+        launch_dyn_tend(dyn_args(u, v, theta, su, sv, sw, nx, ny, nz, p), (hipStream_t)stream),
+        "dyn_tend");
+}
+
+int monc_combine_step(int nfields, const double* const* in, const double* const* ta,
+                      const double* const* tb, double* const* out, int nx, int ny, int nz,
+                      double dt, monc_stream_t stream) {
+    TRY(check_grid(nx, ny, nz));
+    TRY(check_dt(dt));
+    if (nfields < 1 || nfields > 3 + MONC_MAX_SCALARS)
+        return fail(MONC_EINVAL, "nfields must be in [1, %d]", 3 + MONC_MAX_SCALARS);
+    TRY(check_ptrs(nfields, in, "in"));
+    TRY(check_ptrs(nfields, ta, "ta"));
+    TRY(check_ptrs(nfields, out, "out"));
+    TRY(check_alias(nfields, (const void* const*)in, nfields, (const void* const*)out));
+    TRY(check_alias(nfields, (const void* const*)ta, nfields, (const void* const*)out));
+    if (tb) {
+        for (int f = 0; f < nfields; f++)
+            for (int g = 0; g < nfields; g++)
+                if (tb[f] && tb[f] == out[g])
+                    return fail(MONC_EINVAL, "output %d aliases tb[%d]", g, f);
+    }
+    return hip_status(launch_combine(nfields, in, ta, tb, out, nx, ny, nz, dt,
+                                     (hipStream_t)stream),
+                      "combine_step");
+}
+
+int monc_hybrid_step(double* const* state_in, double* const* state_out, double* const* tend,
+                     double* const* dyn_tend, int nscal, int nx, int ny, int nz, double dx,
+                     double dy, const double* rdz, const double* rho, const double* rhon,
+                     double dt, const monc_dyn_params* p, monc_stream_t stream,
+                     monc_stream_t side_stream) {
+    TRY(check_grid(nx, ny, nz));
+    TRY(check_spacing(dx, dy));
+    TRY(check_dt(dt));
+    TRY(check_prof(rdz, rho, rhon));
+    TRY(check_nscal(nscal));
+    TRY(check_dyn(p));
+    if (nscal < 1) return fail(MONC_EINVAL, "the hybrid step needs theta (nscal >= 1)");
+    const int nf = 3 + nscal;
+    TRY(check_ptrs(nf, state_in, "state_in"));
+    TRY(check_ptrs(nf, state_out, "state_out"));
+    TRY(check_ptrs(nf, tend, "tend"));
+    TRY(check_ptrs(3, dyn_tend, "dyn_tend"));
+    {
+        // no buffer written here may alias any other buffer of the call
+        const void* all[4 * (3 + MAXS)];
+        int n = 0;
+        for (int f = 0; f < nf; f++) all[n++] = state_in[f];
+        const int nin = n;
+        for (int f = 0; f < nf; f++) all[n++] = state_out[f];
+        for (int f = 0; f < nf; f++) all[n++] = tend[f];
+        for (int f = 0; f < 3; f++) all[n++] = dyn_tend[f];
+        TRY(check_alias(nin, all, n - nin, all + nin));
+    }
+    hipStream_t s = (hipStream_t)stream, side = (hipStream_t)side_stream;
+    const bool two = side != s;
+    hipEvent_t start = nullptr, done = nullptr;
+    if (two) {
+        TRY(hip_status(hipEventCreateWithFlags(&start, hipEventDisableTiming), "event"));
+        TRY(hip_status(hipEventCreateWithFlags(&done, hipEventDisableTiming), "event"));
+        TRY(hip_status(hipEventRecord(start, s), "event record"));
+        TRY(hip_status(hipStreamWaitEvent(side, start, 0), "stream wait"));
+    }
+    // the other components on the side stream
+    TRY(hip_status(launch_dyn_tend(dyn_args(state_in[0], state_in[1], state_in[3], dyn_tend[0],
+                                            dyn_tend[1], dyn_tend[2], nx, ny, nz, p),
+                                   two ? side : s),
+                   "hybrid/dyn_tend"));
+    if (two) TRY(hip_status(hipEventRecord(done, side), "event record"));
+    // the advection source terms on the main stream
+    AdvArgs a;
+    fill_args(a, nx, ny, nz, dx, dy, dt, rdz, rho, rhon, nscal);
+    for (int f = 0; f < nf; f++) {
+        a.in[f] = state_in[f];
+        a.out[f] = tend[f];
+    }
+    TRY(hip_status(launch_advect(MONC_F64, TEND, true, true, false, a, s), "hybrid/advect"));
+    if (two) {
+        TRY(hip_status(hipStreamWaitEvent(s, done, 0), "stream wait"));
+        // released by the runtime once the recorded work has completed
+        hipEventDestroy(start);
+        hipEventDestroy(done);
+    }
+    const double* tb[3 + MAXS];
+    for (int f = 0; f < nf; f++) tb[f] = f < 3 ? dyn_tend[f] : nullptr;
+    return hip_status(launch_combine(nf, (const double* const*)state_in,
+                                     (const double* const*)tend, tb, state_out, nx, ny, nz,
+                                     dt, s),
+                      "hybrid/combine");
+}
+
+int monc_step_dyn(double* const* state_in, double* const* state_out, int nscal, int nx,
+                  int ny, int nz, double dx, double dy, const double* rdz, const double* rho,
+                  const double* rhon, double dt, const monc_dyn_params* p,
+                  monc_stream_t stream) {
+    TRY(check_grid(nx, ny, nz));
+    TRY(check_spacing(dx, dy));
+    TRY(check_dt(dt));
+    TRY(check_prof(rdz, rho, rhon));
+    TRY(check_nscal(nscal));
+    TRY(check_dyn(p));
+    if (nscal < 1) return fail(MONC_EINVAL, "the fused dynamics step needs theta (nscal >= 1)");
+    const int nf = 3 + nscal;
+    TRY(check_ptrs(nf, state_in, "state_in"));
+    TRY(check_ptrs(nf, state_out, "state_out"));
+    TRY(check_alias(nf, (const void* const*)state_in, nf, (const void* const*)state_out));
+    AdvArgs a;
+    fill_args(a, nx, ny, nz, dx, dy, dt, rdz, rho, rhon, nscal);
+    for (int f = 0; f < nf; f++) {
+        a.in[f] = state_in[f];
+        a.out[f] = state_out[f];
+    }
+    set_dyn(a, p);
+    return hip_status(launch_advect(MONC_F64, STEP, true, true, false, a, (hipStream_t)stream),
+                      "step_dyn");
 }
 
 int monc_cast_working(int dtype, int nfields, const double* const* src, void* const* work,
@@ -503,7 +672,7 @@ int monc_correct_step(double* const* state_in, double* const* tend, const float*
         return fail(MONC_EINVAL, "NULL pointer");
     if (!(growth > 0.0)) return fail(MONC_EINVAL, "growth must be > 0 (got %g)", growth);
     for (int q = 0; q < 4; q++)
-        if (!std::isfinite(scale[q])) return fail(MONC_EINVAL, "scale[%d] is not finite", q);
+        if (!isfinite(scale[q])) return fail(MONC_EINVAL, "scale[%d] is not finite", q);
     return hip_status(launch_correct_step(state_in, tend, gx, gy, state_out, nx, ny, nz, dx, dy,
                                           scale, rdz, rho, rhon, dt, growth, flags, workspace,
                                           (hipStream_t)stream),

@@ -200,7 +200,7 @@ struct TileJob {
     int first_pass;       // write the budget slots this group does not own
 };
 
-template <typename Ts, typename T, int MODE, bool PW, int NS, bool BUD, int NCH>
+template <typename Ts, typename T, int MODE, bool PW, int NS, bool BUD, int NCH, bool DYN>
 __device__ __forceinline__ void march_tile(const AdvArgs& a, const TileJob& tj,
                                            unsigned char* smem_raw) {
     using To = typename std::conditional<std::is_same<T, double>::value, double, float>::type;
@@ -592,9 +592,27 @@ __device__ __forceinline__ void march_tile(const AdvArgs& a, const TileJob& tj,
                 bstore(plane_rsrc((To*)a.out[1] + gplane, wbytes), woff, (To)sv);
                 bstore(plane_rsrc((To*)a.out[2] + gplane, wbytes), woff, (To)sw);
             } else {
-                const double nu = (double)U[1] + dt * (double)su;
-                const double nv = (double)V[1] + dt * (double)sv;
-                const double nw = k < nz - 1 ? (double)W[1] + dt * (double)sw : 0.0;
+                double nu, nv, nw;
+                if constexpr (DYN) {
+                    // the other dynamics source terms, added to the advection
+                    // source terms before the step (scalar 0 is theta; FP64
+                    // state, no anomaly offset)
+                    static_assert(NS >= 1 && std::is_same<T, double>::value, "DYN needs theta");
+                    const double du = coriolis_u(a.fcor, a.vg, (double)vc, (double)ve,
+                                                 (double)vs, (double)v_es);
+                    const double dv = coriolis_v(a.fcor, a.ug, (double)uc, (double)um,
+                                                 (double)un, (double)u_nw);
+                    const double th_k = (double)P[0][1];
+                    const double th_kp = (double)sph[owns + 1] + off[0];
+                    const double dw = buoyancy_w(a.gth, a.th0, th_k, th_kp);
+                    nu = (double)U[1] + dt * ((double)su + du);
+                    nv = (double)V[1] + dt * ((double)sv + dv);
+                    nw = k < nz - 1 ? (double)W[1] + dt * ((double)sw + dw) : 0.0;
+                } else {
+                    nu = (double)U[1] + dt * (double)su;
+                    nv = (double)V[1] + dt * (double)sv;
+                    nw = k < nz - 1 ? (double)W[1] + dt * (double)sw : 0.0;
+                }
                 bstore(plane_rsrc((double*)a.out[0] + gplane, wbytes64), woff64, nu);
                 bstore(plane_rsrc((double*)a.out[1] + gplane, wbytes64), woff64, nv);
                 bstore(plane_rsrc((double*)a.out[2] + gplane, wbytes64), woff64, nw);
@@ -656,14 +674,17 @@ __device__ __forceinline__ void march_tile(const AdvArgs& a, const TileJob& tj,
                       phi0c[s] * D * rhon_inv;
             FXm[s] = fxp[s];
         }
-        // the tile's y-faces j0-1/2: one (scalar, chunk) job per wave from
-        // wave 0 up, so that the extra work lands on different SIMDs
-        for (int jb = wv; jb < NS * NCH; jb += MARCH_WAVES) {
-            const int s = jb / NCH;
-            const int kb = 64 * (jb % NCH) + lane;
-            const T* ph = sph + s * SC * CSZ + 2 * CSZ + 2 + kb;  // column j0
-            sfy[(s * FC) * NZP + kb] = tvd_flux<T>(v_i[2 + kb], ph[-2 * CSZ], ph[-CSZ], ph[0],
-                                                   ph[CSZ], cfy, rfy, (T)1);
+        // the tile's first column also computes the y-face j0-1/2 (one
+        // wave-uniform block for all scalars; spreading these faces over
+        // waves on different SIMDs measured no faster)
+        if (cc == 0) {
+#pragma unroll
+            for (int s = 0; s < NS; s++) {
+                const T* ph = sph + s * SC * CSZ;
+                sfy[(s * FC) * NZP + k] =
+                    tvd_flux<T>(vs, ph[owns - 2 * CSZ], ph[owns - CSZ], ph[owns], ph[owns + CSZ],
+                                cfy, rfy, (T)1);
+            }
         }
         __syncthreads();
 
@@ -748,7 +769,8 @@ __device__ __forceinline__ void march_tile(const AdvArgs& a, const TileJob& tj,
 }
 
 // One workgroup per tile.
-template <typename Ts, typename T, int MODE, bool PW, int NS, bool BUD, int NCH>
+template <typename Ts, typename T, int MODE, bool PW, int NS, bool BUD, int NCH,
+          bool DYN = false>
 __global__ void __launch_bounds__((march_waves<Ts, T>() * 64))
     __attribute__((amdgpu_waves_per_eu(2))) advect_march(MarchArgs m) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -765,7 +787,7 @@ __global__ void __launch_bounds__((march_waves<Ts, T>() * 64))
     t.seg = b / m.njt;
     t.partial_row = BUD ? m.a.partials + (size_t)blockIdx.x * NB : nullptr;
     t.first_pass = m.first_pass;
-    march_tile<Ts, T, MODE, PW, NS, BUD, NCH>(m.a, t, smem_raw);
+    march_tile<Ts, T, MODE, PW, NS, BUD, NCH, DYN>(m.a, t, smem_raw);
 }
 
 }  // namespace monc

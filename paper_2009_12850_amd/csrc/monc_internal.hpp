@@ -29,6 +29,10 @@ struct AdvArgs {
     const double* rho;
     const double* rhon;
     double* partials;           // [nblocks][NB] budget partials, or null
+    // other dynamics source terms fused into the step (monc_step_dyn):
+    // Coriolis toward (ug, vg) and buoyancy of scalar 0 (theta)
+    int dyn;
+    double fcor, ug, vg, gth, th0;
 };
 
 // Number of workgroups of the fused step launch (fixed for a grid so budget
@@ -47,6 +51,18 @@ hipError_t launch_budget_final(const double* partials, int nblocks,
 hipError_t launch_cast(int dtype, int nfields, const double* const* src,
                        void* const* dst, const double* offset, long n,
                        hipStream_t s);
+
+// Other dynamics source terms and the combined step (dynamics.hip).
+struct DynArgs {
+    const double *u, *v, *th;
+    double *su, *sv, *sw;
+    int nx, ny, nz;
+    double fcor, ug, vg, gth, th0;
+};
+hipError_t launch_dyn_tend(const DynArgs& d, hipStream_t s);
+hipError_t launch_combine(int nfields, const double* const* in, const double* const* ta,
+                          const double* const* tb, double* const* out, int nx, int ny,
+                          int nz, double dt, hipStream_t s);
 
 // Learned correction (learned.hip).
 hipError_t launch_restrict4(int nscal, const double* const* fine, double* const* coarse, int nx,

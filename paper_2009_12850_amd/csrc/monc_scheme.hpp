@@ -172,6 +172,33 @@ __device__ __forceinline__ T tvd_flux(T a, T pm, T p0, T p1, T p2, T cfac, T rfa
     return mass * fma(a, C, copysign(lim, d1));
 }
 
+// ---------------------------------------------------------------------------
+// Other source terms of the dynamics group, combined with the advection
+// source terms before the fields are stepped (the paper's hybrid structure,
+// Sec. 3: the non-advection components run beside the advection).  The paper
+// defines no such component; the two here are the f-plane Coriolis force
+// toward a geostrophic wind and the buoyancy of theta.
+//   coriolis_u: at the u point (i+1/2, j); v_c, v_e = v at (i, j), (i+1, j),
+//               v_s, v_es = v at (i, j-1), (i+1, j-1) (the four v points
+//               around it)
+//   coriolis_v: at the v point (i, j+1/2); u_c, u_w = u at (i, j), (i-1, j),
+//               u_n, u_nw = u at (i, j+1), (i-1, j+1)
+//   buoyancy_w: at the top face of cell k (k < nz-1): theta of cells k, k+1,
+//               gth = grav / th0
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double coriolis_u(double fcor, double vg, double v_c, double v_e,
+                                             double v_s, double v_es) {
+    return fcor * ((((v_c + v_e) + v_s) + v_es) * 0.25 - vg);
+}
+__device__ __forceinline__ double coriolis_v(double fcor, double ug, double u_c, double u_w,
+                                             double u_n, double u_nw) {
+    return -fcor * ((((u_c + u_w) + u_n) + u_nw) * 0.25 - ug);
+}
+__device__ __forceinline__ double buoyancy_w(double gth, double th0, double th_k,
+                                             double th_kp) {
+    return gth * ((th_k + th_kp) * 0.5 - th0);
+}
+
 // First-order upwind flux (used where the far-upwind cell lies outside the
 // column, next to the ground and the lid).
 template <typename T>

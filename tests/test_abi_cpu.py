@@ -209,3 +209,35 @@ def test_learned_entry_points_validate_before_launch():
                                None) == M.MONC_EINVAL
     assert M.monc_correct_step_workspace_bytes(8, 8, 8) > 0
     assert M.monc_mlp_backward_workspace_bytes(0) == 0
+
+
+def test_dynamics_entries_reject_bad_arguments():
+    # every case fails validation before any HIP call
+    L = M.lib()
+    good = M.DynParams(1e-4, 5.0, 0.0, 9.81, 300.0)
+    f = [C.c_void_p(0x1000 + 0x100 * n) for n in range(6)]
+    for bad in (M.DynParams(1e-4, 5.0, 0.0, 9.81, 0.0), M.DynParams(float("nan"), 0, 0, 9.81, 300),
+                M.DynParams(1e-4, float("inf"), 0, 9.81, 300)):
+        assert L.monc_dyn_tend(*f, 8, 8, 8, C.byref(bad), None) == M.MONC_EINVAL
+    assert L.monc_dyn_tend(*f, 8, 8, 8, None, None) == M.MONC_EINVAL
+    assert L.monc_dyn_tend(f[0], f[1], f[2], f[0], f[4], f[5], 8, 8, 8, C.byref(good),
+                           None) == M.MONC_EINVAL  # output aliases an input
+    assert L.monc_dyn_tend(*f, 8, 0, 8, C.byref(good), None) == M.MONC_EINVAL
+    ins = _arr([0x1000 + 0x100 * n for n in range(4)])
+    outs = _arr([0x9000 + 0x100 * n for n in range(4)])
+    tend = _arr([0x5000 + 0x100 * n for n in range(4)])
+    dyn = _arr([0x7000 + 0x100 * n for n in range(3)])
+    call_h = lambda nscal, i=ins, o=outs, t=tend, d=dyn, p=good: L.monc_hybrid_step(
+        i, o, t, d, nscal, 8, 8, 8, 1.0, 1.0, *_prof3(), 0.5, C.byref(p), None, None)
+    assert call_h(0) == M.MONC_EINVAL  # needs theta
+    assert call_h(1, t=outs) == M.MONC_EINVAL  # tendencies alias the output state
+    assert call_h(1, p=M.DynParams(0, 0, 0, 9.81, -1.0)) == M.MONC_EINVAL
+    call_s = lambda nscal, p=good: L.monc_step_dyn(ins, outs, nscal, 8, 8, 8, 1.0, 1.0,
+                                                   *_prof3(), 0.5, C.byref(p), None)
+    assert call_s(0) == M.MONC_EINVAL
+    assert call_s(1, M.DynParams(0, 0, 0, 9.81, 0.0)) == M.MONC_EINVAL
+    assert L.monc_combine_step(0, ins, tend, None, outs, 8, 8, 8, 0.5, None) == M.MONC_EINVAL
+    assert L.monc_combine_step(4, ins, tend, None, ins, 8, 8, 8, 0.5, None) == M.MONC_EINVAL
+    tb = _arr([0x9000, 0, 0, 0])  # tb[0] aliases out[0]
+    assert L.monc_combine_step(4, ins, tend, tb, outs, 8, 8, 8, 0.5, None) == M.MONC_EINVAL
+    assert L.monc_combine_step(4, ins, tend, None, outs, 8, 8, 8, 0.0, None) == M.MONC_EINVAL
