@@ -406,8 +406,84 @@ __device__ __forceinline__ bf16x8_t row_fragment(const RowGather& g, int kk) {
     return __builtin_bit_cast(bf16x8_t, t);
 }
 
+// Staged gather (STAGED): on grids of 32 levels whose columns come in groups of
+// four along y (ny % 4 == 0), a tile's 128 rows are four whole columns of one
+// x-plane.  The tile's whole neighbourhood -- 5 x-planes, the 4 columns plus 2
+// on each side, 32 levels, 4 fields: 160 columns of 32 values -- is read once,
+// every load issued before any is used, standardised and rounded to BF16 into
+// the LDS that later holds the hidden activations; the operand fragments are
+// then gathered from LDS.  The values are the same operations on the same
+// numbers, so the outputs are bitwise those of the direct gather.
+constexpr int SNZ = 32;                        // levels of a staged grid
+constexpr int SCOLS = FWD_ROWS / SNZ + 4;      // staged columns per x-plane (8)
+constexpr int SPT = 4 * 5 * SCOLS * SNZ / 256; // staged values per thread (20)
+constexpr int STAGE_BYTES_MAX = 4 * 32 * (HID + 8) * 2;  // the activation area
+static_assert(4 * 5 * SCOLS * SNZ * 2 <= STAGE_BYTES_MAX, "staged tile fits");
+static_assert(4 * 5 * SCOLS * SNZ == SPT * 256, "whole passes");
+
+__host__ __device__ constexpr bool infer_staged_ok(int ny, int nz) {
+    return nz == SNZ && ny % (FWD_ROWS / SNZ) == 0;
+}
+
 template <int ORIENT>
-__global__ void __launch_bounds__(256) mlp_infer(InferArgs a) {
+__device__ __forceinline__ void stage_tile(const InferArgs& a, long tile, uint16_t* st) {
+    const int nx = a.nx, ny = a.ny;
+    const long col0 = tile * (FWD_ROWS / SNZ);  // first column (i * ny + j) of the tile
+    const int i = (int)(col0 / ny), j0 = (int)(col0 % ny);
+    const int kk = threadIdx.x % SNZ;
+    double v[SPT];
+    // all loads first: SPT independent requests in flight per thread
+#pragma unroll
+    for (int q = 0; q < SPT; q++) {
+        const int col = q * (256 / SNZ) + (int)threadIdx.x / SNZ;  // (f, xi, c) column
+        const int c = col % SCOLS, xi = (col / SCOLS) % 5, f = col / (5 * SCOLS);
+        int ii = i + xi - 2, jj = j0 + c - 2;
+        ii = ii < 0 ? ii + nx : (ii >= nx ? ii - nx : ii);
+        ii = ii < 0 ? ii + nx : (ii >= nx ? ii - nx : ii);
+        jj = jj < 0 ? jj + ny : (jj >= ny ? jj - ny : jj);
+        jj = jj < 0 ? jj + ny : (jj >= ny ? jj - ny : jj);
+        v[q] = a.f[f][((long)(ii + 2) * (ny + 4) + (jj + 2)) * SNZ + kk];
+    }
+#pragma unroll
+    for (int q = 0; q < SPT; q++) {
+        const int col = q * (256 / SNZ) + (int)threadIdx.x / SNZ;
+        const int f = col / (5 * SCOLS);
+        st[q * 256 + threadIdx.x] = f2bf((float)((v[q] - a.mean[f]) * a.inv_std[f]));
+    }
+}
+
+// Fragment of block kk from the staged tile: lane's local column lc, level k.
+template <int ORIENT>
+__device__ __forceinline__ bf16x8_t row_fragment_staged(const uint16_t* st, int lc, int k,
+                                                        int h, int kk) {
+    const int pr = kk / 10, p0 = 8 * (kk % 10);
+    const int fi = 2 * pr + h;
+    const int src = ORIENT ? (fi == 0 ? 1 : (fi == 1 ? 0 : fi)) : fi;
+    const uint16_t* base = st + src * 5 * SCOLS * SNZ + lc * SNZ;
+    int kc[3];
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        const int q = k + c - 1;
+        kc[c] = q < 0 ? 0 : (q > SNZ - 1 ? SNZ - 1 : q);
+    }
+    u16x8 t;
+#pragma unroll
+    for (int e = 0; e < 8; e++) {
+        const int pos = p0 + e;
+        if (pos < 75) {
+            const int a5 = pos / 15, b5 = (pos / 3) % 5, c3 = pos % 3;
+            const int xi = ORIENT ? b5 : a5, yj = ORIENT ? a5 : b5;
+            t.v[e] = base[(xi * SCOLS + yj) * SNZ + kc[c3]];
+        } else {
+            t.v[e] = 0;
+        }
+    }
+    return __builtin_bit_cast(bf16x8_t, t);
+}
+
+template <int ORIENT, bool STAGED>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+    mlp_infer(InferArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     uint16_t* sw = reinterpret_cast<uint16_t*>(smem);  // pack
     uint16_t* sH = sw + S_WEND;                           // [4][32][LWH]
@@ -426,19 +502,37 @@ __global__ void __launch_bounds__(256) mlp_infer(InferArgs a) {
         const long row0 = tile * FWD_ROWS + 32 * w;
         const long ar = row0 + (lane & 31);
         const bool live = ar < a.m;
-        RowGather g;
-        row_setup<ORIENT>(a, live ? ar : 0, h, g);
-        // layer 1: fragments built block by block straight from the fields
         f32x16_t acc1[2] = {{}, {}};
-        // fully unrolled: every slot index is then a constant and the gather
-        // state stays in registers
+        if constexpr (STAGED) {
+            uint16_t* st = sH;  // the activation area, free until layer 1 ends
+            stage_tile<ORIENT>(a, tile, st);
+            __syncthreads();
+            const int lc = w, k = lane & 31;  // 32 rows per wave = one column
 #pragma unroll
-        for (int kk = 0; kk < KP / 16; kk++) {
-            const int ks = kslot(kk, h);
-            const bf16x8_t av = live ? row_fragment(g, kk) : zero8();
+            for (int kk = 0; kk < KP / 16; kk++) {
+                const int ks = kslot(kk, h);
+                const bf16x8_t av = row_fragment_staged<ORIENT>(st, lc, k, h, kk);
 #pragma unroll
-            for (int nt = 0; nt < 2; nt++)
-                acc1[nt] = mfma(av, ld8(sw + S_W1 + (32 * nt + (lane & 31)) * LW1 + ks), acc1[nt]);
+                for (int nt = 0; nt < 2; nt++)
+                    acc1[nt] =
+                        mfma(av, ld8(sw + S_W1 + (32 * nt + (lane & 31)) * LW1 + ks), acc1[nt]);
+            }
+            __syncthreads();  // every wave is done with the staged tile
+        } else {
+            RowGather g;
+            row_setup<ORIENT>(a, live ? ar : 0, h, g);
+            // layer 1: fragments built block by block straight from the
+            // fields; fully unrolled, so every slot index is a constant and the
+            // gather state stays in registers
+#pragma unroll
+            for (int kk = 0; kk < KP / 16; kk++) {
+                const int ks = kslot(kk, h);
+                const bf16x8_t av = live ? row_fragment(g, kk) : zero8();
+#pragma unroll
+                for (int nt = 0; nt < 2; nt++)
+                    acc1[nt] =
+                        mfma(av, ld8(sw + S_W1 + (32 * nt + (lane & 31)) * LW1 + ks), acc1[nt]);
+            }
         }
 #pragma unroll
         for (int nt = 0; nt < 2; nt++) {
@@ -1029,12 +1123,18 @@ hipError_t launch_mlp_infer(const double* const* state, int nx, int ny, int nz,
                            const uint16_t* wpack, float* Y, hipStream_t s) {
     static bool attr[2] = {false, false};
     static int ncu = 0;
-    const void* kern = orient ? (const void*)mlp_infer<1> : (const void*)mlp_infer<0>;
-    if (!attr[orient]) {
+    static bool attr_st[2] = {false, false};
+    const bool staged = infer_staged_ok(ny, nz);
+    const void* kern = staged ? (orient ? (const void*)mlp_infer<1, true>
+                                        : (const void*)mlp_infer<0, true>)
+                              : (orient ? (const void*)mlp_infer<1, false>
+                                        : (const void*)mlp_infer<0, false>);
+    bool& done = staged ? attr_st[orient] : attr[orient];
+    if (!done) {
         hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                            (int)FWD_LDS);
         if (e != hipSuccess) return e;
-        attr[orient] = true;
+        done = true;
     }
     if (ncu == 0) {
         int dev = 0;
@@ -1057,10 +1157,17 @@ hipError_t launch_mlp_infer(const double* const* state, int nx, int ny, int nz,
     a.Y = Y;
     const long ntiles = (a.m + FWD_ROWS - 1) / FWD_ROWS;
     const int grid = (int)(ntiles < 2L * ncu ? ntiles : 2L * ncu);
-    if (orient)
-        mlp_infer<1><<<grid, 256, FWD_LDS, s>>>(a);
-    else
-        mlp_infer<0><<<grid, 256, FWD_LDS, s>>>(a);
+    if (staged) {
+        if (orient)
+            mlp_infer<1, true><<<grid, 256, FWD_LDS, s>>>(a);
+        else
+            mlp_infer<0, true><<<grid, 256, FWD_LDS, s>>>(a);
+    } else {
+        if (orient)
+            mlp_infer<1, false><<<grid, 256, FWD_LDS, s>>>(a);
+        else
+            mlp_infer<0, false><<<grid, 256, FWD_LDS, s>>>(a);
+    }
     return hipGetLastError();
 }
 
