@@ -204,6 +204,7 @@ template <typename Ts, typename T, int MODE, bool PW, int NS, bool BUD, int NCH,
 __device__ __forceinline__ void march_tile(const AdvArgs& a, const TileJob& tj,
                                            unsigned char* smem_raw) {
     using To = typename std::conditional<std::is_same<T, double>::value, double, float>::type;
+    constexpr bool STEP64 = MODE == STEP && std::is_same<T, double>::value;
     constexpr int MARCH_WAVES = march_waves<Ts, T>();
     constexpr int TJ = MARCH_WAVES / NCH;
     constexpr int NZP = 64 * NCH;
@@ -295,8 +296,11 @@ __device__ __forceinline__ void march_tile(const AdvArgs& a, const TileJob& tj,
 #pragma unroll
     for (int s = 0; s < NS; s++) {
         fptr[3 + s] = (const Ts*)a.in[3 + tj.s0 + s];
-        off[s] = MODE == STEP ? a.phi0[tj.s0 + s] : 0.0;
-        phi0c[s] = (T)a.phi0[tj.s0 + s];
+        // the FP64 step keeps the state as it is (no anomaly offset): a
+        // compile-time zero, so the subtractions and the constant's term fold
+        // away
+        off[s] = STEP64 ? 0.0 : (MODE == STEP ? a.phi0[tj.s0 + s] : 0.0);
+        phi0c[s] = STEP64 ? (T)0 : (T)a.phi0[tj.s0 + s];
     }
     // Periodic neighbours are read at wrapped indices: the arrays' halos are
     // never read.  plane ii of field pointer p (uniform) ...
@@ -670,8 +674,8 @@ __device__ __forceinline__ void march_tile(const AdvArgs& a, const TileJob& tj,
             // everything but the faces shared with the neighbours (j-1/2,
             // k-1/2); stored values are anomalies from phi0: add the term of
             // the constant
-            part[s] = -((fxp[s] - FXm[s]) * rdx + fyp * rdy) - rhon_inv * rdz * fz -
-                      phi0c[s] * D * rhon_inv;
+            part[s] = -((fxp[s] - FXm[s]) * rdx + fyp * rdy) - rhon_inv * rdz * fz;
+            if constexpr (!STEP64) part[s] -= phi0c[s] * D * rhon_inv;
             FXm[s] = fxp[s];
         }
         // the tile's first column also computes the y-face j0-1/2 (one
