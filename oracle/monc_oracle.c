@@ -694,3 +694,52 @@ int oracle_dyn(const double *u, const double *v, const double *th, double *su,
     }
     return OR_OK;
 }
+
+/* ---------------------------------------------------------------------------
+ * MONC's other scalar scheme: the scalar advected with the centred flux form
+ * (the Piacsek-Williams scheme of Sec. 3.1 applied to a cell-centred field).
+ * Face value = mean of the two cells beside the face:
+ *   Fx(i+1/2) = rhon_k u_i (phi_i + phi_{i+1})/2,   Fy alike,
+ *   Fz(k+1/2) = rho_k w_k (phi_k + phi_{k+1})/2 for k < nz-1, zero through
+ *   the ground and the lid,
+ *   s = -(1/rhon_k)[(Fx(i+1/2)-Fx(i-1/2))/dx + (Fy(j+1/2)-Fy(j-1/2))/dy
+ *                   + rdz_k (Fz(k+1/2)-Fz(k-1/2))].
+ * Neighbours at wrapped periodic indices.
+ * ------------------------------------------------------------------------- */
+static double cflux_x(const grid_t *g, const double *u, const double *phi, int i, int j,
+                      int k, const double *rhon) {
+    int ip = posmod(i + 1, g->nx);
+    int ii = posmod(i, g->nx);
+    return rhon[k] * u[at(g, ii, j, k)] * (phi[at(g, ii, j, k)] + phi[at(g, ip, j, k)]) / 2.0;
+}
+static double cflux_y(const grid_t *g, const double *v, const double *phi, int i, int j,
+                      int k, const double *rhon) {
+    int jp = posmod(j + 1, g->ny);
+    int jj = posmod(j, g->ny);
+    return rhon[k] * v[at(g, i, jj, k)] * (phi[at(g, i, jj, k)] + phi[at(g, i, jp, k)]) / 2.0;
+}
+static double cflux_z(const grid_t *g, const double *w, const double *phi, int i, int j,
+                      int k, const double *rho) {
+    if (k < 0 || k >= g->nz - 1) return 0.0;
+    return rho[k] * w[at(g, i, j, k)] * (phi[at(g, i, j, k)] + phi[at(g, i, j, k + 1)]) / 2.0;
+}
+
+int oracle_pw_scalar(const double *u, const double *v, const double *w, const double *phi,
+                     double *s, int nx, int ny, int nz, double dx, double dy,
+                     const double *rdz, const double *rho, const double *rhon) {
+    if (!u || !v || !w || !phi || !s || nx < 1 || ny < 1 || nz < 1) return OR_EINVAL;
+    grid_t g = {nx, ny, nz};
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < nx; i++)
+        for (int j = 0; j < ny; j++)
+            for (int k = 0; k < nz; k++) {
+                double fx = (cflux_x(&g, u, phi, i, j, k, rhon) -
+                             cflux_x(&g, u, phi, i - 1, j, k, rhon)) / dx;
+                double fy = (cflux_y(&g, v, phi, i, j, k, rhon) -
+                             cflux_y(&g, v, phi, i, j - 1, k, rhon)) / dy;
+                double fz = rdz[k] * (cflux_z(&g, w, phi, i, j, k, rho) -
+                                      cflux_z(&g, w, phi, i, j, k - 1, rho));
+                s[at(&g, i, j, k)] = -(fx + fy + fz) / rhon[k];
+            }
+    return OR_OK;
+}

@@ -65,6 +65,7 @@ def lib():
         L.oracle_restrict4.argtypes = [C.POINTER(dp), C.POINTER(dp), i, i, i, i, dp, dp, dp,
                                        dp, dp, dp]
         L.oracle_dyn.argtypes = [dp, dp, dp, dp, dp, dp, i, i, i, d, d, d, d, d]
+        L.oracle_pw_scalar.argtypes = [dp, dp, dp, dp, dp, i, i, i, d, d, dp, dp, dp]
         _lib = L
     return _lib
 
@@ -238,4 +239,29 @@ def step_dyn(state, g, dt, fcor, ug, vg, grav, th0, allow_cfl=False):
     for s in range(len(state) - 3):
         st = tvd(state[0], state[1], state[2], state[3 + s], g, dt, allow_cfl=allow_cfl)
         out[3 + s][sl] = state[3 + s][sl] + dt * st[sl]
+    return out
+
+
+def pw_scalar(u, v, w, phi, g):
+    """Source term of a scalar advected with the centred flux form."""
+    nx, ny, nz = _shape(u)
+    s = np.zeros_like(phi)
+    rdz, rho, rhon = _prof(g)
+    _check(lib().oracle_pw_scalar(_p(u), _p(v), _p(w), _p(phi), _p(s), nx, ny, nz, g.dx, g.dy,
+                                  _p(rdz), _p(rho), _p(rhon)), "pw_scalar")
+    return s
+
+
+def step_pw_scalars(state, g, dt):
+    """One forward step with PW momentum and centred-flux scalars:
+    f_out = f_in + dt s, w = 0 on the lid (inputs are not modified)."""
+    nx, ny, nz = _shape(state[0])
+    state = [halo_fill(f) for f in state]
+    tend = list(pw(state[0], state[1], state[2], g))
+    tend += [pw_scalar(state[0], state[1], state[2], q, g) for q in state[3:]]
+    out = [np.full_like(f, np.nan) for f in state]
+    sl = (slice(2, nx + 2), slice(2, ny + 2), slice(None))
+    for f in range(len(state)):
+        out[f][sl] = state[f][sl] + dt * tend[f][sl]
+    out[2][2:nx + 2, 2:ny + 2, nz - 1] = 0.0
     return out
