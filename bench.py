@@ -184,6 +184,9 @@ def bench_dynamics(torch, M, state, g, prof, w, stream, npts, nf, reps):
                                                   side_stream=side),
         "fused": lambda: M.monc_step_dyn(state[0], state[1], g.dx, g.dy, prof, w.dt,
                                          DYN_PARAMS, stream),
+        # MONC's other scalar scheme (centred flux form) in the same pass
+        "pw_scalars_step": lambda: M.monc_step_pw_scalars(state[0], state[1], g.dx, g.dy,
+                                                          prof, w.dt, stream),
     }
     for name, fn in runs.items():
         fn()

@@ -410,6 +410,20 @@ int monc_step_dyn(double *const *state_in, double *const *state_out, int nscal, 
                   const double *rho, const double *rhon, double dt,
                   const monc_dyn_params *p, monc_stream_t stream);
 
+/* ---------------------------------------------------------------------------
+ * The FP64 step with MONC's other scalar scheme: every scalar advected with
+ * the centred flux form (the PW scheme of Sec. 3.1 applied to a cell-centred
+ * field) instead of the TVD scheme; momentum as in monc_step.  The face value
+ * is the mean of the two cells beside the face; the flux through a z-face is
+ * rho_k w_k times that mean, zero through the ground and the lid.  Centred
+ * fluxes are not bounded: this is the cheap, non-monotone choice.  Arguments
+ * as monc_step without budgets.
+ * ------------------------------------------------------------------------- */
+int monc_step_pw_scalars(double *const *state_in, double *const *state_out, int nscal,
+                         int nx, int ny, int nz, double dx, double dy, const double *rdz,
+                         const double *rho, const double *rhon, double dt,
+                         monc_stream_t stream);
+
 /* Map a budgets array (HOST copy, after synchronising) to a status:
  * MONC_ENONFINITE if any non-finite value was written, MONC_ECFL if the
  * largest Courant number exceeds 1, else MONC_OK. */

@@ -59,6 +59,7 @@ _SIGS = {
     "monc_hybrid_step": ([PP, PP, PP, PP, ip, ip, ip, ip, dp, dp, vp, vp, vp, dp, vp, vp, vp],
                          ip),
     "monc_step_dyn": ([PP, PP, ip, ip, ip, ip, dp, dp, vp, vp, vp, dp, vp, vp], ip),
+    "monc_step_pw_scalars": ([PP, PP, ip, ip, ip, ip, dp, dp, vp, vp, vp, dp, vp], ip),
     "monc_budgets_check": ([DPTR], ip),
     "monc_restrict4": ([ip, PP, PP, ip, ip, ip, vp, vp, vp, vp, vp, vp, vp], ip),
     "monc_mlp_features": ([PP, ip, ip, ip, DPTR, ip, vp, ip, vp, vp], ip),
@@ -347,6 +348,19 @@ def monc_step_dyn(state_in, state_out, dx, dy, prof, dt, params, stream=None):
     rc = lib().monc_step_dyn(ia, oa, nscal, nx, ny, nz, float(dx), float(dy), *_prof(prof),
                              float(dt), _dyn(params), _stream(stream))
     _check(rc, "monc_step_dyn")
+
+
+def monc_step_pw_scalars(state_in, state_out, dx, dy, prof, dt, stream=None):
+    """The FP64 step with the scalars advected by the centred (PW) flux form."""
+    torch = _torch()
+    nx, ny, nz = _grid(state_in[0])
+    sh = tuple(state_in[0].shape)
+    nscal = len(state_in) - 3
+    ia = _ptrs(state_in, torch.float64, sh, "state_in")
+    oa = _ptrs(state_out, torch.float64, sh, "state_out")
+    rc = lib().monc_step_pw_scalars(ia, oa, nscal, nx, ny, nz, float(dx), float(dy),
+                                    *_prof(prof), float(dt), _stream(stream))
+    _check(rc, "monc_step_pw_scalars")
 
 
 def monc_step_mixed(state_in, state_out, phi0, dx, dy, prof, dt, budgets=None,

@@ -107,6 +107,7 @@ void fill_args(AdvArgs& a, int nx, int ny, int nz, double dx, double dy, double 
     a.partials = nullptr;
     a.dyn = 0;
     a.fcor = a.ug = a.vg = a.gth = a.th0 = 0.0;
+    a.spw = 0;
 }
 
 int do_halo(int bytes, int nfields, void* const* fields, int nx, int ny, int nz,
@@ -454,6 +455,31 @@ int monc_step_dyn(double* const* state_in, double* const* state_out, int nscal, 
     set_dyn(a, p);
     return hip_status(launch_advect(MONC_F64, STEP, true, true, false, a, (hipStream_t)stream),
                       "step_dyn");
+}
+
+int monc_step_pw_scalars(double* const* state_in, double* const* state_out, int nscal,
+                         int nx, int ny, int nz, double dx, double dy, const double* rdz,
+                         const double* rho, const double* rhon, double dt,
+                         monc_stream_t stream) {
+    TRY(check_grid(nx, ny, nz));
+    TRY(check_spacing(dx, dy));
+    TRY(check_dt(dt));
+    TRY(check_prof(rdz, rho, rhon));
+    TRY(check_nscal(nscal));
+    const int nf = 3 + nscal;
+    TRY(check_ptrs(nf, state_in, "state_in"));
+    TRY(check_ptrs(nf, state_out, "state_out"));
+    TRY(check_alias(nf, (const void* const*)state_in, nf, (const void* const*)state_out));
+    AdvArgs a;
+    fill_args(a, nx, ny, nz, dx, dy, dt, rdz, rho, rhon, nscal);
+    for (int f = 0; f < nf; f++) {
+        a.in[f] = state_in[f];
+        a.out[f] = state_out[f];
+    }
+    a.spw = 1;
+    return hip_status(launch_advect(MONC_F64, STEP, true, nscal > 0, false, a,
+                                    (hipStream_t)stream),
+                      "step_pw_scalars");
 }
 
 int monc_cast_working(int dtype, int nfields, const double* const* src, void* const* work,

@@ -46,7 +46,7 @@ __global__ void __launch_bounds__(ENS_WAVES * 64) __attribute__((amdgpu_waves_pe
         t.seg = w.z;
         t.partial_row = nullptr;
         t.first_pass = 1;
-        march_tile<double, float, STEP, true, NS, false, NCH, false>(M->a[parity], t, smem_raw);
+        march_tile<double, float, STEP, true, NS, false, NCH, 0>(M->a[parity], t, smem_raw);
         __syncthreads();  // the LDS is reused by the next item
     }
 }

@@ -200,11 +200,28 @@ struct TileJob {
     int first_pass;       // write the budget slots this group does not own
 };
 
-template <typename Ts, typename T, int MODE, bool PW, int NS, bool BUD, int NCH, bool DYN>
+// Options of the fused step (FP64 STEP only): OPT_DYN adds the other dynamics
+// source terms (Coriolis, buoyancy of scalar 0) to the momentum; OPT_SPW
+// advects the scalars with the centred (PW) flux form instead of TVD.
+enum { OPT_DYN = 1, OPT_SPW = 2 };
+
+template <typename Ts, typename T, int MODE, bool PW, int NS, bool BUD, int NCH, int OPT>
 __device__ __forceinline__ void march_tile(const AdvArgs& a, const TileJob& tj,
                                            unsigned char* smem_raw) {
     using To = typename std::conditional<std::is_same<T, double>::value, double, float>::type;
     constexpr bool STEP64 = MODE == STEP && std::is_same<T, double>::value;
+    constexpr bool DYN = (OPT & OPT_DYN) != 0;
+    constexpr bool SPW = (OPT & OPT_SPW) != 0;
+    static_assert(OPT == 0 || STEP64, "options of the FP64 step only");
+    // scalar face flux: TVD, or the centred flux form when SPW
+    auto sflux = [&](T a_, T pm, T p0, T p1, T p2, T cfac, T rfac, T mass) -> T {
+        if constexpr (SPW) {
+            (void)pm, (void)p2, (void)cfac, (void)rfac;
+            return centred_flux<T>(a_, p0, p1, mass);
+        } else {
+            return tvd_flux<T>(a_, pm, p0, p1, p2, cfac, rfac, mass);
+        }
+    };
     constexpr int MARCH_WAVES = march_waves<Ts, T>();
     constexpr int TJ = MARCH_WAVES / NCH;
     constexpr int NZP = 64 * NCH;
@@ -443,7 +460,7 @@ __device__ __forceinline__ void march_tile(const AdvArgs& a, const TileJob& tj,
 #pragma unroll
         for (int p = 0; p < 4; p++) P[s][p] = ld(fptr[3 + s], i0 - 2 + p, roff_s);
         // x-face i0-1/2: u of plane i0-1, scalars of planes i0-2 .. i0+1
-        FXm[s] = tvd_flux<T>(cvt0<T, Ts>(U[1]), cvt<T, Ts>(P[s][0], off[s]),
+        FXm[s] = sflux(cvt0<T, Ts>(U[1]), cvt<T, Ts>(P[s][0], off[s]),
                              cvt<T, Ts>(P[s][1], off[s]), cvt<T, Ts>(P[s][2], off[s]),
                              cvt<T, Ts>(P[s][3], off[s]), cfx, rfx, (T)1);
     }
@@ -547,7 +564,7 @@ __device__ __forceinline__ void march_tile(const AdvArgs& a, const TileJob& tj,
         // x-faces first: they need registers only, and overlap the LDS reads
 #pragma unroll
         for (int s = 0; s < NS; s++) {
-            fxp[s] = tvd_flux<T>(uc, cvt<T, Ts>(P[s][0], off[s]), cvt<T, Ts>(P[s][1], off[s]),
+            fxp[s] = sflux(uc, cvt<T, Ts>(P[s][0], off[s]), cvt<T, Ts>(P[s][1], off[s]),
                                  cvt<T, Ts>(P[s][2], off[s]), cvt<T, Ts>(P[s][3], off[s]), cfx,
                                  rfx, (T)1);
         }
@@ -656,13 +673,13 @@ __device__ __forceinline__ void march_tile(const AdvArgs& a, const TileJob& tj,
             const T pc = cvt<T, Ts>(P[s][1], off[s]);
             // lateral fluxes are computed without the common rhon factor
             const T ps = ph[owns - CSZ], pn = ph[owns + CSZ], pnn = ph[owns + 2 * CSZ];
-            const T fyp = tvd_flux<T>(vc, ps, pc, pn, pnn, cfy, rfy, (T)1);
+            const T fyp = sflux(vc, ps, pc, pn, pnn, cfy, rfy, (T)1);
             sfy[(s * FC + cc + 1) * NZP + k] = fyp;
             // top face k+1/2.  Where the far-upwind cell is outside the column
             // it is replaced by the upwind cell, which makes the limiter return
             // the upwind value (first-order upwind); on the lid w is zero.
             const T pb = ph[owns - 1], pt = ph[owns + 1], ptt = ph[owns + 2];
-            const T fz = tvd_flux<T>(wc, bottom ? pc : pb, pc, pt, top2 ? pt : ptt, cfz, rfz, rho);
+            const T fz = sflux(wc, bottom ? pc : pb, pc, pt, top2 ? pt : ptt, cfz, rfz, rho);
             fzk[s] = fz;
             // the chunk's top face, for the chunk above: lane 63 stores it, the
             // other lanes store into the sink (no branch; 64 lanes writing one
@@ -686,7 +703,7 @@ __device__ __forceinline__ void march_tile(const AdvArgs& a, const TileJob& tj,
             for (int s = 0; s < NS; s++) {
                 const T* ph = sph + s * SC * CSZ;
                 sfy[(s * FC) * NZP + k] =
-                    tvd_flux<T>(vs, ph[owns - 2 * CSZ], ph[owns - CSZ], ph[owns], ph[owns + CSZ],
+                    sflux(vs, ph[owns - 2 * CSZ], ph[owns - CSZ], ph[owns], ph[owns + CSZ],
                                 cfy, rfy, (T)1);
             }
         }
@@ -774,7 +791,7 @@ __device__ __forceinline__ void march_tile(const AdvArgs& a, const TileJob& tj,
 
 // One workgroup per tile.
 template <typename Ts, typename T, int MODE, bool PW, int NS, bool BUD, int NCH,
-          bool DYN = false>
+          int OPT = 0>
 __global__ void __launch_bounds__((march_waves<Ts, T>() * 64))
     __attribute__((amdgpu_waves_per_eu(2))) advect_march(MarchArgs m) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -791,7 +808,7 @@ __global__ void __launch_bounds__((march_waves<Ts, T>() * 64))
     t.seg = b / m.njt;
     t.partial_row = BUD ? m.a.partials + (size_t)blockIdx.x * NB : nullptr;
     t.first_pass = m.first_pass;
-    march_tile<Ts, T, MODE, PW, NS, BUD, NCH, DYN>(m.a, t, smem_raw);
+    march_tile<Ts, T, MODE, PW, NS, BUD, NCH, OPT>(m.a, t, smem_raw);
 }
 
 }  // namespace monc

@@ -12,9 +12,9 @@ struct Tiling {
 };
 Tiling march_tiling(int nx, int ny, int nz, int waves);
 
-template <typename Ts, typename T, int MODE, bool PW, int NS, bool BUD, int R, bool DYN>
+template <typename Ts, typename T, int MODE, bool PW, int NS, bool BUD, int R, int OPT>
 hipError_t launch_one(const MarchArgs& m, const Tiling& t, hipStream_t s) {
-    auto kern = advect_march<Ts, T, MODE, PW, NS, BUD, R, DYN>;
+    auto kern = advect_march<Ts, T, MODE, PW, NS, BUD, R, OPT>;
     constexpr size_t lds = march_lds_bytes<Ts, T, NS, R>();
     static bool attr_done = false;
     if (!attr_done) {
@@ -27,25 +27,26 @@ hipError_t launch_one(const MarchArgs& m, const Tiling& t, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <typename Ts, typename T, int MODE, bool PW, bool BUD, int R, bool DYN>
+template <typename Ts, typename T, int MODE, bool PW, bool BUD, int R, int OPT>
 hipError_t launch_ns(const MarchArgs& m, const Tiling& t, hipStream_t s) {
     switch (m.ns) {
         case 0:  // momentum only (the fused dynamics terms need theta)
-            if constexpr (PW && !DYN) return launch_one<Ts, T, MODE, PW, 0, BUD, R, DYN>(m, t, s);
+            if constexpr (PW && !(OPT & OPT_DYN))
+                return launch_one<Ts, T, MODE, PW, 0, BUD, R, OPT>(m, t, s);
             break;
-        case 1: return launch_one<Ts, T, MODE, PW, 1, BUD, R, DYN>(m, t, s);
-        case 2: return launch_one<Ts, T, MODE, PW, 2, BUD, R, DYN>(m, t, s);
+        case 1: return launch_one<Ts, T, MODE, PW, 1, BUD, R, OPT>(m, t, s);
+        case 2: return launch_one<Ts, T, MODE, PW, 2, BUD, R, OPT>(m, t, s);
         case 3:  // groups of three only without budgets
-            if constexpr (!BUD) return launch_one<Ts, T, MODE, PW, 3, BUD, R, DYN>(m, t, s);
+            if constexpr (!BUD) return launch_one<Ts, T, MODE, PW, 3, BUD, R, OPT>(m, t, s);
             break;
     }
     return hipErrorInvalidValue;
 }
 
-template <typename Ts, typename T, int MODE, bool PW, bool BUD, bool DYN = false>
+template <typename Ts, typename T, int MODE, bool PW, bool BUD, int OPT = 0>
 hipError_t launch_r(const MarchArgs& m, const Tiling& t, hipStream_t s) {
-    if (m.a.nz <= 64) return launch_ns<Ts, T, MODE, PW, BUD, 1, DYN>(m, t, s);
-    return launch_ns<Ts, T, MODE, PW, BUD, 2, DYN>(m, t, s);
+    if (m.a.nz <= 64) return launch_ns<Ts, T, MODE, PW, BUD, 1, OPT>(m, t, s);
+    return launch_ns<Ts, T, MODE, PW, BUD, 2, OPT>(m, t, s);
 }
 
 // Launch the whole evaluation: scalars in groups of at most 3 per pass (2
@@ -71,13 +72,23 @@ hipError_t launch_march_t(bool pw, bool tvd, const AdvArgs& a, hipStream_t s) {
         m.first_pass = first ? 1 : 0;
         const bool with_pw = pw && first;
         hipError_t e;
-        if (with_pw && a.dyn) {
-            // the other dynamics source terms ride on the momentum pass: FP64
-            // step only, no budgets, theta (scalar 0) in the first group
+        if ((a.dyn && with_pw) || a.spw) {
+            // options of the FP64 step, no budgets: the other dynamics
+            // source terms ride on the momentum pass (theta, scalar 0, in the
+            // first group; later groups are plain); the centred scalar
+            // scheme replaces TVD in every group
             if constexpr (MODE == STEP && std::is_same<Ts, double>::value &&
                           std::is_same<T, double>::value) {
-                if (bud || m.ns < 1) return hipErrorInvalidValue;
-                e = launch_r<Ts, T, MODE, true, false, true>(m, t, s);
+                if (bud || (a.dyn && a.spw)) return hipErrorInvalidValue;
+                if (a.dyn) {
+                    if (m.ns < 1) return hipErrorInvalidValue;
+                    e = launch_r<Ts, T, MODE, true, false, OPT_DYN>(m, t, s);
+                } else if (with_pw) {
+                    e = launch_r<Ts, T, MODE, true, false, OPT_SPW>(m, t, s);
+                } else {
+                    if (m.ns == 0) break;
+                    e = launch_r<Ts, T, MODE, false, false, OPT_SPW>(m, t, s);
+                }
             } else {
                 return hipErrorInvalidValue;
             }

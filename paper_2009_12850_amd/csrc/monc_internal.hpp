@@ -33,6 +33,8 @@ struct AdvArgs {
     // Coriolis toward (ug, vg) and buoyancy of scalar 0 (theta)
     int dyn;
     double fcor, ug, vg, gth, th0;
+    // scalars advected with the centred flux form (monc_step_pw_scalars)
+    int spw;
 };
 
 // Number of workgroups of the fused step launch (fixed for a grid so budget

@@ -199,6 +199,13 @@ __device__ __forceinline__ double buoyancy_w(double gth, double th0, double th_k
     return gth * ((th_k + th_kp) * 0.5 - th0);
 }
 
+// Centred flux (the PW flux form applied to a scalar, MONC's alternative
+// scalar scheme): the face value is the mean of the two cells beside the face.
+template <typename T>
+__device__ __forceinline__ T centred_flux(T a, T p0, T p1, T mass) {
+    return mass * a * ((p0 + p1) * (T)0.5);
+}
+
 // First-order upwind flux (used where the far-upwind cell lies outside the
 // column, next to the ground and the lid).
 template <typename T>

@@ -241,3 +241,15 @@ def test_dynamics_entries_reject_bad_arguments():
     tb = _arr([0x9000, 0, 0, 0])  # tb[0] aliases out[0]
     assert L.monc_combine_step(4, ins, tend, tb, outs, 8, 8, 8, 0.5, None) == M.MONC_EINVAL
     assert L.monc_combine_step(4, ins, tend, None, outs, 8, 8, 8, 0.0, None) == M.MONC_EINVAL
+
+
+def test_step_pw_scalars_rejects_bad_arguments():
+    L = M.lib()
+    ins = _arr([0x1000 + 0x100 * n for n in range(5)])
+    outs = _arr([0x9000 + 0x100 * n for n in range(5)])
+    assert L.monc_step_pw_scalars(ins, outs, 2, 8, 8, 8, 1.0, 1.0, *_prof3(), 0.0,
+                                  None) == M.MONC_EINVAL
+    assert L.monc_step_pw_scalars(ins, ins, 2, 8, 8, 8, 1.0, 1.0, *_prof3(), 0.5,
+                                  None) == M.MONC_EINVAL
+    assert L.monc_step_pw_scalars(ins, outs, 9, 8, 8, 8, 1.0, 1.0, *_prof3(), 0.5,
+                                  None) == M.MONC_EINVAL
