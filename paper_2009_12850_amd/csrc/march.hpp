@@ -259,6 +259,7 @@ __device__ __forceinline__ void march_tile(const AdvArgs& a, const TileJob& tj,
     const bool store = active && kin;
 
     const double dt = a.dt;
+    const double cdx = dt / a.dx, cdy = dt / a.dy;  // Courant number per unit speed
     // ---- level table (vertical geometry from rdz, rho, rhon) ----
     for (int kk = threadIdx.x; kk < NZP; kk += MARCH_WAVES * 64) {
         double v[NLEV];
@@ -655,9 +656,8 @@ __device__ __forceinline__ void march_tile(const AdvArgs& a, const TileJob& tj,
                         acc[MONC_B_QW] += -0.25 * dzk * Dd * (wcd * wcd + wbd * wbd);
                         acc[MONC_B_CW] += wmass * (double)sw;
                         acc[MONC_B_PW] += wmass * wcd * (double)sw;
-                        const double cr =
-                            fmax(fmax(fabs(ucd) * dt / a.dx, fabs(vcd) * dt / a.dy),
-                                 fabs(wcd) * dt * (double)L.rdzn);
+                        const double cr = fmax(fmax(fabs(ucd) * cdx, fabs(vcd) * cdy),
+                                               fabs(wcd) * dt * (double)L.rdzn);
                         acc[MONC_B_COURANT] = fmax(acc[MONC_B_COURANT], cr);
                         acc[MONC_B_NONFINITE] +=
                             (double)((!isfinite(nu)) + (!isfinite(nv)) + (!isfinite(nw)));
