@@ -159,7 +159,7 @@ int monc_advect_tvd(const double *u, const double *v, const double *w,
  * of nscal doubles, may be NULL = zeros) gives the constant each stored scalar
  * is an anomaly from: the source term returned is that of phi0 + stored value,
  * i.e. the stored anomaly's term minus phi0*D/rhon (exact by the affine
- * equivariance of the flux form).  Halos must be valid.
+ * equivariance of the flux form).  Halos are not read.
  * ------------------------------------------------------------------------- */
 int monc_advect(int dtype, const void *const *in, void *const *out, int nscal,
                 const double *phi0, int nx, int ny, int nz, double dx,
