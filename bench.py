@@ -204,6 +204,62 @@ def bench_dynamics(torch, M, state, g, prof, w, stream, npts, nf, reps):
     return out
 
 
+def copy_ceiling_gbps(torch, dev, stream, reps=20):
+    """Read + write bandwidth of a plain 1 GiB device-to-device copy."""
+    src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    ms = event_time_ms(torch, stream, lambda: dst.copy_(src), reps)
+    del src, dst
+    return 2.0 * (1 << 30) / (ms * 1e-3) / 1e9
+
+
+def synthetic_state(torch, dev, shape, nscal, seed):
+    """Seeded device-side fields of the usual kinds for throughput-only runs
+    (the kernels have no data-dependent branches): velocities of a few m/s, w
+    zero on the lid, theta near 300 K, positive tracers."""
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(seed)
+    r = lambda s: torch.randn(shape, dtype=torch.float64, device=dev, generator=gen) * s
+    u, v, w = r(2.0), r(2.0), r(0.2)
+    w[:, :, -1] = 0.0
+    out = [u, v, w, 300.0 + r(1.0)]
+    out += [1e-3 * torch.exp(r(0.5)) for _ in range(nscal - 1)]
+    return out
+
+
+def bench_step_shape(torch, M, I, dev, stream, nx, ny, nz, nscal, reps, seed):
+    """GPUPS of monc_step (with budgets) on another grid shape."""
+    g = I.make_geometry(nx, ny, nz, 50.0, 50.0)
+    prof = [torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in (g.rdz, g.rho, g.rhon)]
+    A = synthetic_state(torch, dev, (nx + 4, ny + 4, nz), nscal, seed)
+    B = [torch.empty_like(a) for a in A]
+    bud = torch.zeros(M.MONC_NBUDGET, dtype=torch.float64, device=dev)
+    ws = torch.empty(M.monc_step_workspace_bytes(nx, ny, nz, nscal), dtype=torch.uint8,
+                     device=dev)
+    st = [A, B]
+
+    def step():
+        M.monc_step(st[0], st[1], g.dx, g.dy, prof, 0.5, bud, ws, stream)
+        st.reverse()
+
+    step()
+    torch.cuda.synchronize()
+    ms = event_time_ms(torch, stream, step, reps)
+    torch.cuda.synchronize()
+    status = M.monc_budgets_check(bud.cpu().numpy())
+    npts = nx * ny * nz
+    nf = 3 + nscal
+    out = {"grid": [nx, ny, nz], "fields": nf, "ms": ms, "gpups": npts / (ms * 1e-3),
+           "hbm_frac": 16.0 * nf * npts / (ms * 1e-3) / HBM_PEAK,
+           "status": "ok" if status == M.MONC_OK else M.lib().monc_strerror(status).decode(),
+           "data": "seeded device-side random fields (throughput only)"}
+    del A, B, st
+    torch.cuda.empty_cache()
+    return out
+
+
 def bench_ensemble(torch, M, I, dev, steps, log):
     """64 uneven members (nx, ny in {64..256}, nz in {64, 96}), FP32 source
     terms from the FP64 state, `steps` steps in one captured graph launch,
@@ -255,7 +311,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the advection "
-              "path has no multi-GPU leg in this build", file=sys.stderr)
+              "path runs on a single device", file=sys.stderr)
         sys.exit(2)
     import torch
 
@@ -312,9 +368,15 @@ def main():
     bytes_alg = 16.0 * nf * npts  # read + write of every FP64 field
     achieved = bytes_alg / (k_ms * 1e-3)
     traffic = measured_traffic(args.workload)
+    copy_gbps = copy_ceiling_gbps(torch, dev, stream)
     roofline = {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9,
                 "unit": "GB/s", "frac": achieved / HBM_PEAK,
                 "traffic": traffic / 1e9 if traffic else None, "traffic_unit": "GB per launch",
+                # measured bytes of the launch (counters) over its duration, vs the peak
+                "traffic_frac": (traffic / (k_ms * 1e-3) / HBM_PEAK) if traffic else None,
+                # a plain 1 GiB device-to-device copy on this device: the streaming ceiling
+                "copy_ceiling_gbps": copy_gbps,
+                "frac_of_copy_ceiling": achieved / 1e9 / copy_gbps,
                 "kernel": "monc_step (fused PW+TVD+update, FP64)",
                 "bytes_per_launch": bytes_alg, "launch_ms": k_ms}
 
@@ -353,6 +415,13 @@ def main():
         forms["mixed_step"] = {"ms": tm, "gpups": npts / (tm * 1e-3)}
         forms["dynamics"] = bench_dynamics(torch, M, state, g, prof, w, stream, npts, nf,
                                            args.steps)
+        # the step on the other grids the method is quoted on: 512 x 512 x 128
+        # with 7 fields, and the paper's tank-case shape 2048 x 2048 x 64 with
+        # 9 fields (its strong-scaling problem, on one device)
+        forms["steps512_step"] = bench_step_shape(torch, M, I, dev, stream, 512, 512, 128, 4,
+                                                  args.steps, 21)
+        forms["tank_shape_step"] = bench_step_shape(torch, M, I, dev, stream, 2048, 2048, 64,
+                                                    6, max(5, args.steps // 4), 22)
 
     if not args.no_forms:
         del B
