@@ -36,8 +36,9 @@ hipError_t launch_ns(const MarchArgs& m, const Tiling& t, hipStream_t s) {
             break;
         case 1: return launch_one<Ts, T, MODE, PW, 1, BUD, R, OPT>(m, t, s);
         case 2: return launch_one<Ts, T, MODE, PW, 2, BUD, R, OPT>(m, t, s);
-        case 3:  // groups of three only without budgets
-            if constexpr (!BUD) return launch_one<Ts, T, MODE, PW, 3, BUD, R, OPT>(m, t, s);
+        case 3:  // with budgets, groups of three only on one-chunk columns
+            if constexpr (!BUD || R == 1)
+                return launch_one<Ts, T, MODE, PW, 3, BUD, R, OPT>(m, t, s);
             break;
     }
     return hipErrorInvalidValue;
@@ -50,7 +51,7 @@ hipError_t launch_r(const MarchArgs& m, const Tiling& t, hipStream_t s) {
 }
 
 // Launch the whole evaluation: scalars in groups of at most 3 per pass (2
-// when budgets are accumulated) so that a wave's state fits its 256
+// when budgets are accumulated on columns of more than 64 levels) so that a wave's state fits its 256
 // registers without spilling; the first pass also does the momentum (if
 // requested).
 template <typename Ts, typename T, int MODE>
@@ -58,7 +59,8 @@ hipError_t launch_march_t(bool pw, bool tvd, const AdvArgs& a, hipStream_t s) {
     const Tiling t = march_tiling(a.nx, a.ny, a.nz, march_waves<Ts, T>());
     const bool bud = a.partials != nullptr;
     const int nscal = tvd ? a.nscal : 0;
-    const int group = bud ? 2 : 3;
+    // columns of two chunks hold fewer accumulators in registers
+    const int group = bud && a.nz > 64 ? 2 : 3;
     int s0 = 0;
     bool first = true;
     do {

@@ -125,7 +125,7 @@ def test_many_scalars_use_several_passes(nscal):
     T.cuda.synchronize()
     for n, (a, r) in enumerate(zip(out, ref)):
         assert rel_err(a.cpu().numpy(), r) <= TOL64, n
-    # the step with budgets (scalars in passes of two)
+    # the step with budgets (passes of three scalars on these 40-level columns)
     stp = O.step([h.copy() for h in host], g, dt)
     out = [T.full_like(x, float("nan")) for x in d]
     b = T.zeros(M.MONC_NBUDGET, dtype=T.float64, device=dev())

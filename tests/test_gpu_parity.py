@@ -239,10 +239,12 @@ def test_big1024_subdomains_match_oracle():
 
 
 @pytest.mark.parametrize("nscal,nz,budgets", [(1, 128, False), (1, 128, True), (2, 128, False),
-                                             (3, 96, False), (4, 128, False), (1, 64, False)])
+                                             (3, 96, False), (4, 128, False), (1, 64, False),
+                                             (4, 64, True), (5, 128, True)])
 def test_step_with_unfilled_halos_every_grouping(nscal, nz, budgets):
-    """NaN halos, every scalar grouping (passes of 2 or 3 scalars), one and two
-    z-chunks, with and without budgets: the step matches the oracle."""
+    """NaN halos, every scalar grouping (passes of 2 or 3 scalars; with budgets
+    3 on one-chunk columns, 2 on two-chunk ones), one and two z-chunks, with
+    and without budgets: the step matches the oracle."""
     say(f"unfilled halos step nscal={nscal} nz={nz} budgets={budgets}")
     g, host = case(20, 14, nz, nscal, seed=540 + nscal + nz)
     dt = 0.5
