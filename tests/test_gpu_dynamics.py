@@ -210,3 +210,32 @@ def test_step_pw_scalars_matches_oracle(shape, nscal):
         inc = I.interior(o) - I.interior(host[f])
         inc_ref = I.interior(ref[f]) - I.interior(host[f])
         assert np.abs(inc - inc_ref).max() <= TOL * np.abs(inc_ref).max() + 1e-300, f
+
+
+def test_full_size_pw_scalars_step_properties():
+    """At the benchmark's size: momentum bitwise that of monc_step, and the
+    centred scalar fluxes conserve each scalar's mass (sum of rhon dz times
+    the increment vanishes to rounding)."""
+    w = I.WORKLOADS["big1024"]
+    say(f"full size pw scalars {w.nx}x{w.ny}x{w.nz}")
+    T = torch()
+    g = I.make_geometry(w.nx, w.ny, w.nz, w.dx, w.dx)
+    names = ["u", "v", "w"] + I.scalar_names(w.nscal)
+    f = I.make_fields(g, w.nscal, w.seed, padded=True)
+    d = [T.from_numpy(f[n]).to(dev()) for n in names]
+    del f
+    prof = prof_dev(g)
+    a = [T.empty_like(x) for x in d]
+    M.monc_step_pw_scalars(d, a, g.dx, g.dy, prof, w.dt)
+    b = [T.empty_like(x) for x in d]
+    M.monc_step(d, b, g.dx, g.dy, prof, w.dt)
+    T.cuda.synchronize()
+    for q in range(3):
+        assert T.equal(a[q][2:-2, 2:-2], b[q][2:-2, 2:-2]), q
+    del b
+    mass = T.from_numpy(np.ascontiguousarray((1.0 / g.rdz) * g.rhon)).to(dev())
+    for q in range(3, len(d)):
+        inc = a[q][2:-2, 2:-2] - d[q][2:-2, 2:-2]
+        total = float((inc * mass).sum())
+        scale = float((inc.abs() * mass).sum())
+        assert abs(total) <= 1e-12 * scale, (q, total, scale)
