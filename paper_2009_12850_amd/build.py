@@ -18,8 +18,13 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # so a formula gives the same bits wherever the compiler inlines it (the march
 # is unrolled by two; with fusion across statements the two copies rounded
 # differently and the result depended on the parity of the plane).
+# The machine scheduler favours instruction-level parallelism over register
+# pressure: the march kernels are bound by issue and latency at two to four
+# waves per SIMD, and this ordering measured 2-7 % faster on every form with no
+# spills (the register ceilings come from the launch bounds).
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-ffp-contract=on",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-mllvm", "-amdgpu-sched-strategy=max-ilp",
          "-Wall", "-Wno-unused-function", "-Wno-unknown-pragmas"]
 
 

@@ -151,8 +151,9 @@ hipError_t upload_class(EnsemblePlan& P, int cls, int ti) {
     if (e0 != hipSuccess) return e0;
     std::vector<int4> items = build_items(P, cls, ti);
     if (P.d_items[cls]) {
-        hipFree(P.d_items[cls]);
+        const hipError_t ef = hipFree(P.d_items[cls]);
         P.d_items[cls] = nullptr;
+        if (ef != hipSuccess) return ef;
     }
     P.nitems[cls] = (int)items.size();
     P.ti[cls] = ti;
@@ -185,8 +186,8 @@ hipError_t launch_step(EnsemblePlan& P, int parity, hipStream_t s) {
 std::string cache_key(int cls, int nscal) {
     hipDeviceProp_t prop;
     int dev = 0;
-    hipGetDevice(&dev);
-    hipGetDeviceProperties(&prop, dev);
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+        return "unknown-device:" + std::to_string(cls) + ":" + std::to_string(nscal);
     char buf[256];
     snprintf(buf, sizeof buf, "%s|nz%s|fp32-tend-fp64-state|nscal%d", prop.gcnArchName,
              cls == 0 ? "<=64" : "<=128", nscal);
