@@ -276,7 +276,7 @@ def bench_ensemble(torch, M, I, dev, steps, log):
         s1 = [torch.empty_like(x) for x in s0]
         prof = [torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in (g.rdz, g.rho, g.rhon)]
         members.append(dict(state0=s0, state1=s1, prof=prof, dx=md["dx"], dy=md["dx"], dt=0.5,
-                            phi0=[300.0, 0.0]))
+                            phi0=[300.0, 1e-3]))
     pts = sum(md["nx"] * md["ny"] * md["nz"] for md in geo)
     cache = os.path.join(tempfile.gettempdir(), "monc_ensemble_tune.json")
     log("ensemble: plan + autotune")
@@ -391,7 +391,7 @@ def main():
         forms["f64_tendencies"] = {"ms": t64, "gpups": npts / (t64 * 1e-3),
                                    "hbm_frac": 16.0 * nf * npts / (t64 * 1e-3) / HBM_PEAK}
         del tend64
-        phi0 = [300.0] + [0.0] * (w.nscal - 1)
+        phi0 = [300.0] + [1e-3] * (w.nscal - 1)  # nominal theta and tracer values
         offs = [0.0, 0.0, 0.0] + phi0
         for dt_name, code, tdt in (("f32", M.MONC_F32, torch.float32),
                                    ("bf16", M.MONC_BF16, torch.int16)):

@@ -212,3 +212,46 @@ def test_steps512_budgets_every_step():
         if step % 20 == 0:
             say(f"  step {step}: courant {gb['courant']:.3f} C_u {gb['C_u']:.2e} "
                 f"P_u-Q_u {gb['P_u'] - gb['Q_u']:.2e}")
+
+
+def test_big1024_precision_forms_match_oracle():
+    """The precision forms at the headline size and in the launch configuration
+    the benchmark times (FP32 and BF16 working copies with the scalars stored
+    as anomalies from their nominal values, the mixed step), over the whole
+    domain against the FP64 oracle, per field max |gpu - oracle| /
+    max |oracle|."""
+    say("big1024 precision forms")
+    w, g, f = I.make_workload("big1024")
+    names = ["u", "v", "w"] + I.scalar_names(w.nscal)
+    T = torch()
+    hosts = [O.halo_fill(I.pad(f.pop(n))) for n in names]
+    d = [T.from_numpy(h).to(dev()) for h in hosts]
+    prof = prof_dev(g)
+    # scalars stored as anomalies from their nominal values (theta 300 K,
+    # tracers 1e-3): the working copies then round the variation, not the mean
+    phi0 = [300.0] + [1e-3] * (w.nscal - 1)
+    offs = [0.0, 0.0, 0.0] + phi0
+    outs = {}
+    for name, code, tdt in (("f32", M.MONC_F32, T.float32), ("bf16", M.MONC_BF16, T.int16)):
+        work = [T.empty(x.shape, dtype=tdt, device=dev()) for x in d]
+        M.monc_cast_working(code, d, work, offs)
+        o = [T.empty(x.shape, dtype=T.float32, device=dev()) for x in d]
+        M.monc_advect(code, work, o, g.dx, g.dy, prof, w.dt, phi0=phi0)
+        outs[name] = o
+        del work
+    mixed = [T.empty_like(x) for x in d]
+    M.monc_step_mixed(d, mixed, phi0, g.dx, g.dy, prof, w.dt)
+    T.cuda.synchronize()
+    say("  oracle over the whole domain")
+    ref = oracle_tendencies(hosts, g, w.dt)
+    for n in range(len(d)):
+        exp = I.interior(ref[n])
+        den = np.abs(exp).max()
+        e32 = np.abs(I.interior(outs["f32"][n].double().cpu().numpy()) - exp).max() / den
+        e16 = np.abs(I.interior(outs["bf16"][n].double().cpu().numpy()) - exp).max() / den
+        inc = I.interior(mixed[n].cpu().numpy()) - I.interior(hosts[n])
+        emx = np.abs(inc - w.dt * exp).max() / (w.dt * den)
+        say(f"  field {n}: fp32 {e32:.2e} bf16 {e16:.2e} mixed {emx:.2e}")
+        assert e32 <= 1e-5, (n, e32)
+        assert e16 <= 0.25, (n, e16)
+        assert emx <= 1e-5, (n, emx)
