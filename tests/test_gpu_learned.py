@@ -397,14 +397,14 @@ def test_experiment_driver_small():
 
 
 @pytest.mark.parametrize("shape", [(12, 10, 7), (16, 16, 8), (5, 3, 33), (8, 12, 32), (3, 32, 4),
-                                   (6, 4, 32)])
+                                   (6, 4, 32), (128, 128, 32)])
 @pytest.mark.parametrize("orient", [0, 1])
 def test_fused_inference_equals_features_then_forward(shape, orient):
     """The fused gather + MLP kernel gives bitwise the outputs of the feature
     gather followed by the forward pass, over every cell.  Grids of 32 levels
     with ny a multiple of 4 take the LDS-staged gather, the others the direct
     one; (6, 4, 32) stages more columns than the grid has (periodic
-    duplicates)."""
+    duplicates); (128, 128, 32) is the learned form's coarse grid."""
     NX, NY, NZ = shape
     say(f"infer {shape} orient={orient}")
     T = torch()
