@@ -297,7 +297,7 @@ def oracle_correct(s, tend, gx, gy, rdz, rho, rhon, scale, dt, growth, dx=200.0,
 
 
 @pytest.mark.parametrize("shape,theta_scale", [((9, 7, 5), 1.0), ((16, 12, 8), 0.05),
-                                               ((32, 32, 32), 0.3)])
+                                               ((32, 32, 32), 0.3), ((128, 128, 32), 0.3)])
 def test_corrected_step_matches_oracle_and_conserves(shape, theta_scale):
     NX, NY, NZ = shape
     say(f"correct_step {shape} theta_scale={theta_scale}")
@@ -308,7 +308,9 @@ def test_corrected_step_matches_oracle_and_conserves(shape, theta_scale):
                                                   1e300)
     say(f"  clamped theta faces: gpu {flags[3]}, oracle {nclamp} of {2 * NX * NY * NZ}")
     assert flags[1] == 0 and flags[2] == 0 and nonfin == 0 and grown == 0
-    assert abs(int(flags[3]) - nclamp) <= 2
+    # a face whose corrected value sits on the interval's end to within
+    # rounding may be counted on one side or the other
+    assert abs(int(flags[3]) - nclamp) <= 2 + 2e-6 * (2 * NX * NY * NZ)
     assert 0 < nclamp < 2 * NX * NY * NZ
     for q in range(4):
         a = I.interior(out[q])
