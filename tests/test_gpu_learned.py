@@ -53,7 +53,8 @@ def coarse_state(NX, NY, NZ, seed):
     return s
 
 
-@pytest.mark.parametrize("shape,nscal", [((32, 32, 32), 1), ((16, 24, 8), 2), ((8, 4, 128), 1)])
+@pytest.mark.parametrize("shape,nscal", [((32, 32, 32), 1), ((16, 24, 8), 2), ((8, 4, 128), 1),
+                                         ((512, 512, 128), 1)])
 def test_restriction_matches_oracle(shape, nscal):
     nx, ny, nz = shape
     say(f"restrict4 {shape} nscal={nscal}")
