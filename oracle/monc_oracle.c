@@ -743,3 +743,219 @@ int oracle_pw_scalar(const double *u, const double *v, const double *w, const do
             }
     return OR_OK;
 }
+
+/* ---------------------------------------------------------------------------
+ * TVD advection of momentum: the ULTIMATE scheme of Sec. 3.1 applied to the
+ * velocity components themselves (MONC offers it as the alternative to PW for
+ * momentum; the paper gives no formulas).  Each velocity component has its
+ * own control volume on the C-grid.  The mass flux through each face of that
+ * volume is the one the PW scheme above uses, and the value carried through
+ * the face is the ULTIMATE-limited QUICKEST value of the advected component
+ * along the flux direction, upwind by the sign of the mass flux.  With the
+ * mean of the two values beside each face in place of the limited value the
+ * scheme is exactly PW (the `centred` switch; used only to check that).
+ *
+ *   u at (i+1/2, j, k):
+ *     x-face at the centre of cell i+1:  m = rhon_k (u_i + u_{i+1})/2
+ *     y-face at (i+1/2, j+1/2):          m = rhon_k (v_{i,j} + v_{i+1,j})/2
+ *     z-face at (i+1/2, j, k+1/2):       m = rho_k (w_{i,k} + w_{i+1,k})/2 for
+ *                                        k < nz-1; none through ground or lid
+ *     su = -(1/rhon_k)[(Fx_{i+1}-Fx_i)/dx + (Fy_{j+1/2}-Fy_{j-1/2})/dy
+ *                      + rdz_k (Fz_{k+1/2}-Fz_{k-1/2})]
+ *   v alike with the roles of x and y exchanged.
+ *   w at (i, j, k+1/2), k < nz-1, with a_k, b_k of the PW w-equation:
+ *     x-face at (i+1/2, j, k+1/2):       m = a_k u_{i,k} + b_k u_{i,k+1}
+ *     y-face alike with v
+ *     z-face at the centre of cell q, between w_{q-1} and w_q (q = 0..nz-1):
+ *                                        m = (rho_{q-1} w_{q-1} + rho_q w_q)/2
+ *     sw = -(1/rho_k)[(Fx_{i+1/2}-Fx_{i-1/2})/dx + (Fy_{j+1/2}-Fy_{j-1/2})/dy
+ *                     + rdzn_k (Fz_{k+1}-Fz_k)],   sw_{nz-1} = 0.
+ *   The ground face w_{-1} and the lid w_{nz-1} are values of w (both 0).
+ *
+ * Courant number of a face: |m| divided by the reference density where the
+ * face sits, times dt over the distance between the two values beside it --
+ * rhon_k with dx or dy for the lateral faces of u and v, rho_k with dzn_k for
+ * their z-faces, rho_k with dx or dy for the lateral faces of w, rhon_q with
+ * dz_q for the z-faces of w.  A z-stencil whose far-upwind value does not
+ * exist (u, v: levels 0..nz-1; w: faces -1..nz-1) takes the upwind value.
+ * Neighbours at wrapped periodic indices; halos are not read.  Returns OR_ECFL
+ * (after filling the outputs) when a Courant number exceeds 1; *cmax_out, if
+ * given, receives the largest one met.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    grid_t g;
+    double dx, dy, dt;
+    const double *rdz, *rho, *rhon;
+    const vgeom_t *vg;
+    int centred;
+} momctx_t;
+
+/* value at wrapped lateral indices */
+static inline double fv(const momctx_t *M, const double *f, int i, int j, int k) {
+    return f[at(&M->g, posmod(i, M->g.nx), posmod(j, M->g.ny), k)];
+}
+
+/* w at wrapped lateral indices with the ground and lid set to zero */
+static inline double wv(const momctx_t *M, const double *w, int i, int j, int k) {
+    if (k < 0 || k >= M->g.nz - 1) return 0.0;
+    return fv(M, w, i, j, k);
+}
+
+/* Value carried through a face with mass flux m: p0, p1 the values beside the
+ * face (p0 on the lower-index side), pm and p2 the next ones out, has_pm and
+ * has_p2 whether those exist. */
+static double mom_face(const momctx_t *M, double m, double c, double pm, double p0,
+                       double p1, double p2, int has_pm, int has_p2) {
+    if (M->centred) return 0.5 * (p0 + p1);
+    if (m >= 0.0) return has_pm ? oracle_ultimate_face(pm, p0, p1, c) : p0;
+    return has_p2 ? oracle_ultimate_face(p2, p1, p0, c) : p1;
+}
+
+static inline void note_c(double c, double *cmax) {
+    if (c > *cmax) *cmax = c;
+}
+
+/* u-equation fluxes.  ux: face between u_{i} and u_{i+1}. */
+static double fu_x(const momctx_t *M, const double *u, int i, int j, int k, double *cm) {
+    double a = (fv(M, u, i, j, k) + fv(M, u, i + 1, j, k)) / 2.0;
+    double c = fabs(a) * M->dt / M->dx;
+    note_c(c, cm);
+    double pf = mom_face(M, a, c, fv(M, u, i - 1, j, k), fv(M, u, i, j, k),
+                         fv(M, u, i + 1, j, k), fv(M, u, i + 2, j, k), 1, 1);
+    return M->rhon[k] * a * pf;
+}
+/* face between u_{i,j} and u_{i,j+1} */
+static double fu_y(const momctx_t *M, const double *u, const double *v, int i, int j, int k,
+                   double *cm) {
+    double a = (fv(M, v, i, j, k) + fv(M, v, i + 1, j, k)) / 2.0;
+    double c = fabs(a) * M->dt / M->dy;
+    note_c(c, cm);
+    double pf = mom_face(M, a, c, fv(M, u, i, j - 1, k), fv(M, u, i, j, k),
+                         fv(M, u, i, j + 1, k), fv(M, u, i, j + 2, k), 1, 1);
+    return M->rhon[k] * a * pf;
+}
+/* face between u_{i,j,k} and u_{i,j,k+1}; zero through ground and lid */
+static double fu_z(const momctx_t *M, const double *u, const double *w, int i, int j, int k,
+                   double *cm) {
+    int nz = M->g.nz;
+    if (k < 0 || k >= nz - 1) return 0.0;
+    double a = (wv(M, w, i, j, k) + wv(M, w, i + 1, j, k)) / 2.0;
+    double c = fabs(a) * M->dt * M->vg->rdzn[k];
+    note_c(c, cm);
+    double pm = k - 1 >= 0 ? fv(M, u, i, j, k - 1) : 0.0;
+    double p2 = k + 2 <= nz - 1 ? fv(M, u, i, j, k + 2) : 0.0;
+    double pf = mom_face(M, a, c, pm, fv(M, u, i, j, k), fv(M, u, i, j, k + 1), p2,
+                         k - 1 >= 0, k + 2 <= nz - 1);
+    return M->rho[k] * a * pf;
+}
+
+/* v-equation fluxes (x and y exchanged). */
+static double fv_x(const momctx_t *M, const double *u, const double *v, int i, int j, int k,
+                   double *cm) {
+    double a = (fv(M, u, i, j, k) + fv(M, u, i, j + 1, k)) / 2.0;
+    double c = fabs(a) * M->dt / M->dx;
+    note_c(c, cm);
+    double pf = mom_face(M, a, c, fv(M, v, i - 1, j, k), fv(M, v, i, j, k),
+                         fv(M, v, i + 1, j, k), fv(M, v, i + 2, j, k), 1, 1);
+    return M->rhon[k] * a * pf;
+}
+static double fv_y(const momctx_t *M, const double *v, int i, int j, int k, double *cm) {
+    double a = (fv(M, v, i, j, k) + fv(M, v, i, j + 1, k)) / 2.0;
+    double c = fabs(a) * M->dt / M->dy;
+    note_c(c, cm);
+    double pf = mom_face(M, a, c, fv(M, v, i, j - 1, k), fv(M, v, i, j, k),
+                         fv(M, v, i, j + 1, k), fv(M, v, i, j + 2, k), 1, 1);
+    return M->rhon[k] * a * pf;
+}
+static double fv_z(const momctx_t *M, const double *v, const double *w, int i, int j, int k,
+                   double *cm) {
+    int nz = M->g.nz;
+    if (k < 0 || k >= nz - 1) return 0.0;
+    double a = (wv(M, w, i, j, k) + wv(M, w, i, j + 1, k)) / 2.0;
+    double c = fabs(a) * M->dt * M->vg->rdzn[k];
+    note_c(c, cm);
+    double pm = k - 1 >= 0 ? fv(M, v, i, j, k - 1) : 0.0;
+    double p2 = k + 2 <= nz - 1 ? fv(M, v, i, j, k + 2) : 0.0;
+    double pf = mom_face(M, a, c, pm, fv(M, v, i, j, k), fv(M, v, i, j, k + 1), p2,
+                         k - 1 >= 0, k + 2 <= nz - 1);
+    return M->rho[k] * a * pf;
+}
+
+/* w-equation fluxes at level k (k < nz-1).  wx: face between w_i and w_{i+1}. */
+static double fw_x(const momctx_t *M, const double *u, const double *w, int i, int j, int k,
+                   double *cm) {
+    const vgeom_t *vg = M->vg;
+    double a = vg->dz[k] * M->rhon[k] / (2.0 * vg->dzn[k]);
+    double b = vg->dz[k + 1] * M->rhon[k + 1] / (2.0 * vg->dzn[k]);
+    double m = a * fv(M, u, i, j, k) + b * fv(M, u, i, j, k + 1);
+    double c = fabs(m) / M->rho[k] * M->dt / M->dx;
+    note_c(c, cm);
+    double pf = mom_face(M, m, c, wv(M, w, i - 1, j, k), wv(M, w, i, j, k),
+                         wv(M, w, i + 1, j, k), wv(M, w, i + 2, j, k), 1, 1);
+    return m * pf;
+}
+static double fw_y(const momctx_t *M, const double *v, const double *w, int i, int j, int k,
+                   double *cm) {
+    const vgeom_t *vg = M->vg;
+    double a = vg->dz[k] * M->rhon[k] / (2.0 * vg->dzn[k]);
+    double b = vg->dz[k + 1] * M->rhon[k + 1] / (2.0 * vg->dzn[k]);
+    double m = a * fv(M, v, i, j, k) + b * fv(M, v, i, j, k + 1);
+    double c = fabs(m) / M->rho[k] * M->dt / M->dy;
+    note_c(c, cm);
+    double pf = mom_face(M, m, c, wv(M, w, i, j - 1, k), wv(M, w, i, j, k),
+                         wv(M, w, i, j + 1, k), wv(M, w, i, j + 2, k), 1, 1);
+    return m * pf;
+}
+/* face at the centre of cell q, between w_{q-1} and w_q (q = 0..nz-1) */
+static double fw_z(const momctx_t *M, const double *w, int i, int j, int q, double *cm) {
+    int nz = M->g.nz;
+    double lo = q - 1 >= 0 ? M->rho[q - 1] * wv(M, w, i, j, q - 1) : 0.0; /* ground: w = 0 */
+    double m = (lo + M->rho[q] * wv(M, w, i, j, q)) / 2.0;
+    double c = fabs(m) / M->rhon[q] * M->dt * M->rdz[q];
+    note_c(c, cm);
+    double pf = mom_face(M, m, c, wv(M, w, i, j, q - 2), wv(M, w, i, j, q - 1),
+                         wv(M, w, i, j, q), wv(M, w, i, j, q + 1), q - 2 >= -1,
+                         q + 1 <= nz - 1);
+    return m * pf;
+}
+
+int oracle_tvd_momentum(const double *u, const double *v, const double *w, double *su,
+                        double *sv, double *sw, int nx, int ny, int nz, double dx,
+                        double dy, const double *rdz, const double *rho,
+                        const double *rhon, double dt, int centred, double *cmax_out) {
+    if (!u || !v || !w || !su || !sv || !sw || !rdz || !rho || !rhon) return OR_EINVAL;
+    if (nx < 1 || ny < 1 || nz < 2 || !(dx > 0) || !(dy > 0) || !(dt >= 0))
+        return OR_EINVAL;
+    vgeom_t vg;
+    vgeom_make(&vg, rdz, nz);
+    momctx_t M = {{nx, ny, nz}, dx, dy, dt, rdz, rho, rhon, &vg, centred};
+    double cmax = 0.0;
+
+#pragma omp parallel for schedule(static) reduction(max : cmax)
+    for (int i = 0; i < nx; i++)
+        for (int j = 0; j < ny; j++)
+            for (int k = 0; k < nz; k++) {
+                long c = at(&M.g, i, j, k);
+                double ex = fu_x(&M, u, i, j, k, &cmax) - fu_x(&M, u, i - 1, j, k, &cmax);
+                double ey = fu_y(&M, u, v, i, j, k, &cmax) - fu_y(&M, u, v, i, j - 1, k, &cmax);
+                double ez = fu_z(&M, u, w, i, j, k, &cmax) - fu_z(&M, u, w, i, j, k - 1, &cmax);
+                su[c] = -(1.0 / rhon[k]) * (ex / dx + ey / dy + rdz[k] * ez);
+
+                ex = fv_x(&M, u, v, i, j, k, &cmax) - fv_x(&M, u, v, i - 1, j, k, &cmax);
+                ey = fv_y(&M, v, i, j, k, &cmax) - fv_y(&M, v, i, j - 1, k, &cmax);
+                ez = fv_z(&M, v, w, i, j, k, &cmax) - fv_z(&M, v, w, i, j, k - 1, &cmax);
+                sv[c] = -(1.0 / rhon[k]) * (ex / dx + ey / dy + rdz[k] * ez);
+
+                if (k == nz - 1) {
+                    sw[c] = 0.0;
+                    continue;
+                }
+                ex = fw_x(&M, u, w, i, j, k, &cmax) - fw_x(&M, u, w, i - 1, j, k, &cmax);
+                ey = fw_y(&M, v, w, i, j, k, &cmax) - fw_y(&M, v, w, i, j - 1, k, &cmax);
+                ez = fw_z(&M, w, i, j, k + 1, &cmax) - fw_z(&M, w, i, j, k, &cmax);
+                sw[c] = -(1.0 / rho[k]) * (ex / dx + ey / dy + vg.rdzn[k] * ez);
+            }
+    vgeom_free(&vg);
+    if (cmax_out) *cmax_out = cmax;
+    return cmax > 1.0 ? OR_ECFL : OR_OK;
+}

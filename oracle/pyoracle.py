@@ -66,6 +66,8 @@ def lib():
                                        dp, dp, dp]
         L.oracle_dyn.argtypes = [dp, dp, dp, dp, dp, dp, i, i, i, d, d, d, d, d]
         L.oracle_pw_scalar.argtypes = [dp, dp, dp, dp, dp, i, i, i, d, d, dp, dp, dp]
+        L.oracle_tvd_momentum.argtypes = [dp, dp, dp, dp, dp, dp, i, i, i, d, d, dp, dp, dp,
+                                          d, i, dp]
         _lib = L
     return _lib
 
@@ -259,6 +261,39 @@ def step_pw_scalars(state, g, dt):
     state = [halo_fill(f) for f in state]
     tend = list(pw(state[0], state[1], state[2], g))
     tend += [pw_scalar(state[0], state[1], state[2], q, g) for q in state[3:]]
+    out = [np.full_like(f, np.nan) for f in state]
+    sl = (slice(2, nx + 2), slice(2, ny + 2), slice(None))
+    for f in range(len(state)):
+        out[f][sl] = state[f][sl] + dt * tend[f][sl]
+    out[2][2:nx + 2, 2:ny + 2, nz - 1] = 0.0
+    return out
+
+
+def tvd_momentum(u, v, w, g, dt, centred=False, allow_cfl=False):
+    """TVD source terms of the momentum (su, sv, sw) and the largest Courant
+    number of the momentum faces.  Wrapped periodic neighbours (halos are not
+    read).  centred=True carries the mean of the two values beside each face
+    instead of the limited value, which is the PW scheme."""
+    nx, ny, nz = _shape(u)
+    su, sv, sw = (np.zeros_like(u) for _ in range(3))
+    rdz, rho, rhon = _prof(g)
+    cmax = C.c_double(0.0)
+    rc = lib().oracle_tvd_momentum(_p(u), _p(v), _p(w), _p(su), _p(sv), _p(sw), nx, ny, nz,
+                                   g.dx, g.dy, _p(rdz), _p(rho), _p(rhon), float(dt),
+                                   int(bool(centred)), C.byref(cmax))
+    if not (allow_cfl and rc == OR_ECFL):
+        _check(rc, "tvd_momentum")
+    return su, sv, sw, cmax.value
+
+
+def step_tvd_momentum(state, g, dt, allow_cfl=False):
+    """One forward step with TVD for the momentum and the scalars:
+    f_out = f_in + dt s, w = 0 on the lid (inputs are not modified)."""
+    nx, ny, nz = _shape(state[0])
+    state = [halo_fill(f) for f in state]
+    su, sv, sw, _ = tvd_momentum(state[0], state[1], state[2], g, dt, allow_cfl=allow_cfl)
+    tend = [su, sv, sw] + [tvd(state[0], state[1], state[2], q, g, dt, allow_cfl=allow_cfl)
+                           for q in state[3:]]
     out = [np.full_like(f, np.nan) for f in state]
     sl = (slice(2, nx + 2), slice(2, ny + 2), slice(None))
     for f in range(len(state)):
