@@ -204,6 +204,29 @@ def bench_dynamics(torch, M, state, g, prof, w, stream, npts, nf, reps):
     return out
 
 
+def bench_tvd_momentum(torch, M, state, g, prof, w, stream, npts, plain_ms, reps):
+    """TVD advection of momentum: the source-term pass alone (one read of u, v,
+    w and one write of su, sv, sw: 48 bytes per point) and the all-TVD step
+    (that pass stepping u, v, w, then the scalar march)."""
+    src = [torch.empty_like(a) for a in state[0][:3]]
+    run = lambda: M.monc_advect_tvd_momentum(*state[0][:3], *src, g.dx, g.dy, prof, w.dt,
+                                             stream=stream)
+    step = lambda: M.monc_step_tvd_momentum(state[0], state[1], g.dx, g.dy, prof, w.dt,
+                                            stream=stream)
+    out = {}
+    for name, fn in (("source_terms", run), ("step", step)):
+        fn()
+        torch.cuda.synchronize()
+        ms = event_time_ms(torch, stream, fn, reps)
+        out[name] = {"ms": ms, "gpups": npts / (ms * 1e-3)}
+    gbps = 48.0 * npts / (out["source_terms"]["ms"] * 1e-3) / 1e9
+    out["source_terms"].update({"bytes_per_point": 48.0, "achieved_gbps": gbps,
+                                "hbm_frac": gbps * 1e9 / HBM_PEAK})
+    out["step_cost_vs_pw_step"] = out["step"]["ms"] / plain_ms
+    del src
+    return out
+
+
 def copy_ceiling_gbps(torch, dev, stream, reps=20):
     """Read + write bandwidth of a plain 1 GiB device-to-device copy."""
     src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
@@ -415,6 +438,9 @@ def main():
         forms["mixed_step"] = {"ms": tm, "gpups": npts / (tm * 1e-3)}
         forms["dynamics"] = bench_dynamics(torch, M, state, g, prof, w, stream, npts, nf,
                                            args.steps)
+        forms["tvd_momentum"] = bench_tvd_momentum(torch, M, state, g, prof, w, stream, npts,
+                                                   forms["dynamics"]["plain_step"]["ms"],
+                                                   args.steps)
         # the step on the other grids the method is quoted on: 512 x 512 x 128
         # with 7 fields, and the paper's tank-case shape 2048 x 2048 x 64 with
         # 9 fields (its strong-scaling problem, on one device)

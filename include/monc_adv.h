@@ -424,6 +424,51 @@ int monc_step_pw_scalars(double *const *state_in, double *const *state_out, int 
                          const double *rho, const double *rhon, double dt,
                          monc_stream_t stream);
 
+/* ---------------------------------------------------------------------------
+ * TVD advection of momentum: the ULTIMATE scheme of Sec. 3.1 (there used for
+ * the scalars) applied to u, v and w, the alternative to PW for momentum.  The
+ * mass flux through each face of a velocity's control volume is the PW one,
+ * and the value carried through the face is the ULTIMATE-limited QUICKEST
+ * value of that velocity component along the flux direction, upwind by the
+ * sign of the mass flux (with the mean of the two values beside the face it
+ * is PW):
+ *   u at (i+1/2,j,k): x-faces at cell centres carry rhon_k (u_i + u_{i+1})/2,
+ *     y-faces at (i+1/2,j+1/2) rhon_k (v_{ij} + v_{i+1,j})/2, z-faces at
+ *     (i+1/2,j,k+1/2) rho_k (w_{ik} + w_{i+1,k})/2, none through ground or lid;
+ *     su = -(1/rhon_k)[dFx/dx + dFy/dy + rdz_k dFz];  v likewise in y;
+ *   w at (i,j,k+1/2), k < nz-1: lateral faces carry a_k u_k + b_k u_{k+1} with
+ *     a_k = dz_k rhon_k/(2 dzn_k), b_k = dz_{k+1} rhon_{k+1}/(2 dzn_k); the
+ *     z-face at the centre of cell q carries (rho_{q-1} w_{q-1} + rho_q w_q)/2
+ *     with w = 0 on the ground and the lid; sw = -(1/rho_k)[dFx/dx + dFy/dy
+ *     + dFz/dzn_k], sw = 0 on the lid.
+ * Courant number of a face: |mass flux| / (reference density where the face
+ * sits) * dt / (distance between the two values beside it).  A z-stencil
+ * whose far-upwind value does not exist takes the upwind value.
+ *
+ * u, v, w: FP64 device fields; su, sv, sw: FP64 device outputs (interior
+ * written, halos untouched).  cmax: device double or NULL; when given it is
+ * overwritten with the largest Courant number of the momentum faces (the
+ * scheme needs <= 1; beyond that the values are unspecified).  Halos are not
+ * read.  Outputs must not alias inputs or each other.
+ * ------------------------------------------------------------------------- */
+int monc_advect_tvd_momentum(const double *u, const double *v, const double *w, double *su,
+                             double *sv, double *sw, int nx, int ny, int nz, double dx,
+                             double dy, const double *rdz, const double *rho,
+                             const double *rhon, double dt, double *cmax,
+                             monc_stream_t stream);
+
+/* One forward step with TVD for every field: the momentum as in
+ * monc_advect_tvd_momentum, the scalars as in monc_step; state_out = state_in
+ * + dt * s, w lid = 0.  Two passes on `stream`: the momentum pass writes
+ * u, v, w of state_out, the scalar march the scalars.  Arguments as monc_step
+ * without budgets; cmax as above (momentum faces only; the scalar faces use
+ * the face velocities, whose largest Courant number monc_step's budgets
+ * report). */
+int monc_step_tvd_momentum(double *const *state_in, double *const *state_out, int nscal,
+                           int nx, int ny, int nz, double dx, double dy, const double *rdz,
+                           const double *rho, const double *rhon, double dt, double *cmax,
+                           monc_stream_t stream);
+
 /* Map a budgets array (HOST copy, after synchronising) to a status:
  * MONC_ENONFINITE if any non-finite value was written, MONC_ECFL if the
  * largest Courant number exceeds 1, else MONC_OK. */

@@ -778,9 +778,10 @@ int oracle_pw_scalar(const double *u, const double *v, const double *w, const do
  * their z-faces, rho_k with dx or dy for the lateral faces of w, rhon_q with
  * dz_q for the z-faces of w.  A z-stencil whose far-upwind value does not
  * exist (u, v: levels 0..nz-1; w: faces -1..nz-1) takes the upwind value.
- * Neighbours at wrapped periodic indices; halos are not read.  Returns OR_ECFL
- * (after filling the outputs) when a Courant number exceeds 1; *cmax_out, if
- * given, receives the largest one met.
+ * Computes the points i in [i0,i1), j in [j0,j1), all k.  Neighbours at
+ * wrapped periodic indices; halos are not read.  Returns OR_ECFL (after
+ * filling the outputs) when a Courant number exceeds 1; *cmax_out, if given,
+ * receives the largest one met.
  * ------------------------------------------------------------------------- */
 typedef struct {
     grid_t g;
@@ -922,18 +923,20 @@ static double fw_z(const momctx_t *M, const double *w, int i, int j, int q, doub
 int oracle_tvd_momentum(const double *u, const double *v, const double *w, double *su,
                         double *sv, double *sw, int nx, int ny, int nz, double dx,
                         double dy, const double *rdz, const double *rho,
-                        const double *rhon, double dt, int centred, double *cmax_out) {
+                        const double *rhon, double dt, int centred, int i0, int i1,
+                        int j0, int j1, double *cmax_out) {
     if (!u || !v || !w || !su || !sv || !sw || !rdz || !rho || !rhon) return OR_EINVAL;
     if (nx < 1 || ny < 1 || nz < 2 || !(dx > 0) || !(dy > 0) || !(dt >= 0))
         return OR_EINVAL;
+    if (i0 < 0 || i1 > nx || j0 < 0 || j1 > ny || i0 > i1 || j0 > j1) return OR_EINVAL;
     vgeom_t vg;
     vgeom_make(&vg, rdz, nz);
     momctx_t M = {{nx, ny, nz}, dx, dy, dt, rdz, rho, rhon, &vg, centred};
     double cmax = 0.0;
 
 #pragma omp parallel for schedule(static) reduction(max : cmax)
-    for (int i = 0; i < nx; i++)
-        for (int j = 0; j < ny; j++)
+    for (int i = i0; i < i1; i++)
+        for (int j = j0; j < j1; j++)
             for (int k = 0; k < nz; k++) {
                 long c = at(&M.g, i, j, k);
                 double ex = fu_x(&M, u, i, j, k, &cmax) - fu_x(&M, u, i - 1, j, k, &cmax);

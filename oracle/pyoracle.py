@@ -67,7 +67,7 @@ def lib():
         L.oracle_dyn.argtypes = [dp, dp, dp, dp, dp, dp, i, i, i, d, d, d, d, d]
         L.oracle_pw_scalar.argtypes = [dp, dp, dp, dp, dp, i, i, i, d, d, dp, dp, dp]
         L.oracle_tvd_momentum.argtypes = [dp, dp, dp, dp, dp, dp, i, i, i, d, d, dp, dp, dp,
-                                          d, i, dp]
+                                          d, i, i, i, i, i, dp]
         _lib = L
     return _lib
 
@@ -269,18 +269,20 @@ def step_pw_scalars(state, g, dt):
     return out
 
 
-def tvd_momentum(u, v, w, g, dt, centred=False, allow_cfl=False):
+def tvd_momentum(u, v, w, g, dt, centred=False, allow_cfl=False, region=None):
     """TVD source terms of the momentum (su, sv, sw) and the largest Courant
     number of the momentum faces.  Wrapped periodic neighbours (halos are not
     read).  centred=True carries the mean of the two values beside each face
-    instead of the limited value, which is the PW scheme."""
+    instead of the limited value, which is the PW scheme.  region = (i0, i1,
+    j0, j1) restricts the points computed (the rest stay 0)."""
     nx, ny, nz = _shape(u)
+    i0, i1, j0, j1 = region or (0, nx, 0, ny)
     su, sv, sw = (np.zeros_like(u) for _ in range(3))
     rdz, rho, rhon = _prof(g)
     cmax = C.c_double(0.0)
     rc = lib().oracle_tvd_momentum(_p(u), _p(v), _p(w), _p(su), _p(sv), _p(sw), nx, ny, nz,
                                    g.dx, g.dy, _p(rdz), _p(rho), _p(rhon), float(dt),
-                                   int(bool(centred)), C.byref(cmax))
+                                   int(bool(centred)), i0, i1, j0, j1, C.byref(cmax))
     if not (allow_cfl and rc == OR_ECFL):
         _check(rc, "tvd_momentum")
     return su, sv, sw, cmax.value

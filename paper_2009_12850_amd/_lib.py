@@ -60,6 +60,9 @@ _SIGS = {
                          ip),
     "monc_step_dyn": ([PP, PP, ip, ip, ip, ip, dp, dp, vp, vp, vp, dp, vp, vp], ip),
     "monc_step_pw_scalars": ([PP, PP, ip, ip, ip, ip, dp, dp, vp, vp, vp, dp, vp], ip),
+    "monc_advect_tvd_momentum": ([vp, vp, vp, vp, vp, vp, ip, ip, ip, dp, dp, vp, vp, vp, dp,
+                                  vp, vp], ip),
+    "monc_step_tvd_momentum": ([PP, PP, ip, ip, ip, ip, dp, dp, vp, vp, vp, dp, vp, vp], ip),
     "monc_budgets_check": ([DPTR], ip),
     "monc_restrict4": ([ip, PP, PP, ip, ip, ip, vp, vp, vp, vp, vp, vp, vp], ip),
     "monc_mlp_features": ([PP, ip, ip, ip, DPTR, ip, vp, ip, vp, vp], ip),
@@ -361,6 +364,35 @@ def monc_step_pw_scalars(state_in, state_out, dx, dy, prof, dt, stream=None):
     rc = lib().monc_step_pw_scalars(ia, oa, nscal, nx, ny, nz, float(dx), float(dy),
                                     *_prof(prof), float(dt), _stream(stream))
     _check(rc, "monc_step_pw_scalars")
+
+
+def monc_advect_tvd_momentum(u, v, w, su, sv, sw, dx, dy, prof, dt, cmax=None,
+                             stream=None):
+    """TVD momentum source terms; cmax (float64 device tensor of one element,
+    optional) receives the largest Courant number of the momentum faces."""
+    torch = _torch()
+    nx, ny, nz = _grid(u)
+    sh = tuple(u.shape)
+    ps = [_ptr(t, torch.float64, sh, n) for t, n in zip((u, v, w, su, sv, sw),
+                                                       ("u", "v", "w", "su", "sv", "sw"))]
+    cm = C.c_void_p(None) if cmax is None else _ptr(cmax, torch.float64, (1,), "cmax")
+    _check(lib().monc_advect_tvd_momentum(*ps, nx, ny, nz, float(dx), float(dy), *_prof(prof),
+                                          float(dt), cm, _stream(stream)),
+           "monc_advect_tvd_momentum")
+
+
+def monc_step_tvd_momentum(state_in, state_out, dx, dy, prof, dt, cmax=None, stream=None):
+    """The FP64 step with TVD for momentum and scalars."""
+    torch = _torch()
+    nx, ny, nz = _grid(state_in[0])
+    sh = tuple(state_in[0].shape)
+    nscal = len(state_in) - 3
+    ia = _ptrs(state_in, torch.float64, sh, "state_in")
+    oa = _ptrs(state_out, torch.float64, sh, "state_out")
+    cm = C.c_void_p(None) if cmax is None else _ptr(cmax, torch.float64, (1,), "cmax")
+    rc = lib().monc_step_tvd_momentum(ia, oa, nscal, nx, ny, nz, float(dx), float(dy),
+                                      *_prof(prof), float(dt), cm, _stream(stream))
+    _check(rc, "monc_step_tvd_momentum")
 
 
 def monc_step_mixed(state_in, state_out, phi0, dx, dy, prof, dt, budgets=None,

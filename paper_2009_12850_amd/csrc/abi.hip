@@ -420,8 +420,8 @@ int monc_hybrid_step(double* const* state_in, double* const* state_out, double* 
     if (two) {
         TRY(hip_status(hipStreamWaitEvent(s, done, 0), "stream wait"));
         // released by the runtime once the recorded work has completed
-        hipEventDestroy(start);
-        hipEventDestroy(done);
+        (void)hipEventDestroy(start);
+        (void)hipEventDestroy(done);
     }
     const double* tb[3 + MAXS];
     for (int f = 0; f < nf; f++) tb[f] = f < 3 ? dyn_tend[f] : nullptr;
@@ -480,6 +480,86 @@ int monc_step_pw_scalars(double* const* state_in, double* const* state_out, int 
     return hip_status(launch_advect(MONC_F64, STEP, true, nscal > 0, false, a,
                                     (hipStream_t)stream),
                       "step_pw_scalars");
+}
+
+static TvdMomArgs tvdmom_args(const double* u, const double* v, const double* w, double* ou,
+                       double* ov, double* ow, int nx, int ny, int nz, double dx, double dy,
+                       const double* rdz, const double* rho, const double* rhon, double dt,
+                       double* cmax) {
+    TvdMomArgs t;
+    t.u = u;
+    t.v = v;
+    t.w = w;
+    t.out_u = ou;
+    t.out_v = ov;
+    t.out_w = ow;
+    t.nx = nx;
+    t.ny = ny;
+    t.nz = nz;
+    t.dt = dt;
+    t.rdt = 1.0 / dt;
+    t.rdx = 1.0 / dx;
+    t.rdy = 1.0 / dy;
+    t.cdx = dt / dx;
+    t.cdy = dt / dy;
+    t.rfx = dx / dt;
+    t.rfy = dy / dt;
+    t.rdz = rdz;
+    t.rho = rho;
+    t.rhon = rhon;
+    t.cmax = cmax;
+    return t;
+}
+
+int monc_advect_tvd_momentum(const double* u, const double* v, const double* w, double* su,
+                             double* sv, double* sw, int nx, int ny, int nz, double dx,
+                             double dy, const double* rdz, const double* rho,
+                             const double* rhon, double dt, double* cmax,
+                             monc_stream_t stream) {
+    TRY(check_grid(nx, ny, nz));
+    TRY(check_spacing(dx, dy));
+    TRY(check_dt(dt));
+    TRY(check_prof(rdz, rho, rhon));
+    const void* in[3] = {u, v, w};
+    const void* out[4] = {su, sv, sw, cmax};
+    TRY(check_ptrs(3, in, "velocity"));
+    TRY(check_ptrs(3, out, "source term"));
+    TRY(check_alias(3, in, cmax ? 4 : 3, out));
+    const TvdMomArgs t = tvdmom_args(u, v, w, su, sv, sw, nx, ny, nz, dx, dy, rdz, rho, rhon,
+                                     dt, cmax);
+    return hip_status(launch_tvd_momentum(t, false, (hipStream_t)stream), "advect_tvd_momentum");
+}
+
+int monc_step_tvd_momentum(double* const* state_in, double* const* state_out, int nscal,
+                           int nx, int ny, int nz, double dx, double dy, const double* rdz,
+                           const double* rho, const double* rhon, double dt, double* cmax,
+                           monc_stream_t stream) {
+    TRY(check_grid(nx, ny, nz));
+    TRY(check_spacing(dx, dy));
+    TRY(check_dt(dt));
+    TRY(check_prof(rdz, rho, rhon));
+    TRY(check_nscal(nscal));
+    const int nf = 3 + nscal;
+    TRY(check_ptrs(nf, state_in, "state_in"));
+    TRY(check_ptrs(nf, state_out, "state_out"));
+    const void* outs[3 + MONC_MAX_SCALARS + 1];
+    for (int f = 0; f < nf; f++) outs[f] = state_out[f];
+    outs[nf] = cmax;
+    TRY(check_alias(nf, (const void* const*)state_in, cmax ? nf + 1 : nf, outs));
+    const TvdMomArgs t = tvdmom_args(state_in[0], state_in[1], state_in[2], state_out[0],
+                                     state_out[1], state_out[2], nx, ny, nz, dx, dy, rdz, rho,
+                                     rhon, dt, cmax);
+    hipError_t e = launch_tvd_momentum(t, true, (hipStream_t)stream);
+    if (e == hipSuccess && nscal > 0) {
+        AdvArgs a;
+        fill_args(a, nx, ny, nz, dx, dy, dt, rdz, rho, rhon, nscal);
+        for (int f = 0; f < nf; f++) {
+            a.in[f] = state_in[f];
+            a.out[f] = state_out[f];
+        }
+        e = launch_advect(MONC_F64, STEP, false, true, false, a, (hipStream_t)stream);
+    }
+    return hip_status(e, "step_tvd_momentum");
 }
 
 int monc_cast_working(int dtype, int nfields, const double* const* src, void* const* work,

@@ -66,6 +66,19 @@ hipError_t launch_combine(int nfields, const double* const* in, const double* co
                           const double* const* tb, double* const* out, int nx, int ny,
                           int nz, double dt, hipStream_t s);
 
+// TVD advection of momentum (tvdmom.hip).  out_* receive the source terms,
+// or the stepped velocities when `step` is set; cmax (device, may be null)
+// receives the largest Courant number of the momentum faces.
+struct TvdMomArgs {
+    const double *u, *v, *w;
+    double *out_u, *out_v, *out_w;
+    int nx, ny, nz;
+    double dt, rdt, rdx, rdy, cdx, cdy, rfx, rfy;
+    const double *rdz, *rho, *rhon;
+    double* cmax;
+};
+hipError_t launch_tvd_momentum(const TvdMomArgs& a, bool step, hipStream_t s);
+
 // Learned correction (learned.hip).
 hipError_t launch_restrict4(int nscal, const double* const* fine, double* const* coarse, int nx,
                             int ny, int nz, const double* rdz, const double* rho,

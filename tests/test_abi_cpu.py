@@ -253,3 +253,27 @@ def test_step_pw_scalars_rejects_bad_arguments():
                                   None) == M.MONC_EINVAL
     assert L.monc_step_pw_scalars(ins, outs, 9, 8, 8, 8, 1.0, 1.0, *_prof3(), 0.5,
                                   None) == M.MONC_EINVAL
+
+
+def test_tvd_momentum_entries_reject_bad_arguments():
+    L = M.lib()
+    P = [C.c_void_p(0x1000 * (n + 1)) for n in range(7)]  # u v w su sv sw cmax
+    ok = (4, 4, 8, 50.0, 50.0, *_prof3(), 1.0)
+    assert L.monc_advect_tvd_momentum(*P[:6], *ok[:8], 0.0, P[6], None) == M.MONC_EINVAL
+    assert L.monc_advect_tvd_momentum(*P[:6], 4, 4, 1, 50.0, 50.0, *_prof3(), 1.0, P[6],
+                                      None) == M.MONC_EINVAL
+    assert L.monc_advect_tvd_momentum(P[0], P[1], P[2], P[0], P[4], P[5], *ok, P[6],
+                                      None) == M.MONC_EINVAL  # su aliases u
+    assert L.monc_advect_tvd_momentum(*P[:6], *ok, P[1], None) == M.MONC_EINVAL  # cmax = v
+    assert b"alias" in L.monc_last_error()
+    assert L.monc_advect_tvd_momentum(*P[:5], None, *ok, None, None) == M.MONC_EINVAL
+    ins = _arr([0x1000 + 0x100 * n for n in range(5)])
+    outs = _arr([0x9000 + 0x100 * n for n in range(5)])
+    assert L.monc_step_tvd_momentum(ins, outs, 2, 8, 8, 8, 1.0, 1.0, *_prof3(), 0.0, None,
+                                    None) == M.MONC_EINVAL
+    assert L.monc_step_tvd_momentum(ins, ins, 2, 8, 8, 8, 1.0, 1.0, *_prof3(), 0.5, None,
+                                    None) == M.MONC_EINVAL
+    assert L.monc_step_tvd_momentum(ins, outs, 9, 8, 8, 8, 1.0, 1.0, *_prof3(), 0.5, None,
+                                    None) == M.MONC_EINVAL
+    assert L.monc_step_tvd_momentum(ins, outs, 2, 8, 8, 8, 1.0, 1.0, *_prof3(), 0.5,
+                                    C.c_void_p(0x9100), None) == M.MONC_EINVAL  # cmax = out

@@ -1,0 +1,163 @@
+"""GPU tests of the TVD advection of momentum and the all-TVD step.
+
+* monc_advect_tvd_momentum against the FP64 oracle, per field
+  max |gpu - oracle| / max |oracle| <= 1e-13, on several tiles of columns with
+  ragged edges, one- and two-chunk columns, the smallest grids; halos are not
+  read (NaN there) and not written; the largest Courant number agrees with the
+  oracle's to 1e-14.
+* monc_step_tvd_momentum against the oracle's step (1e-13 on the increments).
+* At the benchmark's full size (1024 x 1024 x 128, 5 fields, the launch the
+  benchmark times) the step matches the oracle on sampled blocks of columns,
+  including the periodic edges, and conserves u and v momentum.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from gpu_util import case, dev, prof_dev, rel_err, to_dev, torch
+from oracle import pyoracle as O
+from paper_2009_12850_amd import _lib as M
+from paper_2009_12850_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+DT = 4.0
+TOL = 1e-13
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _setup():
+    O.build(force=False)
+    M.lib()
+
+
+def nan_halo(a):
+    b = np.full_like(a, np.nan)
+    b[2:-2, 2:-2, :] = a[2:-2, 2:-2, :]
+    return b
+
+
+SHAPES = [(16, 16, 32), (23, 17, 50), (9, 6, 128), (1, 1, 7), (40, 12, 64), (2, 3, 2),
+          (5, 9, 65)]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_tvd_momentum_matches_oracle(shape):
+    nx, ny, nz = shape
+    say(f"tvd_momentum {shape}")
+    g, host = case(nx, ny, nz, 0, seed=1300 + nx + nz)
+    su, sv, sw, cmax = O.tvd_momentum(*host[:3], g, DT)
+    T = torch()
+    d = to_dev([nan_halo(h) for h in host[:3]])
+    out = [T.full(d[0].shape, -7.0, dtype=T.float64, device=dev()) for _ in range(3)]
+    cm = T.full((1,), -1.0, dtype=T.float64, device=dev())
+    M.monc_advect_tvd_momentum(*d, *out, g.dx, g.dy, prof_dev(g), DT, cmax=cm)
+    T.cuda.synchronize()
+    for n, (o, r) in enumerate(zip(out, (su, sv, sw))):
+        got = o.cpu().numpy()
+        e = rel_err(got, r)
+        assert e <= TOL, f"field {n}: {e:.3e}"
+        halo = got.copy()
+        halo[2:-2, 2:-2, :] = -7.0
+        assert np.all(halo == -7.0), f"field {n}: halo written"
+    assert abs(cm.item() - cmax) <= 1e-14 * cmax
+
+
+def test_tvd_momentum_without_cmax_and_stream():
+    g, host = case(12, 10, 40, 0, seed=1400)
+    ref = O.tvd_momentum(*host[:3], g, DT)
+    T = torch()
+    s = T.cuda.Stream()
+    d = to_dev(host[:3])
+    out = [T.empty_like(d[0]) for _ in range(3)]
+    with T.cuda.stream(s):
+        M.monc_advect_tvd_momentum(*d, *out, g.dx, g.dy, prof_dev(g), DT, stream=s)
+    s.synchronize()
+    for n in range(3):
+        assert rel_err(out[n].cpu().numpy(), ref[n]) <= TOL, n
+
+
+@pytest.mark.parametrize("shape,nscal", [((16, 16, 32), 2), ((13, 7, 128), 3), ((4, 4, 3), 0),
+                                         ((10, 8, 70), 1)])
+def test_step_tvd_momentum_matches_oracle(shape, nscal):
+    nx, ny, nz = shape
+    say(f"step_tvd_momentum {shape} nscal={nscal}")
+    g, host = case(nx, ny, nz, nscal, seed=1500 + nx + nscal)
+    ref = O.step_tvd_momentum([h.copy() for h in host], g, DT)
+    T = torch()
+    d = to_dev([nan_halo(h) for h in host])
+    out = [T.full(d[0].shape, -7.0, dtype=T.float64, device=dev()) for _ in host]
+    cm = T.zeros(1, dtype=T.float64, device=dev())
+    M.monc_step_tvd_momentum(d, out, g.dx, g.dy, prof_dev(g), DT, cmax=cm)
+    T.cuda.synchronize()
+    _, _, _, cref = O.tvd_momentum(*host[:3], g, DT)
+    for n, (o, r) in enumerate(zip(out, ref)):
+        got = o.cpu().numpy()
+        e = rel_err(got - host[n], r - host[n])
+        assert e <= TOL, f"field {n}: {e:.3e}"
+    assert np.all(out[2].cpu().numpy()[2:-2, 2:-2, nz - 1] == 0.0)
+    assert abs(cm.item() - cref) <= 1e-14 * cref
+
+
+def test_tvd_momentum_rejects_bad_arguments():
+    T = torch()
+    g, host = case(4, 4, 8, 0, seed=1600)
+    d = to_dev(host[:3])
+    out = [T.empty_like(d[0]) for _ in range(3)]
+    with pytest.raises(M.MoncError):
+        M.monc_advect_tvd_momentum(*d, *out, g.dx, g.dy, prof_dev(g), 0.0)
+    with pytest.raises(M.MoncError):  # output aliases an input
+        M.monc_advect_tvd_momentum(*d, d[0], out[1], out[2], g.dx, g.dy, prof_dev(g), DT)
+
+
+def test_full_size_step_matches_oracle_on_sampled_blocks():
+    """1024 x 1024 x 128 with five fields, in the launch the benchmark times:
+    the increments of every field on blocks of 8 x 8 full columns (corner,
+    periodic edges, middle) against the oracle, and u, v momentum conserved
+    over the whole domain."""
+    nx, ny, nz = 1024, 1024, 128
+    say("full-size step_tvd_momentum")
+    g = I.make_geometry(nx, ny, nz)
+    f = I.make_fields(g, 2, 7, padded=True)
+    names = ["u", "v", "w", "th", "q1"]
+    host = [f[n] for n in names]
+    host[3] = host[3] - 300.0  # anomalies keep the sampled relative errors meaningful
+    T = torch()
+    d = to_dev(host)
+    out = [T.empty_like(d[0]) for _ in host]
+    cm = T.zeros(1, dtype=T.float64, device=dev())
+    prof = prof_dev(g)
+    M.monc_step_tvd_momentum(d, out, g.dx, g.dy, prof, 0.5, cmax=cm)
+    su = [T.empty_like(d[0]) for _ in range(3)]
+    M.monc_advect_tvd_momentum(d[0], d[1], d[2], *su, g.dx, g.dy, prof, 0.5)
+    T.cuda.synchronize()
+    mass = T.from_numpy((1.0 / g.rdz) * g.rhon).to(dev())
+    for n in range(2):
+        t = su[n][2:-2, 2:-2, :] * mass
+        assert abs(t.sum().item()) <= 1e-12 * t.abs().sum().item(), n
+    del su
+    filled = [O.halo_fill(h) for h in host]
+    blocks = [(0, 8, 0, 8), (nx - 8, nx, ny - 8, ny), (0, 8, ny - 8, ny), (509, 517, 300, 308)]
+    got = [o.cpu().numpy() for o in out]
+    cmax = 0.0
+    for (i0, i1, j0, j1) in blocks:
+        ms = O.tvd_momentum(*filled[:3], g, 0.5, region=(i0, i1, j0, j1))
+        cmax = max(cmax, ms[3])
+        tend = list(ms[:3]) + [O.tvd(*filled[:3], q, g, 0.5, region=(i0, i1, j0, j1))
+                               for q in filled[3:]]
+        for n in range(5):
+            ref = 0.5 * I.interior(tend[n])[i0:i1, j0:j1]
+            inc = I.interior(got[n])[i0:i1, j0:j1] - I.interior(host[n])[i0:i1, j0:j1]
+            if n == 2:
+                ref[:, :, -1] = -I.interior(host[2])[i0:i1, j0:j1, -1]
+            e = np.abs(inc - ref).max() / np.abs(ref).max()
+            assert e <= TOL, f"block {(i0, i1, j0, j1)} field {names[n]}: {e:.3e}"
+    # the device maximum covers the whole domain, so it bounds the sampled one
+    assert cm.item() >= cmax * (1 - 1e-14)
+    assert cm.item() <= 1.0

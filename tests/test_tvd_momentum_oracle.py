@@ -321,3 +321,12 @@ def test_step_tvd_momentum_scalars_equal_plain_step():
         if fi == 2:
             ref[:, :, -1] = 0.0
         np.testing.assert_array_equal(interior(a[fi]), ref)
+
+
+def test_region_equals_whole_domain():
+    g, (u, v, w) = flow(11, 9, 10, 14)
+    full = O.tvd_momentum(u, v, w, g, 1.0)
+    part = O.tvd_momentum(u, v, w, g, 1.0, region=(3, 8, 0, 5))
+    for f in range(3):
+        np.testing.assert_array_equal(interior(part[f])[3:8, 0:5], interior(full[f])[3:8, 0:5])
+        assert np.abs(interior(part[f])[:3]).max() == 0.0
