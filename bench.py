@@ -81,6 +81,8 @@ def parse():
     p.add_argument("--workload", default="big1024")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-forms", action="store_true")
+    p.add_argument("--only-form", choices=["tvd_momentum", "dynamics"], default=None,
+                   help="after the headline, run only this form (for profiling it)")
     p.add_argument("--cpu-seconds", type=float, default=12.0)
     p.add_argument("--no-learned", action="store_true",
                    help="skip the learned-correction form (fine runs, training, coarse runs)")
@@ -404,7 +406,17 @@ def main():
                 "bytes_per_launch": bytes_alg, "launch_ms": k_ms}
 
     forms = None
-    if not args.no_forms:
+    if not args.no_forms and args.only_form:
+        log(f"form {args.only_form}")
+        if args.only_form == "dynamics":
+            forms = {"dynamics": bench_dynamics(torch, M, state, g, prof, w, stream, npts, nf,
+                                                args.steps)}
+        else:
+            plain = event_time_ms(torch, stream, lambda: M.monc_step(
+                state[0], state[1], g.dx, g.dy, prof, w.dt, None, None, stream), args.steps)
+            forms = {"tvd_momentum": bench_tvd_momentum(torch, M, state, g, prof, w, stream,
+                                                        npts, plain, args.steps)}
+    elif not args.no_forms:
         log("precision forms")
         forms = {}
         tend64 = [torch.empty_like(a) for a in A]
@@ -449,12 +461,12 @@ def main():
         forms["tank_shape_step"] = bench_step_shape(torch, M, I, dev, stream, 2048, 2048, 64,
                                                     6, max(5, args.steps // 4), 22)
 
-    if not args.no_forms:
+    if not args.no_forms and not args.only_form:
         del B
         state.clear()
         torch.cuda.empty_cache()
         forms["ensemble"] = bench_ensemble(torch, M, I, dev, 50, log)
-    if not args.no_forms and not args.no_learned:
+    if not args.no_forms and not args.only_form and not args.no_learned:
         from paper_2009_12850_amd import learned as L
         log("learned correction: fine runs, training, coarse runs")
         ns = args.learned_seeds

@@ -43,6 +43,7 @@ namespace {
 // lateral face is evaluated once inside a tile.
 constexpr int TM_TX = 2, TM_TY = 2;
 constexpr int TM_WAVES = TM_TX * TM_TY;
+constexpr int TM_BAND = 8;  // tile rows per band of the traversal
 // Level table of the chunk: levels k0-1 .. k0+64.
 constexpr int TM_LEV = 66;
 enum { L_RDZ, L_RHON, L_RHO, L_DZ, L_RHONI, L_RHOI, L_RDZN, L_DZN, L_ALPHA, L_BETA, L_CZ, L_RZ,
@@ -83,11 +84,19 @@ __global__ void __launch_bounds__(64 * TM_WAVES)
     int b = blockIdx.x;
     const int nb = gridDim.x;
     if ((nb & 7) == 0) b = (b & 7) * (nb >> 3) + (b >> 3);
+    // Tiles are walked along x inside bands of TM_BAND tile rows, so the
+    // columns a tile shares with its x-neighbours (two on each side) are
+    // still in L2 when those neighbours run.
     const int nchunk = (nz + 63) / 64;
     const int nty = (ny + TM_TY - 1) / TM_TY;
-    const int chunk = b % nchunk;
-    const int ty = (b / nchunk) % nty;
-    const int tx = b / (nchunk * nty);
+    const int ntx = (nx + TM_TX - 1) / TM_TX;
+    const int per_band = TM_BAND * nchunk * ntx;
+    const int band = b / per_band;
+    const int rows = min(TM_BAND, nty - band * TM_BAND);  // the last band may be short
+    const int rb = b - band * per_band;
+    const int chunk = rb % nchunk;
+    const int ty = band * TM_BAND + (rb / nchunk) % rows;
+    const int tx = rb / (nchunk * rows);
     const int wv = (int)threadIdx.y;  // wave in the tile
     const int wx = wv % TM_TX, wy = wv / TM_TX;
     const int lane = (int)threadIdx.x;
