@@ -12,6 +12,8 @@
 * 20 all-TVD steps against 20 oracle steps (1e-11); a periodic shift of the
   inputs shifts the source terms bitwise, whichever place in a 2 x 2 tile a
   column takes (so a face evaluated by either of its columns is the same).
+* Courant numbers near 1 (0.95) match the oracle; above 1 the largest one is
+  still reported exactly.
 """
 import sys
 
@@ -207,3 +209,39 @@ def test_tvd_momentum_translation_invariance_bitwise():
     shifted = run([I.pad(np.roll(I.interior(h), (3, -5), axis=(0, 1))) for h in host[:3]])
     for a, b in zip(base, shifted):
         np.testing.assert_array_equal(np.roll(a, (3, -5), axis=(0, 1)), b)
+
+
+def test_courant_near_one_matches_oracle():
+    """dt chosen so that the largest Courant number is about 0.95 (the
+    QUICKEST term depends most on c there)."""
+    say("tvd_momentum near Courant 1")
+    g, host = case(9, 6, 128, 0, seed=1300 + 9 + 128)
+    _, _, _, c1 = O.tvd_momentum(*host[:3], g, 1.0)
+    dt = 0.95 / c1  # the Courant numbers scale with dt
+    su, sv, sw, cmax = O.tvd_momentum(*host[:3], g, dt)
+    assert 0.9 < cmax <= 1.0
+    T = torch()
+    d = to_dev(host[:3])
+    out = [T.empty_like(d[0]) for _ in range(3)]
+    cm = T.zeros(1, dtype=T.float64, device=dev())
+    M.monc_advect_tvd_momentum(*d, *out, g.dx, g.dy, prof_dev(g), dt, cmax=cm)
+    T.cuda.synchronize()
+    for n, r in enumerate((su, sv, sw)):
+        assert rel_err(out[n].cpu().numpy(), r) <= TOL, n
+    assert abs(cm.item() - cmax) <= 1e-14 * cmax
+
+
+def test_courant_above_one_is_reported():
+    """Beyond the scheme's limit the values are unspecified, but the largest
+    Courant number is still reported exactly."""
+    g, host = case(8, 8, 16, 0, seed=1900)
+    dt = 200.0
+    _, _, _, cmax = O.tvd_momentum(*host[:3], g, dt, allow_cfl=True)
+    assert cmax > 1.0
+    T = torch()
+    d = to_dev(host[:3])
+    out = [T.empty_like(d[0]) for _ in range(3)]
+    cm = T.zeros(1, dtype=T.float64, device=dev())
+    M.monc_advect_tvd_momentum(*d, *out, g.dx, g.dy, prof_dev(g), dt, cmax=cm)
+    T.cuda.synchronize()
+    assert abs(cm.item() - cmax) <= 1e-14 * cmax
