@@ -68,10 +68,13 @@ __global__ void tvdmom_clear(double* cmax) {
     if (threadIdx.x == 0) cmax[0] = 0.0;
 }
 
-// Three waves per SIMD: the kernel is bound by FP64 issue and load latency;
-// left alone the compiler keeps 205 registers (two waves per SIMD), and at the
-// three-wave ceiling of 168 it spills four, which measured 15 % faster than
-// two waves and 11 % faster than the untiled form at three.
+// Three waves per SIMD: the kernel is bound by latency.  With every load
+// issued at the top the compiler keeps 205 registers (two waves per SIMD);
+// the loads are therefore issued phase by phase (x-stencils and east faces,
+// y-stencils and north faces, the edge faces, z-stencils and z-faces) with
+// scheduling barriers between the phases, which holds 156 registers without
+// spilling.  Three waves measured 15 % faster than two; four need spills and
+// run at half speed.
 template <bool STEPF>
 __global__ void __launch_bounds__(64 * TM_WAVES)
     __attribute__((amdgpu_waves_per_eu(3))) tvdmom_kernel(TvdMomArgs A) {
@@ -155,26 +158,6 @@ __global__ void __launch_bounds__(64 * TM_WAVES)
     const bool zm1 = kc >= 1, zm2 = kc >= 2, zp1 = kc + 1 <= nz - 1, zp2 = kc + 2 <= nz - 1;
     const bool wlev = kc <= nz - 2;  // w at level k is not the lid
 
-    const double u0 = U[c00 + kc], v0 = V[c00 + kc], w0 = wlev ? W[c00 + kc] : 0.0;
-    const double uxm1 = U[cxm1 + kc], uxp1 = U[cxp1 + kc], uxp2 = U[cxp2 + kc];
-    const double uym1 = U[cym1 + kc], uyp1 = U[cyp1 + kc], uyp2 = U[cyp2 + kc];
-    const double vxm1 = V[cxm1 + kc], vxp1 = V[cxp1 + kc], vxp2 = V[cxp2 + kc];
-    const double vym1 = V[cym1 + kc], vyp1 = V[cyp1 + kc], vyp2 = V[cyp2 + kc];
-    // w: zero on the ground (level -1) and the lid (level nz-1)
-    const double wxm1 = wlev ? W[cxm1 + kc] : 0.0, wxp1 = wlev ? W[cxp1 + kc] : 0.0;
-    const double wxp2 = wlev ? W[cxp2 + kc] : 0.0;
-    const double wym1 = wlev ? W[cym1 + kc] : 0.0, wyp1 = wlev ? W[cyp1 + kc] : 0.0;
-    const double wyp2 = wlev ? W[cyp2 + kc] : 0.0;
-    const double uzm2 = zm2 ? U[c00 + kc - 2] : 0.0, uzm1 = zm1 ? U[c00 + kc - 1] : 0.0;
-    const double uzp1 = zp1 ? U[c00 + kc + 1] : 0.0, uzp2 = zp2 ? U[c00 + kc + 2] : 0.0;
-    const double vzm2 = zm2 ? V[c00 + kc - 2] : 0.0, vzm1 = zm1 ? V[c00 + kc - 1] : 0.0;
-    const double vzp1 = zp1 ? V[c00 + kc + 1] : 0.0, vzp2 = zp2 ? V[c00 + kc + 2] : 0.0;
-    const double wzm1 = zm1 ? W[c00 + kc - 1] : 0.0, wzm2 = zm2 ? W[c00 + kc - 2] : 0.0;
-    const double wzp1 = kc + 1 <= nz - 2 ? W[c00 + kc + 1] : 0.0;
-    const double wzp2 = kc + 2 <= nz - 2 ? W[c00 + kc + 2] : 0.0;
-    const double w_xp1zm1 = zm1 ? W[cxp1 + kc - 1] : 0.0;
-    const double w_yp1zm1 = zm1 ? W[cyp1 + kc - 1] : 0.0;
-
     __syncthreads();  // level table ready
     const int r = kc - k0 + 1;  // row of level k; k-1 and k+1 are its neighbours
     const double rdz_k = tab[L_RDZ][r], rhon_k = tab[L_RHON][r], rho_k = tab[L_RHO][r];
@@ -190,22 +173,38 @@ __global__ void __launch_bounds__(64 * TM_WAVES)
     const double cwx = cdx * rho_inv, cwy = cdy * rho_inv;
     const double rwx = rfx * rho_k, rwy = rfy * rho_k;
 
-    // ---- east and north faces of this column ----
-    const double a_ue = 0.5 * (u0 + uxp1), a_un = 0.5 * (v0 + vxp1);
-    const double a_ve = 0.5 * (u0 + uyp1), a_vn = 0.5 * (v0 + vyp1);
-    const double m_we = alpha * u0 + beta * uzp1, m_wn = alpha * v0 + beta * vzp1;
+    // phase x: the x-stencils and the east faces
+    const double u0 = U[c00 + kc], v0 = V[c00 + kc], w0 = wlev ? W[c00 + kc] : 0.0;
+    const double uxm1 = U[cxm1 + kc], uxp1 = U[cxp1 + kc], uxp2 = U[cxp2 + kc];
+    const double vxm1 = V[cxm1 + kc], vxp1 = V[cxp1 + kc], vxp2 = V[cxp2 + kc];
+    const double wxm1 = wlev ? W[cxm1 + kc] : 0.0, wxp1 = wlev ? W[cxp1 + kc] : 0.0;
+    const double wxp2 = wlev ? W[cxp2 + kc] : 0.0;
+    const double uyp1 = U[cyp1 + kc];
+    const double uzp1 = zp1 ? U[c00 + kc + 1] : 0.0;
+    const double a_ue = 0.5 * (u0 + uxp1), a_ve = 0.5 * (u0 + uyp1);
+    const double m_we = alpha * u0 + beta * uzp1;
     const double fe_u = tvd_flux(a_ue, uxm1, u0, uxp1, uxp2, cdx, rfx, rhon_k);
-    const double fn_u = tvd_flux(a_un, uym1, u0, uyp1, uyp2, cdy, rfy, rhon_k);
     const double fe_v = tvd_flux(a_ve, vxm1, v0, vxp1, vxp2, cdx, rfx, rhon_k);
-    const double fn_v = tvd_flux(a_vn, vym1, v0, vyp1, vyp2, cdy, rfy, rhon_k);
     const double fe_w = tvd_flux(m_we, wxm1, w0, wxp1, wxp2, cwx, rwx, 1.0);
-    const double fn_w = tvd_flux(m_wn, wym1, w0, wyp1, wyp2, cwy, rwy, 1.0);
     east[wv][0][lane] = fe_u;
     east[wv][1][lane] = fe_v;
     east[wv][2][lane] = fe_w;
+    __builtin_amdgcn_sched_barrier(0);
+    // phase y: the y-stencils and the north faces
+    const double uym1 = U[cym1 + kc], uyp2 = U[cyp2 + kc];
+    const double vym1 = V[cym1 + kc], vyp1 = V[cyp1 + kc], vyp2 = V[cyp2 + kc];
+    const double wym1 = wlev ? W[cym1 + kc] : 0.0, wyp1 = wlev ? W[cyp1 + kc] : 0.0;
+    const double wyp2 = wlev ? W[cyp2 + kc] : 0.0;
+    const double vzp1 = zp1 ? V[c00 + kc + 1] : 0.0;
+    const double a_un = 0.5 * (v0 + vxp1), a_vn = 0.5 * (v0 + vyp1);
+    const double m_wn = alpha * v0 + beta * vzp1;
+    const double fn_u = tvd_flux(a_un, uym1, u0, uyp1, uyp2, cdy, rfy, rhon_k);
+    const double fn_v = tvd_flux(a_vn, vym1, v0, vyp1, vyp2, cdy, rfy, rhon_k);
+    const double fn_w = tvd_flux(m_wn, wym1, w0, wyp1, wyp2, cwy, rwy, 1.0);
     north[wv][0][lane] = fn_u;
     north[wv][1][lane] = fn_v;
     north[wv][2][lane] = fn_w;
+    __builtin_amdgcn_sched_barrier(0);
 
     // ---- west faces: evaluated on the tile's west edge, else the neighbour's east ----
     double fw_u, fw_v, fw_w, cw = 0.0;
@@ -238,7 +237,17 @@ __global__ void __launch_bounds__(64 * TM_WAVES)
         cs = fmax(fmax(fabs(a_us), fabs(a_vs)) * cdy, wlev ? fabs(m_ws) * cwy : 0.0);
     }
 
+    __builtin_amdgcn_sched_barrier(0);
     // ---- z faces (top k+1/2 and bottom k-1/2 of u, v; centres k+1 and k of w) ----
+    const double uzm2 = zm2 ? U[c00 + kc - 2] : 0.0, uzm1 = zm1 ? U[c00 + kc - 1] : 0.0;
+    const double uzp2 = zp2 ? U[c00 + kc + 2] : 0.0;
+    const double vzm2 = zm2 ? V[c00 + kc - 2] : 0.0, vzm1 = zm1 ? V[c00 + kc - 1] : 0.0;
+    const double vzp2 = zp2 ? V[c00 + kc + 2] : 0.0;
+    const double wzm1 = zm1 ? W[c00 + kc - 1] : 0.0, wzm2 = zm2 ? W[c00 + kc - 2] : 0.0;
+    const double wzp1 = kc + 1 <= nz - 2 ? W[c00 + kc + 1] : 0.0;
+    const double wzp2 = kc + 2 <= nz - 2 ? W[c00 + kc + 2] : 0.0;
+    const double w_xp1zm1 = zm1 ? W[cxp1 + kc - 1] : 0.0;
+    const double w_yp1zm1 = zm1 ? W[cyp1 + kc - 1] : 0.0;
     const double a_ut = 0.5 * (w0 + wxp1), a_ub = 0.5 * (wzm1 + w_xp1zm1);
     const double a_vt = 0.5 * (w0 + wyp1), a_vb = 0.5 * (wzm1 + w_yp1zm1);
     const double ft_u = wlev ? zface(a_ut, uzm1, u0, uzp1, uzp2, zm1, zp2, A.dt * rdzn_k,
