@@ -46,8 +46,7 @@ constexpr int TM_WAVES = TM_TX * TM_TY;
 constexpr int TM_BAND = 8;  // tile rows per band of the traversal
 // Level table of the chunk: levels k0-1 .. k0+64.
 constexpr int TM_LEV = 66;
-enum { L_RDZ, L_RHON, L_RHO, L_DZ, L_RHONI, L_RHOI, L_RDZN, L_DZN, L_ALPHA, L_BETA, L_CZ, L_RZ,
-       L_N };
+enum { L_RDZ, L_RHON, L_RHO, L_RHONI, L_RHOI, L_RDZN, L_DZN, L_ALPHA, L_BETA, L_CZ, L_RZ, L_N };
 
 // Flux through a z-face whose far-upwind value may not exist (next to the
 // ground or the lid): first-order upwind there.
@@ -72,7 +71,7 @@ __global__ void tvdmom_clear(double* cmax) {
 // issued at the top the compiler keeps 205 registers (two waves per SIMD);
 // the loads are therefore issued phase by phase (x-stencils and east faces,
 // y-stencils and north faces, the edge faces, z-stencils and z-faces) with
-// scheduling barriers between the phases, which holds 156 registers without
+// scheduling barriers between the phases, which holds 154 registers without
 // spilling.  Three waves measured 15 % faster than two; four need spills and
 // run at half speed.
 template <bool STEPF>
@@ -125,7 +124,6 @@ __global__ void __launch_bounds__(64 * TM_WAVES)
                 row[L_RDZ] = rdz;
                 row[L_RHON] = rhon;
                 row[L_RHO] = rho;
-                row[L_DZ] = dz;
                 row[L_RHONI] = 1.0 / rhon;
                 row[L_RHOI] = 1.0 / rho;
                 row[L_CZ] = A.dt * rdz * row[L_RHONI];  // w z-face at the centre of cell q
