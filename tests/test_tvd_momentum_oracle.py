@@ -330,3 +330,33 @@ def test_region_equals_whole_domain():
     for f in range(3):
         np.testing.assert_array_equal(interior(part[f])[3:8, 0:5], interior(full[f])[3:8, 0:5])
         assert np.abs(interior(part[f])[:3]).max() == 0.0
+
+
+def test_worked_example_1d():
+    """Hand-derived fixture (tests/golden/tvd_momentum_1d.txt): the face values
+    of every limiter case (flat upwind, active QUICKEST, the ULTIMATE bound
+    binding, extrema, zero mass flux) and the resulting su."""
+    import os
+    gold = {}
+    with open(os.path.join(os.path.dirname(__file__), "golden", "tvd_momentum_1d.txt")) as fh:
+        for line in fh:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                key, *vals = line.split()
+                gold[key] = np.array([float(x) for x in vals])
+    u = gold["u"]
+    a = (u + np.roll(u, -1)) / 2
+    faces = [O.ultimate_face(u[i - 1], u[i], u[(i + 1) % 6], a[i] * 0.25) for i in range(6)]
+    np.testing.assert_allclose(faces, gold["face"], rtol=1e-15, atol=0)
+    np.testing.assert_allclose(a * gold["face"], gold["flux"], rtol=1e-15, atol=0)
+    one = np.ones(2)
+    zf = np.arange(1, 3, dtype=float)
+    g = I.Geometry(6, 1, 2, 1.0, 1.0, one.copy(), one.copy(), one.copy(), zf, zf - 0.5)
+    U = padded(np.repeat(u[:, None, None], 2, axis=2))
+    Z = padded(np.zeros((6, 1, 2)))
+    su, sv, sw, cm = O.tvd_momentum(U, Z, Z.copy(), g, 0.25)
+    for k in range(2):
+        np.testing.assert_allclose(interior(su)[:, 0, k], gold["su"], rtol=0, atol=1e-15)
+    assert np.all(interior(sv) == 0) and np.all(interior(sw) == 0)
+    assert gold["su"].sum() == 0.0
+    assert cm == 0.75
