@@ -22,13 +22,15 @@
 // upwind value.  tvd_flux takes any flux-like advecting quantity a with its
 // own dt/spacing factor, so the w faces pass the mass flux itself.
 //
-// One thread per grid point: a wave covers 64 levels of one column, a
-// workgroup a 2 x 2 tile of columns, and neighbours come through the caches.
-// A lateral face inside a tile is evaluated once and handed to the other
-// column through LDS; the z-faces of a column are evaluated by both levels
-// that share them.  The per-level geometry is built once per workgroup in
-// LDS.  Periodic neighbours are read at wrapped indices; halos are neither
-// read nor written.
+// One thread per grid point of a column's 64-level chunk.  A workgroup is
+// four columns along y (one wave each) that march together through a segment
+// of x-planes: the x-stencil of each column stays in a four-plane register
+// window, the east face of a plane is the next plane's west face, and the
+// north face of a column is handed to the next column's wave through LDS, so
+// a lateral face is evaluated once (the faces on segment and workgroup edges
+// twice).  The z-faces of a column are evaluated by both levels that share
+// them.  The per-level geometry is built once per workgroup in LDS.  Periodic
+// neighbours are read at wrapped indices; halos are neither read nor written.
 #include "monc_internal.hpp"
 #include "monc_scheme.hpp"
 
@@ -36,14 +38,8 @@ namespace monc {
 
 namespace {
 
-// A workgroup is a 2 x 2 tile of columns (one wave each) over one 64-level
-// chunk.  Each wave evaluates the east and north faces of its column; the
-// waves on the tile's west (south) edge also evaluate their west (south)
-// faces, and the others take them from their neighbour through LDS, so a
-// lateral face is evaluated once inside a tile.
-constexpr int TM_TX = 2, TM_TY = 2;
-constexpr int TM_WAVES = TM_TX * TM_TY;
-constexpr int TM_BAND = 8;  // tile rows per band of the traversal
+constexpr int TM_TJ = 4;   // columns (waves) per workgroup, along y
+constexpr int TM_TI = 64;  // x-planes per segment
 // Level table of the chunk: levels k0-1 .. k0+64.
 constexpr int TM_LEV = 66;
 enum { L_RDZ, L_RHON, L_RHO, L_RHONI, L_RHOI, L_RDZN, L_DZN, L_ALPHA, L_BETA, L_CZ, L_RZ, L_N };
@@ -67,48 +63,35 @@ __global__ void tvdmom_clear(double* cmax) {
     if (threadIdx.x == 0) cmax[0] = 0.0;
 }
 
-// Three waves per SIMD: the kernel is bound by latency.  With every load
-// issued at the top the compiler keeps 205 registers (two waves per SIMD);
-// the loads are therefore issued phase by phase (x-stencils and east faces,
-// y-stencils and north faces, the edge faces, z-stencils and z-faces) with
-// scheduling barriers between the phases, which holds 154 registers without
-// spilling.  Three waves measured 15 % faster than two; four need spills and
-// run at half speed.
+// Two waves per SIMD: the march holds 215 registers without spilling.  A
+// three-wave ceiling (168) spills 21 of them inside the plane loop and ran
+// 38 % slower; with scheduling barriers between the loop's phases it still
+// spills 12 and ran 9 % slower.
 template <bool STEPF>
-__global__ void __launch_bounds__(64 * TM_WAVES)
-    __attribute__((amdgpu_waves_per_eu(3))) tvdmom_kernel(TvdMomArgs A) {
+__global__ void __launch_bounds__(64 * TM_TJ) tvdmom_kernel(TvdMomArgs A) {
     __shared__ double tab[L_N][TM_LEV];
-    __shared__ double east[TM_WAVES][3][64];
-    __shared__ double north[TM_WAVES][3][64];
+    __shared__ double north[2][TM_TJ][3][64];  // by plane parity
     const int nx = A.nx, ny = A.ny, nz = A.nz;
     // Consecutive workgroups go to the same XCD (they are dealt to the 8 XCDs
-    // round-robin), so neighbouring tiles share that XCD's L2.
+    // round-robin); neighbouring column groups of one segment are consecutive,
+    // so the columns they share are still in that XCD's L2.
     int b = blockIdx.x;
     const int nb = gridDim.x;
     if ((nb & 7) == 0) b = (b & 7) * (nb >> 3) + (b >> 3);
-    // Tiles are walked along x inside bands of TM_BAND tile rows, so the
-    // columns a tile shares with its x-neighbours (two on each side) are
-    // still in L2 when those neighbours run.
     const int nchunk = (nz + 63) / 64;
-    const int nty = (ny + TM_TY - 1) / TM_TY;
-    const int ntx = (nx + TM_TX - 1) / TM_TX;
-    const int per_band = TM_BAND * nchunk * ntx;
-    const int band = b / per_band;
-    const int rows = min(TM_BAND, nty - band * TM_BAND);  // the last band may be short
-    const int rb = b - band * per_band;
-    const int chunk = rb % nchunk;
-    const int ty = band * TM_BAND + (rb / nchunk) % rows;
-    const int tx = rb / (nchunk * rows);
-    const int wv = (int)threadIdx.y;  // wave in the tile
-    const int wx = wv % TM_TX, wy = wv / TM_TX;
+    const int njt = (ny + TM_TJ - 1) / TM_TJ;
+    const int chunk = b % nchunk;
+    const int jt = (b / nchunk) % njt;
+    const int seg = b / (nchunk * njt);
+    const int wv = (int)threadIdx.y;  // column in the workgroup
     const int lane = (int)threadIdx.x;
     const int k0 = 64 * chunk;
     const int k = k0 + lane;
-    const int i = __builtin_amdgcn_readfirstlane(TM_TX * tx + wx);
-    const int j = __builtin_amdgcn_readfirstlane(TM_TY * ty + wy);
-    const bool live = k < nz && i < nx && j < ny;
+    const int j = __builtin_amdgcn_readfirstlane(TM_TJ * jt + wv);
+    const int i0 = TM_TI * seg;
+    const int i1 = min(i0 + TM_TI, nx);
+    const bool live = k < nz && j < ny;
     const int kc = k < nz ? k : nz - 1;  // dead lanes load in bounds, store nothing
-    const int ic = i < nx ? i : nx - 1;
     const int jc = j < ny ? j : ny - 1;
 
     // level table (one division set per level per workgroup)
@@ -142,19 +125,34 @@ __global__ void __launch_bounds__(64 * TM_WAVES)
         }
     }
 
-    auto col = [&](int ii, int jj) -> long {
-        return ((long)(wrap(ii, nx) + 2) * (ny + 4) + (wrap(jj, ny) + 2)) * nz;
-    };
-    const bool west_edge = wx == 0, south_edge = wy == 0;
-    const long c00 = col(ic, jc);
-    const long cxm1 = col(ic - 1, jc), cxp1 = col(ic + 1, jc), cxp2 = col(ic + 2, jc);
-    const long cym1 = col(ic, jc - 1), cyp1 = col(ic, jc + 1), cyp2 = col(ic, jc + 2);
-
     const double* __restrict__ U = A.u;
     const double* __restrict__ V = A.v;
     const double* __restrict__ W = A.w;
     const bool zm1 = kc >= 1, zm2 = kc >= 2, zp1 = kc + 1 <= nz - 1, zp2 = kc + 2 <= nz - 1;
     const bool wlev = kc <= nz - 2;  // w at level k is not the lid
+    const long sx = (long)(ny + 4) * nz;
+    auto px = [&](int ii) -> long { return (long)(wrap(ii, nx) + 2) * sx; };
+    auto oy = [&](int jj) -> long { return (long)(wrap(jj, ny) + 2) * nz; };
+    const long oj = oy(jc), ojm1 = oy(jc - 1), ojm2 = oy(jc - 2), ojp1 = oy(jc + 1),
+               ojp2 = oy(jc + 2);
+
+    // x-window of the own column: planes i-1, i, i+1, i+2; the plane after
+    // is prefetched one step ahead
+    double xu[4], xv[4], xw[4];
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+        const long p = px(i0 - 1 + d) + oj + kc;
+        xu[d] = U[p];
+        xv[d] = V[p];
+        xw[d] = wlev ? W[p] : 0.0;
+    }
+    double nu, nv, nw;
+    {
+        const long p = px(i0 + 2) + oj + kc;
+        nu = U[p];
+        nv = V[p];
+        nw = wlev ? W[p] : 0.0;
+    }
 
     __syncthreads();  // level table ready
     const int r = kc - k0 + 1;  // row of level k; k-1 and k+1 are its neighbours
@@ -170,150 +168,162 @@ __global__ void __launch_bounds__(64 * TM_WAVES)
     const double cdx = A.cdx, cdy = A.cdy, rfx = A.rfx, rfy = A.rfy;
     const double cwx = cdx * rho_inv, cwy = cdy * rho_inv;
     const double rwx = rfx * rho_k, rwy = rfy * rho_k;
+    const double czu_t = A.dt * rdzn_k, rzu_t = dzn_k * A.rdt;
+    const double czu_b = A.dt * rdzn_km, rzu_b = dzn_km * A.rdt;
 
-    // phase x: the x-stencils and the east faces
-    const double u0 = U[c00 + kc], v0 = V[c00 + kc], w0 = wlev ? W[c00 + kc] : 0.0;
-    const double uxm1 = U[cxm1 + kc], uxp1 = U[cxp1 + kc], uxp2 = U[cxp2 + kc];
-    const double vxm1 = V[cxm1 + kc], vxp1 = V[cxp1 + kc], vxp2 = V[cxp2 + kc];
-    const double wxm1 = wlev ? W[cxm1 + kc] : 0.0, wxp1 = wlev ? W[cxp1 + kc] : 0.0;
-    const double wxp2 = wlev ? W[cxp2 + kc] : 0.0;
-    const double uyp1 = U[cyp1 + kc];
-    const double uzp1 = zp1 ? U[c00 + kc + 1] : 0.0;
-    const double a_ue = 0.5 * (u0 + uxp1), a_ve = 0.5 * (u0 + uyp1);
-    const double m_we = alpha * u0 + beta * uzp1;
-    const double fe_u = tvd_flux(a_ue, uxm1, u0, uxp1, uxp2, cdx, rfx, rhon_k);
-    const double fe_v = tvd_flux(a_ve, vxm1, v0, vxp1, vxp2, cdx, rfx, rhon_k);
-    const double fe_w = tvd_flux(m_we, wxm1, w0, wxp1, wxp2, cwx, rwx, 1.0);
-    east[wv][0][lane] = fe_u;
-    east[wv][1][lane] = fe_v;
-    east[wv][2][lane] = fe_w;
-    __builtin_amdgcn_sched_barrier(0);
-    // phase y: the y-stencils and the north faces
-    const double uym1 = U[cym1 + kc], uyp2 = U[cyp2 + kc];
-    const double vym1 = V[cym1 + kc], vyp1 = V[cyp1 + kc], vyp2 = V[cyp2 + kc];
-    const double wym1 = wlev ? W[cym1 + kc] : 0.0, wyp1 = wlev ? W[cyp1 + kc] : 0.0;
-    const double wyp2 = wlev ? W[cyp2 + kc] : 0.0;
-    const double vzp1 = zp1 ? V[c00 + kc + 1] : 0.0;
-    const double a_un = 0.5 * (v0 + vxp1), a_vn = 0.5 * (v0 + vyp1);
-    const double m_wn = alpha * v0 + beta * vzp1;
-    const double fn_u = tvd_flux(a_un, uym1, u0, uyp1, uyp2, cdy, rfy, rhon_k);
-    const double fn_v = tvd_flux(a_vn, vym1, v0, vyp1, vyp2, cdy, rfy, rhon_k);
-    const double fn_w = tvd_flux(m_wn, wym1, w0, wyp1, wyp2, cwy, rwy, 1.0);
-    north[wv][0][lane] = fn_u;
-    north[wv][1][lane] = fn_v;
-    north[wv][2][lane] = fn_w;
-    __builtin_amdgcn_sched_barrier(0);
-
-    // ---- west faces: evaluated on the tile's west edge, else the neighbour's east ----
-    double fw_u, fw_v, fw_w, cw = 0.0;
-    if (west_edge) {
-        const long cxm2 = col(ic - 2, jc), cxm1yp1 = col(ic - 1, jc + 1);
-        const double uxm2 = U[cxm2 + kc], vxm2 = V[cxm2 + kc];
-        const double wxm2 = wlev ? W[cxm2 + kc] : 0.0;
-        const double u_xm1yp1 = U[cxm1yp1 + kc];
-        const double u_xm1zp1 = zp1 ? U[cxm1 + kc + 1] : 0.0;
-        const double a_uw = 0.5 * (uxm1 + u0), a_vw = 0.5 * (uxm1 + u_xm1yp1);
-        const double m_ww = alpha * uxm1 + beta * u_xm1zp1;
-        fw_u = tvd_flux(a_uw, uxm2, uxm1, u0, uxp1, cdx, rfx, rhon_k);
-        fw_v = tvd_flux(a_vw, vxm2, vxm1, v0, vxp1, cdx, rfx, rhon_k);
-        fw_w = tvd_flux(m_ww, wxm2, wxm1, w0, wxp1, cwx, rwx, 1.0);
-        cw = fmax(fmax(fabs(a_uw), fabs(a_vw)) * cdx, wlev ? fabs(m_ww) * cwx : 0.0);
-    }
-    // ---- south faces likewise ----
-    double fs_u, fs_v, fs_w, cs = 0.0;
-    if (south_edge) {
-        const long cym2 = col(ic, jc - 2), cxp1ym1 = col(ic + 1, jc - 1);
-        const double uym2 = U[cym2 + kc], vym2 = V[cym2 + kc];
-        const double wym2 = wlev ? W[cym2 + kc] : 0.0;
-        const double v_xp1ym1 = V[cxp1ym1 + kc];
-        const double v_ym1zp1 = zp1 ? V[cym1 + kc + 1] : 0.0;
-        const double a_us = 0.5 * (vym1 + v_xp1ym1), a_vs = 0.5 * (vym1 + v0);
-        const double m_ws = alpha * vym1 + beta * v_ym1zp1;
-        fs_u = tvd_flux(a_us, uym2, uym1, u0, uyp1, cdy, rfy, rhon_k);
-        fs_v = tvd_flux(a_vs, vym2, vym1, v0, vyp1, cdy, rfy, rhon_k);
-        fs_w = tvd_flux(m_ws, wym2, wym1, w0, wyp1, cwy, rwy, 1.0);
-        cs = fmax(fmax(fabs(a_us), fabs(a_vs)) * cdy, wlev ? fabs(m_ws) * cwy : 0.0);
+    // west faces of the first plane: the east faces of the plane before it,
+    // evaluated the same way
+    double fw_u, fw_v, fw_w, cm;
+    {
+        const long pm1 = px(i0 - 1), pm2 = px(i0 - 2);
+        const double um2 = U[pm2 + oj + kc], vm2 = V[pm2 + oj + kc];
+        const double wm2 = wlev ? W[pm2 + oj + kc] : 0.0;
+        const double u_xm1yp1 = U[pm1 + ojp1 + kc];
+        const double u_xm1zp1 = zp1 ? U[pm1 + oj + kc + 1] : 0.0;
+        const double a_u = 0.5 * (xu[0] + xu[1]), a_v = 0.5 * (xu[0] + u_xm1yp1);
+        const double m_w = alpha * xu[0] + beta * u_xm1zp1;
+        fw_u = tvd_flux(a_u, um2, xu[0], xu[1], xu[2], cdx, rfx, rhon_k);
+        fw_v = tvd_flux(a_v, vm2, xv[0], xv[1], xv[2], cdx, rfx, rhon_k);
+        fw_w = tvd_flux(m_w, wm2, xw[0], xw[1], xw[2], cwx, rwx, 1.0);
+        cm = fmax(fmax(fabs(a_u), fabs(a_v)) * cdx, wlev ? fabs(m_w) * cwx : 0.0);
     }
 
-    __builtin_amdgcn_sched_barrier(0);
-    // ---- z faces (top k+1/2 and bottom k-1/2 of u, v; centres k+1 and k of w) ----
-    const double uzm2 = zm2 ? U[c00 + kc - 2] : 0.0, uzm1 = zm1 ? U[c00 + kc - 1] : 0.0;
-    const double uzp2 = zp2 ? U[c00 + kc + 2] : 0.0;
-    const double vzm2 = zm2 ? V[c00 + kc - 2] : 0.0, vzm1 = zm1 ? V[c00 + kc - 1] : 0.0;
-    const double vzp2 = zp2 ? V[c00 + kc + 2] : 0.0;
-    const double wzm1 = zm1 ? W[c00 + kc - 1] : 0.0, wzm2 = zm2 ? W[c00 + kc - 2] : 0.0;
-    const double wzp1 = kc + 1 <= nz - 2 ? W[c00 + kc + 1] : 0.0;
-    const double wzp2 = kc + 2 <= nz - 2 ? W[c00 + kc + 2] : 0.0;
-    const double w_xp1zm1 = zm1 ? W[cxp1 + kc - 1] : 0.0;
-    const double w_yp1zm1 = zm1 ? W[cyp1 + kc - 1] : 0.0;
-    const double a_ut = 0.5 * (w0 + wxp1), a_ub = 0.5 * (wzm1 + w_xp1zm1);
-    const double a_vt = 0.5 * (w0 + wyp1), a_vb = 0.5 * (wzm1 + w_yp1zm1);
-    const double ft_u = wlev ? zface(a_ut, uzm1, u0, uzp1, uzp2, zm1, zp2, A.dt * rdzn_k,
-                                     dzn_k * A.rdt, rho_k)
-                             : 0.0;
-    const double fb_u = zm1 ? zface(a_ub, uzm2, uzm1, u0, uzp1, zm2, zp1, A.dt * rdzn_km,
-                                    dzn_km * A.rdt, rho_km)
-                            : 0.0;
-    const double ft_v = wlev ? zface(a_vt, vzm1, v0, vzp1, vzp2, zm1, zp2, A.dt * rdzn_k,
-                                     dzn_k * A.rdt, rho_k)
-                             : 0.0;
-    const double fb_v = zm1 ? zface(a_vb, vzm2, vzm1, v0, vzp1, zm2, zp1, A.dt * rdzn_km,
-                                    dzn_km * A.rdt, rho_km)
-                            : 0.0;
-    const double m_wt = 0.5 * (rho_k * w0 + rho_kp * wzp1);
-    const double m_wb = 0.5 * (rho_km * wzm1 + rho_k * w0);
-    // top: between w_k and w_{k+1}, far values w_{k-1} (always there: the
-    // ground at k = 0) and w_{k+2} (there up to the lid)
-    const double ft_w = zface(m_wt, wzm1, w0, wzp1, wzp2, true, kc + 2 <= nz - 1, cz_t, rz_t,
-                              1.0);
-    // bottom: between w_{k-1} and w_k, far values w_{k-2} (there from k = 1)
-    // and w_{k+1}
-    const double fb_w = zface(m_wb, wzm2, wzm1, w0, wzp1, zm1, true, cz_b, rz_b, 1.0);
+    for (int i = i0; i < i1; i++) {
+        xu[3] = nu;
+        xv[3] = nv;
+        xw[3] = nw;
+        if (i + 1 < i1) {  // prefetch plane i+3
+            const long p = px(i + 3) + oj + kc;
+            nu = U[p];
+            nv = V[p];
+            nw = wlev ? W[p] : 0.0;
+        }
+        const long p0 = px(i), pp1 = px(i + 1);
+        const long c00 = p0 + oj;
+        const double u0 = xu[1], v0 = xv[1], w0 = xw[1];
 
-    __syncthreads();  // east and north faces of the tile in LDS
-    if (!west_edge) {
-        fw_u = east[wv - 1][0][lane];
-        fw_v = east[wv - 1][1][lane];
-        fw_w = east[wv - 1][2][lane];
-    }
-    if (!south_edge) {
-        fs_u = north[wv - TM_TX][0][lane];
-        fs_v = north[wv - TM_TX][1][lane];
-        fs_w = north[wv - TM_TX][2][lane];
-    }
+        // y-stencils at plane i
+        const double uym1 = U[p0 + ojm1 + kc], uyp1 = U[p0 + ojp1 + kc], uyp2 = U[p0 + ojp2 + kc];
+        const double vym1 = V[p0 + ojm1 + kc], vyp1 = V[p0 + ojp1 + kc], vyp2 = V[p0 + ojp2 + kc];
+        const double wym1 = wlev ? W[p0 + ojm1 + kc] : 0.0;
+        const double wyp1 = wlev ? W[p0 + ojp1 + kc] : 0.0;
+        const double wyp2 = wlev ? W[p0 + ojp2 + kc] : 0.0;
+        // z-stencils of the own column at plane i
+        const double uzm2 = zm2 ? U[c00 + kc - 2] : 0.0, uzm1 = zm1 ? U[c00 + kc - 1] : 0.0;
+        const double uzp1 = zp1 ? U[c00 + kc + 1] : 0.0, uzp2 = zp2 ? U[c00 + kc + 2] : 0.0;
+        const double vzm2 = zm2 ? V[c00 + kc - 2] : 0.0, vzm1 = zm1 ? V[c00 + kc - 1] : 0.0;
+        const double vzp1 = zp1 ? V[c00 + kc + 1] : 0.0, vzp2 = zp2 ? V[c00 + kc + 2] : 0.0;
+        const double wzm1 = zm1 ? W[c00 + kc - 1] : 0.0, wzm2 = zm2 ? W[c00 + kc - 2] : 0.0;
+        const double wzp1 = kc + 1 <= nz - 2 ? W[c00 + kc + 1] : 0.0;
+        const double wzp2 = kc + 2 <= nz - 2 ? W[c00 + kc + 2] : 0.0;
+        const double w_xp1zm1 = zm1 ? W[pp1 + oj + kc - 1] : 0.0;
+        const double w_yp1zm1 = zm1 ? W[p0 + ojp1 + kc - 1] : 0.0;
 
-    const double su =
-        -rhon_inv * ((fe_u - fw_u) * A.rdx + (fn_u - fs_u) * A.rdy + rdz_k * (ft_u - fb_u));
-    const double sv =
-        -rhon_inv * ((fe_v - fw_v) * A.rdx + (fn_v - fs_v) * A.rdy + rdz_k * (ft_v - fb_v));
-    const double sw = wlev ? -rho_inv * ((fe_w - fw_w) * A.rdx + (fn_w - fs_w) * A.rdy +
-                                         rdzn_k * (ft_w - fb_w))
-                           : 0.0;
+        // ---- east faces (the next plane's west faces) ----
+        const double a_ue = 0.5 * (u0 + xu[2]), a_ve = 0.5 * (u0 + uyp1);
+        const double m_we = alpha * u0 + beta * uzp1;
+        const double fe_u = tvd_flux(a_ue, xu[0], u0, xu[2], xu[3], cdx, rfx, rhon_k);
+        const double fe_v = tvd_flux(a_ve, xv[0], v0, xv[2], xv[3], cdx, rfx, rhon_k);
+        const double fe_w = tvd_flux(m_we, xw[0], w0, xw[2], xw[3], cwx, rwx, 1.0);
+        // ---- north faces (the next column's south faces) ----
+        const double a_un = 0.5 * (v0 + xv[2]), a_vn = 0.5 * (v0 + vyp1);
+        const double m_wn = alpha * v0 + beta * vzp1;
+        const double fn_u = tvd_flux(a_un, uym1, u0, uyp1, uyp2, cdy, rfy, rhon_k);
+        const double fn_v = tvd_flux(a_vn, vym1, v0, vyp1, vyp2, cdy, rfy, rhon_k);
+        const double fn_w = tvd_flux(m_wn, wym1, w0, wyp1, wyp2, cwy, rwy, 1.0);
+        const int par = i & 1;
+        north[par][wv][0][lane] = fn_u;
+        north[par][wv][1][lane] = fn_v;
+        north[par][wv][2][lane] = fn_w;
+        // ---- south faces: evaluated by the first column of the workgroup ----
+        double fs_u = 0.0, fs_v = 0.0, fs_w = 0.0;
+        if (wv == 0) {
+            const double uym2 = U[p0 + ojm2 + kc], vym2 = V[p0 + ojm2 + kc];
+            const double wym2 = wlev ? W[p0 + ojm2 + kc] : 0.0;
+            const double v_xp1ym1 = V[pp1 + ojm1 + kc];
+            const double v_ym1zp1 = zp1 ? V[p0 + ojm1 + kc + 1] : 0.0;
+            const double a_us = 0.5 * (vym1 + v_xp1ym1), a_vs = 0.5 * (vym1 + v0);
+            const double m_ws = alpha * vym1 + beta * v_ym1zp1;
+            fs_u = tvd_flux(a_us, uym2, uym1, u0, uyp1, cdy, rfy, rhon_k);
+            fs_v = tvd_flux(a_vs, vym2, vym1, v0, vyp1, cdy, rfy, rhon_k);
+            fs_w = tvd_flux(m_ws, wym2, wym1, w0, wyp1, cwy, rwy, 1.0);
+            cm = fmax(cm, fmax(fmax(fabs(a_us), fabs(a_vs)) * cdy, wlev ? fabs(m_ws) * cwy : 0.0));
+        }
+        // ---- z faces (top k+1/2 and bottom k-1/2 of u, v; centres k+1 and k of w) ----
+        const double a_ut = 0.5 * (w0 + xw[2]), a_ub = 0.5 * (wzm1 + w_xp1zm1);
+        const double a_vt = 0.5 * (w0 + wyp1), a_vb = 0.5 * (wzm1 + w_yp1zm1);
+        const double ft_u = wlev ? zface(a_ut, uzm1, u0, uzp1, uzp2, zm1, zp2, czu_t, rzu_t, rho_k)
+                                 : 0.0;
+        const double fb_u = zm1 ? zface(a_ub, uzm2, uzm1, u0, uzp1, zm2, zp1, czu_b, rzu_b, rho_km)
+                                : 0.0;
+        const double ft_v = wlev ? zface(a_vt, vzm1, v0, vzp1, vzp2, zm1, zp2, czu_t, rzu_t, rho_k)
+                                 : 0.0;
+        const double fb_v = zm1 ? zface(a_vb, vzm2, vzm1, v0, vzp1, zm2, zp1, czu_b, rzu_b, rho_km)
+                                : 0.0;
+        const double m_wt = 0.5 * (rho_k * w0 + rho_kp * wzp1);
+        const double m_wb = 0.5 * (rho_km * wzm1 + rho_k * w0);
+        // top: between w_k and w_{k+1}, far values w_{k-1} (always there: the
+        // ground at k = 0) and w_{k+2} (there up to the lid)
+        const double ft_w = zface(m_wt, wzm1, w0, wzp1, wzp2, true, kc + 2 <= nz - 1, cz_t, rz_t,
+                                  1.0);
+        // bottom: between w_{k-1} and w_k, far values w_{k-2} (there from k = 1)
+        // and w_{k+1}
+        const double fb_w = zface(m_wb, wzm2, wzm1, w0, wzp1, zm1, true, cz_b, rz_b, 1.0);
 
-    if (live) {
-        const long c = c00 + k;
-        if constexpr (STEPF) {
-            A.out_u[c] = u0 + A.dt * su;
-            A.out_v[c] = v0 + A.dt * sv;
-            A.out_w[c] = wlev ? w0 + A.dt * sw : 0.0;
-        } else {
-            A.out_u[c] = su;
-            A.out_v[c] = sv;
-            A.out_w[c] = sw;
+        // The north faces of this plane are in LDS.  They are double-buffered
+        // by plane parity: a wave writes the other buffer next, and cannot
+        // reach the plane after that before every wave has passed this barrier.
+        __syncthreads();
+        if (wv > 0) {
+            fs_u = north[par][wv - 1][0][lane];
+            fs_v = north[par][wv - 1][1][lane];
+            fs_w = north[par][wv - 1][2][lane];
+        }
+
+        const double su =
+            -rhon_inv * ((fe_u - fw_u) * A.rdx + (fn_u - fs_u) * A.rdy + rdz_k * (ft_u - fb_u));
+        const double sv =
+            -rhon_inv * ((fe_v - fw_v) * A.rdx + (fn_v - fs_v) * A.rdy + rdz_k * (ft_v - fb_v));
+        const double sw = wlev ? -rho_inv * ((fe_w - fw_w) * A.rdx + (fn_w - fs_w) * A.rdy +
+                                             rdzn_k * (ft_w - fb_w))
+                               : 0.0;
+        if (live) {
+            const long c = c00 + k;
+            if constexpr (STEPF) {
+                A.out_u[c] = u0 + A.dt * su;
+                A.out_v[c] = v0 + A.dt * sv;
+                A.out_w[c] = wlev ? w0 + A.dt * sw : 0.0;
+            } else {
+                A.out_u[c] = su;
+                A.out_v[c] = sv;
+                A.out_w[c] = sw;
+            }
+        }
+        if (A.cmax) {
+            cm = fmax(cm, fmax(fmax(fabs(a_ue), fabs(a_ve)) * cdx,
+                               fmax(fabs(a_un), fabs(a_vn)) * cdy));
+            if (wlev) {
+                cm = fmax(cm, fmax(fabs(a_ut), fabs(a_vt)) * czu_t);
+                cm = fmax(cm, fmax(fabs(m_we) * cwx, fabs(m_wn) * cwy));
+                cm = fmax(cm, fmax(fabs(m_wt) * cz_t, fabs(m_wb) * cz_b));
+            }
+            if (zm1) cm = fmax(cm, fmax(fabs(a_ub), fabs(a_vb)) * czu_b);
+        }
+
+        fw_u = fe_u;
+        fw_v = fe_v;
+        fw_w = fe_w;
+#pragma unroll
+        for (int d = 0; d < 3; d++) {
+            xu[d] = xu[d + 1];
+            xv[d] = xv[d + 1];
+            xw[d] = xw[d + 1];
         }
     }
 
     if (A.cmax) {
         // largest Courant number of the faces this wave evaluated; every face
-        // of a live point is evaluated by some wave of its tile
-        double cm = fmax(fmax(fabs(a_ue), fabs(a_ve)) * cdx, fmax(fabs(a_un), fabs(a_vn)) * cdy);
-        cm = fmax(cm, fmax(cw, cs));
-        if (wlev) {
-            cm = fmax(cm, fmax(fabs(a_ut), fabs(a_vt)) * (A.dt * rdzn_k));
-            cm = fmax(cm, fmax(fabs(m_we) * cwx, fabs(m_wn) * cwy));
-            cm = fmax(cm, fmax(fabs(m_wt) * cz_t, fabs(m_wb) * cz_b));
-        }
-        if (zm1) cm = fmax(cm, fmax(fabs(a_ub), fabs(a_vb)) * (A.dt * rdzn_km));
+        // of a live point is evaluated by some wave of its workgroup
         if (!live) cm = 0.0;
         for (int o = 32; o > 0; o >>= 1) cm = fmax(cm, __shfl_xor(cm, o, 64));
         // Non-negative doubles order like their bit patterns.  The atomic is
@@ -336,13 +346,13 @@ hipError_t launch_tvd_momentum(const TvdMomArgs& a, bool step, hipStream_t s) {
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    const long nb = (long)((a.nz + 63) / 64) * ((a.ny + TM_TY - 1) / TM_TY) *
-                    ((a.nx + TM_TX - 1) / TM_TX);
+    const long nb = (long)((a.nz + 63) / 64) * ((a.ny + TM_TJ - 1) / TM_TJ) *
+                    ((a.nx + TM_TI - 1) / TM_TI);
     if (nb > 0x7fffffffL) return hipErrorInvalidValue;
     if (step)
-        tvdmom_kernel<true><<<(unsigned)nb, dim3(64, TM_WAVES), 0, s>>>(a);
+        tvdmom_kernel<true><<<(unsigned)nb, dim3(64, TM_TJ), 0, s>>>(a);
     else
-        tvdmom_kernel<false><<<(unsigned)nb, dim3(64, TM_WAVES), 0, s>>>(a);
+        tvdmom_kernel<false><<<(unsigned)nb, dim3(64, TM_TJ), 0, s>>>(a);
     return hipGetLastError();
 }
 
