@@ -4,7 +4,7 @@
   max |gpu - oracle| / max |oracle| <= 1e-13, on several tiles of columns with
   ragged edges, one- and two-chunk columns, the smallest grids; halos are not
   read (NaN there) and not written; the largest Courant number agrees with the
-  oracle's to 1e-14.
+  oracle's to 1e-14; several x-segments of the march with a ragged last one.
 * monc_step_tvd_momentum against the oracle's step (1e-13 on the increments).
 * At the benchmark's full size (1024 x 1024 x 128, 5 fields, the launch the
   benchmark times) the step matches the oracle on sampled blocks of columns,
@@ -48,8 +48,10 @@ def nan_halo(a):
     return b
 
 
+# the march takes x-segments of 64 planes: 130 and 200 give several segments
+# and a ragged last one
 SHAPES = [(16, 16, 32), (23, 17, 50), (9, 6, 128), (1, 1, 7), (40, 12, 64), (2, 3, 2),
-          (5, 9, 65)]
+          (5, 9, 65), (130, 6, 40), (200, 5, 70)]
 
 
 @pytest.mark.parametrize("shape", SHAPES)
@@ -89,7 +91,7 @@ def test_tvd_momentum_without_cmax_and_stream():
 
 
 @pytest.mark.parametrize("shape,nscal", [((16, 16, 32), 2), ((13, 7, 128), 3), ((4, 4, 3), 0),
-                                         ((10, 8, 70), 1)])
+                                         ((10, 8, 70), 1), ((131, 6, 33), 1)])
 def test_step_tvd_momentum_matches_oracle(shape, nscal):
     nx, ny, nz = shape
     say(f"step_tvd_momentum {shape} nscal={nscal}")
