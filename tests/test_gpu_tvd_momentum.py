@@ -10,8 +10,9 @@
   benchmark times) the step matches the oracle on sampled blocks of columns,
   including the periodic edges, and conserves u and v momentum.
 * 20 all-TVD steps against 20 oracle steps (1e-11); a periodic shift of the
-  inputs shifts the source terms bitwise, whichever place in a 2 x 2 tile a
-  column takes (so a face evaluated by either of its columns is the same).
+  inputs shifts the source terms bitwise, wherever a column falls in its
+  workgroup and its x-segment (so a face evaluated by either of its columns,
+  or carried from the plane before, is the same).
 * Courant numbers near 1 (0.95) match the oracle; above 1 the largest one is
   still reported exactly.
 """
@@ -192,11 +193,14 @@ def test_all_tvd_trajectory_matches_oracle():
         assert e <= 1e-11, f"field {n}: {e:.3e}"
 
 
-def test_tvd_momentum_translation_invariance_bitwise():
-    """A periodic shift of the inputs shifts the source terms bitwise (the
-    tile a column falls in does not change its arithmetic)."""
-    say("tvd_momentum translation")
-    g, host = case(22, 18, 70, 0, seed=1800)
+@pytest.mark.parametrize("shape", [(22, 18, 70), (130, 10, 40)])
+def test_tvd_momentum_translation_invariance_bitwise(shape):
+    """A periodic shift of the inputs shifts the source terms bitwise: where a
+    column falls in its workgroup or its x-segment (the west face evaluated
+    at a segment's start or carried from the plane before) does not change
+    its arithmetic."""
+    say(f"tvd_momentum translation {shape}")
+    g, host = case(*shape, 0, seed=1800)
     T = torch()
     prof = prof_dev(g)
 
