@@ -469,6 +469,25 @@ int monc_step_tvd_momentum(double *const *state_in, double *const *state_out, in
                            const double *rho, const double *rhon, double dt, double *cmax,
                            monc_stream_t stream);
 
+/* ---------------------------------------------------------------------------
+ * Streaming ceiling (measurement).  The HBM rate this device reaches with
+ * plain coalesced traffic, the yardstick for the roofline fractions of the
+ * advection kernels (which are bandwidth-bound, Sec. 3.1 and 4: advection
+ * moves every field through memory once per step).  mode:
+ *   MONC_CEIL_READ   read nbytes of src; dst receives
+ *                    monc_ceiling_sink_bytes(blocks) bytes of folded words;
+ *   MONC_CEIL_WRITE  write nbytes of a constant to dst (src unused);
+ *   MONC_CEIL_COPY   copy nbytes from src to dst (must not overlap).
+ * src, dst: device pointers, 16-byte aligned; nbytes a multiple of 16.
+ * blocks: workgroups of 256 lanes (1 .. 65536); every lane moves 16 bytes
+ * per access, stores are non-temporal.  Returns MONC_EINVAL on bad
+ * arguments, MONC_EHIP if the launch fails.
+ * ------------------------------------------------------------------------- */
+enum { MONC_CEIL_READ = 0, MONC_CEIL_WRITE = 1, MONC_CEIL_COPY = 2 };
+size_t monc_ceiling_sink_bytes(int blocks);
+int monc_stream_ceiling(int mode, const void *src, void *dst, size_t nbytes, int blocks,
+                        monc_stream_t stream);
+
 /* Map a budgets array (HOST copy, after synchronising) to a status:
  * MONC_ENONFINITE if any non-finite value was written, MONC_ECFL if the
  * largest Courant number exceeds 1, else MONC_OK. */

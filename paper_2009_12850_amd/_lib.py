@@ -63,6 +63,8 @@ _SIGS = {
     "monc_advect_tvd_momentum": ([vp, vp, vp, vp, vp, vp, ip, ip, ip, dp, dp, vp, vp, vp, dp,
                                   vp, vp], ip),
     "monc_step_tvd_momentum": ([PP, PP, ip, ip, ip, ip, dp, dp, vp, vp, vp, dp, vp, vp], ip),
+    "monc_ceiling_sink_bytes": ([ip], C.c_size_t),
+    "monc_stream_ceiling": ([ip, vp, vp, C.c_size_t, ip, vp], ip),
     "monc_budgets_check": ([DPTR], ip),
     "monc_restrict4": ([ip, PP, PP, ip, ip, ip, vp, vp, vp, vp, vp, vp, vp], ip),
     "monc_mlp_features": ([PP, ip, ip, ip, DPTR, ip, vp, ip, vp, vp], ip),
@@ -412,6 +414,21 @@ def monc_cast_working(dtype, src, work, offset=None, stream=None):
         off = (C.c_double * len(src))(*[float(x) for x in offset])
     _check(lib().monc_cast_working(dtype, len(src), sa, wa, off, nx, ny, nz,
                                    _stream(stream)), "monc_cast_working")
+
+
+MONC_CEIL_READ, MONC_CEIL_WRITE, MONC_CEIL_COPY = 0, 1, 2
+
+
+def monc_stream_ceiling(mode, src, dst, nbytes, blocks, stream=None):
+    """Streaming ceiling kernel: src, dst are device tensors (src may be None
+    for MONC_CEIL_WRITE); nbytes bytes are read, written or copied."""
+    sp = src.data_ptr() if src is not None else None
+    _check(lib().monc_stream_ceiling(mode, sp, dst.data_ptr(), nbytes, blocks,
+                                     _stream(stream)), "monc_stream_ceiling")
+
+
+def monc_ceiling_sink_bytes(blocks):
+    return int(lib().monc_ceiling_sink_bytes(blocks))
 
 
 def monc_budgets_check(host_budgets):

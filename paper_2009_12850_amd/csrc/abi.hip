@@ -37,6 +37,10 @@ int check_grid(int nx, int ny, int nz) {
         return fail(MONC_EINVAL, "nz must be in [2, %d] (got %d)", MONC_MAX_NZ, nz);
     const double n = (double)(nx + 4) * (ny + 4) * nz;
     if (n > 4.0e12) return fail(MONC_EINVAL, "grid too large");
+    // the kernels address one x-plane of a field with 32-bit byte offsets
+    if ((double)(ny + 4) * nz * sizeof(double) > 2147483647.0)
+        return fail(MONC_EINVAL, "one x-plane of a field ((ny+4)*nz*8 = %.0f bytes) must stay "
+                                 "below 2 GiB", (double)(ny + 4) * nz * sizeof(double));
     return MONC_OK;
 }
 
@@ -783,6 +787,30 @@ int monc_correct_step(double* const* state_in, double* const* tend, const float*
                                           scale, rdz, rho, rhon, dt, growth, flags, workspace,
                                           (hipStream_t)stream),
                       "correct_step");
+}
+
+size_t monc_ceiling_sink_bytes(int blocks) {
+    return blocks < 1 ? 0 : ceiling_sink_bytes(blocks);
+}
+
+int monc_stream_ceiling(int mode, const void* src, void* dst, size_t nbytes, int blocks,
+                        monc_stream_t stream) {
+    if (mode != MONC_CEIL_READ && mode != MONC_CEIL_WRITE && mode != MONC_CEIL_COPY)
+        return fail(MONC_EINVAL, "mode must be MONC_CEIL_READ, _WRITE or _COPY (got %d)", mode);
+    if (blocks < 1 || blocks > 65536)
+        return fail(MONC_EINVAL, "blocks must be in [1, 65536] (got %d)", blocks);
+    if (nbytes == 0 || nbytes % 16 != 0)
+        return fail(MONC_EINVAL, "nbytes must be a positive multiple of 16");
+    if (!dst || (mode != MONC_CEIL_WRITE && !src))
+        return fail(MONC_EINVAL, "NULL buffer");
+    if (((uintptr_t)dst | (mode == MONC_CEIL_WRITE ? 0 : (uintptr_t)src)) % 16 != 0)
+        return fail(MONC_EINVAL, "buffers must be 16-byte aligned");
+    if (mode == MONC_CEIL_COPY) {
+        const uintptr_t a = (uintptr_t)src, b = (uintptr_t)dst;
+        if (a < b + nbytes && b < a + nbytes) return fail(MONC_EINVAL, "src and dst overlap");
+    }
+    return hip_status(launch_ceiling(mode, src, dst, nbytes, blocks, (hipStream_t)stream),
+                      "stream_ceiling");
 }
 
 int monc_budgets_check(const double* b) {

@@ -1,6 +1,4 @@
 // advect.hip -- dispatch of the fused advection launches and the x-y tiling.
-#include <stdlib.h>
-
 #include "march_launch.hpp"
 
 namespace monc {
@@ -13,8 +11,9 @@ hipError_t launch_march_stepmix(bool pw, bool tvd, const AdvArgs& a, hipStream_t
 
 // Tiles of `waves` columns along y (half as many when a column needs two
 // 64-level chunks); the x range is cut into segments so that the grid holds
-// about 1024 workgroups (4 per CU), each marching >= 8 planes.  MONC_TI
-// overrides the segment length (experiments).
+// about 1024 workgroups (4 per CU), each marching >= 8 planes.  The tiling
+// depends on the grid alone, so the number of budget partial rows, and with
+// it the budgets' summation order, is fixed for a grid.
 Tiling march_tiling(int nx, int ny, int nz, int waves) {
     Tiling t;
     t.tj = nz <= 64 ? waves : waves / 2;
@@ -24,11 +23,6 @@ Tiling march_tiling(int nx, int ny, int nz, int waves) {
     if (nseg > max_seg) nseg = max_seg;
     if (nseg < 1) nseg = 1;
     t.ti = (nx + nseg - 1) / nseg;
-    const char* env = getenv("MONC_TI");
-    if (env) {
-        const int v = atoi(env);
-        if (v >= 1) t.ti = v;
-    }
     if (t.ti > nx) t.ti = nx;
     t.nseg = (nx + t.ti - 1) / t.ti;
     t.nblocks = t.njt * t.nseg;

@@ -1106,13 +1106,9 @@ hipError_t launch_mlp_pack(const float* params, uint16_t* wpack, hipStream_t s) 
 hipError_t launch_mlp_forward(const uint16_t* X, int m, const float* params,
                               const uint16_t* wpack, float* Y, uint16_t* H1, uint16_t* H2,
                               float* Z1, float* Z2, hipStream_t s) {
-    static bool attr = false;
-    if (!attr) {
-        hipError_t e = hipFuncSetAttribute((const void*)mlp_forward,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)FWD_LDS);
-        if (e != hipSuccess) return e;
-        attr = true;
-    }
+    static std::atomic<unsigned long long> attr{0};
+    hipError_t e = set_lds_limit_once((const void*)mlp_forward, FWD_LDS, &attr);
+    if (e != hipSuccess) return e;
     mlp_forward<<<(m + FWD_ROWS - 1) / FWD_ROWS, 256, FWD_LDS, s>>>(X, m, params, wpack, Y, H1, H2,
                                                                     Z1, Z2);
     return hipGetLastError();
@@ -1121,27 +1117,19 @@ hipError_t launch_mlp_forward(const uint16_t* X, int m, const float* params,
 hipError_t launch_mlp_infer(const double* const* state, int nx, int ny, int nz,
                            const double* norm, int orient, const float* params,
                            const uint16_t* wpack, float* Y, hipStream_t s) {
-    static bool attr[2] = {false, false};
-    static int ncu = 0;
-    static bool attr_st[2] = {false, false};
+    static std::atomic<unsigned long long> attr[2][2] = {{{0}, {0}}, {{0}, {0}}};
     const bool staged = infer_staged_ok(ny, nz);
     const void* kern = staged ? (orient ? (const void*)mlp_infer<1, true>
                                         : (const void*)mlp_infer<0, true>)
                               : (orient ? (const void*)mlp_infer<1, false>
                                         : (const void*)mlp_infer<0, false>);
-    bool& done = staged ? attr_st[orient] : attr[orient];
-    if (!done) {
-        hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)FWD_LDS);
-        if (e != hipSuccess) return e;
-        done = true;
-    }
-    if (ncu == 0) {
-        int dev = 0;
-        hipError_t e = hipGetDevice(&dev);
-        if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-        if (e != hipSuccess) return e;
-    }
+    hipError_t e = set_lds_limit_once(kern, FWD_LDS, &attr[staged ? 1 : 0][orient ? 1 : 0]);
+    if (e != hipSuccess) return e;
+    // the current device's compute units (devices may differ)
+    int dev = 0, ncu = 0;
+    e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
     InferArgs a;
     for (int f = 0; f < 4; f++) {
         a.f[f] = state[f];
@@ -1178,13 +1166,9 @@ size_t mlp_backward_workspace(int m) {
 hipError_t launch_mlp_backward(const uint16_t* X, const uint16_t* H1, const uint16_t* H2,
                                const float* Z1, const float* Z2, const float* dY, int m,
                                const uint16_t* wpack, float* grad, void* ws, hipStream_t s) {
-    static bool attr = false;
-    if (!attr) {
-        hipError_t e = hipFuncSetAttribute((const void*)mlp_backward,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)BWD_LDS);
-        if (e != hipSuccess) return e;
-        attr = true;
-    }
+    static std::atomic<unsigned long long> attr{0};
+    hipError_t e = set_lds_limit_once((const void*)mlp_backward, BWD_LDS, &attr);
+    if (e != hipSuccess) return e;
     const int nb = (m + BWD_ROWS - 1) / BWD_ROWS;
     mlp_backward<<<nb, 256, BWD_LDS, s>>>(X, H1, H2, Z1, Z2, dY, m, wpack, (float*)ws);
     reduce_partials<<<blocks_for(NPARAM), 256, 0, s>>>((const float*)ws, nb, NPARAM, grad);

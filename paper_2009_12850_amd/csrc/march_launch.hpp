@@ -16,13 +16,9 @@ template <typename Ts, typename T, int MODE, bool PW, int NS, bool BUD, int R, i
 hipError_t launch_one(const MarchArgs& m, const Tiling& t, hipStream_t s) {
     auto kern = advect_march<Ts, T, MODE, PW, NS, BUD, R, OPT>;
     constexpr size_t lds = march_lds_bytes<Ts, T, NS, R>();
-    static bool attr_done = false;
-    if (!attr_done) {
-        hipError_t e = hipFuncSetAttribute((const void*)kern,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-        attr_done = true;
-    }
+    static std::atomic<unsigned long long> attr_done{0};
+    hipError_t e = set_lds_limit_once((const void*)kern, lds, &attr_done);
+    if (e != hipSuccess) return e;
     kern<<<t.nblocks, march_waves<Ts, T>() * 64, lds, s>>>(m);
     return hipGetLastError();
 }

@@ -5,6 +5,7 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <atomic>
 #include <string>
 
 #include "../../include/monc_adv.h"
@@ -37,6 +38,21 @@ struct AdvArgs {
     int spw;
 };
 
+// Raise a kernel's dynamic-LDS limit once per device: `done` holds one bit
+// per device index (a function-local static at the call site).  Threads that
+// race here both set the same attribute, which is harmless.
+inline hipError_t set_lds_limit_once(const void* kern, size_t lds,
+                                     std::atomic<unsigned long long>* done) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    const unsigned long long bit = dev >= 0 && dev < 64 ? 1ull << dev : 0ull;
+    if (bit && (done->load(std::memory_order_acquire) & bit)) return hipSuccess;
+    e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e == hipSuccess && bit) done->fetch_or(bit, std::memory_order_acq_rel);
+    return e;
+}
+
 // Number of workgroups of the fused step launch (fixed for a grid so budget
 // sums are repeatable), and the budget workspace it needs.
 int step_blocks(int nx, int ny, int nz);
@@ -53,6 +69,11 @@ hipError_t launch_budget_final(const double* partials, int nblocks,
 hipError_t launch_cast(int dtype, int nfields, const double* const* src,
                        void* const* dst, const double* offset, long n,
                        hipStream_t s);
+
+// Streaming ceiling kernels (ceiling.hip).
+size_t ceiling_sink_bytes(int blocks);
+hipError_t launch_ceiling(int mode, const void* src, void* dst, size_t nbytes, int blocks,
+                          hipStream_t s);
 
 // Other dynamics source terms and the combined step (dynamics.hip).
 struct DynArgs {

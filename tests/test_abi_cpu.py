@@ -36,6 +36,20 @@ def test_advect_pw_rejects_bad_grid(nx, ny, nz):
     assert L.monc_last_error()
 
 
+def test_grid_whose_plane_exceeds_32bit_offsets_is_rejected():
+    """One x-plane of a field is addressed with 32-bit byte offsets, so a grid
+    with (ny+4)*nz*8 bytes per plane past 2 GiB must be refused up front."""
+    L = M.lib()
+    ny = (1 << 31) // (8 * 128)  # (ny+4)*128*8 just above 2^31
+    rc = L.monc_advect_pw(FAKE, FAKE, FAKE, C.c_void_p(0x2000), C.c_void_p(0x3000),
+                          C.c_void_p(0x4000), 4, ny, 128, 50.0, 50.0, *_prof3(), None)
+    assert rc == M.MONC_EINVAL and b"2 GiB" in L.monc_last_error()
+    ok_ny = (1 << 31) // (8 * 128) - 5  # just below
+    rc = L.monc_advect_pw(FAKE, FAKE, FAKE, C.c_void_p(0x2000), C.c_void_p(0x3000),
+                          C.c_void_p(0x4000), 4, ok_ny, 128, -1.0, 50.0, *_prof3(), None)
+    assert rc == M.MONC_EINVAL and b"dx, dy" in L.monc_last_error()
+
+
 @pytest.mark.parametrize("dx,dy", [(0.0, 1.0), (1.0, -1.0), (float("nan"), 1.0),
                                    (float("inf"), 1.0)])
 def test_advect_pw_rejects_bad_spacing(dx, dy):
