@@ -83,7 +83,6 @@ def parse():
     p.add_argument("--no-forms", action="store_true")
     p.add_argument("--only-form", choices=["tvd_momentum", "dynamics"], default=None,
                    help="after the headline, run only this form (for profiling it)")
-    p.add_argument("--cpu-seconds", type=float, default=12.0)
     p.add_argument("--no-learned", action="store_true",
                    help="skip the learned-correction form (fine runs, training, coarse runs)")
     p.add_argument("--learned-seeds", type=int, default=16,
@@ -132,36 +131,54 @@ def bench_scaled(torch, M, vel64, g, prof, stream, npts, reps):
     return out
 
 
-def cpu_baseline(seconds):
-    """The FP64 oracle, unchanged, on a 256 x 256 x 128 slab of the same kind
-    of input (5 fields), stepped until about `seconds` of CPU work is done."""
+def cpu_baseline():
+    """The FP64 oracle, unchanged, timed on the host cores with one thread and
+    with all of them: one forward step (every source term and the update) of
+    an x-slab of each of the two FP64 workloads (64 x 1024 x 128 with u v w th
+    q1, of the 1024 x 1024 x 128 grid; 32 x 512 x 128 with u v w th q1 q2 q3,
+    of the 512 x 512 x 128 grid), same generator and profiles, periodic on the
+    slab; median of 5 timed steps after one warm-up.  A slab's cost per point
+    is that of the whole grid (the oracle's loops are per point), and it keeps
+    the run bounded."""
     from oracle import pyoracle as O
     from paper_2009_12850_amd import inputs as I
     O.build(force=False)
-    g = I.make_geometry(256, 256, 128)
-    f = I.make_fields(g, 2, seed=3, padded=True)
-    st = [f[n] for n in ["u", "v", "w", "th", "q1"]]
-    O.step(st, g, 0.5)  # warm-up
-    n = 0
-    t0 = time.perf_counter()
-    while True:
-        st = O.step(st, g, 0.5)
-        n += 1
-        el = time.perf_counter() - t0
-        if el >= seconds:
-            break
-    pts = 256 * 256 * 128 * n
     try:
-        cores = len(os.sched_getaffinity(0))
+        ncores = len(os.sched_getaffinity(0))
     except AttributeError:
-        cores = os.cpu_count()
+        ncores = os.cpu_count()
     omp = os.environ.get("OMP_NUM_THREADS")
     if omp:
-        cores = min(cores, int(omp))
-    return {"value": pts / el, "unit": "grid-point updates/s", "cores": cores,
+        ncores = min(ncores, int(omp))
+    rows = []
+    for name, (nx, ny, nz, nscal, seed) in (("big1024", (64, 1024, 128, 2, 3)),
+                                            ("steps512", (32, 512, 128, 4, 2))):
+        g = I.make_geometry(nx, ny, nz)
+        f = I.make_fields(g, nscal, seed=seed, padded=True)
+        st = [f[n] for n in ["u", "v", "w"] + I.scalar_names(nscal)]
+        out = [np.empty_like(x) for x in st]
+        nf = 3 + nscal
+        for threads in (1, ncores):
+            used = O.set_threads(threads)
+            O.step(st, g, 0.5, out=out)  # warm-up
+            times = []
+            for _ in range(5):
+                t0 = time.perf_counter()
+                O.step(st, g, 0.5, out=out)
+                times.append(time.perf_counter() - t0)
+            med = float(np.median(times))
+            pts = nx * ny * nz
+            rows.append({"workload": name, "sample": f"{nx}x{ny}x{nz} slab, {nf} fields",
+                         "threads": used, "median_s": med, "gpups": pts / med,
+                         "gbps": 16.0 * nf * pts / med / 1e9})
+            log(f"  oracle {name} slab, {used} threads: {med:.3f} s per step")
+    O.set_threads(ncores)
+    head = [r for r in rows if r["workload"] == "big1024" and r["threads"] == ncores][0]
+    return {"value": head["gpups"], "unit": "grid-point updates/s", "cores": head["threads"],
             "kind": "oracle",
-            "sample": f"{n} oracle steps of a 256x256x128 grid, 5 fields "
-                      f"(u v w th q1), {el:.1f} s"}
+            "sample": "one oracle step of a 64x1024x128 slab of the headline grid "
+                      "(u v w th q1), median of 5 after 1 warm-up, all cores",
+            "rows": rows}
 
 
 DYN_PARAMS = (1.0e-4, 5.0, 0.0, 9.81, 300.0)  # fcor, ug, vg, grav, th0
@@ -480,7 +497,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
-        cpu = cpu_baseline(args.cpu_seconds)
+        cpu = cpu_baseline()
 
     rec = {
         "metric": "advection grid-point updates/s + % HBM peak; FP64 plain vs FP32/batched/learned",

@@ -195,7 +195,8 @@ int monc_step_mixed(double *const *state_in, double *const *state_out,
 /* Marshalling (Sec. 4.1): write a narrower working copy of FP64 fields.
  * dtype MONC_F32 or MONC_BF16 (round to nearest even); work[f] receives
  * src[f] - offset[f] (offset may be NULL = zeros) over the whole padded array,
- * halo included. */
+ * halo included.  src[f] and work[f] must be 16-byte aligned (MONC_EINVAL
+ * otherwise); a streaming pass of 12 (FP32) or 10 (BF16) bytes per value. */
 int monc_cast_working(int dtype, int nfields, const double *const *src,
                       void *const *work, const double *offset, int nx, int ny,
                       int nz, monc_stream_t stream);
@@ -229,6 +230,20 @@ typedef struct monc_ensemble monc_ensemble;
 int monc_ensemble_create(const monc_member *members, int nmembers, int nscal,
                          const char *tune_cache, int tune, monc_ensemble **plan);
 int monc_ensemble_run(monc_ensemble *plan, int nsteps, monc_stream_t stream);
+
+/* Budgets of every member and every step (the FP64 checks of Sec. 3.1 kept
+ * on the device for the batched form).  budgets: device float64 array of
+ * nslots x nmembers x MONC_NBUDGET, owned by the caller and kept by the plan
+ * until detached (budgets = NULL) or the plan is destroyed.  Once attached,
+ * step t (t = 0 .. N-1) of a monc_ensemble_run of N steps writes, in slot t,
+ * member m's budgets at [(t * nmembers + m) * MONC_NBUDGET], with the
+ * meaning of monc_step_mixed's budgets (of the state the step reads);
+ * monc_ensemble_step writes slot 0.  A run of more than nslots steps returns
+ * MONC_EINVAL.  The plan allocates one row of partials per work item (its
+ * own memory, freed on detach or destroy); attaching or detaching waits for
+ * the device and drops the captured graphs.  Each member's sums run in a
+ * fixed order, so repeated runs give the same bits. */
+int monc_ensemble_set_budgets(monc_ensemble *plan, double *budgets, int nslots);
 int monc_ensemble_step(monc_ensemble *plan, monc_stream_t stream);
 int monc_ensemble_parity(const monc_ensemble *plan);
 int monc_ensemble_info(const monc_ensemble *plan, int *ti, int *grid, int *nitems);

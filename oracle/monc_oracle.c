@@ -38,9 +38,25 @@
 #include <stdlib.h>
 #include <string.h>
 
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
 #define OR_OK 0
 #define OR_EINVAL (-1)
 #define OR_ECFL (-3)
+
+/* Number of OpenMP threads of the parallel loops below (the CPU baseline times
+ * one thread and all of them); returns the count in effect, 1 without OpenMP. */
+int oracle_set_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
+}
 
 typedef struct {
     int nx, ny, nz;

@@ -48,6 +48,8 @@ def lib():
         i = C.c_int
         d = C.c_double
         L.oracle_halo_fill.argtypes = [dp, i, i, i]
+        L.oracle_set_threads.argtypes = [i]
+        L.oracle_set_threads.restype = i
         L.oracle_pw.argtypes = [dp, dp, dp, dp, dp, dp, i, i, i, d, d, dp, dp, dp,
                                 i, i, i, i]
         L.oracle_tvd.argtypes = [dp, dp, dp, dp, dp, i, i, i, d, d, dp, dp, dp, d,
@@ -87,6 +89,12 @@ def _check(rc, what):
         raise CourantError(f"{what}: Courant number above 1")
     if rc != OR_OK:
         raise ValueError(f"{what}: oracle returned {rc}")
+
+
+def set_threads(n: int) -> int:
+    """OpenMP threads of the oracle's loops (n <= 0 leaves it); returns the
+    count in effect."""
+    return int(lib().oracle_set_threads(int(n)))
 
 
 def halo_fill(f: np.ndarray) -> np.ndarray:
@@ -141,12 +149,19 @@ def divergence(u, v, w, g):
     return d
 
 
-def step(state, g, dt, allow_cfl=False):
+def step(state, g, dt, allow_cfl=False, out=None):
     """One forward step.  state = [u, v, w, scalars...] (padded arrays).
-    Returns the new state (the inputs' halos are refreshed in place)."""
+    Returns the new state (the inputs' halos are refreshed in place); `out`,
+    if given, is a list of arrays of the state's shape that receive it."""
     nx, ny, nz = _shape(state[0])
     nscal = len(state) - 3
-    out = [np.full_like(s, np.nan) for s in state]
+    if out is None:
+        out = [np.full_like(s, np.nan) for s in state]
+    else:
+        assert len(out) == len(state)
+        for o, s in zip(out, state):
+            assert o.shape == s.shape and o.dtype == np.float64 and o.flags.c_contiguous
+            assert not np.shares_memory(o, s)
     arr_in = (C.POINTER(C.c_double) * len(state))(*[_p(s) for s in state])
     arr_out = (C.POINTER(C.c_double) * len(state))(*[_p(s) for s in out])
     rdz, rho, rhon = _prof(g)

@@ -82,6 +82,7 @@ _SIGS = {
                            vp, vp, vp], ip),
     "monc_ensemble_create": ([vp, ip, ip, C.c_char_p, ip, C.POINTER(vp)], ip),
     "monc_ensemble_run": ([vp, ip, vp], ip),
+    "monc_ensemble_set_budgets": ([vp, vp, ip], ip),
     "monc_ensemble_step": ([vp, vp], ip),
     "monc_ensemble_parity": ([vp], ip),
     "monc_ensemble_info": ([vp, C.POINTER(ip), C.POINTER(ip), C.POINTER(ip)], ip),
@@ -494,6 +495,25 @@ class Ensemble:
     def run(self, nsteps, stream=None):
         _check(lib().monc_ensemble_run(self._plan, int(nsteps), _stream(stream)),
                "monc_ensemble_run")
+
+    def set_budgets(self, budgets):
+        """Attach a float64 device tensor of shape (nslots, nmembers,
+        MONC_NBUDGET) (step t of a run writes slot t), or detach with None."""
+        torch = _torch()
+        if budgets is None:
+            _check(lib().monc_ensemble_set_budgets(self._plan, None, 0),
+                   "monc_ensemble_set_budgets")
+            self._budgets = None
+            return
+        n = len(self._keep)
+        if (budgets.dtype != torch.float64 or not budgets.is_cuda or budgets.dim() != 3
+                or tuple(budgets.shape[1:]) != (n, MONC_NBUDGET) or not budgets.is_contiguous()):
+            raise ValueError(f"budgets must be a contiguous float64 device tensor of shape "
+                             f"(nslots, {n}, {MONC_NBUDGET})")
+        _check(lib().monc_ensemble_set_budgets(self._plan, budgets.data_ptr(),
+                                               int(budgets.shape[0])),
+               "monc_ensemble_set_budgets")
+        self._budgets = budgets
 
     def step(self, stream=None):
         _check(lib().monc_ensemble_step(self._plan, _stream(stream)), "monc_ensemble_step")

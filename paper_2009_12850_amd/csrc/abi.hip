@@ -575,6 +575,9 @@ int monc_cast_working(int dtype, int nfields, const double* const* src, void* co
         return fail(MONC_EINVAL, "nfields must be in [1, %d]", 3 + MONC_MAX_SCALARS);
     TRY(check_ptrs(nfields, src, "src"));
     TRY(check_ptrs(nfields, work, "work"));
+    for (int f = 0; f < nfields; f++)
+        if ((uintptr_t)src[f] % 16 != 0 || (uintptr_t)work[f] % 16 != 0)
+            return fail(MONC_EINVAL, "field %d: src and work must be 16-byte aligned", f);
     const long n = (long)(nx + 4) * (ny + 4) * nz;
     return hip_status(launch_cast(dtype, nfields, src, work, offset, n, (hipStream_t)stream),
                       "cast_working");
@@ -613,9 +616,22 @@ int monc_ensemble_create(const monc_member* members, int nmembers, int nscal,
     return MONC_OK;
 }
 
+int monc_ensemble_set_budgets(monc_ensemble* plan, double* budgets, int nslots) {
+    if (!plan) return fail(MONC_EINVAL, "plan is NULL");
+    if (budgets && nslots < 1) return fail(MONC_EINVAL, "nslots must be >= 1 (got %d)", nslots);
+    std::string err;
+    const int rc = ensemble_set_budgets(reinterpret_cast<EnsemblePlan*>(plan), budgets,
+                                        budgets ? nslots : 0, &err);
+    if (rc != MONC_OK) return fail(rc, "ensemble_set_budgets: %s", err.c_str());
+    return MONC_OK;
+}
+
 int monc_ensemble_run(monc_ensemble* plan, int nsteps, monc_stream_t stream) {
     if (!plan) return fail(MONC_EINVAL, "plan is NULL");
     if (nsteps < 1) return fail(MONC_EINVAL, "nsteps must be >= 1");
+    const int slots = ensemble_budget_slots(reinterpret_cast<EnsemblePlan*>(plan));
+    if (slots >= 0 && nsteps > slots)
+        return fail(MONC_EINVAL, "nsteps %d exceeds the %d attached budget slots", nsteps, slots);
     std::string err;
     const int rc = ensemble_run(reinterpret_cast<EnsemblePlan*>(plan), nsteps,
                                 (hipStream_t)stream, &err);

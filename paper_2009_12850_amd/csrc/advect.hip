@@ -11,14 +11,17 @@ hipError_t launch_march_stepmix(bool pw, bool tvd, const AdvArgs& a, hipStream_t
 
 // Tiles of `waves` columns along y (half as many when a column needs two
 // 64-level chunks); the x range is cut into segments so that the grid holds
-// about 1024 workgroups (4 per CU), each marching >= 8 planes.  The tiling
+// about MONC_TILE_TARGET workgroups, each marching >= 8 planes.  The tiling
 // depends on the grid alone, so the number of budget partial rows, and with
 // it the budgets' summation order, is fixed for a grid.
+#ifndef MONC_TILE_TARGET
+#define MONC_TILE_TARGET 1024
+#endif
 Tiling march_tiling(int nx, int ny, int nz, int waves) {
     Tiling t;
     t.tj = nz <= 64 ? waves : waves / 2;
     t.njt = (ny + t.tj - 1) / t.tj;
-    int nseg = 1024 / t.njt;
+    int nseg = MONC_TILE_TARGET / t.njt;
     const int max_seg = nx / 8 > 0 ? nx / 8 : 1;
     if (nseg > max_seg) nseg = max_seg;
     if (nseg < 1) nseg = 1;

@@ -7,7 +7,9 @@
 // hipGraph and replayed with one hipGraphLaunch.  The segment length and the
 // persistent grid size of each class are chosen by timing candidates on the
 // plan's own members (cached in a small JSON file keyed by device, class,
-// precision and scalar count).
+// precision and scalar count).  With budgets attached, every work item also
+// leaves one row of FP64 budget partials and a small pass sums each member's
+// rows in a fixed order (the checks of every step, Sec. 3.1).
 #include <math.h>
 #include <stdio.h>
 #include <stdlib.h>
@@ -31,10 +33,10 @@ struct EnsMember {
     int njt;       // tiles along y
 };
 
-template <int NCH, int NS>
+template <int NCH, int NS, bool BUD>
 __global__ void __launch_bounds__(ENS_WAVES * 64) __attribute__((amdgpu_waves_per_eu(2)))
     ensemble_step(const EnsMember* __restrict__ mem, const int4* __restrict__ items, int nitems,
-                  int parity) {
+                  int parity, double* __restrict__ partials) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
         const int4 w = items[it];
@@ -44,57 +46,83 @@ __global__ void __launch_bounds__(ENS_WAVES * 64) __attribute__((amdgpu_waves_pe
         t.ti = M->ti;
         t.jt = w.y;
         t.seg = w.z;
-        t.partial_row = nullptr;
+        t.partial_row = BUD ? partials + (size_t)it * NB : nullptr;
         t.first_pass = 1;
-        march_tile<double, float, STEP, true, NS, false, NCH, 0>(M->a[parity], t, smem_raw);
+        march_tile<double, float, STEP, true, NS, BUD, NCH, 0>(M->a[parity], t, smem_raw);
         __syncthreads();  // the LDS is reused by the next item
     }
 }
 
-template <int NCH, int NS>
+// Budgets of every member from its items' partial rows: one workgroup per
+// member, lane q sums entry q over the member's rows in list order (so the
+// result is repeatable bit for bit).
+__global__ void __launch_bounds__(64) ensemble_budget_final(const double* __restrict__ partials,
+                                                            const int* __restrict__ rowoff,
+                                                            const int* __restrict__ rows,
+                                                            double* __restrict__ out) {
+    const int m = blockIdx.x, q = threadIdx.x;
+    if (q >= NB) return;
+    const int op = bud_op(q);
+    double v = bud_ident(op);
+    for (int r = rowoff[m]; r < rowoff[m + 1]; r++)
+        v = bud_comb(v, partials[(size_t)rows[r] * NB + q], op);
+    out[(size_t)m * NB + q] = v;
+}
+
+template <int NCH, int NS, bool BUD>
 hipError_t launch_class(const EnsMember* mem, const int4* items, int nitems, int grid, int parity,
-                        hipStream_t s) {
+                        double* partials, hipStream_t s) {
     constexpr size_t lds = march_lds_bytes<double, float, NS, NCH>();
-    ensemble_step<NCH, NS><<<grid, ENS_WAVES * 64, lds, s>>>(mem, items, nitems, parity);
+    ensemble_step<NCH, NS, BUD><<<grid, ENS_WAVES * 64, lds, s>>>(mem, items, nitems, parity,
+                                                                  partials);
     return hipGetLastError();
 }
 
-hipError_t set_attrs() {
-    const size_t l10 = march_lds_bytes<double, float, 0, 1>(), l11 = march_lds_bytes<double, float, 1, 1>();
-    const size_t l12 = march_lds_bytes<double, float, 2, 1>(), l13 = march_lds_bytes<double, float, 3, 1>();
-    const size_t l20 = march_lds_bytes<double, float, 0, 2>(), l21 = march_lds_bytes<double, float, 1, 2>();
-    const size_t l22 = march_lds_bytes<double, float, 2, 2>(), l23 = march_lds_bytes<double, float, 3, 2>();
-    const void* k[8] = {(const void*)ensemble_step<1, 0>, (const void*)ensemble_step<1, 1>,
-                        (const void*)ensemble_step<1, 2>, (const void*)ensemble_step<1, 3>,
-                        (const void*)ensemble_step<2, 0>, (const void*)ensemble_step<2, 1>,
-                        (const void*)ensemble_step<2, 2>, (const void*)ensemble_step<2, 3>};
-    const size_t l[8] = {l10, l11, l12, l13, l20, l21, l22, l23};
-    for (int q = 0; q < 8; q++) {
-        hipError_t e = hipFuncSetAttribute(k[q], hipFuncAttributeMaxDynamicSharedMemorySize, (int)l[q]);
-        if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
+template <int NCH, int NS, bool BUD>
+hipError_t set_attr_one() {
+    return hipFuncSetAttribute((const void*)ensemble_step<NCH, NS, BUD>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)march_lds_bytes<double, float, NS, NCH>());
 }
 
-hipError_t launch_any(int nch, int ns, const EnsMember* mem, const int4* items, int nitems,
-                      int grid, int parity, hipStream_t s) {
-    if (nitems <= 0) return hipSuccess;
-    if (nch == 1) {
-        switch (ns) {
-            case 0: return launch_class<1, 0>(mem, items, nitems, grid, parity, s);
-            case 1: return launch_class<1, 1>(mem, items, nitems, grid, parity, s);
-            case 2: return launch_class<1, 2>(mem, items, nitems, grid, parity, s);
-            case 3: return launch_class<1, 3>(mem, items, nitems, grid, parity, s);
-        }
-    } else {
-        switch (ns) {
-            case 0: return launch_class<2, 0>(mem, items, nitems, grid, parity, s);
-            case 1: return launch_class<2, 1>(mem, items, nitems, grid, parity, s);
-            case 2: return launch_class<2, 2>(mem, items, nitems, grid, parity, s);
-            case 3: return launch_class<2, 3>(mem, items, nitems, grid, parity, s);
-        }
+template <int NCH, bool BUD>
+hipError_t set_attrs_nch() {
+    hipError_t e = set_attr_one<NCH, 0, BUD>();
+    if (e == hipSuccess) e = set_attr_one<NCH, 1, BUD>();
+    if (e == hipSuccess) e = set_attr_one<NCH, 2, BUD>();
+    if (e == hipSuccess) e = set_attr_one<NCH, 3, BUD>();
+    return e;
+}
+
+hipError_t set_attrs() {
+    hipError_t e = set_attrs_nch<1, false>();
+    if (e == hipSuccess) e = set_attrs_nch<2, false>();
+    if (e == hipSuccess) e = set_attrs_nch<1, true>();
+    if (e == hipSuccess) e = set_attrs_nch<2, true>();
+    return e;
+}
+
+template <int NCH, bool BUD>
+hipError_t launch_ns(int ns, const EnsMember* mem, const int4* items, int nitems, int grid,
+                     int parity, double* partials, hipStream_t s) {
+    switch (ns) {
+        case 0: return launch_class<NCH, 0, BUD>(mem, items, nitems, grid, parity, partials, s);
+        case 1: return launch_class<NCH, 1, BUD>(mem, items, nitems, grid, parity, partials, s);
+        case 2: return launch_class<NCH, 2, BUD>(mem, items, nitems, grid, parity, partials, s);
+        case 3: return launch_class<NCH, 3, BUD>(mem, items, nitems, grid, parity, partials, s);
     }
     return hipErrorInvalidValue;
+}
+
+// partials: the class's first budget row, or nullptr (no budgets)
+hipError_t launch_any(int nch, int ns, const EnsMember* mem, const int4* items, int nitems,
+                      int grid, int parity, double* partials, hipStream_t s) {
+    if (nitems <= 0) return hipSuccess;
+    if (partials)
+        return nch == 1 ? launch_ns<1, true>(ns, mem, items, nitems, grid, parity, partials, s)
+                        : launch_ns<2, true>(ns, mem, items, nitems, grid, parity, partials, s);
+    return nch == 1 ? launch_ns<1, false>(ns, mem, items, nitems, grid, parity, nullptr, s)
+                    : launch_ns<2, false>(ns, mem, items, nitems, grid, parity, nullptr, s);
 }
 
 }  // namespace
@@ -116,6 +144,15 @@ struct EnsemblePlan {
     hipGraphExec_t exec[2] = {nullptr, nullptr};  // by starting parity
     int exec_steps[2] = {0, 0};
     int parity = 0;
+    std::vector<int4> hitems[2];  // the uploaded work lists (host copies)
+    // budgets (attached by the caller): slots of n x NB doubles, one per step
+    // of a run; one partial row per work item (class 0's rows first) and each
+    // member's row list (CSR)
+    double* budgets = nullptr;
+    int nslots = 0;
+    double* d_partials = nullptr;
+    int* d_rowoff = nullptr;
+    int* d_rows = nullptr;
 };
 
 namespace {
@@ -156,6 +193,7 @@ hipError_t upload_class(EnsemblePlan& P, int cls, int ti) {
         if (ef != hipSuccess) return ef;
     }
     P.nitems[cls] = (int)items.size();
+    P.hitems[cls] = items;
     P.ti[cls] = ti;
     for (int m = 0; m < P.n; m++) {
         const int nch = P.members[m].nz <= 64 ? 1 : 2;
@@ -173,13 +211,61 @@ hipError_t upload_members(EnsemblePlan& P) {
                      hipMemcpyHostToDevice);
 }
 
-hipError_t launch_step(EnsemblePlan& P, int parity, hipStream_t s) {
+// One step of every member; with budgets attached, the budgets of the step's
+// input state go to slot `slot`.
+hipError_t launch_step(EnsemblePlan& P, int parity, int slot, hipStream_t s) {
+    const bool bud = P.budgets != nullptr;
     for (int c = 0; c < 2; c++) {
+        double* rows = bud ? P.d_partials + (size_t)(c == 0 ? 0 : P.nitems[0]) * NB : nullptr;
         hipError_t e = launch_any(c + 1, P.nscal, P.d_mem, P.d_items[c], P.nitems[c], P.grid[c],
-                                  parity, s);
+                                  parity, rows, s);
         if (e != hipSuccess) return e;
     }
+    if (bud) {
+        ensemble_budget_final<<<P.n, 64, 0, s>>>(P.d_partials, P.d_rowoff, P.d_rows,
+                                                 P.budgets + (size_t)slot * P.n * NB);
+        return hipGetLastError();
+    }
     return hipSuccess;
+}
+
+// Row lists of the members from the current work lists: member m's rows are
+// the indices of its items (class 0 first, then class 1 offset by class 0's
+// count), in list order.
+hipError_t build_budget_rows(EnsemblePlan& P) {
+    std::vector<std::vector<int>> per(P.n);
+    for (int c = 0; c < 2; c++) {
+        const int base = c == 0 ? 0 : P.nitems[0];
+        for (int it = 0; it < P.nitems[c]; it++) per[P.hitems[c][it].x].push_back(base + it);
+    }
+    std::vector<int> off(P.n + 1, 0), rows;
+    for (int m = 0; m < P.n; m++) {
+        off[m + 1] = off[m] + (int)per[m].size();
+        rows.insert(rows.end(), per[m].begin(), per[m].end());
+    }
+    const size_t nrows = (size_t)P.nitems[0] + P.nitems[1];
+    hipError_t e = hipMalloc(&P.d_partials, std::max<size_t>(nrows, 1) * NB * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&P.d_rowoff, off.size() * sizeof(int));
+    if (e == hipSuccess) e = hipMalloc(&P.d_rows, std::max<size_t>(rows.size(), 1) * sizeof(int));
+    if (e == hipSuccess)
+        e = hipMemcpy(P.d_rowoff, off.data(), off.size() * sizeof(int), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !rows.empty())
+        e = hipMemcpy(P.d_rows, rows.data(), rows.size() * sizeof(int), hipMemcpyHostToDevice);
+    return e;
+}
+
+hipError_t free_budget_rows(EnsemblePlan& P) {
+    hipError_t e = hipSuccess;
+    void* bufs[3] = {P.d_partials, P.d_rowoff, P.d_rows};
+    for (void* b : bufs) {
+        if (!b) continue;
+        const hipError_t ef = hipFree(b);
+        if (e == hipSuccess) e = ef;
+    }
+    P.d_partials = nullptr;
+    P.d_rowoff = nullptr;
+    P.d_rows = nullptr;
+    return e;
 }
 
 // --- tiny JSON cache: {"key": [ti, grid], ...} -------------------------------
@@ -242,11 +328,11 @@ float time_class(EnsemblePlan& P, int cls, int reps) {
     hipEventCreate(&a);
     hipEventCreate(&b);
     launch_any(cls + 1, P.nscal, P.d_mem, P.d_items[cls], P.nitems[cls], P.grid[cls], P.parity,
-               P.cap);
+               nullptr, P.cap);
     hipEventRecord(a, P.cap);
     for (int r = 0; r < reps; r++)
         launch_any(cls + 1, P.nscal, P.d_mem, P.d_items[cls], P.nitems[cls], P.grid[cls],
-                   P.parity, P.cap);
+                   P.parity, nullptr, P.cap);
     hipEventRecord(b, P.cap);
     hipEventSynchronize(b);
     float ms = 0;
@@ -351,8 +437,37 @@ int ensemble_create(const monc_member* members, int n, int nscal, const char* tu
     return MONC_OK;
 }
 
+int ensemble_set_budgets(EnsemblePlan* P, double* budgets, int nslots, std::string* err) {
+    hipError_t e = hipStreamSynchronize(P->cap);
+    if (e == hipSuccess) e = hipDeviceSynchronize();  // captured graphs may still run
+    for (int c = 0; c < 2; c++) {
+        if (P->exec[c]) hipGraphExecDestroy(P->exec[c]);
+        P->exec[c] = nullptr;
+        P->exec_steps[c] = 0;
+    }
+    if (e == hipSuccess) e = free_budget_rows(*P);
+    P->budgets = nullptr;
+    P->nslots = 0;
+    if (e == hipSuccess && budgets) {
+        e = build_budget_rows(*P);
+        if (e == hipSuccess) {
+            P->budgets = budgets;
+            P->nslots = nslots;
+        } else {
+            free_budget_rows(*P);
+        }
+    }
+    if (e != hipSuccess) {
+        *err = hipGetErrorString(e);
+        return MONC_EHIP;
+    }
+    return MONC_OK;
+}
+
+int ensemble_budget_slots(const EnsemblePlan* P) { return P->budgets ? P->nslots : -1; }
+
 int ensemble_step_eager(EnsemblePlan* P, hipStream_t s, std::string* err) {
-    hipError_t e = launch_step(*P, P->parity, s);
+    hipError_t e = launch_step(*P, P->parity, 0, s);
     if (e != hipSuccess) {
         *err = hipGetErrorString(e);
         return MONC_EHIP;
@@ -370,7 +485,8 @@ int ensemble_run(EnsemblePlan* P, int nsteps, hipStream_t s, std::string* err) {
         }
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamBeginCapture(P->cap, hipStreamCaptureModeThreadLocal);
-        for (int k = 0; k < nsteps && e == hipSuccess; k++) e = launch_step(*P, p0 ^ (k & 1), P->cap);
+        for (int k = 0; k < nsteps && e == hipSuccess; k++)
+            e = launch_step(*P, p0 ^ (k & 1), k, P->cap);
         hipError_t e2 = hipStreamEndCapture(P->cap, &g);
         if (e == hipSuccess) e = e2;
         if (e == hipSuccess) e = hipGraphInstantiate(&P->exec[p0], g, nullptr, nullptr, 0);
@@ -408,6 +524,7 @@ void ensemble_destroy(EnsemblePlan* P) {
         if (P->d_items[c]) hipFree(P->d_items[c]);
     }
     if (P->d_mem) hipFree(P->d_mem);
+    free_budget_rows(*P);
     if (P->cap) hipStreamDestroy(P->cap);
     delete P;
 }

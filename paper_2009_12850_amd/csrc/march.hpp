@@ -90,11 +90,17 @@ __device__ __forceinline__ bf16 bload<bf16>(__amdgpu_buffer_rsrc_t r, uint32_t o
     x.bits = (uint16_t)__builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0);
     return x;
 }
+// Cache policy of the stores (2 = non-temporal: the outputs are not read
+// again by the launch, so they need not stay in L2).
+#ifndef MONC_STORE_AUX
+#define MONC_STORE_AUX 0
+#endif
 __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t off, double v) {
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(march_v2i, v), r, off, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(march_v2i, v), r, off, 0,
+                                          MONC_STORE_AUX);
 }
 __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t off, float v) {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(int, v), r, off, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(int, v), r, off, 0, MONC_STORE_AUX);
 }
 
 // storage -> compute, subtracting `off` first when the storage is FP64
@@ -442,6 +448,8 @@ __device__ __forceinline__ void march_tile(const AdvArgs& a, const TileJob& tj,
     constexpr int DEPTH = 2;
     Ahead S[DEPTH];
     double acc[BUD ? NACC : 1];
+    int nonfinite = 0;  // non-finite values written by this wave
+    double amax[3] = {0.0, 0.0, 0.0};  // largest |u|, |v|, |w| (FP32 compute only)
     if constexpr (BUD) {
 #pragma unroll
         for (int q = 0; q < NACC; q++) acc[q] = bud_ident(bud_op(q));
@@ -638,30 +646,40 @@ __device__ __forceinline__ void march_tile(const AdvArgs& a, const TileJob& tj,
                 bstore(plane_rsrc((double*)a.out[0] + gplane, wbytes64), woff64, nu);
                 bstore(plane_rsrc((double*)a.out[1] + gplane, wbytes64), woff64, nv);
                 bstore(plane_rsrc((double*)a.out[2] + gplane, wbytes64), woff64, nw);
-                if (store) {
-                    if constexpr (BUD) {
+                if constexpr (BUD) {
+                    // Per-lane sums over the march (one level k per lane): the
+                    // level's weights (rhon dz, rho dzn, -dz/4) multiply once at
+                    // the end, and non-finite values are counted per wave.
+                    if (store) {
                         const double ucd = (double)U[1], umd = (double)U[0];
                         const double vcd = (double)V[1], vsd = (double)vs;
                         const double wcd = (double)W[1], wbd = (double)wb;
                         const double Dd = (double)D;
-                        const double mass = (double)lev[LV_MASS * NZP + k];
-                        const double wmass = (double)lev[LV_WMASS * NZP + k];
-                        const double dzk = (double)lev[LV_DZ * NZP + k];
-                        acc[MONC_B_CU] += mass * (double)su;
-                        acc[MONC_B_CV] += mass * (double)sv;
-                        acc[MONC_B_PU] += mass * ucd * (double)su;
-                        acc[MONC_B_PV] += mass * vcd * (double)sv;
-                        acc[MONC_B_QU] += -0.25 * dzk * Dd * (ucd * ucd + umd * umd);
-                        acc[MONC_B_QV] += -0.25 * dzk * Dd * (vcd * vcd + vsd * vsd);
-                        acc[MONC_B_QW] += -0.25 * dzk * Dd * (wcd * wcd + wbd * wbd);
-                        acc[MONC_B_CW] += wmass * (double)sw;
-                        acc[MONC_B_PW] += wmass * wcd * (double)sw;
-                        const double cr = fmax(fmax(fabs(ucd) * cdx, fabs(vcd) * cdy),
-                                               fabs(wcd) * dt * (double)L.rdzn);
-                        acc[MONC_B_COURANT] = fmax(acc[MONC_B_COURANT], cr);
-                        acc[MONC_B_NONFINITE] +=
-                            (double)((!isfinite(nu)) + (!isfinite(nv)) + (!isfinite(nw)));
+                        acc[MONC_B_CU] += (double)su;
+                        acc[MONC_B_CV] += (double)sv;
+                        acc[MONC_B_PU] = fma(ucd, (double)su, acc[MONC_B_PU]);
+                        acc[MONC_B_PV] = fma(vcd, (double)sv, acc[MONC_B_PV]);
+                        acc[MONC_B_QU] = fma(Dd, fma(ucd, ucd, umd * umd), acc[MONC_B_QU]);
+                        acc[MONC_B_QV] = fma(Dd, fma(vcd, vcd, vsd * vsd), acc[MONC_B_QV]);
+                        acc[MONC_B_QW] = fma(Dd, fma(wcd, wcd, wbd * wbd), acc[MONC_B_QW]);
+                        acc[MONC_B_CW] += (double)sw;
+                        acc[MONC_B_PW] = fma(wcd, (double)sw, acc[MONC_B_PW]);
+                        if constexpr (std::is_same<T, double>::value) {
+                            const double cr = fmax(fmax(fabs(ucd) * cdx, fabs(vcd) * cdy),
+                                                   fabs(wcd) * dt * (double)L.rdzn);
+                            acc[MONC_B_COURANT] = fmax(acc[MONC_B_COURANT], cr);
+                        } else {
+                            // FP32 level table: keep |u|, |v|, |w| and scale by
+                            // the FP64 spacings at the end (scaling is monotone,
+                            // so the maximum is the same)
+                            amax[0] = fmax(amax[0], fabs(ucd));
+                            amax[1] = fmax(amax[1], fabs(vcd));
+                            amax[2] = fmax(amax[2], fabs(wcd));
+                        }
                     }
+                    nonfinite += __popcll(__ballot(store && !isfinite(nu))) +
+                                 __popcll(__ballot(store && !isfinite(nv))) +
+                                 __popcll(__ballot(store && !isfinite(nw)));
                 }
             }
         }
@@ -730,15 +748,14 @@ __device__ __forceinline__ void march_tile(const AdvArgs& a, const TileJob& tj,
                 // the state is FP64 whatever the compute type
                 const double nsv = (double)P[s][1] + dt * (double)val;
                 bstore(plane_rsrc((double*)a.out[3 + tj.s0 + s] + gplane, wbytes64), woff64, nsv);
-                if (store) {
-                    if constexpr (BUD) {
+                if constexpr (BUD) {
+                    if (store) {
                         const double phd = (double)P[s][1];
-                        const double mass = (double)lev[LV_MASS * NZP + k];
-                        acc[MONC_B_SCALAR0 + 3 * s] += mass * (double)val;
-                        acc[MONC_B_SCALAR0 + 3 * s + 1] += mass * phd;
+                        acc[MONC_B_SCALAR0 + 3 * s] += (double)val;
+                        acc[MONC_B_SCALAR0 + 3 * s + 1] += phd;
                         acc[MONC_B_SCALAR0 + 3 * s + 2] = fmin(acc[MONC_B_SCALAR0 + 3 * s + 2], phd);
-                        acc[MONC_B_NONFINITE] += (double)(!isfinite(nsv));
                     }
+                    nonfinite += __popcll(__ballot(store && !isfinite(nsv)));
                 }
             }
         }
@@ -757,6 +774,40 @@ __device__ __forceinline__ void march_tile(const AdvArgs& a, const TileJob& tj,
     }
 
     if constexpr (BUD) {
+        // the level's weights in FP64 from the profiles (the level table may
+        // be FP32), the wave's count (lane 0)
+        {
+            double mass = 0.0, wmass = 0.0, qf = 0.0, rdzn = 0.0;
+            if (k < nz) {
+                const double dzk = 1.0 / a.rdz[k];
+                mass = a.rhon[k] * dzk;
+                qf = -0.25 * dzk;
+                if (k < nz - 1) {
+                    const double dzn = 0.5 * (dzk + 1.0 / a.rdz[k + 1]);
+                    wmass = a.rho[k] * dzn;
+                    rdzn = 1.0 / dzn;
+                }
+            }
+            acc[MONC_B_CU] *= mass;
+            acc[MONC_B_CV] *= mass;
+            acc[MONC_B_PU] *= mass;
+            acc[MONC_B_PV] *= mass;
+            acc[MONC_B_QU] *= qf;
+            acc[MONC_B_QV] *= qf;
+            acc[MONC_B_QW] *= qf;
+            acc[MONC_B_CW] *= wmass;
+            acc[MONC_B_PW] *= wmass;
+#pragma unroll
+            for (int s = 0; s < NS; s++) {
+                acc[MONC_B_SCALAR0 + 3 * s] *= mass;
+                acc[MONC_B_SCALAR0 + 3 * s + 1] *= mass;
+            }
+            if constexpr (PW && !std::is_same<T, double>::value)
+                acc[MONC_B_COURANT] =
+                    fmax(fmax(amax[0] * cdx, amax[1] * cdy), amax[2] * dt * rdzn);
+            (void)rdzn;
+            acc[MONC_B_NONFINITE] = lane == 0 ? (double)nonfinite : 0.0;
+        }
         // block reduction in a fixed order, reusing the LDS
         __syncthreads();
         double* red = reinterpret_cast<double*>(smem_raw);  // [waves][NACC]

@@ -143,6 +143,8 @@ struct EnsemblePlan;
 int ensemble_create(const monc_member* members, int n, int nscal, const char* tune_cache,
                     int tune, EnsemblePlan** out, std::string* err);
 int ensemble_step_eager(EnsemblePlan* P, hipStream_t s, std::string* err);
+int ensemble_set_budgets(EnsemblePlan* P, double* budgets, int nslots, std::string* err);
+int ensemble_budget_slots(const EnsemblePlan* P);  // -1: no budgets attached
 int ensemble_run(EnsemblePlan* P, int nsteps, hipStream_t s, std::string* err);
 void ensemble_info(const EnsemblePlan* P, int* ti, int* grid, int* nitems);
 int ensemble_parity(const EnsemblePlan* P);

@@ -54,7 +54,10 @@ __global__ void __launch_bounds__(256) halo_kernel(HaloArgs a) {
 
 // ---------------------------------------------------------------------------
 // Marshalling (Sec. 4.1): FP64 field minus a constant, rounded to FP32 or
-// BF16 (round to nearest even), over the whole padded array.
+// BF16 (round to nearest even), over the whole padded array.  A streaming
+// copy: blockIdx.y picks the field, every lane converts four consecutive
+// values per trip (two 16-byte loads, one 16- or 8-byte store, all
+// non-temporal), and the last n % 4 values of a field go to the first lanes.
 // ---------------------------------------------------------------------------
 struct CastArgs {
     const double* src[3 + MAXS];
@@ -64,19 +67,39 @@ struct CastArgs {
     long n;
 };
 
+typedef double cast_d2 __attribute__((ext_vector_type(2)));
+typedef float cast_f4 __attribute__((ext_vector_type(4)));
+typedef unsigned int cast_u2 __attribute__((ext_vector_type(2)));
+
 template <int DT>
 __global__ void __launch_bounds__(256) cast_kernel(CastArgs a) {
-    const long total = a.n * a.nfields;
-    for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < total;
-         t += (long)gridDim.x * blockDim.x) {
-        const int f = (int)(t / a.n);
-        const long e = t - (long)f * a.n;
-        const double x = a.src[f][e] - a.off[f];
+    const int f = blockIdx.y;
+    const double* __restrict__ src = a.src[f];
+    const double off = a.off[f];
+    const long n4 = a.n >> 2;
+    const long stride = (long)gridDim.x * blockDim.x;
+    const long t0 = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    for (long t = t0; t < n4; t += stride) {
+        const cast_d2 x0 = __builtin_nontemporal_load((const cast_d2*)src + 2 * t);
+        const cast_d2 x1 = __builtin_nontemporal_load((const cast_d2*)src + 2 * t + 1);
+        const float y0 = (float)(x0.x - off), y1 = (float)(x0.y - off);
+        const float y2 = (float)(x1.x - off), y3 = (float)(x1.y - off);
         if constexpr (DT == MONC_F32) {
-            ((float*)a.dst[f])[e] = (float)x;
+            const cast_f4 y = {y0, y1, y2, y3};
+            __builtin_nontemporal_store(y, (cast_f4*)a.dst[f] + t);
         } else {
-            ((uint16_t*)a.dst[f])[e] = f32_to_bf16_rne((float)x);
+            const cast_u2 y = {(unsigned)f32_to_bf16_rne(y0) | ((unsigned)f32_to_bf16_rne(y1) << 16),
+                               (unsigned)f32_to_bf16_rne(y2) | ((unsigned)f32_to_bf16_rne(y3) << 16)};
+            __builtin_nontemporal_store(y, (cast_u2*)a.dst[f] + t);
         }
+    }
+    const long e = 4 * n4 + t0;  // the tail (fewer than four values)
+    if (e < a.n) {
+        const float y = (float)(src[e] - off);
+        if constexpr (DT == MONC_F32)
+            ((float*)a.dst[f])[e] = y;
+        else
+            ((uint16_t*)a.dst[f])[e] = f32_to_bf16_rne(y);
     }
 }
 
@@ -150,11 +173,16 @@ hipError_t launch_cast(int dtype, int nfields, const double* const* src,
     }
     a.nfields = nfields;
     a.n = n;
-    const int g = grid_for(n * nfields);
+    // about 2048 workgroups in all, each lane a few trips of four values
+    long gx = ((n >> 2) + 255) / 256;
+    const long cap = (2048 + nfields - 1) / nfields;
+    if (gx > cap) gx = cap;
+    if (gx < 1) gx = 1;
+    const dim3 grid((unsigned)gx, (unsigned)nfields);
     if (dtype == MONC_F32)
-        cast_kernel<MONC_F32><<<g, 256, 0, s>>>(a);
+        cast_kernel<MONC_F32><<<grid, 256, 0, s>>>(a);
     else
-        cast_kernel<MONC_BF16><<<g, 256, 0, s>>>(a);
+        cast_kernel<MONC_BF16><<<grid, 256, 0, s>>>(a);
     return hipGetLastError();
 }
 

@@ -115,6 +115,9 @@ def test_advect_rejects_unknown_dtype_and_tvd_needs_scalars():
     assert rc == M.MONC_EINVAL
     rc = L.monc_cast_working(M.MONC_F64, 1, q, sq, None, 8, 8, 8, None)
     assert rc == M.MONC_EINVAL
+    # the streaming cast needs 16-byte aligned buffers
+    rc = L.monc_cast_working(M.MONC_F32, 1, _arr([0x1308]), sq, None, 8, 8, 8, None)
+    assert rc == M.MONC_EINVAL and b"aligned" in L.monc_last_error()
 
 
 def test_budgets_check_maps_device_flags():
@@ -165,6 +168,7 @@ def test_ensemble_create_validates_members():
     assert L.monc_ensemble_create(C.cast(arr, C.c_void_p), 1, 4, None, 0,
                                   C.byref(plan)) == M.MONC_EUNSUPPORTED
     assert L.monc_ensemble_run(None, 5, None) == M.MONC_EINVAL
+    assert L.monc_ensemble_set_budgets(None, C.c_void_p(0x7000), 3) == M.MONC_EINVAL
 
 
 @pytest.mark.parametrize("dtype,work", [(M.MONC_F64, 0), (M.MONC_F64, M.MONC_MAX_WORK + 1),

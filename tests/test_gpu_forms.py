@@ -18,6 +18,11 @@ from paper_2009_12850_amd import inputs as I
 
 pytestmark = pytest.mark.gpu
 TOL64 = 1e-13
+# After n steps the GPU and oracle states may differ by one rounding of the
+# new value per step (the GPU adds dt s with a fused multiply-add), carried
+# along by the scheme: the bar is this factor times n units in the last place
+# of the field's largest value.
+STEPS512_GROWTH = 10.0
 
 
 def say(msg):
@@ -73,6 +78,40 @@ def test_bf16_storage_error_is_bounded(shape):
     # themselves.  The bound only guards against a broken path; the errors
     # are what the precision form reports.
     assert max(errs) <= 0.25, errs
+
+
+@pytest.mark.parametrize("shape", [(3, 2, 5), (4, 4, 7), (5, 1, 9), (16, 12, 64), (1, 1, 2)])
+def test_cast_working_is_exact_rounding(shape):
+    """The marshalling cast writes round-to-nearest-even of (x - offset) in
+    FP32, and BF16 as the FP32 value rounded again to nearest even, over the
+    whole padded array; padded sizes with every remainder modulo 4 (the
+    kernel converts four values per lane and leaves the rest to a tail)."""
+    from oracle import mlp_ref as R
+    nx, ny, nz = shape
+    say(f"cast {shape}")
+    T = torch()
+    rng = np.random.default_rng(nx * 100 + ny * 10 + nz)
+    src = [rng.standard_normal((nx + 4, ny + 4, nz)) * 10.0 ** rng.integers(-3, 3)
+           for _ in range(4)]
+    src[3] = 300.0 + src[3]
+    src[0][0, 0, 0] = np.inf
+    src[1][-1, -1, -1] = np.nan
+    offs = [0.0, 1.5, -2.25, 300.0]
+    d = to_dev(src)
+    w32 = [T.full(x.shape, np.nan, dtype=T.float32, device=dev()) for x in d]
+    w16 = [T.full(x.shape, -1, dtype=T.int16, device=dev()) for x in d]
+    M.monc_cast_working(M.MONC_F32, d, w32, offs)
+    M.monc_cast_working(M.MONC_BF16, d, w16, offs)
+    T.cuda.synchronize()
+    for n in range(4):
+        exp32 = (src[n] - offs[n]).astype(np.float32)
+        got32 = w32[n].cpu().numpy()
+        assert np.array_equal(got32.view(np.uint32), exp32.view(np.uint32)) or \
+            np.array_equal(got32, exp32, equal_nan=True), n
+        exp16 = R.bf16(src[n] - offs[n])
+        got16 = (w16[n].cpu().numpy().astype(np.int32) & 0xFFFF).astype(np.uint32) << 16
+        got16 = got16.view(np.float32).astype(np.float64)
+        assert np.array_equal(got16, exp16, equal_nan=True), n
 
 
 def test_anomaly_offset_is_exact_in_fp64():
@@ -158,6 +197,7 @@ def test_ragged_column_heights(shape):
         assert rel_err(a.cpu().numpy(), r) <= TOL64, n
 
 
+@pytest.mark.timeout(900)
 def test_steps512_budgets_every_step():
     """512 x 512 x 128, u v w th q1 q2 q3 (divergence-free flow), 100 forward
     steps at dt = 0.5 s with the budgets checked after every step: momentum
@@ -168,6 +208,7 @@ def test_steps512_budgets_every_step():
     names = ["u", "v", "w"] + I.scalar_names(w.nscal)
     say("steps512: oracle budgets of the first state")
     hosts = [O.halo_fill(f.pop(n)) for n in names]
+    first = [h.copy() for h in hosts]
     tend = oracle_tendencies(hosts, g, w.dt)
     ob, sc = O.budgets(*hosts[:3], *tend[:3], hosts[3:], tend[3:], g)
     scal_scale = [np.sum(np.abs(I.interior(t)) * (g.rhon / g.rdz)[None, None, :]) for t in tend[3:]]
@@ -212,6 +253,28 @@ def test_steps512_budgets_every_step():
         if step % 20 == 0:
             say(f"  step {step}: courant {gb['courant']:.3f} C_u {gb['C_u']:.2e} "
                 f"P_u-Q_u {gb['P_u'] - gb['Q_u']:.2e}")
+
+    # the state after the 100 steps against 100 oracle steps, whole domain
+    say("steps512: 100 oracle steps")
+    cur = [x.copy() for x in first]
+    nxt = [np.empty_like(x) for x in first]
+    for step in range(w.steps):
+        O.step(cur, g, w.dt, out=nxt)
+        cur, nxt = nxt, cur
+        if step % 20 == 0:
+            say(f"  oracle step {step}")
+    del nxt
+    T.cuda.synchronize()
+    for n in range(3 + w.nscal):
+        got = I.interior(A[n].cpu().numpy())
+        exp = I.interior(cur[n])
+        start = I.interior(first[n])
+        change = np.abs(exp - start).max()
+        err = np.abs(got - exp).max()
+        bar = STEPS512_GROWTH * w.steps * np.spacing(np.abs(exp).max())
+        say(f"  field {n}: |gpu - oracle| {err:.3e}, bar {bar:.3e}, "
+            f"relative to the change {err / change:.3e}")
+        assert err <= bar, (n, err, bar)
 
 
 def test_big1024_precision_forms_match_oracle():

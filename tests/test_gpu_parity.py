@@ -238,6 +238,73 @@ def test_big1024_subdomains_match_oracle():
             assert e <= TOL64, f"region {(i0, i1, j0, j1)} field {n}: {e:.3e}"
 
 
+def test_big1024_budgeted_step_matches_oracle():
+    """The launch the benchmark times: monc_step with budgets on 1024 x 1024 x
+    128 (u v w th q1), inputs straight from the generator (halos never
+    filled), in the benchmark's configuration.  Increments on five column
+    blocks (the periodic seams among them) against the oracle; every budget
+    entry against the oracle's budgets of the whole domain.
+
+    Bars (derived from the arithmetic): the GPU forms f + dt s with one
+    rounding (a fused multiply-add) and the oracle rounds dt s first, so the
+    new values may differ by one unit in the last place of the new value on
+    top of the source terms' 1e-13; sums of N terms taken in two orders differ
+    by at most (chain lengths) x 2^-53 x sum |terms| (the oracle's chain is
+    one x-slab, ny nz terms, then nx slabs; the GPU's is one lane's planes,
+    then a wave, a workgroup and the partial rows)."""
+    say("big1024 budgeted step")
+    w, g, f = I.make_workload("big1024")
+    names = ["u", "v", "w"] + I.scalar_names(w.nscal)
+    T = torch()
+    raw = [I.pad(f.pop(n)) for n in names]  # NaN halos, as the benchmark hands them over
+    d = [T.from_numpy(h).to(dev()) for h in raw]
+    hosts = [O.halo_fill(h) for h in raw]
+    del raw
+    out = [T.empty_like(x) for x in d]
+    b = T.zeros(M.MONC_NBUDGET, dtype=T.float64, device=dev())
+    ws = T.empty(M.monc_step_workspace_bytes(w.nx, w.ny, w.nz, w.nscal), dtype=T.uint8,
+                 device=dev())
+    M.monc_step(d, out, g.dx, g.dy, prof_dev(g), w.dt, b, ws)
+    T.cuda.synchronize()
+    del d
+    regions = [(0, 128, 0, 128), (1020, 1024, 0, 8), (0, 8, 1018, 1024),
+               (1021, 1024, 1021, 1024), (500, 516, 700, 716)]
+    for (i0, i1, j0, j1) in regions:
+        ref = oracle_tendencies(hosts, g, w.dt, region=(i0, i1, j0, j1))
+        for n, o in enumerate(out):
+            sl = (slice(i0 + 2, i1 + 2), slice(j0 + 2, j1 + 2))
+            old = hosts[n][sl]
+            new_o = old + w.dt * ref[n][sl]
+            if n == 2:
+                new_o[:, :, -1] = 0.0
+            got = o[sl].cpu().numpy()
+            inc_o = new_o - old
+            bar = TOL64 * np.abs(inc_o).max() + np.spacing(np.abs(new_o).max())
+            err = np.abs((got - old) - inc_o).max()
+            assert err <= bar, f"region {(i0, i1, j0, j1)} field {n}: {err:.3e} > {bar:.3e}"
+    del out
+    say("  oracle budgets of the whole domain")
+    tend = oracle_tendencies(hosts, g, w.dt)
+    ob, sc = O.budgets(*hosts[:3], *tend[:3], hosts[3:], tend[3:], g)
+    gb = M.budgets_dict(b.cpu().numpy(), w.nscal)
+    chains = (w.ny * w.nz + w.nx + 4096) * 2.0 ** -53
+    for name in ["C_u", "C_v", "C_w", "P_u", "Q_u", "P_v", "Q_v", "P_w", "Q_w"]:
+        scale = sc[name]
+        bar = (chains + TOL64) * scale
+        assert abs(gb[name] - ob[name]) <= bar, (name, gb[name], ob[name], bar)
+    mass = (g.rhon / g.rdz)[None, None, :]
+    for s in range(w.nscal):
+        t = I.interior(tend[3 + s])
+        scale = np.sum(np.abs(t) * mass)
+        assert abs(gb[f"C_s{s}"] - ob[f"C_s{s}"]) <= (chains + TOL64) * scale, s
+        assert abs(gb[f"M_s{s}"] - ob[f"M_s{s}"]) <= chains * abs(ob[f"M_s{s}"]), s
+        assert gb[f"min_s{s}"] == ob[f"min_s{s}"], s
+    cmax = O.max_courant(*hosts[:3], g, w.dt)
+    assert abs(gb["courant"] - cmax) <= 1e-15 * cmax
+    assert gb["nonfinite"] == 0
+    say("  budgets " + " ".join(f"{k}={v:.3e}" for k, v in gb.items()))
+
+
 @pytest.mark.parametrize("nscal,nz,budgets", [(1, 128, False), (1, 128, True), (2, 128, False),
                                              (3, 96, False), (4, 128, False), (1, 64, False),
                                              (4, 64, True), (5, 128, True)])
