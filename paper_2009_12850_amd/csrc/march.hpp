@@ -23,7 +23,11 @@
 //     neighbouring wave through LDS, the z-face k-1/2 from the neighbouring
 //     lane through a cross-lane shuffle (across a chunk boundary, through a
 //     small LDS array).
-// Per plane: store slices, barrier, compute values and faces, barrier, finish.
+// Per plane: store slices, barrier, finish the scalars of the previous plane
+// (their y- and chunk faces come from other waves), compute values and faces.
+// One barrier per plane: the velocity slices rotate over three planes and the
+// scalar slices and face arrays over two, so a wave that runs ahead into the
+// next plane's stores never overwrites what a slower wave still reads.
 #pragma once
 
 #include <type_traits>
@@ -90,10 +94,13 @@ __device__ __forceinline__ bf16 bload<bf16>(__amdgpu_buffer_rsrc_t r, uint32_t o
     x.bits = (uint16_t)__builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0);
     return x;
 }
-// Cache policy of the stores (2 = non-temporal: the outputs are not read
-// again by the launch, so they need not stay in L2).
+// Cache policy of the stores: 2 = non-temporal.  The outputs are not read
+// again by the launch; streamed past L2 they leave it to the input planes, and
+// the neighbouring tiles' halo columns then hit there more often (measured on
+// the FP64 step at 1024 x 1024 x 128: fetched bytes 1.30 -> 1.13 x the
+// algorithmic reads).
 #ifndef MONC_STORE_AUX
-#define MONC_STORE_AUX 0
+#define MONC_STORE_AUX 2
 #endif
 __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t off, double v) {
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(march_v2i, v), r, off, 0,
@@ -180,9 +187,9 @@ template <typename Ts, typename T, int NS, int NCH>
 __host__ __device__ constexpr size_t march_lds_bytes() {
     constexpr int MARCH_WAVES = march_waves<Ts, T>();
     constexpr int TJ = MARCH_WAVES / NCH;
-    return (size_t)(6 * (TJ + 2) + NS * (TJ + 4)) * march_csz<NCH>() * sizeof(T) +
-           (size_t)(NS * (TJ + 1) + NLEV) * (64 * NCH) * sizeof(T) +
-           (size_t)(NS > 0 ? NS : 1) * MARCH_WAVES * sizeof(T) + 64 * sizeof(T);
+    return (size_t)(9 * (TJ + 2) + 2 * NS * (TJ + 4)) * march_csz<NCH>() * sizeof(T) +
+           (size_t)(2 * NS * (TJ + 1) + NLEV) * (64 * NCH) * sizeof(T) +
+           (size_t)2 * (NS > 0 ? NS : 1) * MARCH_WAVES * sizeof(T) + 64 * sizeof(T);
 }
 
 __device__ __forceinline__ int bud_op(int q) {
@@ -240,12 +247,15 @@ __device__ __forceinline__ void march_tile(const AdvArgs& a, const TileJob& tj,
     constexpr int NJ = (6 + 4 * NS) * NCH;
     constexpr int NACC = MONC_B_SCALAR0 + 3 * NS;
 
-    T* const vel = reinterpret_cast<T*>(smem_raw);  // [3][2][VC][CSZ]
-    T* const sph = vel + 6 * VC * CSZ;              // [NS][SC][CSZ]
-    T* const sfy = sph + NS * SC * CSZ;             // [NS][FC][NZP]
-    T* const lev = sfy + NS * FC * NZP;             // [NLEV][NZP]
-    T* const fzc = lev + NLEV * NZP;                // [NS][TJ][NCH] chunk-top faces
-    T* const sink = fzc + NSA * MARCH_WAVES;         // [64] stores of unused halo jobs
+    constexpr int VSL = VC * CSZ;       // one velocity slice (one field, one plane)
+    constexpr int SSL = NS * SC * CSZ;  // the scalar slices of one plane
+    constexpr int FSL = NS * FC * NZP;  // the y-faces of one plane
+    T* const vel = reinterpret_cast<T*>(smem_raw);  // [3][plane % 3][VC][CSZ]
+    T* const sph0 = vel + 9 * VSL;                  // [plane % 2][NS][SC][CSZ]
+    T* const sfy0 = sph0 + 2 * SSL;                 // [plane % 2][NS][FC][NZP]
+    T* const lev = sfy0 + 2 * FSL;                  // [NLEV][NZP]
+    T* const fzc0 = lev + NLEV * NZP;               // [plane % 2][NS][TJ][NCH] chunk-top faces
+    T* const sink = fzc0 + 2 * NSA * MARCH_WAVES;   // [64] stores of unused halo jobs
 
     const int nx = a.nx, ny = a.ny, nz = a.nz;
     const size_t sx = (size_t)(ny + 4) * nz;
@@ -298,7 +308,7 @@ __device__ __forceinline__ void march_tile(const AdvArgs& a, const TileJob& tj,
         for (int q = 0; q < NLEV; q++) lev[q * NZP + kk] = (T)v[q];
     }
     // zero the padding levels of every slice column
-    for (int t = threadIdx.x; t < (6 * VC + NS * SC) * 4; t += MARCH_WAVES * 64) {
+    for (int t = threadIdx.x; t < (9 * VC + 2 * NS * SC) * 4; t += MARCH_WAVES * 64) {
         const int col = t >> 2, w4 = t & 3;
         vel[(size_t)col * CSZ + (w4 < 2 ? w4 : NZP + w4)] = (T)0;
     }
@@ -406,9 +416,11 @@ __device__ __forceinline__ void march_tile(const AdvArgs& a, const TileJob& tj,
         // LDS element offset (velocity slots: the parity term hj_par is added
         // on odd planes); a job without a column stores into the sink
         hj_lds[q] = !valid ? (int)(sink - vel) + lane
-                    : f < 3 ? ((f * 2) * VC + c) * CSZ + 2 + kk
-                            : (int)(sph - vel) + ((f - 3) * SC + c) * CSZ + 2 + kk;
-        hj_par[q] = valid && f < 3 ? VC * CSZ : 0;
+                    : f < 3 ? ((f * 3) * VC + c) * CSZ + 2 + kk
+                            : (int)(sph0 - vel) + ((f - 3) * SC + c) * CSZ + 2 + kk;
+        // slot stride: velocity slices rotate over three planes, scalar
+        // slices over two (sink stores take no offset)
+        hj_par[q] = !valid ? 0 : (f < 3 ? VSL : SSL);
         double o = 0.0;
 #pragma unroll
         for (int s = 0; s < NS; s++)
@@ -419,14 +431,18 @@ __device__ __forceinline__ void march_tile(const AdvArgs& a, const TileJob& tj,
     auto job_load = [&](int q, size_t o1, size_t o2) -> Ts {
         return ldo(hj_ptr[q], hj_dpl[q] ? o2 : o1, hj_boff[q]);
     };
+    // planes i >= -1 to their slots
+    auto slot3 = [](int plane_i) -> int { return (plane_i + 3) % 3; };
     // no branch: every job stores, unused ones into the sink
     auto job_store = [&](int q, int i, Ts x) {
-        vel[hj_lds[q] + (((i + hj_dpl[q]) & 1) ? hj_par[q] : 0)] = cvt<T, Ts>(x, hj_o[q]);
+        const int slot = hj_f[q] < 3 ? slot3(i + hj_dpl[q]) : (i & 1);
+        vel[hj_lds[q] + slot * hj_par[q]] = cvt<T, Ts>(x, hj_o[q]);
     };
     // own column slot addresses
-    auto vslot = [&](int f, int plane_i) -> T* {
-        return vel + (size_t)((f * 2 + (plane_i & 1)) * VC) * CSZ;
-    };
+    auto vslot = [&](int f, int plane_i) -> T* { return vel + (f * 3 + slot3(plane_i)) * VSL; };
+    auto sphs = [&](int plane_i) -> T* { return sph0 + (plane_i & 1) * SSL; };
+    auto sfys = [&](int plane_i) -> T* { return sfy0 + (plane_i & 1) * FSL; };
+    auto fzcs = [&](int plane_i) -> T* { return fzc0 + (plane_i & 1) * (NSA * MARCH_WAVES); };
     const int ownv = (cc + 1) * CSZ + 2 + k;  // own column in a velocity slot
     const int owns = (cc + 2) * CSZ + 2 + k;  // own column in a scalar slice
 
@@ -519,6 +535,48 @@ __device__ __forceinline__ void march_tile(const AdvArgs& a, const TileJob& tj,
     const bool bottom = k == 0;           // the ground face is below
     const bool top2 = k + 2 >= nz;        // no far-upwind cell above the top face
 
+    // ---- finishing a plane's scalars: the y-face below from LDS, the z-face
+    // below from the neighbouring lane (or the chunk below); pv: 0 or 1, the
+    // window slot that holds the plane's own values at the call ----
+    T part_c[NSA], up_c[NSA];
+    auto finish = [&](int ip, int pv) __attribute__((always_inline)) {
+        const T rdz = lev[LV_RDZ * NZP + k];
+        const T rhon_inv = lev[LV_RHONINV * NZP + k];
+        const size_t gplane = (size_t)(ip + 2) * sx;
+#pragma unroll
+        for (int s = 0; s < NS; s++) {
+            T fzm = up_c[s];
+            if constexpr (NCH > 1) {
+                // read unconditionally (one address: a broadcast), then select
+                const T below =
+                    wave_uniform(fzcs(ip)[(s * TJ + cc) * NCH + (ch > 0 ? ch - 1 : 0)]);
+                fzm = lane == 0 ? (ch == 0 ? (T)0 : below) : fzm;
+            } else {
+                fzm = lane == 0 ? (T)0 : fzm;
+            }
+            const T fym = sfys(ip)[(s * FC + cc) * NZP + k];
+            const T val = part_c[s] + fym * rdy + rhon_inv * rdz * fzm;
+            const Ts pown = P[s][pv];
+            if constexpr (MODE == TEND) {
+                (void)pown;
+                bstore(plane_rsrc((To*)a.out[3 + tj.s0 + s] + gplane, wbytes), woff, (To)val);
+            } else {
+                // the state is FP64 whatever the compute type
+                const double nsv = (double)pown + dt * (double)val;
+                bstore(plane_rsrc((double*)a.out[3 + tj.s0 + s] + gplane, wbytes64), woff64, nsv);
+                if constexpr (BUD) {
+                    if (store) {
+                        const double phd = (double)pown;
+                        acc[MONC_B_SCALAR0 + 3 * s] += (double)val;
+                        acc[MONC_B_SCALAR0 + 3 * s + 1] += phd;
+                        acc[MONC_B_SCALAR0 + 3 * s + 2] = fmin(acc[MONC_B_SCALAR0 + 3 * s + 2], phd);
+                    }
+                    nonfinite += __popcll(__ballot(store && !isfinite(nsv)));
+                }
+            }
+        }
+    };
+
     // ---- the march: one step; Xs holds step i's data and receives step
     // i+DEPTH's ----
     auto march_step = [&](int i, Ahead& Xs) __attribute__((always_inline)) {
@@ -544,7 +602,7 @@ __device__ __forceinline__ void march_tile(const AdvArgs& a, const TileJob& tj,
         vslot(1, i + 1)[ownv] = cvt0<T, Ts>(V[2]);
         vslot(2, i + 1)[ownv] = cvt0<T, Ts>(W[2]);
 #pragma unroll
-        for (int s = 0; s < NS; s++) sph[s * SC * CSZ + owns] = cvt<T, Ts>(P[s][1], off[s]);
+        for (int s = 0; s < NS; s++) sphs(i)[s * SC * CSZ + owns] = cvt<T, Ts>(P[s][1], off[s]);
 #pragma unroll
         for (int q = 0; q < NQ; q++) job_store(q, i, Xs.h[q]);
         // prefetch of step i+DEPTH (planes stay in bounds past the segment end:
@@ -557,6 +615,9 @@ __device__ __forceinline__ void march_tile(const AdvArgs& a, const TileJob& tj,
 #pragma unroll
         for (int q = 0; q < NQ; q++) Xs.h[q] = job_load(q, o_h, o_v);
         __syncthreads();
+        // the previous plane's scalars: their y-faces and chunk faces are
+        // visible now (after this step's shift its values are P[s][0])
+        if (i > i0) finish(i - 1, 0);
 
         const T* u_i = vslot(0, i);
         const T* u_im = vslot(0, i - 1);
@@ -566,9 +627,10 @@ __device__ __forceinline__ void march_tile(const AdvArgs& a, const TileJob& tj,
         const T* w_ip = vslot(2, i + 1);
         const size_t gplane = (size_t)(i + 2) * sx;
 
-        // Scalars keep across the face barrier only a partial sum and their
-        // top-face flux; momentum is finished (and stored) before it.
-        T part[NSA], fzk[NSA], fxp[NSA];
+        // Scalars keep until the next plane's barrier only a partial sum and
+        // the top face of the level below (part_c, up_c); momentum is finished
+        // (and stored) now.
+        T fxp[NSA];
         const T uc = cvt0<T, Ts>(U[1]), um = cvt0<T, Ts>(U[0]);
         // x-faces first: they need registers only, and overlap the LDS reads
 #pragma unroll
@@ -633,7 +695,7 @@ __device__ __forceinline__ void march_tile(const AdvArgs& a, const TileJob& tj,
                     const double dv = coriolis_v(a.fcor, a.ug, (double)uc, (double)um,
                                                  (double)un, (double)u_nw);
                     const double th_k = (double)P[0][1];
-                    const double th_kp = (double)sph[owns + 1] + off[0];
+                    const double th_kp = (double)sphs(i)[owns + 1] + off[0];
                     const double dw = buoyancy_w(a.gth, a.th0, th_k, th_kp);
                     nu = (double)U[1] + dt * ((double)su + du);
                     nv = (double)V[1] + dt * ((double)sv + dv);
@@ -687,30 +749,30 @@ __device__ __forceinline__ void march_tile(const AdvArgs& a, const TileJob& tj,
         const T cfz = dtc * lev[LV_RDZN * NZP + k];
 #pragma unroll
         for (int s = 0; s < NS; s++) {
-            const T* ph = sph + s * SC * CSZ;
+            const T* ph = sphs(i) + s * SC * CSZ;
             const T pc = cvt<T, Ts>(P[s][1], off[s]);
             // lateral fluxes are computed without the common rhon factor
             const T ps = ph[owns - CSZ], pn = ph[owns + CSZ], pnn = ph[owns + 2 * CSZ];
             const T fyp = sflux(vc, ps, pc, pn, pnn, cfy, rfy, (T)1);
-            sfy[(s * FC + cc + 1) * NZP + k] = fyp;
+            sfys(i)[(s * FC + cc + 1) * NZP + k] = fyp;
             // top face k+1/2.  Where the far-upwind cell is outside the column
             // it is replaced by the upwind cell, which makes the limiter return
             // the upwind value (first-order upwind); on the lid w is zero.
             const T pb = ph[owns - 1], pt = ph[owns + 1], ptt = ph[owns + 2];
             const T fz = sflux(wc, bottom ? pc : pb, pc, pt, top2 ? pt : ptt, cfz, rfz, rho);
-            fzk[s] = fz;
+            up_c[s] = __shfl_up(fz, 1, 64);  // the face below, from the lane below
             // the chunk's top face, for the chunk above: lane 63 stores it, the
             // other lanes store into the sink (no branch; 64 lanes writing one
             // address would serialise in the LDS)
             if constexpr (NCH > 1) {
-                T* const dst = lane == 63 ? fzc + (s * TJ + cc) * NCH + ch : sink + lane;
+                T* const dst = lane == 63 ? fzcs(i) + (s * TJ + cc) * NCH + ch : sink + lane;
                 *dst = fz;
             }
             // everything but the faces shared with the neighbours (j-1/2,
             // k-1/2); stored values are anomalies from phi0: add the term of
             // the constant
-            part[s] = -((fxp[s] - FXm[s]) * rdx + fyp * rdy) - rhon_inv * rdz * fz;
-            if constexpr (!STEP64) part[s] -= phi0c[s] * D * rhon_inv;
+            part_c[s] = -((fxp[s] - FXm[s]) * rdx + fyp * rdy) - rhon_inv * rdz * fz;
+            if constexpr (!STEP64) part_c[s] -= phi0c[s] * D * rhon_inv;
             FXm[s] = fxp[s];
         }
         // the tile's first column also computes the y-face j0-1/2 (one
@@ -719,47 +781,12 @@ __device__ __forceinline__ void march_tile(const AdvArgs& a, const TileJob& tj,
         if (cc == 0) {
 #pragma unroll
             for (int s = 0; s < NS; s++) {
-                const T* ph = sph + s * SC * CSZ;
-                sfy[(s * FC) * NZP + k] =
+                const T* ph = sphs(i) + s * SC * CSZ;
+                sfys(i)[(s * FC) * NZP + k] =
                     sflux(vs, ph[owns - 2 * CSZ], ph[owns - CSZ], ph[owns], ph[owns + CSZ],
                                 cfy, rfy, (T)1);
             }
         }
-        __syncthreads();
-
-        // finish the scalars: the y-face below from LDS, the z-face below from
-        // the neighbouring lane (or the chunk below)
-#pragma unroll
-        for (int s = 0; s < NS; s++) {
-            const T up1 = __shfl_up(fzk[s], 1, 64);
-            T fzm = up1;
-            if constexpr (NCH > 1) {
-                // read unconditionally (one address: a broadcast), then select
-                const T below = wave_uniform(fzc[(s * TJ + cc) * NCH + (ch > 0 ? ch - 1 : 0)]);
-                fzm = lane == 0 ? (ch == 0 ? (T)0 : below) : fzm;
-            } else {
-                fzm = lane == 0 ? (T)0 : fzm;
-            }
-            const T fym = sfy[(s * FC + cc) * NZP + k];
-            const T val = part[s] + fym * rdy + rhon_inv * rdz * fzm;
-            if constexpr (MODE == TEND) {
-                bstore(plane_rsrc((To*)a.out[3 + tj.s0 + s] + gplane, wbytes), woff, (To)val);
-            } else {
-                // the state is FP64 whatever the compute type
-                const double nsv = (double)P[s][1] + dt * (double)val;
-                bstore(plane_rsrc((double*)a.out[3 + tj.s0 + s] + gplane, wbytes64), woff64, nsv);
-                if constexpr (BUD) {
-                    if (store) {
-                        const double phd = (double)P[s][1];
-                        acc[MONC_B_SCALAR0 + 3 * s] += (double)val;
-                        acc[MONC_B_SCALAR0 + 3 * s + 1] += phd;
-                        acc[MONC_B_SCALAR0 + 3 * s + 2] = fmin(acc[MONC_B_SCALAR0 + 3 * s + 2], phd);
-                    }
-                    nonfinite += __popcll(__ballot(store && !isfinite(nsv)));
-                }
-            }
-        }
-
         // advance the plane offsets
         o_h = o_v;
         o_v = o_s;
@@ -772,6 +799,9 @@ __device__ __forceinline__ void march_tile(const AdvArgs& a, const TileJob& tj,
         for (int d = 1; d < DEPTH; d++)
             if (i + d < i1) march_step(i + d, S[d]);
     }
+    // the last plane's scalars (no shift followed: its values are P[s][1])
+    __syncthreads();
+    if (i1 > i0) finish(i1 - 1, 1);
 
     if constexpr (BUD) {
         // the level's weights in FP64 from the profiles (the level table may
