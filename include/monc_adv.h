@@ -182,6 +182,27 @@ int monc_step(double *const *state_in, double *const *state_out, int nscal,
               const double *rho, const double *rhon, double dt,
               double *budgets, void *workspace, monc_stream_t stream);
 
+/* monc_step with budgets, allocation-free: for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation).  Same arguments as monc_step without the
+ * workspace; budgets (device float64 [MONC_NBUDGET]) is required.  The
+ * budget partial rows (one per workgroup of the launch, MONC_NBUDGET doubles
+ * each) go to a static device array of MONC_STATIC_MAX_ROWS rows (2.3 MB)
+ * that the library holds on every device it runs on until the process ends;
+ * grids that need more rows (monc_step_workspace_bytes / (8 * MONC_NBUDGET))
+ * return MONC_EINVAL.  No allocation happens on any call; the first call on a
+ * device looks the array's address up once.  Every call on one device shares
+ * the array: calls that overlap on one device (other streams, other threads)
+ * race and must be serialised by the caller.  Nothing in the array needs to
+ * start at zero (every row is written before it is read).  Results and budgets
+ * are bitwise those of monc_step with a workspace. */
+#define MONC_STATIC_MAX_ROWS 8192
+#define MONC_STATIC_MAX_DEVICES 64
+int monc_step_static(double *const *state_in, double *const *state_out, int nscal,
+                     int nx, int ny, int nz, double dx, double dy, const double *rdz,
+                     const double *rho, const double *rhon, double dt, double *budgets,
+                     monc_stream_t stream);
+
 /* The same step with the tendencies computed in FP32 from the FP64 state
  * (scalars first reduced by phi0 in FP64, then rounded) and accumulated in
  * FP64: the single-precision advection of Sec. 4.1 without a separate

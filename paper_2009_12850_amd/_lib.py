@@ -51,6 +51,7 @@ _SIGS = {
     "monc_advect": ([ip, PP, PP, ip, DPTR, ip, ip, ip, dp, dp, vp, vp, vp, dp, vp], ip),
     "monc_step_workspace_bytes": ([ip, ip, ip, ip], C.c_size_t),
     "monc_step": ([PP, PP, ip, ip, ip, ip, dp, dp, vp, vp, vp, dp, vp, vp, vp], ip),
+    "monc_step_static": ([PP, PP, ip, ip, ip, ip, dp, dp, vp, vp, vp, dp, vp, vp], ip),
     "monc_step_mixed": ([PP, PP, ip, DPTR, ip, ip, ip, dp, dp, vp, vp, vp, dp, vp, vp, vp],
                         ip),
     "monc_cast_working": ([ip, ip, PP, PP, DPTR, ip, ip, ip, vp], ip),
@@ -255,6 +256,20 @@ def monc_advect(dtype, inputs, outputs, dx, dy, prof, dt, phi0=None, stream=None
 
 def monc_step_workspace_bytes(nx, ny, nz, nscal):
     return int(lib().monc_step_workspace_bytes(nx, ny, nz, nscal))
+
+
+def monc_step_static(state_in, state_out, dx, dy, prof, dt, budgets, stream=None):
+    """monc_step with budgets and no workspace (the library's static scratch)."""
+    torch = _torch()
+    nx, ny, nz = _grid(state_in[0])
+    sh = tuple(state_in[0].shape)
+    nscal = len(state_in) - 3
+    ia = _ptrs(state_in, torch.float64, sh, "state_in")
+    oa = _ptrs(state_out, torch.float64, sh, "state_out")
+    b = _ptr(budgets, torch.float64, (MONC_NBUDGET,), "budgets")
+    rc = lib().monc_step_static(ia, oa, nscal, nx, ny, nz, float(dx), float(dy), *_prof(prof),
+                                float(dt), b, _stream(stream))
+    _check(rc, "monc_step_static")
 
 
 def monc_step(state_in, state_out, dx, dy, prof, dt, budgets=None, workspace=None,

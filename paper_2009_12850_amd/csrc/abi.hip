@@ -5,6 +5,7 @@
 #include <stdarg.h>
 #include <stdio.h>
 
+#include <mutex>
 #include <string>
 
 #include "monc_internal.hpp"
@@ -322,6 +323,63 @@ int monc_step(double* const* state_in, double* const* state_out, int nscal, int 
               monc_stream_t stream) {
     return do_step(state_in, state_out, nscal, nullptr, nx, ny, nz, dx, dy, rdz, rho, rhon,
                    dt, budgets, workspace, stream, false);
+}
+
+// ---------------------------------------------------------------------------
+// The step with budgets for callers that cannot allocate: the budget partial
+// rows live in a file-scope device array.  Its host-side name is only a
+// stand-in; the device address is looked up once per device (with that
+// device current) and kept.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) double scratch[(size_t)MONC_STATIC_MAX_ROWS * NB];
+
+namespace {
+
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[MONC_STATIC_MAX_DEVICES] = {};
+
+int scratch_on_current_device(double** out) {
+    int dev = -1;
+    TRY(hip_status(hipGetDevice(&dev), "step_static/hipGetDevice"));
+    if (dev < 0 || dev >= MONC_STATIC_MAX_DEVICES)
+        return fail(MONC_EUNSUPPORTED, "device %d: the static scratch serves devices 0..%d", dev,
+                    MONC_STATIC_MAX_DEVICES - 1);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        TRY(hip_status(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)),
+                       "step_static/hipGetSymbolAddress"));
+        if (!p) return fail(MONC_EHIP, "step_static: no device address for the scratch array");
+        g_scratch_ptr[dev] = (double*)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return MONC_OK;
+}
+
+}  // namespace
+
+int monc_step_static(double* const* state_in, double* const* state_out, int nscal, int nx,
+                     int ny, int nz, double dx, double dy, const double* rdz, const double* rho,
+                     const double* rhon, double dt, double* budgets, monc_stream_t stream) {
+    TRY(check_grid(nx, ny, nz));
+    TRY(check_spacing(dx, dy));
+    TRY(check_dt(dt));
+    TRY(check_prof(rdz, rho, rhon));
+    TRY(check_nscal(nscal));
+    const int nf = 3 + nscal;
+    TRY(check_ptrs(nf, state_in, "state_in"));
+    TRY(check_ptrs(nf, state_out, "state_out"));
+    TRY(check_alias(nf, (const void* const*)state_in, nf, (const void* const*)state_out));
+    if (!budgets) return fail(MONC_EINVAL, "budgets is NULL (monc_step_static computes them)");
+    const int rows = step_grid(nx, ny, nz, false);
+    if (rows > MONC_STATIC_MAX_ROWS)
+        return fail(MONC_EINVAL,
+                    "grid %d x %d x %d needs %d budget rows; the static scratch holds %d "
+                    "(use monc_step with a workspace)", nx, ny, nz, rows, MONC_STATIC_MAX_ROWS);
+    double* ws = nullptr;
+    TRY(scratch_on_current_device(&ws));
+    return do_step(state_in, state_out, nscal, nullptr, nx, ny, nz, dx, dy, rdz, rho, rhon, dt,
+                   budgets, ws, stream, false);
 }
 
 int monc_step_mixed(double* const* state_in, double* const* state_out, int nscal,

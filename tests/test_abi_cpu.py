@@ -295,3 +295,18 @@ def test_tvd_momentum_entries_reject_bad_arguments():
                                     None) == M.MONC_EINVAL
     assert L.monc_step_tvd_momentum(ins, outs, 2, 8, 8, 8, 1.0, 1.0, *_prof3(), 0.5,
                                     C.c_void_p(0x9100), None) == M.MONC_EINVAL  # cmax = out
+
+
+def test_static_step_rejects_grids_beyond_its_scratch():
+    """monc_step_static refuses, before any HIP call, a grid whose launch needs
+    more budget rows than its static scratch holds, and a missing budgets
+    array."""
+    L = M.lib()
+    ins = _arr([0x1000 + 0x100 * n for n in range(4)])
+    outs = _arr([0x9000 + 0x100 * n for n in range(4)])
+    # 8 planes x 36000 columns: 9000 tiles of four columns along y
+    rc = L.monc_step_static(ins, outs, 1, 8, 36000, 128, 50.0, 50.0, *_prof3(), 0.5,
+                            C.c_void_p(0x7000), None)
+    assert rc == M.MONC_EINVAL and b"static scratch" in L.monc_last_error()
+    rc = L.monc_step_static(ins, outs, 1, 8, 8, 8, 50.0, 50.0, *_prof3(), 0.5, None, None)
+    assert rc == M.MONC_EINVAL and b"budgets" in L.monc_last_error()
