@@ -107,6 +107,20 @@ def event_time_ms(torch, stream, fn, reps):
     return start.elapsed_time(end) / reps
 
 
+def launch_times_ms(torch, stream, fn, reps):
+    """Durations of `reps` single launches of fn() on `stream`, each bracketed
+    by its own pair of HIP events."""
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(reps)]
+    with torch.cuda.stream(stream):
+        for a, b in ev:
+            a.record(stream)
+            fn()
+            b.record(stream)
+    ev[-1][1].synchronize()
+    return [a.elapsed_time(b) for a, b in ev]
+
+
 PW_FLOP = 92  # floating-point operations of one PW evaluation per grid point
 
 
@@ -128,6 +142,94 @@ def bench_scaled(torch, M, vel64, g, prof, stream, npts, reps):
         out[name] = rows
         del outs
     del vel32
+    return out
+
+
+REGION = (0, 128, 0, 128)  # the subdomain of the precision forms' errors (all levels)
+
+
+def precision_outputs(torch, M, host, g, prof, w, dev, stream):
+    """The precision forms on the benchmark's input: FP32 and BF16 working
+    copies (scalars stored as anomalies from their nominal values) advected in
+    FP32, and the mixed step with budgets.  Returns host arrays of the
+    region's results and the domain sums of the source terms (float64 sums of
+    the GPU's values, measurement only)."""
+    i0, i1, j0, j1 = REGION
+    sl = (slice(i0 + 2, i1 + 2), slice(j0 + 2, j1 + 2))
+    X = [torch.from_numpy(h).to(dev) for h in host]
+    nscal = len(host) - 3
+    phi0 = [300.0] + [1e-3] * (nscal - 1)
+    offs = [0.0, 0.0, 0.0] + phi0
+    mass = torch.from_numpy(g.rhon / g.rdz).to(dev)
+    dzn = 0.5 * (1.0 / g.rdz[:-1] + 1.0 / g.rdz[1:])
+    wm = np.zeros(g.nz)
+    wm[:-1] = g.rho[:-1] * dzn
+    wmass = torch.from_numpy(wm).to(dev)
+    res = {}
+    for name, code, tdt in (("f32", M.MONC_F32, torch.float32), ("bf16", M.MONC_BF16, torch.int16)):
+        work = [torch.empty(x.shape, dtype=tdt, device=dev) for x in X]
+        M.monc_cast_working(code, X, work, offs, stream)
+        outs = [torch.empty(x.shape, dtype=torch.float32, device=dev) for x in X]
+        M.monc_advect(code, work, outs, g.dx, g.dy, prof, w.dt, phi0=phi0, stream=stream)
+        sums = {}
+        for n, o in enumerate(outs):
+            wt = wmass if n == 2 else mass
+            sums[n] = float((o[2:-2, 2:-2, :].double() * wt).sum())
+        res[name] = {"region": [o[sl].double().cpu().numpy() for o in outs], "sums": sums}
+        del work, outs
+    out = [torch.empty_like(x) for x in X]
+    bud = torch.zeros(M.MONC_NBUDGET, dtype=torch.float64, device=dev)
+    ws = torch.empty(M.monc_step_workspace_bytes(g.nx, g.ny, g.nz, nscal), dtype=torch.uint8,
+                     device=dev)
+    M.monc_step_mixed(X, out, phi0, g.dx, g.dy, prof, w.dt, bud, ws, stream)
+    res["mixed"] = {"region_inc": [(o[sl] - x[sl]).cpu().numpy() for o, x in zip(out, X)],
+                    "budgets": M.budgets_dict(bud.cpu().numpy(), nscal)}
+    del X, out
+    torch.cuda.empty_cache()
+    return res
+
+
+def precision_errors(res, host, g, dt):
+    """Errors of the precision forms against the FP64 oracle: per field
+    max |gpu - oracle| / max |oracle| of the source terms on the region (the
+    mixed step: of the increments, against dt times the oracle's source terms),
+    and the domain budgets' differences relative to the oracle's sum of
+    |terms| (conservation sums C, energy production P, scalar mass M)."""
+    from oracle import pyoracle as O
+    O.build(force=False)
+    hosts = [O.halo_fill(h.copy()) for h in host]
+    i0, i1, j0, j1 = REGION
+    sl = (slice(i0 + 2, i1 + 2), slice(j0 + 2, j1 + 2))
+    u, v, w = hosts[:3]
+    full = list(O.pw(u, v, w, g)) + [O.tvd(u, v, w, q, g, dt) for q in hosts[3:]]
+    ob, sc = O.budgets(*hosts[:3], *full[:3], hosts[3:], full[3:], g)
+    mass = (g.rhon / g.rdz)[None, None, :]
+    sscale = [float(np.sum(np.abs(full[3 + s][2:-2, 2:-2]) * mass)) for s in range(len(host) - 3)]
+    names = ["u", "v", "w"] + [f"s{s}" for s in range(len(host) - 3)]
+    out = {"region": f"i, j in [{i0}, {i1}) x [{j0}, {j1}), all levels"}
+    for form in ("f32", "bf16"):
+        errs, berr = {}, {}
+        for n, nm in enumerate(names):
+            exp = full[n][sl]
+            errs[nm] = float(np.abs(res[form]["region"][n] - exp).max() / np.abs(exp).max())
+            key = f"C_{nm}" if n < 3 else f"C_s{n - 3}"
+            scale = sc[key] if n < 3 else sscale[n - 3]
+            berr[key] = abs(res[form]["sums"][n] - ob[key]) / scale
+        out[form] = {"field_rel_err": errs, "budget_rel_err": berr}
+    errs, berr = {}, {}
+    for n, nm in enumerate(names):
+        exp = dt * full[n][sl]
+        if n == 2:
+            exp[:, :, -1] = 0.0
+        errs[nm] = float(np.abs(res["mixed"]["region_inc"][n] - exp).max() / np.abs(exp).max())
+    gb = res["mixed"]["budgets"]
+    for key in ["C_u", "C_v", "C_w", "P_u", "P_v", "P_w"]:
+        berr[key] = abs(gb[key] - ob[key]) / sc[key]
+    for s in range(len(host) - 3):
+        berr[f"C_s{s}"] = abs(gb[f"C_s{s}"] - ob[f"C_s{s}"]) / sscale[s]
+        berr[f"M_s{s}"] = abs(gb[f"M_s{s}"] - ob[f"M_s{s}"]) / abs(ob[f"M_s{s}"])
+        berr[f"min_s{s}"] = abs(gb[f"min_s{s}"] - ob[f"min_s{s}"]) / abs(ob[f"min_s{s}"])
+    out["mixed"] = {"field_rel_err": errs, "budget_rel_err": berr}
     return out
 
 
@@ -246,15 +348,29 @@ def bench_tvd_momentum(torch, M, state, g, prof, w, stream, npts, plain_ms, reps
     return out
 
 
-def copy_ceiling_gbps(torch, dev, stream, reps=20):
-    """Read + write bandwidth of a plain 1 GiB device-to-device copy."""
-    src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+CEIL_BLOCKS = 32768  # workgroups of the streaming kernels (the best of 8192 .. 65536)
+
+
+def stream_ceiling(torch, M, dev, stream, reps=10):
+    """HBM rates of the library's streaming kernels (16-byte accesses,
+    non-temporal stores) over 2 GiB buffers: read only, write only and a 1:1
+    copy (the read/write mix of the advection step), median of `reps`."""
+    nbytes = 1 << 31
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)
     dst = torch.empty_like(src)
-    for _ in range(3):
-        dst.copy_(src)
-    ms = event_time_ms(torch, stream, lambda: dst.copy_(src), reps)
-    del src, dst
-    return 2.0 * (1 << 30) / (ms * 1e-3) / 1e9
+    sink = torch.empty(M.monc_ceiling_sink_bytes(CEIL_BLOCKS), dtype=torch.uint8, device=dev)
+    out = {}
+    for name, mode, a, b, moved in (("read", M.MONC_CEIL_READ, src, sink, nbytes),
+                                    ("write", M.MONC_CEIL_WRITE, None, dst, nbytes),
+                                    ("copy", M.MONC_CEIL_COPY, src, dst, 2 * nbytes)):
+        fn = lambda: M.monc_stream_ceiling(mode, a, b, nbytes, CEIL_BLOCKS, stream)
+        fn()
+        med = float(np.median(launch_times_ms(torch, stream, fn, reps)))
+        out[f"{name}_gbps"] = moved / (med * 1e-3) / 1e9
+    del src, dst, sink
+    torch.cuda.empty_cache()
+    out["kernel"] = "monc_stream_ceiling (16-byte accesses, non-temporal stores)"
+    return out
 
 
 def synthetic_state(torch, dev, shape, nscal, seed):
@@ -369,8 +485,9 @@ def main():
     g = I.make_geometry(w.nx, w.ny, w.nz, w.dx, w.dx)
     names = ["u", "v", "w"] + I.scalar_names(w.nscal)
     f = I.make_fields(g, w.nscal, w.seed, padded=True)
-    A = [torch.from_numpy(f.pop(n)).to(dev) for n in names]
+    host = [f.pop(n) for n in names]  # kept for the oracle's error check
     del f
+    A = [torch.from_numpy(h).to(dev) for h in host]
     B = [torch.empty_like(a) for a in A]
     prof = [torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in (g.rdz, g.rho, g.rhon)]
     budgets = torch.zeros(M.MONC_NBUDGET, dtype=torch.float64, device=dev)
@@ -407,24 +524,34 @@ def main():
     wall = (time.perf_counter() - t0) / args.steps * 1e3
     value = npts / (ms * 1e-3)
 
-    # dominant kernel: the fused advection-step launch (no budget pass)
-    k_ms = event_time_ms(torch, stream, lambda: step(False), args.steps)
-    bytes_alg = 16.0 * nf * npts  # read + write of every FP64 field
-    achieved = bytes_alg / (k_ms * 1e-3)
+    # The dominant kernel is the timed launch itself (the advection march
+    # with budget partials; the final budget pass adds about 5 us): its
+    # average duration over the timed region gives the roofline; the median
+    # of per-launch timings and the same launch without budgets are reported
+    # beside it.
+    bytes_alg = 16.0 * nf * npts  # one read and one write of every FP64 field
+    lt = launch_times_ms(torch, stream, step, max(20, args.steps))
+    lt0 = launch_times_ms(torch, stream, lambda: step(False), max(20, args.steps))
+    achieved = bytes_alg / (ms * 1e-3)
     traffic = measured_traffic(args.workload)
-    copy_gbps = copy_ceiling_gbps(torch, dev, stream)
+    ceil = stream_ceiling(torch, M, dev, stream)
     roofline = {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9,
                 "unit": "GB/s", "frac": achieved / HBM_PEAK,
                 "traffic": traffic / 1e9 if traffic else None, "traffic_unit": "GB per launch",
                 # measured bytes of the launch (counters) over its duration, vs the peak
-                "traffic_frac": (traffic / (k_ms * 1e-3) / HBM_PEAK) if traffic else None,
-                # a plain 1 GiB device-to-device copy on this device: the streaming ceiling
-                "copy_ceiling_gbps": copy_gbps,
-                "frac_of_copy_ceiling": achieved / 1e9 / copy_gbps,
-                "kernel": "monc_step (fused PW+TVD+update, FP64)",
-                "bytes_per_launch": bytes_alg, "launch_ms": k_ms}
+                "traffic_frac": (traffic / (ms * 1e-3) / HBM_PEAK) if traffic else None,
+                "traffic_over_algorithmic": traffic / bytes_alg if traffic else None,
+                "kernel": "monc_step with budgets (fused PW + TVD + update + budget "
+                          "partials, FP64): the timed launch",
+                "bytes_per_launch": bytes_alg, "launch_ms_mean": ms,
+                "launch_ms_median": float(np.median(lt)),
+                "ceiling": ceil,
+                "frac_of_copy_ceiling": achieved / 1e9 / ceil["copy_gbps"],
+                "no_budgets": {"launch_ms_median": float(np.median(lt0)),
+                               "frac": bytes_alg / (np.median(lt0) * 1e-3) / HBM_PEAK}}
 
     forms = None
+    prec_res = None
     if not args.no_forms and args.only_form:
         log(f"form {args.only_form}")
         if args.only_form == "dynamics":
@@ -460,7 +587,19 @@ def main():
                 "ms": t, "gpups": npts / (t * 1e-3),
                 "hbm_frac": (eb + 4.0) * nf * npts / (t * 1e-3) / HBM_PEAK,
                 "speedup_vs_f64": t64 / t}
+            # the marshalling cast of all fields (whole padded arrays: 8 bytes
+            # read and 4 or 2 written per value)
+            tc = event_time_ms(torch, stream, lambda: M.monc_cast_working(
+                code, state[0], work, offs, stream), args.steps)
+            cbytes = (8.0 + eb) * nf * A[0].numel()
+            forms[f"{dt_name}_tendencies"]["cast"] = {
+                "ms": tc, "gbps": cbytes / (tc * 1e-3) / 1e9,
+                "hbm_frac": cbytes / (tc * 1e-3) / HBM_PEAK,
+                # one cast then the FP32 source terms, against the FP64 source terms
+                "cast_plus_tendencies_speedup_vs_f64": t64 / (t + tc)}
             del work, outs
+        log("precision forms on the benchmark input (for the oracle's error check)")
+        prec_res = precision_outputs(torch, M, host, g, prof, w, dev, stream)
         forms["work_scaled_pw"] = bench_scaled(torch, M, state[0][:3], g, prof, stream, npts,
                                                max(3, args.steps // 4))
         mixed = lambda: M.monc_step_mixed(state[0], state[1], phi0, g.dx, g.dy, prof, w.dt,
@@ -498,6 +637,12 @@ def main():
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         cpu = cpu_baseline()
+        if prec_res is not None:
+            # the precision forms' errors against the FP64 oracle (this leg is
+            # the only part of the benchmark that runs the oracle)
+            log("precision forms: errors against the oracle")
+            forms["precision_errors"] = precision_errors(prec_res, host, g, w.dt)
+    del host
 
     rec = {
         "metric": "advection grid-point updates/s + % HBM peak; FP64 plain vs FP32/batched/learned",
