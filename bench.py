@@ -233,6 +233,45 @@ def precision_errors(res, host, g, dt):
     return out
 
 
+def learned_gradient_check(torch, M, dev, m=32768, seed=5):
+    """The learned form's gradients at the training batch's row count (4 face
+    rows for each of 8192 cells): the GPU forward (saving its activations)
+    and backward on seeded features, against the FP64 oracle's backward from
+    the GPU's own activations with BF16 rounding emulated where the kernels
+    round; per parameter block, max |gpu - oracle| / max |oracle|."""
+    from oracle import mlp_ref as R
+    rng = np.random.default_rng(seed)
+    p = R.init_params(seed).astype(np.float32).astype(np.float64)
+    X = rng.standard_normal((m, R.K))
+    X[:, R.PAD] = 0.0
+    Xb = R.bf16(X)
+    Xd = torch.from_numpy(Xb.astype(np.float32)).to(dev).to(torch.bfloat16).view(torch.int16)
+    pd = torch.from_numpy(p.astype(np.float32)).to(dev)
+    wp = torch.zeros(M.MONC_MLP_WPACK, dtype=torch.int16, device=dev)
+    M.monc_mlp_pack(pd, wp)
+    Y = torch.zeros((m, 4), dtype=torch.float32, device=dev)
+    H1 = torch.zeros((m, 64), dtype=torch.int16, device=dev)
+    H2 = torch.zeros_like(H1)
+    Z1 = torch.zeros((m, 64), dtype=torch.float32, device=dev)
+    Z2 = torch.zeros_like(Z1)
+    M.monc_mlp_forward(Xd, m, pd, wp, Y, H1, H2, Z1, Z2)
+    dY = (rng.standard_normal((m, 4)) / m).astype(np.float32)
+    grad = torch.zeros(R.NPARAM, dtype=torch.float32, device=dev)
+    ws = torch.zeros(M.monc_mlp_backward_workspace_bytes(m), dtype=torch.uint8, device=dev)
+    M.monc_mlp_backward(Xd, H1, H2, Z1, Z2, torch.from_numpy(dY).to(dev), m, wp, grad, ws)
+    torch.cuda.synchronize()
+    bf = lambda t: t.view(torch.bfloat16).double().cpu().numpy()
+    _, b1, W2, b2, W3, b3 = R.unpack(p)
+    cache = dict(Xb=Xb, Z1=Z1.double().cpu().numpy(), H1=bf(H1), Z2=Z2.double().cpu().numpy(),
+                 H2=bf(H2), W2b=R.bf16(W2), W3b=R.bf16(W3))
+    ref = R.unpack(R.backward(dY.astype(np.float64), cache, emulate=True))
+    got = R.unpack(grad.double().cpu().numpy())
+    out = {}
+    for name, a, b in zip(["W1", "b1", "W2", "b2", "W3", "b3"], got, ref):
+        out[name] = float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-30))
+    return {"rows": m, "block_rel_err": out}
+
+
 def cpu_baseline():
     """The FP64 oracle, unchanged, timed on the host cores with one thread and
     with all of them: one forward step (every source term and the update) of
@@ -642,6 +681,9 @@ def main():
             # the only part of the benchmark that runs the oracle)
             log("precision forms: errors against the oracle")
             forms["precision_errors"] = precision_errors(prec_res, host, g, w.dt)
+        if forms is not None and "learned" in forms:
+            log("learned form: gradient check against the oracle")
+            forms["learned"]["gradient_check"] = learned_gradient_check(torch, M, dev)
     del host
 
     rec = {

@@ -325,7 +325,12 @@ int monc_mlp_forward(const uint16_t *X, int m, const float *params, const uint16
  * bitwise what monc_mlp_features (cells = NULL, same orient) followed by
  * monc_mlp_forward gives, but the features are gathered from the fields into
  * the matrix operands directly and never stored.  state: host array of 4
- * device pointers (u, v, w, theta); norm: host [8]; wpack 16-byte aligned. */
+ * device pointers (u, v, w, theta); norm: host [8]; wpack 16-byte aligned.
+ * orient 2 evaluates both face orientations (Y[2][nx*ny*nz][4]: x-faces,
+ * then y-faces), on 32-level grids with ny % 4 == 0 from one staged
+ * neighbourhood per tile (the y-face rows use the same 5 x 5 x 3 cells with x
+ * and y exchanged), elsewhere as two launches; each half is bitwise the
+ * single-orientation result. */
 int monc_mlp_infer(const double *const *state, int nx, int ny, int nz, const double *norm,
                    int orient, const float *params, const uint16_t *wpack, float *Y,
                    monc_stream_t stream);

@@ -601,7 +601,8 @@ def monc_mlp_infer(state, norm, orient, params, wpack, Y, stream=None):
     torch = _torch()
     nx, ny, nz = _grid(state[0])
     sa = _ptrs(state, torch.float64, tuple(state[0].shape), "state")
-    _ptr(Y, torch.float32, (nx * ny * nz, 4), "Y")
+    rows = nx * ny * nz * (2 if int(orient) == 2 else 1)
+    _ptr(Y, torch.float32, (rows, 4), "Y")
     _check(lib().monc_mlp_infer(sa, nx, ny, nz, _dbl(norm), int(orient), _ptr(params),
                                 _ptr(wpack), _ptr(Y), _stream(stream)), "monc_mlp_infer")
 

@@ -768,7 +768,7 @@ int monc_mlp_infer(const double* const* state, int nx, int ny, int nz, const dou
     TRY(check_grid(nx, ny, nz));
     TRY(check_ptrs(4, state, "state"));
     if (!norm || !params || !wpack || !Y) return fail(MONC_EINVAL, "NULL pointer");
-    if (orient != 0 && orient != 1) return fail(MONC_EINVAL, "orient must be 0 or 1");
+    if (orient < 0 || orient > 2) return fail(MONC_EINVAL, "orient must be 0, 1 or 2");
     for (int f = 0; f < 4; f++)
         if (!(norm[2 * f + 1] > 0)) return fail(MONC_EINVAL, "norm std %d must be > 0", f);
     if ((uintptr_t)wpack & 15) return fail(MONC_EINVAL, "wpack must be 16-byte aligned");

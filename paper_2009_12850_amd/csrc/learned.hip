@@ -31,7 +31,10 @@ struct u16x8 {
 };
 
 __device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
-__device__ __forceinline__ uint16_t f2bf(float f) { return f32_to_bf16_rne(f); }
+// FP32 -> BF16, round to nearest even: the native conversion of gfx950
+// (v_cvt_pk_bf16_f32), the same rounding as f32_to_bf16_rne in fewer
+// instructions (the activations of every layer pass through it)
+__device__ __forceinline__ uint16_t f2bf(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 
 __device__ __forceinline__ bf16x8_t ld8(const uint16_t* p) {  // 16-byte aligned
     const uint4 v = *reinterpret_cast<const uint4*>(p);
@@ -481,9 +484,13 @@ __device__ __forceinline__ bf16x8_t row_fragment_staged(const uint16_t* st, int 
     return __builtin_bit_cast(bf16x8_t, t);
 }
 
+// ORIENT 0: x-faces, 1: y-faces (the exchanged frame), 2: both from one
+// staged tile (staged grids only): Y receives the x-face rows, then the
+// y-face rows at Y + m * NO.
 template <int ORIENT, bool STAGED>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
     mlp_infer(InferArgs a) {
+    static_assert(ORIENT < 2 || STAGED, "both orientations only from a staged tile");
     extern __shared__ __align__(16) unsigned char smem[];
     uint16_t* sw = reinterpret_cast<uint16_t*>(smem);  // pack
     uint16_t* sH = sw + S_WEND;                           // [4][32][LWH]
@@ -498,48 +505,38 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
     const int h = lane >> 5;
     uint16_t* H = sH + w * 32 * LWH;
     const long ntiles = (a.m + FWD_ROWS - 1) / FWD_ROWS;
-    for (long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const long row0 = tile * FWD_ROWS + 32 * w;
-        const long ar = row0 + (lane & 31);
-        const bool live = ar < a.m;
-        f32x16_t acc1[2] = {{}, {}};
-        if constexpr (STAGED) {
-            uint16_t* st = sH;  // the activation area, free until layer 1 ends
-            stage_tile<ORIENT>(a, tile, st);
-            __syncthreads();
-            const int lc = w, k = lane & 31;  // 32 rows per wave = one column
+    constexpr int NOR = ORIENT == 2 ? 2 : 1;
+    // layer 1 of orientation O from the staged tile
+    auto layer1_staged = [&](auto O, const uint16_t* st, f32x16_t* acc1) {
+        const int lc = w, k = lane & 31;  // 32 rows per wave = one column
 #pragma unroll
-            for (int kk = 0; kk < KP / 16; kk++) {
-                const int ks = kslot(kk, h);
-                const bf16x8_t av = row_fragment_staged<ORIENT>(st, lc, k, h, kk);
+        for (int kk = 0; kk < KP / 16; kk++) {
+            const int ks = kslot(kk, h);
+            const bf16x8_t av = row_fragment_staged<decltype(O)::value>(st, lc, k, h, kk);
 #pragma unroll
-                for (int nt = 0; nt < 2; nt++)
-                    acc1[nt] =
-                        mfma(av, ld8(sw + S_W1 + (32 * nt + (lane & 31)) * LW1 + ks), acc1[nt]);
-            }
-            __syncthreads();  // every wave is done with the staged tile
-        } else {
-            RowGather g;
-            row_setup<ORIENT>(a, live ? ar : 0, h, g);
-            // layer 1: fragments built block by block straight from the
-            // fields; fully unrolled, so every slot index is a constant and the
-            // gather state stays in registers
-#pragma unroll
-            for (int kk = 0; kk < KP / 16; kk++) {
-                const int ks = kslot(kk, h);
-                const bf16x8_t av = live ? row_fragment(g, kk) : zero8();
-#pragma unroll
-                for (int nt = 0; nt < 2; nt++)
-                    acc1[nt] =
-                        mfma(av, ld8(sw + S_W1 + (32 * nt + (lane & 31)) * LW1 + ks), acc1[nt]);
-            }
+            for (int nt = 0; nt < 2; nt++)
+                acc1[nt] = mfma(av, ld8(sw + S_W1 + (32 * nt + (lane & 31)) * LW1 + ks), acc1[nt]);
         }
+    };
+    // the first hidden layer's activations of this lane, BF16, two per word
+    auto activate1 = [&](const f32x16_t* acc1, uint32_t* hv) {
+#pragma unroll
+        for (int nt = 0; nt < 2; nt++) {
+            const float b = sb[32 * nt + (lane & 31)];
+#pragma unroll
+            for (int r = 0; r < 16; r += 2)
+                hv[8 * nt + r / 2] = (uint32_t)f2bf(gelu(acc1[nt][r] + b)) |
+                                     ((uint32_t)f2bf(gelu(acc1[nt][r + 1] + b)) << 16);
+        }
+    };
+    // layers 2 and 3 of one orientation from its first activations; rows to Yo
+    auto finish_rows = [&](const uint32_t* hv, long row0, float* Yo) {
 #pragma unroll
         for (int nt = 0; nt < 2; nt++) {
 #pragma unroll
             for (int r = 0; r < 16; r++) {
                 const int lr = acc_row(r, lane), col = 32 * nt + (lane & 31);
-                H[lr * LWH + col] = f2bf(gelu(acc1[nt][r] + sb[col]));
+                H[lr * LWH + col] = (uint16_t)(hv[8 * nt + r / 2] >> (16 * (r & 1)));
             }
         }
         __syncthreads();
@@ -579,21 +576,79 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
 #pragma unroll
             for (int r = 0; r < 16; r++) {
                 const long row = row0 + acc_row(r, lane);
-                if (row < a.m) a.Y[(size_t)row * NO + col] = acc[r] + sb[2 * HID + col];
+                if (row < a.m) Yo[(size_t)row * NO + col] = acc[r] + sb[2 * HID + col];
             }
         }
-        __syncthreads();  // H is rewritten by the next tile
+        __syncthreads();  // H is rewritten next
+    };
+    for (long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const long row0 = tile * FWD_ROWS + 32 * w;
+        const long ar = row0 + (lane & 31);
+        const bool live = ar < a.m;
+        f32x16_t acc1[2] = {{}, {}};
+        uint32_t hv[NOR][16];  // first activations, per orientation
+        if constexpr (STAGED) {
+            uint16_t* st = sH;  // the activation area, free until layer 1 ends
+            stage_tile<ORIENT == 1 ? 1 : 0>(a, tile, st);
+            __syncthreads();
+            if constexpr (ORIENT == 2) {
+                // x-faces, activated before the y-faces' layer 1 (fewer live sums)
+                layer1_staged(std::integral_constant<int, 0>(), st, acc1);
+                activate1(acc1, hv[0]);
+                acc1[0] = acc1[1] = f32x16_t{};
+                // keep the scheduler from interleaving the two gathers (their
+                // loads in flight together would not fit the registers)
+                __builtin_amdgcn_sched_barrier(0);
+                layer1_staged(std::integral_constant<int, 1>(), st, acc1);
+                activate1(acc1, hv[1]);
+            } else {
+                layer1_staged(std::integral_constant<int, ORIENT>(), st, acc1);
+                activate1(acc1, hv[0]);
+            }
+            __syncthreads();  // every wave is done with the staged tile
+        } else {
+            RowGather g;
+            row_setup<ORIENT>(a, live ? ar : 0, h, g);
+            // layer 1: fragments built block by block straight from the
+            // fields; fully unrolled, so every slot index is a constant and the
+            // gather state stays in registers
+#pragma unroll
+            for (int kk = 0; kk < KP / 16; kk++) {
+                const int ks = kslot(kk, h);
+                const bf16x8_t av = live ? row_fragment(g, kk) : zero8();
+#pragma unroll
+                for (int nt = 0; nt < 2; nt++)
+                    acc1[nt] = mfma(av, ld8(sw + S_W1 + (32 * nt + (lane & 31)) * LW1 + ks),
+                                    acc1[nt]);
+            }
+            activate1(acc1, hv[0]);
+        }
+#pragma unroll
+        for (int o = 0; o < NOR; o++) {
+            finish_rows(hv[o], row0, a.Y + (size_t)o * a.m * NO);
+            __builtin_amdgcn_sched_barrier(0);
+        }
     }
 }
 
 // ---------------------------------------------------------------------------
-// Backward: 64 rows per workgroup (4 waves); per-workgroup partial gradients
-// of every parameter, reduced afterwards in a fixed order.
+// Backward: a persistent grid of at most BWD_GRID workgroups (4 waves); each
+// takes 64-row chunks c = blockIdx.x, blockIdx.x + gridDim.x, ... and keeps
+// its gradient sums in registers across them (the MFMA tiles of dW1 and dW2
+// in their accumulators), then writes one partial row.  The grid depends only
+// on m, so the rows and their fixed-order sum (reduce_partials: one column
+// per lane, rows in order) are repeatable bit for bit.
 // ---------------------------------------------------------------------------
 constexpr int BWD_ROWS = 64;
+constexpr int BWD_GRID = 256;
 constexpr size_t BWD_LDS = (size_t)BWD_ROWS * KP * 2 + 4 * (size_t)BWD_ROWS * HID * 2 +
                            (size_t)HID * HID * 2 + (size_t)BWD_ROWS * NO * 4 + NO * HID * 4 +
                            2 * 256 * 4;
+
+int bwd_grid(int m) {
+    const int chunks = (m + BWD_ROWS - 1) / BWD_ROWS;
+    return chunks < BWD_GRID ? chunks : BWD_GRID;
+}
 
 __global__ void __launch_bounds__(256) mlp_backward(const uint16_t* __restrict__ X,
                                                     const uint16_t* __restrict__ H1,
@@ -614,122 +669,148 @@ __global__ void __launch_bounds__(256) mlp_backward(const uint16_t* __restrict__
     float* sW3 = sdY + BWD_ROWS * NO;                    // [4][64] (bf16 values)
     float* red = sW3 + NO * HID;                          // [2][256]
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int row0 = blockIdx.x * BWD_ROWS;
     float* part = partials + (size_t)blockIdx.x * NPARAM;
+    const int nchunks = (m + BWD_ROWS - 1) / BWD_ROWS;
+    const int kh = 8 * (lane >> 5);
 
-    for (int t = tid; t < BWD_ROWS * KP / 8; t += 256) {
-        const int r = t / (KP / 8);
-        uint4 v = make_uint4(0, 0, 0, 0);
-        if (row0 + r < m) v = reinterpret_cast<const uint4*>(X + (size_t)(row0 + r) * KP)[t % (KP / 8)];
-        reinterpret_cast<uint4*>(sX)[t] = v;
-    }
-    for (int t = tid; t < BWD_ROWS * HID; t += 256) {
-        const int r = t / HID;
-        const bool ok = row0 + r < m;
-        sH1[t] = ok ? H1[(size_t)row0 * HID + t] : (uint16_t)0;
-        sH2[t] = ok ? H2[(size_t)row0 * HID + t] : (uint16_t)0;
-    }
     for (int t = tid; t < HID * HID; t += 256) sW2[t] = wpack[PK_W2 + t];
     for (int t = tid; t < NO * HID; t += 256) sW3[t] = bf2f(wpack[PK_W3 + t]);
-    for (int t = tid; t < BWD_ROWS * NO; t += 256)
-        sdY[t] = (row0 + t / NO < m) ? dY[(size_t)row0 * NO + t] : 0.0f;
-    __syncthreads();
 
-    // dZ2 = (dY W3) * gelu'(Z2); bias gradient b2
-    float db2 = 0.0f;  // thread handles column tid % 64, rows tid/64 + 4q
-    {
-        const int col = tid & 63;
-        for (int r = tid >> 6; r < BWD_ROWS; r += 4) {
-            float dz = 0.0f;
-            if (row0 + r < m) {
-                float dh = 0.0f;
+    // sums kept across the chunks
+    float db2 = 0.0f;     // column tid % 64, rows tid/64 + 4q
+    float colsum1 = 0.0f; // b1: column 32 ct + lane % 32 of this wave's dZ1 tile
+    f32x16_t accW2 = {};  // dW2 tile (w >> 1, w & 1)
+    f32x16_t accW1[5];    // dW1 tiles w, w + 4, .., w + 16 of the 2 x 10
 #pragma unroll
-                for (int q = 0; q < NO; q++) dh += sdY[r * NO + q] * sW3[q * HID + col];
-                dz = dh * gelu_grad(Z2[(size_t)(row0 + r) * HID + col]);
+    for (int q = 0; q < 5; q++) accW1[q] = f32x16_t{};
+    float sW3acc = 0.0f, sB3acc = 0.0f;
+
+    for (int c = blockIdx.x; c < nchunks; c += gridDim.x) {
+        const int row0 = c * BWD_ROWS;
+        __syncthreads();  // the previous chunk is done with the LDS
+        for (int t = tid; t < BWD_ROWS * KP / 8; t += 256) {
+            const int r = t / (KP / 8);
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (row0 + r < m)
+                v = reinterpret_cast<const uint4*>(X + (size_t)(row0 + r) * KP)[t % (KP / 8)];
+            reinterpret_cast<uint4*>(sX)[t] = v;
+        }
+        for (int t = tid; t < BWD_ROWS * HID; t += 256) {
+            const int r = t / HID;
+            const bool ok = row0 + r < m;
+            sH1[t] = ok ? H1[(size_t)row0 * HID + t] : (uint16_t)0;
+            sH2[t] = ok ? H2[(size_t)row0 * HID + t] : (uint16_t)0;
+        }
+        for (int t = tid; t < BWD_ROWS * NO; t += 256)
+            sdY[t] = (row0 + t / NO < m) ? dY[(size_t)row0 * NO + t] : 0.0f;
+        __syncthreads();
+
+        // dZ2 = (dY W3) * gelu'(Z2); bias gradient b2
+        {
+            const int col = tid & 63;
+            for (int r = tid >> 6; r < BWD_ROWS; r += 4) {
+                float dz = 0.0f;
+                if (row0 + r < m) {
+                    float dh = 0.0f;
+#pragma unroll
+                    for (int q = 0; q < NO; q++) dh += sdY[r * NO + q] * sW3[q * HID + col];
+                    dz = dh * gelu_grad(Z2[(size_t)(row0 + r) * HID + col]);
+                }
+                db2 += dz;
+                sdZ2[r * HID + col] = f2bf(dz);
             }
-            db2 += dz;
-            sdZ2[r * HID + col] = f2bf(dz);
+        }
+        __syncthreads();
+
+        // dH1 = dZ2 W2 (MFMA), dZ1 = dH1 * gelu'(Z1): one 32x32 tile per wave;
+        // b1 sums the FP32 dZ1 values (each lane its 16 rows of the tile)
+        {
+            const int rt = w >> 1, ct = w & 1;
+            f32x16_t acc = {};
+#pragma unroll
+            for (int kk = 0; kk < HID / 16; kk++) {
+                const bf16x8_t av = ld8(sdZ2 + (32 * rt + (lane & 31)) * HID + 16 * kk + kh);
+                const bf16x8_t bv = gather8(sW2 + (16 * kk + kh) * HID + 32 * ct + (lane & 31), HID);
+                acc = mfma(av, bv, acc);
+            }
+#pragma unroll
+            for (int r = 0; r < 16; r++) {
+                const int lr = 32 * rt + acc_row(r, lane), col = 32 * ct + (lane & 31);
+                float dz = 0.0f;
+                if (row0 + lr < m) dz = acc[r] * gelu_grad(Z1[(size_t)(row0 + lr) * HID + col]);
+                sdZ1[lr * HID + col] = f2bf(dz);
+                colsum1 += dz;
+            }
+        }
+        __syncthreads();
+        // dW2[j2][j1] += sum_rows dZ2[row][j2] H1[row][j1]
+        {
+            const int it = w >> 1, jt = w & 1;
+#pragma unroll
+            for (int kk = 0; kk < BWD_ROWS / 16; kk++) {
+                const bf16x8_t av = gather8(sdZ2 + (16 * kk + kh) * HID + 32 * it + (lane & 31), HID);
+                const bf16x8_t bv = gather8(sH1 + (16 * kk + kh) * HID + 32 * jt + (lane & 31), HID);
+                accW2 = mfma(av, bv, accW2);
+            }
+        }
+        // dW1[j][k] += sum_rows dZ1[row][j] X[row][k]: tiles tt = w + 4 q
+#pragma unroll
+        for (int q = 0; q < 5; q++) {
+            const int tt = w + 4 * q, it = tt / 10, kt = tt % 10;
+#pragma unroll
+            for (int kk = 0; kk < BWD_ROWS / 16; kk++) {
+                const bf16x8_t av = gather8(sdZ1 + (16 * kk + kh) * HID + 32 * it + (lane & 31), HID);
+                const bf16x8_t bv = gather8(sX + (16 * kk + kh) * KP + 32 * kt + (lane & 31), KP);
+                accW1[q] = mfma(av, bv, accW1[q]);
+            }
+        }
+        // dW3[q][j2] += sum_rows dY[row][q] H2[row][j2]; db3
+        {
+            const int q = tid / HID, j2 = tid % HID;  // 256 = 4 x 64
+            for (int r = 0; r < BWD_ROWS; r++) sW3acc += sdY[r * NO + q] * bf2f(sH2[r * HID + j2]);
+            if (tid < NO)
+                for (int r = 0; r < BWD_ROWS; r++) sB3acc += sdY[r * NO + tid];
         }
     }
-    red[tid] = db2;
-    __syncthreads();
-    if (tid < HID) part[OFF_B2 + tid] = red[tid] + red[tid + 64] + red[tid + 128] + red[tid + 192];
 
-    // dH1 = dZ2 W2 (MFMA), dZ1 = dH1 * gelu'(Z1): one 32x32 tile per wave.
-    // The bias gradient b1 sums the FP32 dZ1 values: each lane sums its 16
-    // rows, then the 4 (row tile, lane half) partials of a column are added in
-    // a fixed order.
-    const int kh = 8 * (lane >> 5);
+    // the workgroup's partial row
+    __syncthreads();
+    red[tid] = db2;
     {
         const int rt = w >> 1, ct = w & 1;
-        f32x16_t acc = {};
-#pragma unroll
-        for (int kk = 0; kk < HID / 16; kk++) {
-            const bf16x8_t av = ld8(sdZ2 + (32 * rt + (lane & 31)) * HID + 16 * kk + kh);
-            const bf16x8_t bv = gather8(sW2 + (16 * kk + kh) * HID + 32 * ct + (lane & 31), HID);
-            acc = mfma(av, bv, acc);
-        }
-        float colsum = 0.0f;
-#pragma unroll
-        for (int r = 0; r < 16; r++) {
-            const int lr = 32 * rt + acc_row(r, lane), col = 32 * ct + (lane & 31);
-            float dz = 0.0f;
-            if (row0 + lr < m) dz = acc[r] * gelu_grad(Z1[(size_t)(row0 + lr) * HID + col]);
-            sdZ1[lr * HID + col] = f2bf(dz);
-            colsum += dz;
-        }
-        red[256 + (2 * rt + (lane >> 5)) * HID + 32 * ct + (lane & 31)] = colsum;
+        red[256 + (2 * rt + (lane >> 5)) * HID + 32 * ct + (lane & 31)] = colsum1;
     }
     __syncthreads();
-    if (tid < HID)
+    if (tid < HID) {
+        part[OFF_B2 + tid] = red[tid] + red[tid + 64] + red[tid + 128] + red[tid + 192];
         part[OFF_B1 + tid] = red[256 + tid] + red[256 + HID + tid] + red[256 + 2 * HID + tid] +
                              red[256 + 3 * HID + tid];
-    // dW2[j2][j1] = sum_rows dZ2[row][j2] H1[row][j1]: one tile per wave
+    }
     {
         const int it = w >> 1, jt = w & 1;
-        f32x16_t acc = {};
-#pragma unroll
-        for (int kk = 0; kk < BWD_ROWS / 16; kk++) {
-            const bf16x8_t av = gather8(sdZ2 + (16 * kk + kh) * HID + 32 * it + (lane & 31), HID);
-            const bf16x8_t bv = gather8(sH1 + (16 * kk + kh) * HID + 32 * jt + (lane & 31), HID);
-            acc = mfma(av, bv, acc);
-        }
 #pragma unroll
         for (int r = 0; r < 16; r++) {
             const int j2 = 32 * it + acc_row(r, lane), j1 = 32 * jt + (lane & 31);
-            part[OFF_W2 + j2 * HID + j1] = acc[r];
+            part[OFF_W2 + j2 * HID + j1] = accW2[r];
         }
     }
-    // dW1[j][k] = sum_rows dZ1[row][j] X[row][k]: 2 x 10 tiles, 5 per wave
-    for (int tt = w; tt < 20; tt += 4) {
-        const int it = tt / 10, kt = tt % 10;
-        f32x16_t acc = {};
 #pragma unroll
-        for (int kk = 0; kk < BWD_ROWS / 16; kk++) {
-            const bf16x8_t av = gather8(sdZ1 + (16 * kk + kh) * HID + 32 * it + (lane & 31), HID);
-            const bf16x8_t bv = gather8(sX + (16 * kk + kh) * KP + 32 * kt + (lane & 31), KP);
-            acc = mfma(av, bv, acc);
-        }
+    for (int q = 0; q < 5; q++) {
+        const int tt = w + 4 * q, it = tt / 10, kt = tt % 10;
 #pragma unroll
         for (int r = 0; r < 16; r++) {
             const int j = 32 * it + acc_row(r, lane), k = 32 * kt + (lane & 31);
-            part[OFF_W1 + j * KP + k] = acc[r];
+            part[OFF_W1 + j * KP + k] = accW1[q][r];
         }
     }
-    // dW3[q][j2] = sum_rows dY[row][q] H2[row][j2]; db3
     {
-        const int q = tid / HID, j2 = tid % HID;  // 256 = 4 x 64
-        float s = 0.0f;
-        for (int r = 0; r < BWD_ROWS; r++) s += sdY[r * NO + q] * bf2f(sH2[r * HID + j2]);
-        part[OFF_W3 + q * HID + j2] = s;
-        if (tid < NO) {
-            float sb = 0.0f;
-            for (int r = 0; r < BWD_ROWS; r++) sb += sdY[r * NO + tid];
-            part[OFF_B3 + tid] = sb;
-        }
+        const int q = tid / HID, j2 = tid % HID;
+        part[OFF_W3 + q * HID + j2] = sW3acc;
+        if (tid < NO) part[OFF_B3 + tid] = sB3acc;
     }
 }
 
+// Sum of the partial rows, one parameter per lane, rows in order.
 __global__ void __launch_bounds__(256) reduce_partials(const float* __restrict__ partials, int nb,
                                                        int n, float* __restrict__ out) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1117,13 +1198,21 @@ hipError_t launch_mlp_forward(const uint16_t* X, int m, const float* params,
 hipError_t launch_mlp_infer(const double* const* state, int nx, int ny, int nz,
                            const double* norm, int orient, const float* params,
                            const uint16_t* wpack, float* Y, hipStream_t s) {
-    static std::atomic<unsigned long long> attr[2][2] = {{{0}, {0}}, {{0}, {0}}};
     const bool staged = infer_staged_ok(ny, nz);
-    const void* kern = staged ? (orient ? (const void*)mlp_infer<1, true>
-                                        : (const void*)mlp_infer<0, true>)
+    if (orient == 2 && !staged) {
+        // no staged tile to share: one launch per orientation
+        hipError_t e = launch_mlp_infer(state, nx, ny, nz, norm, 0, params, wpack, Y, s);
+        if (e != hipSuccess) return e;
+        return launch_mlp_infer(state, nx, ny, nz, norm, 1, params, wpack,
+                                Y + (size_t)nx * ny * nz * NO, s);
+    }
+    static std::atomic<unsigned long long> attr[2][3] = {{{0}, {0}, {0}}, {{0}, {0}, {0}}};
+    const void* kern = staged ? (orient == 2 ? (const void*)mlp_infer<2, true>
+                                 : orient ? (const void*)mlp_infer<1, true>
+                                          : (const void*)mlp_infer<0, true>)
                               : (orient ? (const void*)mlp_infer<1, false>
                                         : (const void*)mlp_infer<0, false>);
-    hipError_t e = set_lds_limit_once(kern, FWD_LDS, &attr[staged ? 1 : 0][orient ? 1 : 0]);
+    hipError_t e = set_lds_limit_once(kern, FWD_LDS, &attr[staged ? 1 : 0][orient]);
     if (e != hipSuccess) return e;
     // the current device's compute units (devices may differ)
     int dev = 0, ncu = 0;
@@ -1146,7 +1235,9 @@ hipError_t launch_mlp_infer(const double* const* state, int nx, int ny, int nz,
     const long ntiles = (a.m + FWD_ROWS - 1) / FWD_ROWS;
     const int grid = (int)(ntiles < 2L * ncu ? ntiles : 2L * ncu);
     if (staged) {
-        if (orient)
+        if (orient == 2)
+            mlp_infer<2, true><<<grid, 256, FWD_LDS, s>>>(a);
+        else if (orient)
             mlp_infer<1, true><<<grid, 256, FWD_LDS, s>>>(a);
         else
             mlp_infer<0, true><<<grid, 256, FWD_LDS, s>>>(a);
@@ -1159,9 +1250,7 @@ hipError_t launch_mlp_infer(const double* const* state, int nx, int ny, int nz,
     return hipGetLastError();
 }
 
-size_t mlp_backward_workspace(int m) {
-    return (size_t)((m + BWD_ROWS - 1) / BWD_ROWS) * NPARAM * sizeof(float);
-}
+size_t mlp_backward_workspace(int m) { return (size_t)bwd_grid(m) * NPARAM * sizeof(float); }
 
 hipError_t launch_mlp_backward(const uint16_t* X, const uint16_t* H1, const uint16_t* H2,
                                const float* Z1, const float* Z2, const float* dY, int m,
@@ -1169,7 +1258,7 @@ hipError_t launch_mlp_backward(const uint16_t* X, const uint16_t* H1, const uint
     static std::atomic<unsigned long long> attr{0};
     hipError_t e = set_lds_limit_once((const void*)mlp_backward, BWD_LDS, &attr);
     if (e != hipSuccess) return e;
-    const int nb = (m + BWD_ROWS - 1) / BWD_ROWS;
+    const int nb = bwd_grid(m);
     mlp_backward<<<nb, 256, BWD_LDS, s>>>(X, H1, H2, Z1, Z2, dY, m, wpack, (float*)ws);
     reduce_partials<<<blocks_for(NPARAM), 256, 0, s>>>((const float*)ws, nb, NPARAM, grad);
     return hipGetLastError();

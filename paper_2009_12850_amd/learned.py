@@ -283,8 +283,7 @@ class CoarseRunner:
             return
         mdl, N = self.model, self.N
         M.monc_advect(M.MONC_F64, A, self.tend, s.dxc, s.dxc, s.prof_c, s.dtc)
-        M.monc_mlp_infer(A, mdl.norm, 0, mdl.params, mdl.wpack, self.G.narrow(0, 0, N))
-        M.monc_mlp_infer(A, mdl.norm, 1, mdl.params, mdl.wpack, self.G.narrow(0, N, N))
+        M.monc_mlp_infer(A, mdl.norm, 2, mdl.params, mdl.wpack, self.G)  # both orientations
         M.monc_correct_step(A, self.tend, self.G.narrow(0, 0, N), self.G.narrow(0, N, N), B,
                             s.dxc, s.dxc, mdl.scale, s.prof_c, s.dtc, self.growth, self.flags,
                             self.ws)
@@ -397,6 +396,15 @@ def run_experiment(nx=512, ny=512, nz=128, seeds=range(2000, 2016), n_train=12, 
                               for n in range(0, len(ser.tend), max(1, len(ser.tend) // 8))]))
 
     loss_zero, loss_trained = held_loss(zero), held_loss(model)
+    # one training step (features, forward, loss, backward with its gradient
+    # reduction, Adam) on its own, timed on a separate copy of the network
+    probe = Correction(device, seed=0, norm=norm, scale=scale, batch=batch)
+    prng = np.random.default_rng(7)
+    probe.train_step(train_set[0], 0, prng)
+    treps = 50
+    t_step = _event_ms(lambda: [probe.train_step(train_set[0], n % len(train_set[0].tend), prng)
+                                for n in range(treps)]) / treps
+    del probe
     nsteps = min(coarse_steps, len(held[0].tend))
     err_plain, err_learned, fb = [], [], [0, 0, 0]
     t_plain = t_learned = 0.0
@@ -421,8 +429,7 @@ def run_experiment(nx=512, ny=512, nz=128, seeds=range(2000, 2016), n_train=12, 
     A0 = held[0].snaps[0]
 
     def infer():
-        M.monc_mlp_infer(A0, model.norm, 0, model.params, model.wpack, runner.G.narrow(0, 0, N))
-        M.monc_mlp_infer(A0, model.norm, 1, model.params, model.wpack, runner.G.narrow(0, N, N))
+        M.monc_mlp_infer(A0, model.norm, 2, model.params, model.wpack, runner.G)
 
     infer()
     reps = 20
@@ -439,6 +446,10 @@ def run_experiment(nx=512, ny=512, nz=128, seeds=range(2000, 2016), n_train=12, 
         "coarse_steps": nsteps, "fields": FIELDS, "norm": norm, "scale": scale,
         "residual_max_over_scale": rmax,
         "err_plain": mean(err_plain), "err_learned": mean(err_learned),
+        # per field: the plain coarse error over the learned one (> 1: the
+        # correction helps)
+        "gain": [p / l for p, l in zip(mean(err_plain), mean(err_learned))],
+        "train_step_ms": t_step,
         "fallback_nonfinite": fb[0], "fallback_growth": fb[1], "theta_faces_clamped": fb[2],
         "t_fine_ms": t_fine, "t_coarse_plain_ms": t_plain, "t_coarse_learned_ms": t_learned,
         "speedup_vs_fine": t_fine / t_learned,

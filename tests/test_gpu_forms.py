@@ -114,6 +114,28 @@ def test_cast_working_is_exact_rounding(shape):
         assert np.array_equal(got16, exp16, equal_nan=True), n
 
 
+@pytest.mark.parametrize("shape", [(32, 32, 32), (40, 36, 128), (17, 23, 96)])
+def test_bf16_path_equals_oracle_of_rounded_inputs(shape):
+    """The BF16 path rounds its inputs (scalars as anomalies from phi0) to
+    BF16 and computes in FP32: it must match the FP64 oracle evaluated on
+    exactly those rounded inputs to the FP32 bar.  (Its difference from the
+    oracle on the unrounded inputs is the storage error the precision form
+    reports.)"""
+    from oracle import mlp_ref as R
+    nx, ny, nz = shape
+    say(f"bf16 vs oracle of rounded inputs {shape}")
+    g, host = case(nx, ny, nz, 2, seed=615 + nx)
+    dt = 0.5
+    phi0 = [300.0, 0.0]
+    offs = [0.0, 0.0, 0.0] + phi0
+    rounded = [o + R.bf16(h - o) for h, o in zip(host, offs)]
+    ref = oracle_tendencies(rounded, g, dt)
+    got = narrow_tendencies(host, g, dt, M.MONC_BF16, phi0)
+    errs = [rel_err(a, b) for a, b in zip(got, ref)]
+    say(f"  relative errors {['%.2e' % e for e in errs]}")
+    assert max(errs) <= 1e-5, errs
+
+
 def test_anomaly_offset_is_exact_in_fp64():
     """Storing theta as an anomaly and passing phi0 gives the FP64 tendency of
     the full field (affine equivariance of the flux form)."""
