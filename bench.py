@@ -28,7 +28,8 @@ if ROOT not in sys.path:
 
 HBM_PEAK = 8.0e12  # B/s, MI355X HBM3E
 
-# Sources of the dominant kernel: a measured HBM traffic figure is reported
+# Sources of the dominant kernel (the timed launch: the FP64 step with budgets):
+# a measured HBM traffic figure is reported
 # only while these files are unchanged since the counters were taken.
 KERNEL_SOURCES = ["paper_2009_12850_amd/csrc/march.hpp",
                   "paper_2009_12850_amd/csrc/march_launch.hpp",
