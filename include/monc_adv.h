@@ -310,7 +310,7 @@ int monc_restrict4(int nscal, const double *const *fine, double *const *coarse, 
 /* Gather BF16 features (rows [ncells][320]) of cells (device linear indices
  * (i*ny + j)*nz + k, or NULL for all cells in that order; a listed cell outside
  * the grid gives a zero row).  state: host array of 4 device pointers (u, v, w,
- * theta); norm: host [8] = mean, std per field. */
+ * theta); norm: host [8] = mean, std per field; X 16-byte aligned. */
 int monc_mlp_features(const double *const *state, int nx, int ny, int nz,
                       const double *norm, int orient, const int *cells, int ncells,
                       uint16_t *X, monc_stream_t stream);

@@ -113,6 +113,7 @@ void fill_args(AdvArgs& a, int nx, int ny, int nz, double dx, double dy, double 
     a.dyn = 0;
     a.fcor = a.ug = a.vg = a.gth = a.th0 = 0.0;
     a.spw = 0;
+    a.work = 1;
 }
 
 int do_halo(int bytes, int nfields, void* const* fields, int nx, int ny, int nz,
@@ -253,9 +254,14 @@ int monc_advect_pw_scaled(int dtype, const void* u, const void* v, const void* w
     TRY(check_ptrs(3, in, "velocity"));
     TRY(check_ptrs(3, out, "tendency"));
     TRY(check_alias(3, in, 3, out));
-    return hip_status(launch_pw_scaled(dtype, u, v, w, su, sv, sw, nx, ny, nz, dx, dy, rdz, rho,
-                                       rhon, work, (hipStream_t)stream),
-                      "advect_pw_scaled");
+    AdvArgs a;
+    fill_args(a, nx, ny, nz, dx, dy, 1.0, rdz, rho, rhon, 0);
+    for (int f = 0; f < 3; f++) {
+        a.in[f] = in[f];
+        a.out[f] = const_cast<void*>(out[f]);
+    }
+    a.work = work;
+    return hip_status(launch_pw_scaled(dtype, a, (hipStream_t)stream), "advect_pw_scaled");
 }
 
 int monc_advect_tvd(const double* u, const double* v, const double* w, int nscal,
@@ -752,6 +758,7 @@ int monc_mlp_features(const double* const* state, int nx, int ny, int nz, const 
         return fail(MONC_EINVAL, "without a cell list ncells must be nx*ny*nz");
     for (int f = 0; f < 4; f++)
         if (!(norm[2 * f + 1] > 0)) return fail(MONC_EINVAL, "norm std %d must be > 0", f);
+    if ((uintptr_t)X & 15) return fail(MONC_EINVAL, "X must be 16-byte aligned");
     return hip_status(launch_features(state, nx, ny, nz, norm, orient, cells, ncells, X,
                                       (hipStream_t)stream),
                       "mlp_features");

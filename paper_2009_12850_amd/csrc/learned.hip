@@ -168,29 +168,44 @@ struct FeatArgs {
 };
 
 __global__ void __launch_bounds__(256) features_kernel(FeatArgs a) {
+    // one thread per (row, 8-slot chunk): 40 chunks of a 320-slot row, one
+    // 16-byte store; the cell is decoded once for its 8 values
     const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= a.ncells * KP) return;
-    const long row = t / KP;
-    const int n = (int)(t - row * KP);
-    uint16_t out = 0;
+    if (t >= a.ncells * (KP / 8)) return;
+    const long row = t / (KP / 8);
+    const int chunk = (int)(t - row * (KP / 8));
+    const int f = chunk / 10, p0 = 8 * (chunk % 10);
     const int cell = a.cells ? a.cells[row] : (int)row;
-    const int f = n / 80, pos = n % 80;
-    if (pos < 75 && (unsigned)cell < (unsigned)(a.nx * a.ny * a.nz)) {
-        const int a5 = pos / 15, b5 = (pos / 3) % 5, c3 = pos % 3;
-        const int k = cell % a.nz, j = (cell / a.nz) % a.ny, i = cell / (a.nz * a.ny);
-        const int src = a.orient ? (f == 0 ? 1 : (f == 1 ? 0 : f)) : f;
-        const int di = a.orient ? b5 - 2 : a5 - 2;
-        const int dj = a.orient ? a5 - 2 : b5 - 2;
-        int ii = (i + di) % a.nx;
-        if (ii < 0) ii += a.nx;
-        int jj = (j + dj) % a.ny;
-        if (jj < 0) jj += a.ny;
-        int kk = k + c3 - 1;
-        kk = kk < 0 ? 0 : (kk > a.nz - 1 ? a.nz - 1 : kk);
-        const double v = a.f[src][((long)(ii + 2) * (a.ny + 4) + (jj + 2)) * a.nz + kk];
-        out = f2bf((float)((v - a.mean[src]) * a.inv_std[src]));
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const bool inside = (unsigned)cell < (unsigned)(nx * ny * nz);
+    const int c = inside ? cell : 0;
+    const int k = c % nz, ij = c / nz;
+    const int j = ij % ny, i = ij / ny;
+    const int src = a.orient ? (f == 0 ? 1 : (f == 1 ? 0 : f)) : f;
+    const double* fld = a.f[src];
+    const double mean = a.mean[src], inv = a.inv_std[src];
+    u16x8 v;
+#pragma unroll
+    for (int e = 0; e < 8; e++) {
+        const int pos = p0 + e;
+        uint16_t out = 0;
+        if (pos < 75 && inside) {
+            const int a5 = pos / 15, b5 = (pos / 3) % 5, c3 = pos % 3;
+            const int di = a.orient ? b5 - 2 : a5 - 2;
+            const int dj = a.orient ? a5 - 2 : b5 - 2;
+            int ii = i + di, jj = j + dj;  // offsets of at most 2 cells: wrap by adds
+            ii = ii < 0 ? ii + nx : (ii >= nx ? ii - nx : ii);
+            ii = ii < 0 ? ii + nx : (ii >= nx ? ii - nx : ii);
+            jj = jj < 0 ? jj + ny : (jj >= ny ? jj - ny : jj);
+            jj = jj < 0 ? jj + ny : (jj >= ny ? jj - ny : jj);
+            int kk = k + c3 - 1;
+            kk = kk < 0 ? 0 : (kk > nz - 1 ? nz - 1 : kk);
+            const double x = fld[((long)(ii + 2) * (ny + 4) + (jj + 2)) * nz + kk];
+            out = f2bf((float)((x - mean) * inv));
+        }
+        v.v[e] = out;
     }
-    a.X[t] = out;
+    reinterpret_cast<uint4*>(a.X)[t] = __builtin_bit_cast(uint4, v);
 }
 
 // ---------------------------------------------------------------------------
@@ -810,14 +825,22 @@ __global__ void __launch_bounds__(256) mlp_backward(const uint16_t* __restrict__
     }
 }
 
-// Sum of the partial rows, one parameter per lane, rows in order.
+// Sum of the partial rows: a workgroup takes 64 parameters (one per lane),
+// its four waves sum consecutive quarters of the rows in order, and the four
+// quarter sums are added in order (a fixed association for a given row count).
 __global__ void __launch_bounds__(256) reduce_partials(const float* __restrict__ partials, int nb,
                                                        int n, float* __restrict__ out) {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n) return;
+    __shared__ float q[4][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int p = blockIdx.x * 64 + lane;
+    const int per = (nb + 3) / 4;
+    const int b0 = w * per, b1 = min(nb, b0 + per);
     float s = 0.0f;
-    for (int b = 0; b < nb; b++) s += partials[(size_t)b * n + p];
-    out[p] = s;
+    if (p < n)
+        for (int b = b0; b < b1; b++) s += partials[(size_t)b * n + p];
+    q[w][lane] = s;
+    __syncthreads();
+    if (w == 0 && p < n) out[p] = ((q[0][lane] + q[1][lane]) + q[2][lane]) + q[3][lane];
 }
 
 // ---------------------------------------------------------------------------
@@ -1175,7 +1198,7 @@ hipError_t launch_features(const double* const* state, int nx, int ny, int nz, c
     a.cells = cells;
     a.ncells = ncells;
     a.X = X;
-    features_kernel<<<blocks_for(ncells * KP), 256, 0, s>>>(a);
+    features_kernel<<<blocks_for(ncells * (KP / 8)), 256, 0, s>>>(a);
     return hipGetLastError();
 }
 
@@ -1260,7 +1283,7 @@ hipError_t launch_mlp_backward(const uint16_t* X, const uint16_t* H1, const uint
     if (e != hipSuccess) return e;
     const int nb = bwd_grid(m);
     mlp_backward<<<nb, 256, BWD_LDS, s>>>(X, H1, H2, Z1, Z2, dY, m, wpack, (float*)ws);
-    reduce_partials<<<blocks_for(NPARAM), 256, 0, s>>>((const float*)ws, nb, NPARAM, grad);
+    reduce_partials<<<(NPARAM + 63) / 64, 256, 0, s>>>((const float*)ws, nb, NPARAM, grad);
     return hipGetLastError();
 }
 

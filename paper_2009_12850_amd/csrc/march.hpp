@@ -216,7 +216,15 @@ struct TileJob {
 // Options of the fused step (FP64 STEP only): OPT_DYN adds the other dynamics
 // source terms (Coriolis, buoyancy of scalar 0) to the momentum; OPT_SPW
 // advects the scalars with the centred (PW) flux form instead of TVD.
-enum { OPT_DYN = 1, OPT_SPW = 2 };
+// OPT_WORK (momentum source terms only, TEND) evaluates the PW arithmetic
+// a.work times on the same values (the work-scaled experiment).
+enum { OPT_DYN = 1, OPT_SPW = 2, OPT_WORK = 4 };
+
+// Makes x opaque to the optimiser and orders it after `dep` (an empty asm).
+template <typename T>
+__device__ __forceinline__ void chain(T& x, T dep) {
+    asm volatile("" : "+v"(x) : "v"(dep));
+}
 
 template <typename Ts, typename T, int MODE, bool PW, int NS, bool BUD, int NCH, int OPT>
 __device__ __forceinline__ void march_tile(const AdvArgs& a, const TileJob& tj,
@@ -225,7 +233,9 @@ __device__ __forceinline__ void march_tile(const AdvArgs& a, const TileJob& tj,
     constexpr bool STEP64 = MODE == STEP && std::is_same<T, double>::value;
     constexpr bool DYN = (OPT & OPT_DYN) != 0;
     constexpr bool SPW = (OPT & OPT_SPW) != 0;
-    static_assert(OPT == 0 || STEP64, "options of the FP64 step only");
+    constexpr bool WORK = (OPT & OPT_WORK) != 0;
+    static_assert((OPT & ~OPT_WORK) == 0 || STEP64, "options of the FP64 step only");
+    static_assert(!WORK || (MODE == TEND && PW && NS == 0), "work repetitions: PW source terms");
     // scalar face flux: TVD, or the centred flux form when SPW
     auto sflux = [&](T a_, T pm, T p0, T p1, T p2, T cfac, T rfac, T mass) -> T {
         if constexpr (SPW) {
@@ -672,12 +682,30 @@ __device__ __forceinline__ void march_tile(const AdvArgs& a, const TileJob& tj,
             const T ws = w_i[ownv - CSZ], wn = w_i[ownv + CSZ];
             const T wt = w_i[ownv + 1], w_nb = w_i[ownv + CSZ - 1];
             const T w_eb = w_ip[ownv - 1];
-            const T su = pw_su<T>(um, uc, up, us, un, ub, ut, vs, v_es, vc, ve, wb, w_eb, wc, we,
-                                  L, r4dx, r4dy);
-            const T sv = pw_sv<T>(vw, vc, ve, vs, vn, vb, vt, um, u_nw, uc, un, wb, w_nb, wc, wn,
-                                  L, r4dx, r4dy);
-            const T swc = pw_sw<T>(uc, ut, um, u_wt, vc, vt, vs, v_st, wc, ww, we, ws, wn, wb, wt,
-                                   L, r2dx, r2dy);
+            T su = pw_su<T>(um, uc, up, us, un, ub, ut, vs, v_es, vc, ve, wb, w_eb, wc, we, L,
+                            r4dx, r4dy);
+            T sv = pw_sv<T>(vw, vc, ve, vs, vn, vb, vt, um, u_nw, uc, un, wb, w_nb, wc, wn, L,
+                            r4dx, r4dy);
+            T swc = pw_sw<T>(uc, ut, um, u_wt, vc, vt, vs, v_st, wc, ww, we, ws, wn, wb, wt, L,
+                             r2dx, r2dy);
+            if constexpr (WORK) {
+                // the same arithmetic again on the same values, every input of a
+                // repetition made to depend on the previous result, so nothing
+                // is merged or dropped and the result is that of one evaluation
+                T x[27] = {um, uc, up, us, un, ub, ut, vs, v_es, vc, ve, wb, w_eb, wc,
+                           we, vw, vn, vb, vt, u_nw, w_nb, wn, u_wt, v_st, ww, ws, wt};
+                for (int r = 1; r < a.work; r++) {
+                    const T dep = su + sv + swc;
+#pragma unroll
+                    for (int q = 0; q < 27; q++) chain(x[q], dep);
+                    su = pw_su<T>(x[0], x[1], x[2], x[3], x[4], x[5], x[6], x[7], x[8], x[9],
+                                  x[10], x[11], x[12], x[13], x[14], L, r4dx, r4dy);
+                    sv = pw_sv<T>(x[15], x[9], x[10], x[7], x[16], x[17], x[18], x[0], x[19],
+                                  x[1], x[4], x[11], x[20], x[13], x[21], L, r4dx, r4dy);
+                    swc = pw_sw<T>(x[1], x[6], x[0], x[22], x[9], x[18], x[7], x[23], x[13],
+                                   x[24], x[14], x[25], x[21], x[11], x[26], L, r2dx, r2dy);
+                }
+            }
             const T sw = k < nz - 1 ? swc : (T)0;
             if constexpr (MODE == TEND) {
                 bstore(plane_rsrc((To*)a.out[0] + gplane, wbytes), woff, (To)su);

@@ -36,6 +36,8 @@ struct AdvArgs {
     double fcor, ug, vg, gth, th0;
     // scalars advected with the centred flux form (monc_step_pw_scalars)
     int spw;
+    // repetitions of the PW arithmetic (the work-scaled experiment); 1 otherwise
+    int work;
 };
 
 // Raise a kernel's dynamic-LDS limit once per device: `done` holds one bit
@@ -127,10 +129,7 @@ hipError_t launch_mlp_loss(const float* Y4, int b, const int* cells, const doubl
 hipError_t launch_mlp_adam(float* params, float* m1, float* m2, const float* grad, int t,
                            double lr, double b1, double b2, double eps, uint16_t* wpack,
                            hipStream_t s);
-hipError_t launch_pw_scaled(int dtype, const void* u, const void* v, const void* w, void* su,
-                            void* sv, void* sw, int nx, int ny, int nz, double dx, double dy,
-                            const double* rdz, const double* rho, const double* rhon, int work,
-                            hipStream_t s);
+hipError_t launch_pw_scaled(int dtype, const AdvArgs& a, hipStream_t s);
 size_t correct_step_workspace_bytes(int nx, int ny, int nz);
 hipError_t launch_correct_step(double* const* in, double* const* tend, const float* gx,
                                const float* gy, double* const* out, int nx, int ny, int nz,

@@ -215,12 +215,29 @@ class Correction:
     def train_step(self, ser, n, rng, lr=1e-3):
         """One Adam step; returns the (device) loss before the update."""
         self._forward_loss(ser, n, rng, save=True)
+        self._backward_adam(lr)
+        return self.loss
+
+    def _backward_adam(self, lr):
         M.monc_mlp_backward(self.X, self.H1, self.H2, self.Z1, self.Z2, self.dY, 4 * self.B,
                             self.wpack, self.grad, self.ws_b)
         self.t += 1
         M.monc_mlp_adam(self.params, self.m1, self.m2, self.grad, self.t, lr, 0.9, 0.999, 1e-8,
                         self.wpack)
-        return self.loss
+
+    def device_step(self, ser, n, nterm, lr=1e-3):
+        """The device work of one training step on the cells already in
+        cx, cy, cells (features, forward, loss, backward, Adam): no host
+        sampling or copies, so it can be captured in a graph."""
+        B = self.B
+        c0, c1, td = ser.snaps[n], ser.snaps[n + 1], ser.tend[n]
+        M.monc_mlp_features(c0, self.norm, 0, self.cx, self.X.narrow(0, 0, 2 * B))
+        M.monc_mlp_features(c0, self.norm, 1, self.cy, self.X.narrow(0, 2 * B, 2 * B))
+        M.monc_mlp_forward(self.X, 4 * B, self.params, self.wpack, self.Y, self.H1, self.H2,
+                           self.Z1, self.Z2)
+        M.monc_mlp_loss(self.Y, B, self.cells, c0, c1, td, ser.dtc, self.scale, ser.prof_c,
+                        1.0 / nterm, self.dY, self.loss, self.ws_l)
+        self._backward_adam(lr)
 
     def evaluate_loss(self, ser, n, rng):
         """Loss on B cells without updating the weights."""
@@ -404,6 +421,23 @@ def run_experiment(nx=512, ny=512, nz=128, seeds=range(2000, 2016), n_train=12, 
     treps = 50
     t_step = _event_ms(lambda: [probe.train_step(train_set[0], n % len(train_set[0].tend), prng)
                                 for n in range(treps)]) / treps
+    # the same step's device work alone: captured once in a graph and replayed
+    # (the host samples no cells and issues no launches in between)
+    t_graph = None
+    try:
+        ser0 = train_set[0]
+        nterm = 4 * batch
+        probe.device_step(ser0, 0, nterm)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            probe.device_step(ser0, 0, nterm)
+        graph.replay()
+        torch.cuda.synchronize()
+        t_graph = _event_ms(lambda: [graph.replay() for _ in range(treps)]) / treps
+        del graph
+    except Exception as exc:  # graph capture unavailable: report the eager time only
+        say(f"  training-step graph not captured: {exc}")
     del probe
     nsteps = min(coarse_steps, len(held[0].tend))
     err_plain, err_learned, fb = [], [], [0, 0, 0]
@@ -449,7 +483,9 @@ def run_experiment(nx=512, ny=512, nz=128, seeds=range(2000, 2016), n_train=12, 
         # per field: the plain coarse error over the learned one (> 1: the
         # correction helps)
         "gain": [p / l for p, l in zip(mean(err_plain), mean(err_learned))],
-        "train_step_ms": t_step,
+        # one training step as issued from Python (host sampling, a copy of
+        # the cell lists, ten launches) and its device work replayed as a graph
+        "train_step_ms": t_step, "train_step_graph_ms": t_graph,
         "fallback_nonfinite": fb[0], "fallback_growth": fb[1], "theta_faces_clamped": fb[2],
         "t_fine_ms": t_fine, "t_coarse_plain_ms": t_plain, "t_coarse_learned_ms": t_learned,
         "speedup_vs_fine": t_fine / t_learned,
