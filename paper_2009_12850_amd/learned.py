@@ -187,6 +187,10 @@ class Correction:
         j = rng.integers(0, NY, B)
         k = rng.integers(0, NZ, B)
         c = (i * NY + j) * NZ + k
+        # in memory order, so that neighbouring rows' feature gathers share
+        # cache lines (the loss is a mean over the cells: order is free)
+        order = np.argsort(c, kind="stable")
+        i, j, k, c = i[order], j[order], k[order], c[order]
         xm = (((i - 1) % NX) * NY + j) * NZ + k
         ym = (i * NY + (j - 1) % NY) * NZ + k
         n_terms = 4 * B - int(np.sum(k == NZ - 1))  # w on the lid is masked
