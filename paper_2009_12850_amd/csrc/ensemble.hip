@@ -2,14 +2,16 @@
 //
 // Every member advances with the mixed-precision step (FP32 source terms from
 // the FP64 state, FP64 accumulation; the single-precision advection of
-// Sec. 4.1).  One persistent launch per column-height class walks a work list
-// of (member, tile) items sorted by cost; N steps are captured once into a
-// hipGraph and replayed with one hipGraphLaunch.  The segment length and the
-// persistent grid size of each class are chosen by timing candidates on the
-// plan's own members (cached in a small JSON file keyed by device, class,
-// precision and scalar count).  With budgets attached, every work item also
-// leaves one row of FP64 budget partials and a small pass sums each member's
-// rows in a fixed order (the checks of every step, Sec. 3.1).
+// Sec. 4.1).  One persistent launch per step takes (member, tile) work items
+// from a list sorted by decreasing cost through an atomic cursor, whatever
+// the member's column height (a member of up to 64 levels runs the one-chunk
+// march, a taller one the two-chunk march, both compiled into the kernel);
+// N steps are captured once into a hipGraph and replayed with one
+// hipGraphLaunch.  The segment length and the persistent grid size are chosen
+// by timing candidates on the plan's own members (cached in a small JSON file
+// keyed by device, precision and scalar count).  With budgets attached, every
+// work item also leaves one row of FP64 budget partials and a small pass sums
+// each member's rows in a fixed order (the checks of every step, Sec. 3.1).
 #include <math.h>
 #include <stdio.h>
 #include <stdlib.h>
@@ -31,14 +33,31 @@ struct EnsMember {
     AdvArgs a[2];  // a[p]: reads state[p], writes state[1-p]
     int ti;        // planes per segment
     int njt;       // tiles along y
+    int nch;       // 64-level chunks per column (1 or 2)
 };
 
-template <int NCH, int NS, bool BUD>
+template <int NS>
+constexpr size_t ens_lds_bytes() {
+    return std::max(march_lds_bytes<double, float, NS, 1>(), march_lds_bytes<double, float, NS, 2>());
+}
+
+// Persistent step of every member.  cursor[0] hands out work items, cursor[1]
+// counts the workgroups that are done: the last one resets both, so the next
+// launch (eager, timed or replayed from a graph) starts from zero.  Every
+// workgroup leaves the loop once the cursor has passed the list, so all of
+// them finish; the results do not depend on which workgroup takes an item.
+template <int NS, bool BUD>
 __global__ void __launch_bounds__(ENS_WAVES * 64) __attribute__((amdgpu_waves_per_eu(2)))
     ensemble_step(const EnsMember* __restrict__ mem, const int4* __restrict__ items, int nitems,
-                  int parity, double* __restrict__ partials) {
+                  int parity, double* __restrict__ partials, int* __restrict__ cursor) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    __shared__ int next;
+    for (;;) {
+        if (threadIdx.x == 0) next = atomicAdd(cursor, 1);
+        __syncthreads();
+        const int it = next;
+        __syncthreads();  // every thread has read `next` before it is written again
+        if (it >= nitems) break;
         const int4 w = items[it];
         const EnsMember* M = mem + w.x;
         TileJob t;
@@ -48,8 +67,18 @@ __global__ void __launch_bounds__(ENS_WAVES * 64) __attribute__((amdgpu_waves_pe
         t.seg = w.z;
         t.partial_row = BUD ? partials + (size_t)it * NB : nullptr;
         t.first_pass = 1;
-        march_tile<double, float, STEP, true, NS, BUD, NCH, 0>(M->a[parity], t, smem_raw);
+        if (M->nch == 1)
+            march_tile<double, float, STEP, true, NS, BUD, 1, 0>(M->a[parity], t, smem_raw);
+        else
+            march_tile<double, float, STEP, true, NS, BUD, 2, 0>(M->a[parity], t, smem_raw);
         __syncthreads();  // the LDS is reused by the next item
+    }
+    if (threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(cursor + 1, 1) == (int)gridDim.x - 1) {
+            atomicExch(cursor, 0);
+            atomicExch(cursor + 1, 0);
+        }
     }
 }
 
@@ -69,60 +98,55 @@ __global__ void __launch_bounds__(64) ensemble_budget_final(const double* __rest
     out[(size_t)m * NB + q] = v;
 }
 
-template <int NCH, int NS, bool BUD>
-hipError_t launch_class(const EnsMember* mem, const int4* items, int nitems, int grid, int parity,
-                        double* partials, hipStream_t s) {
-    constexpr size_t lds = march_lds_bytes<double, float, NS, NCH>();
-    ensemble_step<NCH, NS, BUD><<<grid, ENS_WAVES * 64, lds, s>>>(mem, items, nitems, parity,
-                                                                  partials);
-    return hipGetLastError();
-}
-
-template <int NCH, int NS, bool BUD>
+template <int NS, bool BUD>
 hipError_t set_attr_one() {
-    return hipFuncSetAttribute((const void*)ensemble_step<NCH, NS, BUD>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)march_lds_bytes<double, float, NS, NCH>());
+    return hipFuncSetAttribute((const void*)ensemble_step<NS, BUD>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)ens_lds_bytes<NS>());
 }
 
-template <int NCH, bool BUD>
-hipError_t set_attrs_nch() {
-    hipError_t e = set_attr_one<NCH, 0, BUD>();
-    if (e == hipSuccess) e = set_attr_one<NCH, 1, BUD>();
-    if (e == hipSuccess) e = set_attr_one<NCH, 2, BUD>();
-    if (e == hipSuccess) e = set_attr_one<NCH, 3, BUD>();
+template <bool BUD>
+hipError_t set_attrs_bud() {
+    hipError_t e = set_attr_one<0, BUD>();
+    if (e == hipSuccess) e = set_attr_one<1, BUD>();
+    if (e == hipSuccess) e = set_attr_one<2, BUD>();
+    if (e == hipSuccess) e = set_attr_one<3, BUD>();
     return e;
 }
 
 hipError_t set_attrs() {
-    hipError_t e = set_attrs_nch<1, false>();
-    if (e == hipSuccess) e = set_attrs_nch<2, false>();
-    if (e == hipSuccess) e = set_attrs_nch<1, true>();
-    if (e == hipSuccess) e = set_attrs_nch<2, true>();
+    hipError_t e = set_attrs_bud<false>();
+    if (e == hipSuccess) e = set_attrs_bud<true>();
     return e;
 }
 
-template <int NCH, bool BUD>
-hipError_t launch_ns(int ns, const EnsMember* mem, const int4* items, int nitems, int grid,
-                     int parity, double* partials, hipStream_t s) {
-    switch (ns) {
-        case 0: return launch_class<NCH, 0, BUD>(mem, items, nitems, grid, parity, partials, s);
-        case 1: return launch_class<NCH, 1, BUD>(mem, items, nitems, grid, parity, partials, s);
-        case 2: return launch_class<NCH, 2, BUD>(mem, items, nitems, grid, parity, partials, s);
-        case 3: return launch_class<NCH, 3, BUD>(mem, items, nitems, grid, parity, partials, s);
-    }
-    return hipErrorInvalidValue;
+template <int NS, bool BUD>
+hipError_t launch_ns(const EnsMember* mem, const int4* items, int nitems, int grid, int parity,
+                     double* partials, int* cursor, hipStream_t s) {
+    ensemble_step<NS, BUD><<<grid, ENS_WAVES * 64, ens_lds_bytes<NS>(), s>>>(
+        mem, items, nitems, parity, partials, cursor);
+    return hipGetLastError();
 }
 
-// partials: the class's first budget row, or nullptr (no budgets)
-hipError_t launch_any(int nch, int ns, const EnsMember* mem, const int4* items, int nitems,
-                      int grid, int parity, double* partials, hipStream_t s) {
+// partials: the first budget row, or nullptr (no budgets)
+hipError_t launch_any(int ns, const EnsMember* mem, const int4* items, int nitems, int grid,
+                      int parity, double* partials, int* cursor, hipStream_t s) {
     if (nitems <= 0) return hipSuccess;
-    if (partials)
-        return nch == 1 ? launch_ns<1, true>(ns, mem, items, nitems, grid, parity, partials, s)
-                        : launch_ns<2, true>(ns, mem, items, nitems, grid, parity, partials, s);
-    return nch == 1 ? launch_ns<1, false>(ns, mem, items, nitems, grid, parity, nullptr, s)
-                    : launch_ns<2, false>(ns, mem, items, nitems, grid, parity, nullptr, s);
+    if (partials) {
+        switch (ns) {
+            case 0: return launch_ns<0, true>(mem, items, nitems, grid, parity, partials, cursor, s);
+            case 1: return launch_ns<1, true>(mem, items, nitems, grid, parity, partials, cursor, s);
+            case 2: return launch_ns<2, true>(mem, items, nitems, grid, parity, partials, cursor, s);
+            case 3: return launch_ns<3, true>(mem, items, nitems, grid, parity, partials, cursor, s);
+        }
+    } else {
+        switch (ns) {
+            case 0: return launch_ns<0, false>(mem, items, nitems, grid, parity, nullptr, cursor, s);
+            case 1: return launch_ns<1, false>(mem, items, nitems, grid, parity, nullptr, cursor, s);
+            case 2: return launch_ns<2, false>(mem, items, nitems, grid, parity, nullptr, cursor, s);
+            case 3: return launch_ns<3, false>(mem, items, nitems, grid, parity, nullptr, cursor, s);
+        }
+    }
+    return hipErrorInvalidValue;
 }
 
 }  // namespace
@@ -135,19 +159,19 @@ struct EnsemblePlan {
     std::vector<monc_member> members;
     std::vector<EnsMember> hmem;
     EnsMember* d_mem = nullptr;
-    // per class (0: nz <= 64, 1: 64 < nz <= 128)
-    int4* d_items[2] = {nullptr, nullptr};
-    int nitems[2] = {0, 0};
-    int grid[2] = {0, 0};
-    int ti[2] = {32, 32};
+    int4* d_items = nullptr;
+    int nitems = 0;
+    int nclass[2] = {0, 0};  // items of one-chunk and two-chunk members
+    int grid = 0;
+    int ti = 32;
+    int* d_cursor = nullptr;  // [2]: work cursor, finished workgroups
     hipStream_t cap = nullptr;
     hipGraphExec_t exec[2] = {nullptr, nullptr};  // by starting parity
     int exec_steps[2] = {0, 0};
     int parity = 0;
-    std::vector<int4> hitems[2];  // the uploaded work lists (host copies)
+    std::vector<int4> hitems;  // the uploaded work list (host copy)
     // budgets (attached by the caller): slots of n x NB doubles, one per step
-    // of a run; one partial row per work item (class 0's rows first) and each
-    // member's row list (CSR)
+    // of a run; one partial row per work item and each member's row list (CSR)
     double* budgets = nullptr;
     int nslots = 0;
     double* d_partials = nullptr;
@@ -159,23 +183,20 @@ namespace {
 
 int tj_of(int nch) { return ENS_WAVES / nch; }
 
-// Work list of one class for a segment length: every (member, tile) item,
-// sorted by decreasing cost (planes x levels x columns) so that the
-// round-robin walk of the persistent workgroups balances.
-std::vector<int4> build_items(const EnsemblePlan& P, int cls, int ti) {
+// The work list for a segment length: every (member, tile) item, sorted by
+// decreasing cost (planes x levels x columns), so that the workgroups taking
+// items in order from the cursor finish close together.
+std::vector<int4> build_items(const EnsemblePlan& P, int ti) {
     std::vector<int4> items;
     for (int m = 0; m < P.n; m++) {
         const monc_member& M = P.members[m];
         const int nch = M.nz <= 64 ? 1 : 2;
-        if (nch - 1 != cls) continue;
         const int tj = tj_of(nch);
         const int njt = (M.ny + tj - 1) / tj;
         const int nseg = (M.nx + ti - 1) / ti;
         for (int s = 0; s < nseg; s++) {
             const int planes = std::min(ti, M.nx - s * ti);
-            const int cols = tj;
-            for (int t = 0; t < njt; t++)
-                items.push_back(make_int4(m, t, s, planes * cols * M.nz));
+            for (int t = 0; t < njt; t++) items.push_back(make_int4(m, t, s, planes * tj * M.nz));
         }
     }
     std::stable_sort(items.begin(), items.end(),
@@ -183,27 +204,25 @@ std::vector<int4> build_items(const EnsemblePlan& P, int cls, int ti) {
     return items;
 }
 
-hipError_t upload_class(EnsemblePlan& P, int cls, int ti) {
+hipError_t upload_items(EnsemblePlan& P, int ti) {
     hipError_t e0 = hipStreamSynchronize(P.cap);  // the old list may still be in use
     if (e0 != hipSuccess) return e0;
-    std::vector<int4> items = build_items(P, cls, ti);
-    if (P.d_items[cls]) {
-        const hipError_t ef = hipFree(P.d_items[cls]);
-        P.d_items[cls] = nullptr;
+    std::vector<int4> items = build_items(P, ti);
+    if (P.d_items) {
+        const hipError_t ef = hipFree(P.d_items);
+        P.d_items = nullptr;
         if (ef != hipSuccess) return ef;
     }
-    P.nitems[cls] = (int)items.size();
-    P.hitems[cls] = items;
-    P.ti[cls] = ti;
-    for (int m = 0; m < P.n; m++) {
-        const int nch = P.members[m].nz <= 64 ? 1 : 2;
-        if (nch - 1 == cls) P.hmem[m].ti = ti;
-    }
+    P.nitems = (int)items.size();
+    P.nclass[0] = P.nclass[1] = 0;
+    for (const int4& it : items) P.nclass[P.members[it.x].nz <= 64 ? 0 : 1]++;
+    P.hitems = items;
+    P.ti = ti;
+    for (int m = 0; m < P.n; m++) P.hmem[m].ti = ti;
     if (items.empty()) return hipSuccess;
-    hipError_t e = hipMalloc(&P.d_items[cls], items.size() * sizeof(int4));
+    hipError_t e = hipMalloc(&P.d_items, items.size() * sizeof(int4));
     if (e != hipSuccess) return e;
-    return hipMemcpy(P.d_items[cls], items.data(), items.size() * sizeof(int4),
-                     hipMemcpyHostToDevice);
+    return hipMemcpy(P.d_items, items.data(), items.size() * sizeof(int4), hipMemcpyHostToDevice);
 }
 
 hipError_t upload_members(EnsemblePlan& P) {
@@ -215,12 +234,9 @@ hipError_t upload_members(EnsemblePlan& P) {
 // input state go to slot `slot`.
 hipError_t launch_step(EnsemblePlan& P, int parity, int slot, hipStream_t s) {
     const bool bud = P.budgets != nullptr;
-    for (int c = 0; c < 2; c++) {
-        double* rows = bud ? P.d_partials + (size_t)(c == 0 ? 0 : P.nitems[0]) * NB : nullptr;
-        hipError_t e = launch_any(c + 1, P.nscal, P.d_mem, P.d_items[c], P.nitems[c], P.grid[c],
-                                  parity, rows, s);
-        if (e != hipSuccess) return e;
-    }
+    hipError_t e = launch_any(P.nscal, P.d_mem, P.d_items, P.nitems, P.grid, parity,
+                              bud ? P.d_partials : nullptr, P.d_cursor, s);
+    if (e != hipSuccess) return e;
     if (bud) {
         ensemble_budget_final<<<P.n, 64, 0, s>>>(P.d_partials, P.d_rowoff, P.d_rows,
                                                  P.budgets + (size_t)slot * P.n * NB);
@@ -229,22 +245,17 @@ hipError_t launch_step(EnsemblePlan& P, int parity, int slot, hipStream_t s) {
     return hipSuccess;
 }
 
-// Row lists of the members from the current work lists: member m's rows are
-// the indices of its items (class 0 first, then class 1 offset by class 0's
-// count), in list order.
+// Row lists of the members from the current work list: member m's rows are
+// the indices of its items, in list order.
 hipError_t build_budget_rows(EnsemblePlan& P) {
     std::vector<std::vector<int>> per(P.n);
-    for (int c = 0; c < 2; c++) {
-        const int base = c == 0 ? 0 : P.nitems[0];
-        for (int it = 0; it < P.nitems[c]; it++) per[P.hitems[c][it].x].push_back(base + it);
-    }
+    for (int it = 0; it < P.nitems; it++) per[P.hitems[it].x].push_back(it);
     std::vector<int> off(P.n + 1, 0), rows;
     for (int m = 0; m < P.n; m++) {
         off[m + 1] = off[m] + (int)per[m].size();
         rows.insert(rows.end(), per[m].begin(), per[m].end());
     }
-    const size_t nrows = (size_t)P.nitems[0] + P.nitems[1];
-    hipError_t e = hipMalloc(&P.d_partials, std::max<size_t>(nrows, 1) * NB * sizeof(double));
+    hipError_t e = hipMalloc(&P.d_partials, std::max<size_t>(P.nitems, 1) * NB * sizeof(double));
     if (e == hipSuccess) e = hipMalloc(&P.d_rowoff, off.size() * sizeof(int));
     if (e == hipSuccess) e = hipMalloc(&P.d_rows, std::max<size_t>(rows.size(), 1) * sizeof(int));
     if (e == hipSuccess)
@@ -269,14 +280,13 @@ hipError_t free_budget_rows(EnsemblePlan& P) {
 }
 
 // --- tiny JSON cache: {"key": [ti, grid], ...} -------------------------------
-std::string cache_key(int cls, int nscal) {
+std::string cache_key(int nscal) {
     hipDeviceProp_t prop;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
-        return "unknown-device:" + std::to_string(cls) + ":" + std::to_string(nscal);
+        return "unknown-device:" + std::to_string(nscal);
     char buf[256];
-    snprintf(buf, sizeof buf, "%s|nz%s|fp32-tend-fp64-state|nscal%d", prop.gcnArchName,
-             cls == 0 ? "<=64" : "<=128", nscal);
+    snprintf(buf, sizeof buf, "%s|fp32-tend-fp64-state|nscal%d", prop.gcnArchName, nscal);
     return buf;
 }
 
@@ -322,17 +332,17 @@ void cache_write(const char* path, const std::string& key, int ti, int grid) {
     fclose(f);
 }
 
-// Time one step of one class (average of reps) for the current items/grid.
-float time_class(EnsemblePlan& P, int cls, int reps) {
+// Time one step (average of reps) for the current list and grid.  Timing
+// writes only the members' "next" buffers.
+float time_step(EnsemblePlan& P, int reps) {
     hipEvent_t a, b;
     hipEventCreate(&a);
     hipEventCreate(&b);
-    launch_any(cls + 1, P.nscal, P.d_mem, P.d_items[cls], P.nitems[cls], P.grid[cls], P.parity,
-               nullptr, P.cap);
+    launch_any(P.nscal, P.d_mem, P.d_items, P.nitems, P.grid, P.parity, nullptr, P.d_cursor, P.cap);
     hipEventRecord(a, P.cap);
     for (int r = 0; r < reps; r++)
-        launch_any(cls + 1, P.nscal, P.d_mem, P.d_items[cls], P.nitems[cls], P.grid[cls],
-                   P.parity, nullptr, P.cap);
+        launch_any(P.nscal, P.d_mem, P.d_items, P.nitems, P.grid, P.parity, nullptr, P.d_cursor,
+                   P.cap);
     hipEventRecord(b, P.cap);
     hipEventSynchronize(b);
     float ms = 0;
@@ -350,26 +360,25 @@ int num_cus() {
 }
 
 // The autotuner: segment length x persistent grid size, timed on the plan's
-// own members.  Candidates whose work list is shorter than the grid are
-// clipped.  Timing writes only the members' "next" buffers.
-hipError_t tune_class(EnsemblePlan& P, int cls, const char* cache, bool tune) {
+// own members.  Grids larger than the work list are clipped.
+hipError_t tune(EnsemblePlan& P, const char* cache, bool do_tune) {
     const int cus = num_cus();
-    int best_ti = 32, best_grid = 2 * cus;
-    const std::string key = cache_key(cls, P.nscal);
-    bool have = cache_read(cache, key, &best_ti, &best_grid);
-    if (!have && tune) {
+    int best_ti = 32, best_grid = cus;
+    const std::string key = cache_key(P.nscal);
+    const bool have = cache_read(cache, key, &best_ti, &best_grid);
+    if (!have && do_tune) {
         float best = 1e30f;
         const int tis[] = {16, 32, 64, 128};
         const int grids[] = {cus, 2 * cus, 4 * cus};
         for (int ti : tis) {
-            hipError_t e = upload_class(P, cls, ti);
+            hipError_t e = upload_items(P, ti);
             if (e != hipSuccess) return e;
             e = upload_members(P);
             if (e != hipSuccess) return e;
-            if (P.nitems[cls] == 0) return hipSuccess;
+            if (P.nitems == 0) return hipSuccess;
             for (int g : grids) {
-                P.grid[cls] = std::min(g, P.nitems[cls]);
-                const float ms = time_class(P, cls, 3);
+                P.grid = std::min(g, P.nitems);
+                const float ms = time_step(P, 3);
                 if (ms < best) {
                     best = ms;
                     best_ti = ti;
@@ -379,16 +388,16 @@ hipError_t tune_class(EnsemblePlan& P, int cls, const char* cache, bool tune) {
         }
         cache_write(cache, key, best_ti, best_grid);
     }
-    hipError_t e = upload_class(P, cls, best_ti);
+    hipError_t e = upload_items(P, best_ti);
     if (e != hipSuccess) return e;
-    P.grid[cls] = std::max(1, std::min(best_grid, P.nitems[cls]));
+    P.grid = std::max(1, std::min(best_grid, P.nitems));
     return upload_members(P);
 }
 
 }  // namespace
 
 int ensemble_create(const monc_member* members, int n, int nscal, const char* tune_cache,
-                    int tune, EnsemblePlan** out, std::string* err) {
+                    int do_tune, EnsemblePlan** out, std::string* err) {
     EnsemblePlan* P = new EnsemblePlan();
     P->n = n;
     P->nscal = nscal;
@@ -418,15 +427,22 @@ int ensemble_create(const monc_member* members, int n, int nscal, const char* tu
             a.rho = M.rho;
             a.rhon = M.rhon;
             a.partials = nullptr;
+            a.dyn = 0;
+            a.fcor = a.ug = a.vg = a.gth = a.th0 = 0.0;
+            a.spw = 0;
+            a.work = 1;
         }
         const int nch = M.nz <= 64 ? 1 : 2;
+        P->hmem[m].nch = nch;
         P->hmem[m].njt = (M.ny + tj_of(nch) - 1) / tj_of(nch);
         P->hmem[m].ti = 32;
     }
     hipError_t e = set_attrs();
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&P->cap, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipMalloc(&P->d_mem, sizeof(EnsMember) * n);
-    for (int c = 0; c < 2 && e == hipSuccess; c++) e = tune_class(*P, c, tune_cache, tune != 0);
+    if (e == hipSuccess) e = hipMalloc(&P->d_cursor, 2 * sizeof(int));
+    if (e == hipSuccess) e = hipMemset(P->d_cursor, 0, 2 * sizeof(int));
+    if (e == hipSuccess) e = tune(*P, tune_cache, do_tune != 0);
     if (e == hipSuccess) e = hipStreamSynchronize(P->cap);
     if (e != hipSuccess) {
         *err = hipGetErrorString(e);
@@ -507,11 +523,13 @@ int ensemble_run(EnsemblePlan* P, int nsteps, hipStream_t s, std::string* err) {
     return MONC_OK;
 }
 
+// ti, grid, nitems: [2] each; the single list's segment length and grid in
+// both entries, the items of one-chunk and two-chunk members in nitems.
 void ensemble_info(const EnsemblePlan* P, int* ti, int* grid, int* nitems) {
     for (int c = 0; c < 2; c++) {
-        if (ti) ti[c] = P->ti[c];
-        if (grid) grid[c] = P->grid[c];
-        if (nitems) nitems[c] = P->nitems[c];
+        if (ti) ti[c] = P->ti;
+        if (grid) grid[c] = P->grid;
+        if (nitems) nitems[c] = P->nclass[c];
     }
 }
 
@@ -519,11 +537,11 @@ int ensemble_parity(const EnsemblePlan* P) { return P->parity; }
 
 void ensemble_destroy(EnsemblePlan* P) {
     if (!P) return;
-    for (int c = 0; c < 2; c++) {
+    for (int c = 0; c < 2; c++)
         if (P->exec[c]) hipGraphExecDestroy(P->exec[c]);
-        if (P->d_items[c]) hipFree(P->d_items[c]);
-    }
+    if (P->d_items) hipFree(P->d_items);
     if (P->d_mem) hipFree(P->d_mem);
+    if (P->d_cursor) hipFree(P->d_cursor);
     free_budget_rows(*P);
     if (P->cap) hipStreamDestroy(P->cap);
     delete P;

@@ -1,7 +1,8 @@
 """GPU tests of the batched ensemble: members of uneven size advanced by the
 persistent work-list kernel give bitwise the result of advancing each member
 alone with monc_step_mixed; the captured graph replays bitwise what eager
-launches compute; the autotuner writes and then reuses its cache."""
+launches compute; the autotuner writes and then reuses its cache; every
+member against the FP64 oracle with its budgets."""
 import json
 import os
 import sys
@@ -114,11 +115,13 @@ def test_autotuner_writes_and_reuses_cache():
         info = ens.info()
         ens.close()
         data = json.load(open(path))
-        assert len(data) == 2
+        # one entry: the single work list of both column-height classes
+        assert len(data) == 1
         for key, (ti, grid) in data.items():
-            assert "gfx" in key and ti in (16, 32, 64, 128) and grid > 0
+            assert "gfx" in key and "nscal2" in key and ti in (16, 32, 64, 128) and grid > 0
+        assert info["nitems"][0] > 0 and info["nitems"][1] > 0  # both classes in the list
         ens2 = M.Ensemble(members, 2, tune_cache=path, tune=True)
-        assert ens2.info()["ti"] == info["ti"]
+        assert ens2.info()["ti"] == info["ti"] and ens2.info()["grid"] == info["grid"]
         ens2.close()
 
 
