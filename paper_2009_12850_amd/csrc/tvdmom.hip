@@ -136,6 +136,21 @@ __global__ void __launch_bounds__(64 * TM_TJ) tvdmom_kernel(TvdMomArgs A) {
     const long oj = oy(jc), ojm1 = oy(jc - 1), ojm2 = oy(jc - 2), ojp1 = oy(jc + 1),
                ojp2 = oy(jc + 2);
 
+    // A value of this column (or of a neighbouring one) at level k - d or
+    // k + d of the same plane: the lane d below or above holds it; the lanes
+    // at the chunk's edge load it.  Where the level does not exist (has =
+    // false) the value is 0, as the direct loads gave.
+    auto below = [&](double x, const double* F, long col, int d, bool has) -> double {
+        double y = __shfl_up(x, d, 64);
+        if (lane < d && has) y = F[col + kc - d];
+        return has ? y : 0.0;
+    };
+    auto above = [&](double x, const double* F, long col, int d, bool has) -> double {
+        double y = __shfl_down(x, d, 64);
+        if (lane >= 64 - d && has) y = F[col + kc + d];
+        return has ? y : 0.0;
+    };
+
     // x-window of the own column: planes i-1, i, i+1, i+2; the plane after
     // is prefetched one step ahead
     double xu[4], xv[4], xw[4];
@@ -208,16 +223,16 @@ __global__ void __launch_bounds__(64 * TM_TJ) tvdmom_kernel(TvdMomArgs A) {
         const double wym1 = wlev ? W[p0 + ojm1 + kc] : 0.0;
         const double wyp1 = wlev ? W[p0 + ojp1 + kc] : 0.0;
         const double wyp2 = wlev ? W[p0 + ojp2 + kc] : 0.0;
-        // z-stencils of the own column at plane i
-        const double uzm2 = zm2 ? U[c00 + kc - 2] : 0.0, uzm1 = zm1 ? U[c00 + kc - 1] : 0.0;
-        const double uzp1 = zp1 ? U[c00 + kc + 1] : 0.0, uzp2 = zp2 ? U[c00 + kc + 2] : 0.0;
-        const double vzm2 = zm2 ? V[c00 + kc - 2] : 0.0, vzm1 = zm1 ? V[c00 + kc - 1] : 0.0;
-        const double vzp1 = zp1 ? V[c00 + kc + 1] : 0.0, vzp2 = zp2 ? V[c00 + kc + 2] : 0.0;
-        const double wzm1 = zm1 ? W[c00 + kc - 1] : 0.0, wzm2 = zm2 ? W[c00 + kc - 2] : 0.0;
-        const double wzp1 = kc + 1 <= nz - 2 ? W[c00 + kc + 1] : 0.0;
-        const double wzp2 = kc + 2 <= nz - 2 ? W[c00 + kc + 2] : 0.0;
-        const double w_xp1zm1 = zm1 ? W[pp1 + oj + kc - 1] : 0.0;
-        const double w_yp1zm1 = zm1 ? W[p0 + ojp1 + kc - 1] : 0.0;
+        // z-stencils of the own column at plane i, from the neighbouring lanes
+        const double uzm2 = below(u0, U, c00, 2, zm2), uzm1 = below(u0, U, c00, 1, zm1);
+        const double uzp1 = above(u0, U, c00, 1, zp1), uzp2 = above(u0, U, c00, 2, zp2);
+        const double vzm2 = below(v0, V, c00, 2, zm2), vzm1 = below(v0, V, c00, 1, zm1);
+        const double vzp1 = above(v0, V, c00, 1, zp1), vzp2 = above(v0, V, c00, 2, zp2);
+        const double wzm1 = below(w0, W, c00, 1, zm1), wzm2 = below(w0, W, c00, 2, zm2);
+        const double wzp1 = above(w0, W, c00, 1, kc + 1 <= nz - 2);
+        const double wzp2 = above(w0, W, c00, 2, kc + 2 <= nz - 2);
+        const double w_xp1zm1 = below(xw[2], W, pp1 + oj, 1, zm1);
+        const double w_yp1zm1 = below(wyp1, W, p0 + ojp1, 1, zm1);
 
         // ---- east faces (the next plane's west faces) ----
         const double a_ue = 0.5 * (u0 + xu[2]), a_ve = 0.5 * (u0 + uyp1);
@@ -241,7 +256,7 @@ __global__ void __launch_bounds__(64 * TM_TJ) tvdmom_kernel(TvdMomArgs A) {
             const double uym2 = U[p0 + ojm2 + kc], vym2 = V[p0 + ojm2 + kc];
             const double wym2 = wlev ? W[p0 + ojm2 + kc] : 0.0;
             const double v_xp1ym1 = V[pp1 + ojm1 + kc];
-            const double v_ym1zp1 = zp1 ? V[p0 + ojm1 + kc + 1] : 0.0;
+            const double v_ym1zp1 = above(vym1, V, p0 + ojm1, 1, zp1);
             const double a_us = 0.5 * (vym1 + v_xp1ym1), a_vs = 0.5 * (vym1 + v0);
             const double m_ws = alpha * vym1 + beta * v_ym1zp1;
             fs_u = tvd_flux(a_us, uym2, uym1, u0, uyp1, cdy, rfy, rhon_k);
