@@ -361,6 +361,30 @@ int monc_mlp_loss(const float *Y4, int b, const int *cells, const double *const 
 int monc_mlp_adam(float *params, float *m1, float *m2, const float *grad, int t, double lr,
                   double beta1, double beta2, double eps, uint16_t *wpack,
                   monc_stream_t stream);
+/* One training step of the correction, fused.  For b sampled cells (device
+ * linear indices `cells`, as for monc_mlp_loss), one launch computes the
+ * features of the four face rows of every cell -- x(i), x(i-1), y(j), y(j-1),
+ * the i-1 and j-1 neighbours taken with the periodic wrap -- the forward pass,
+ * the loss and dY, and the parameter gradient, keeping every activation on
+ * chip; a second launch sums the gradient in a fixed order into
+ * grad[MONC_MLP_NPARAM], takes one Adam step (t >= 1) on the FP32 parameters,
+ * writes their BF16 pack and loss[0] (the loss before the update).  Each row's
+ * features, activations, loss terms and dY are the operations of
+ * monc_mlp_features, monc_mlp_forward and monc_mlp_loss on the same numbers;
+ * the gradient is monc_mlp_backward's up to the order of the sum over rows.  A
+ * listed cell outside the grid contributes nothing.  c0, c1, tend: host arrays
+ * of 4 device pointers (u v w theta, padded coarse fields); norm: host [8]
+ * (mean, std per field); scale: host [4]; rho, rhon: device [nz]; wpack
+ * 16-byte aligned; workspace >= monc_mlp_train_workspace_bytes(b) bytes of
+ * device memory.  Deterministic for a given b. */
+size_t monc_mlp_train_workspace_bytes(int b);
+int monc_mlp_train_step(const double *const *c0, const double *const *c1,
+                        const double *const *tend, int nx, int ny, int nz, const double *norm,
+                        const int *cells, int b, double dt, const double *scale,
+                        const double *rho, const double *rhon, double inv_count, float *params,
+                        float *m1, float *m2, int t, double lr, double beta1, double beta2,
+                        double eps, uint16_t *wpack, float *grad, float *loss, void *workspace,
+                        monc_stream_t stream);
 /* Corrected coarse step for u, v, w, theta: out = in + dt (tend + c_q), with
  *   c_q = -scale_q (gx_q(i) - gx_q(i-1) + gy_q(j) - gy_q(j-1)) / rhohat_q(k)
  * for u, v, w, where gx, gy are [nx*ny*nz][4] face outputs of the network (gy

@@ -78,6 +78,9 @@ _SIGS = {
     "monc_mlp_loss": ([vp, ip, vp, PP, PP, PP, ip, ip, ip, dp, DPTR, vp, vp, dp, vp, vp, vp,
                        vp], ip),
     "monc_mlp_adam": ([vp, vp, vp, vp, ip, dp, dp, dp, dp, vp, vp], ip),
+    "monc_mlp_train_workspace_bytes": ([ip], C.c_size_t),
+    "monc_mlp_train_step": ([PP, PP, PP, ip, ip, ip, DPTR, vp, ip, dp, DPTR, vp, vp, dp, vp, vp,
+                             vp, ip, dp, dp, dp, dp, vp, vp, vp, vp, vp], ip),
     "monc_correct_step_workspace_bytes": ([ip, ip, ip], C.c_size_t),
     "monc_correct_step": ([PP, PP, vp, vp, PP, ip, ip, ip, dp, dp, DPTR, vp, vp, vp, dp, dp,
                            vp, vp, vp], ip),
@@ -644,6 +647,26 @@ def monc_mlp_adam(params, m1, m2, grad, t, lr, b1, b2, eps, wpack, stream=None):
     _check(lib().monc_mlp_adam(_ptr(params), _ptr(m1), _ptr(m2), _ptr(grad), int(t), float(lr),
                                float(b1), float(b2), float(eps), _ptr(wpack), _stream(stream)),
            "monc_mlp_adam")
+
+
+def monc_mlp_train_workspace_bytes(b):
+    return int(lib().monc_mlp_train_workspace_bytes(int(b)))
+
+
+def monc_mlp_train_step(c0, c1, tend, norm, cells, dt, scale, prof_c, inv_count, params, m1, m2,
+                        t, lr, b1, b2, eps, wpack, grad, loss, workspace, stream=None):
+    torch = _torch()
+    nx, ny, nz = _grid(c0[0])
+    sh = tuple(c0[0].shape)
+    a0, a1, at = (_ptrs(x, torch.float64, sh, n) for x, n in ((c0, "c0"), (c1, "c1"), (tend, "tend")))
+    rdz, rho, rhon = prof_c
+    _check(lib().monc_mlp_train_step(a0, a1, at, nx, ny, nz, _dbl(norm),
+                                     _ptr(cells, torch.int32, None, "cells"), cells.numel(),
+                                     float(dt), _dbl(scale), _ptr(rho), _ptr(rhon),
+                                     float(inv_count), _ptr(params), _ptr(m1), _ptr(m2), int(t),
+                                     float(lr), float(b1), float(b2), float(eps), _ptr(wpack),
+                                     _ptr(grad), _ptr(loss), _ptr(workspace), _stream(stream)),
+           "monc_mlp_train_step")
 
 
 def monc_correct_step_workspace_bytes(nx, ny, nz):

@@ -842,6 +842,37 @@ int monc_mlp_adam(float* params, float* m1, float* m2, const float* grad, int t,
                       "mlp_adam");
 }
 
+size_t monc_mlp_train_workspace_bytes(int b) { return b < 1 ? 0 : mlp_train_workspace(b); }
+
+int monc_mlp_train_step(const double* const* c0, const double* const* c1,
+                        const double* const* tend, int nx, int ny, int nz, const double* norm,
+                        const int* cells, int b, double dt, const double* scale, const double* rho,
+                        const double* rhon, double inv_count, float* params, float* m1, float* m2,
+                        int t, double lr, double beta1, double beta2, double eps, uint16_t* wpack,
+                        float* grad, float* loss, void* workspace, monc_stream_t stream) {
+    TRY(check_grid(nx, ny, nz));
+    TRY(check_dt(dt));
+    TRY(check_ptrs(4, c0, "c0"));
+    TRY(check_ptrs(4, c1, "c1"));
+    TRY(check_ptrs(4, tend, "tend"));
+    if (!norm || !cells || !scale || !rho || !rhon || !params || !m1 || !m2 || !wpack || !grad ||
+        !loss || !workspace)
+        return fail(MONC_EINVAL, "NULL pointer");
+    if (b < 1) return fail(MONC_EINVAL, "b must be >= 1");
+    if (t < 1) return fail(MONC_EINVAL, "t must be >= 1");
+    if (!(lr > 0) || !(beta1 >= 0 && beta1 < 1) || !(beta2 >= 0 && beta2 < 1) || !(eps > 0))
+        return fail(MONC_EINVAL, "bad Adam hyper-parameters");
+    for (int q = 0; q < 4; q++) {
+        if (!(scale[q] > 0)) return fail(MONC_EINVAL, "scale %d must be > 0", q);
+        if (!(norm[2 * q + 1] > 0)) return fail(MONC_EINVAL, "norm std %d must be > 0", q);
+    }
+    if ((uintptr_t)wpack & 15) return fail(MONC_EINVAL, "wpack must be 16-byte aligned");
+    return hip_status(launch_mlp_train(c0, c1, tend, nx, ny, nz, norm, cells, b, dt, scale, rho,
+                                       rhon, inv_count, params, m1, m2, t, lr, beta1, beta2, eps,
+                                       wpack, grad, loss, workspace, (hipStream_t)stream),
+                      "mlp_train_step");
+}
+
 size_t monc_correct_step_workspace_bytes(int nx, int ny, int nz) {
     if (nx < 1 || ny < 1 || nz < 1) return 0;
     return correct_step_workspace_bytes(nx, ny, nz);

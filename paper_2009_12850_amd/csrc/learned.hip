@@ -939,6 +939,415 @@ __global__ void __launch_bounds__(256) adam_kernel(float* __restrict__ p, float*
 }
 
 // ---------------------------------------------------------------------------
+// Fused training step.  A workgroup (4 waves) takes chunks of TR_CELLS sampled
+// cells; the chunk's 64 rows are the four face rows of its cells (row 16 f + c
+// is face f = x(i), x(i-1), y(j), y(j-1) of cell c), so the loss of a cell sees
+// all of its rows inside the workgroup.  Per chunk: the features are gathered
+// from the fields into LDS, the three layers run with their activations and
+// GELU derivatives kept in LDS, the loss terms and dY follow, then the
+// backward pass, whose parameter-gradient sums stay in registers across the
+// chunks (the dW1/dW2 MFMA tiles in their accumulators).  Every per-row value
+// is the same operation on the same numbers as in features_kernel,
+// mlp_forward, loss_kernel and mlp_backward; only the order in which rows are
+// summed into the gradient differs.  One partial gradient row and one loss
+// partial per workgroup; the grid depends only on the batch size, so the
+// result is repeatable bit for bit.
+// ---------------------------------------------------------------------------
+constexpr int TR_CELLS = 16, TR_ROWS = 4 * TR_CELLS;
+constexpr int TR_GRID = 256;
+constexpr int LX = KP + 8;  // padded feature row in LDS (see LW1)
+constexpr size_t TR_SX = (size_t)S_WEND * 2;                     // X [64][LX] bf16
+constexpr size_t TR_SH1 = TR_SX + (size_t)TR_ROWS * LX * 2;      // H1 [64][LWH] bf16
+constexpr size_t TR_SH2 = TR_SH1 + (size_t)TR_ROWS * LWH * 2;    // H2, then dZ2 [64][LWH] bf16
+constexpr size_t TR_SG1 = TR_SH2 + (size_t)TR_ROWS * LWH * 2;    // gelu'(Z1) [64][64] f32
+constexpr size_t TR_SG2 = TR_SG1 + (size_t)TR_ROWS * HID * 4;    // gelu'(Z2) [64][64] f32
+constexpr size_t TR_SDZ1 = TR_SG2 + (size_t)TR_ROWS * HID * 4;   // dZ1 [64][64] bf16
+constexpr size_t TR_SY = TR_SDZ1 + (size_t)TR_ROWS * HID * 2;    // Y [64][4] f32
+constexpr size_t TR_SDY = TR_SY + (size_t)TR_ROWS * NO * 4;      // dY [64][4] f32
+constexpr size_t TR_SW3 = TR_SDY + (size_t)TR_ROWS * NO * 4;     // W3 (bf16 values) [4][64] f32
+constexpr size_t TR_SB = TR_SW3 + (size_t)NO * HID * 4;          // b1 | b2 | b3 f32
+constexpr size_t TR_LDS = TR_SB + (size_t)(2 * HID + NO) * 4;
+static_assert(TR_LDS <= 160 * 1024, "fused training step fits the LDS");
+static_assert(TR_ROWS * LX * 2 >= 2 * 256 * 4, "end-of-kernel sums fit the feature area");
+
+int train_grid(int b) {
+    const int chunks = (b + TR_CELLS - 1) / TR_CELLS;
+    return chunks < TR_GRID ? chunks : TR_GRID;
+}
+
+struct TrainArgs {
+    const double* c0[4];
+    const double* c1[4];
+    const double* tend[4];
+    double mean[4], inv_std[4];
+    int nx, ny, nz;
+    const int* cells;
+    int B;
+    double inv_dt;
+    double inv_scale[4];
+    const double *rho, *rhon;
+    double inv_n;
+    const float* params;
+    const uint16_t* wpack;
+    float* partials;      // [grid][NPARAM]
+    double* loss_part;    // [grid]
+};
+
+template <typename P>
+__device__ __forceinline__ P pick4(int q, P a0, P a1, P a2, P a3) {
+    return q == 0 ? a0 : (q == 1 ? a1 : (q == 2 ? a2 : a3));
+}
+
+__global__ void __launch_bounds__(256) mlp_train(TrainArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    uint16_t* sw = reinterpret_cast<uint16_t*>(smem);
+    uint16_t* sX = reinterpret_cast<uint16_t*>(smem + TR_SX);
+    uint16_t* sH1 = reinterpret_cast<uint16_t*>(smem + TR_SH1);
+    uint16_t* sH2 = reinterpret_cast<uint16_t*>(smem + TR_SH2);  // later dZ2
+    float* sG1 = reinterpret_cast<float*>(smem + TR_SG1);
+    float* sG2 = reinterpret_cast<float*>(smem + TR_SG2);
+    uint16_t* sdZ1 = reinterpret_cast<uint16_t*>(smem + TR_SDZ1);
+    float* sY = reinterpret_cast<float*>(smem + TR_SY);
+    float* sdY = reinterpret_cast<float*>(smem + TR_SDY);
+    float* sW3 = reinterpret_cast<float*>(smem + TR_SW3);
+    float* sb = reinterpret_cast<float*>(smem + TR_SB);
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int h = lane >> 5, kh = 8 * h;
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const unsigned ncell = (unsigned)nx * ny * nz;
+    const int nchunks = (a.B + TR_CELLS - 1) / TR_CELLS;
+
+    load_pack_padded(a.wpack, sw);
+    for (int t = tid; t < 2 * HID + NO; t += 256)
+        sb[t] = t < HID ? a.params[OFF_B1 + t]
+                        : (t < 2 * HID ? a.params[OFF_B2 + t - HID] : a.params[OFF_B3 + t - 2 * HID]);
+    for (int t = tid; t < NO * HID; t += 256) sW3[t] = bf2f(a.wpack[PK_W3 + t]);
+
+    // sums kept across the chunks
+    float db2 = 0.0f;      // column tid % 64, rows tid/64 + 4q
+    float colsum1 = 0.0f;  // b1: column 32 ct + lane % 32 of this wave's dZ1 tile
+    f32x16_t accW2 = {};   // dW2 tile (w >> 1, w & 1)
+    f32x16_t accW1[5];     // dW1 tiles w, w + 4, .., w + 16 of the 2 x 10
+#pragma unroll
+    for (int q = 0; q < 5; q++) accW1[q] = f32x16_t{};
+    float sW3acc = 0.0f, sB3acc = 0.0f;
+    double lsum = 0.0;     // squared errors (wave 0)
+    const int rt = w >> 1, ct = w & 1;  // this wave's 32 x 32 output tile
+
+    for (int c = blockIdx.x; c < nchunks; c += gridDim.x) {
+        __syncthreads();  // the previous chunk is done with the LDS (and the weights are in)
+
+        // ---- features: lane = row, wave = feature field ----
+        {
+            const int r = lane, face = r >> 4, b = c * TR_CELLS + (r & 15);
+            int cell = b < a.B ? a.cells[b] : -1;
+            const bool valid = (unsigned)cell < ncell;
+            if (!valid) cell = 0;  // gathers in bounds, values masked
+            const int k = cell % nz, ij = cell / nz;
+            int j = ij % ny, i = ij / ny;
+            if (face == 1) i = i == 0 ? nx - 1 : i - 1;
+            if (face == 3) j = j == 0 ? ny - 1 : j - 1;
+            const bool orient = face >= 2;
+            // the stored field of feature field w (y-face rows exchange u, v)
+            const int src = orient && w < 2 ? 1 - w : w;
+            const double* fld = pick4(src, a.c0[0], a.c0[1], a.c0[2], a.c0[3]);
+            const double mean = pick4(src, a.mean[0], a.mean[1], a.mean[2], a.mean[3]);
+            const double inv = pick4(src, a.inv_std[0], a.inv_std[1], a.inv_std[2], a.inv_std[3]);
+            long ao[5], bo[5];
+            int ko[3];
+#pragma unroll
+            for (int d = 0; d < 5; d++) {
+                int ii = i + d - 2, jj = j + d - 2;  // offsets of at most 2 cells: wrap by adds
+                ii = ii < 0 ? ii + nx : (ii >= nx ? ii - nx : ii);
+                ii = ii < 0 ? ii + nx : (ii >= nx ? ii - nx : ii);
+                jj = jj < 0 ? jj + ny : (jj >= ny ? jj - ny : jj);
+                jj = jj < 0 ? jj + ny : (jj >= ny ? jj - ny : jj);
+                const long xoff = (long)(ii + 2) * (ny + 4) * nz, yoff = (long)(jj + 2) * nz;
+                ao[d] = orient ? yoff : xoff;  // first neighbourhood axis
+                bo[d] = orient ? xoff : yoff;  // second
+            }
+#pragma unroll
+            for (int e = 0; e < 3; e++) {
+                const int kk = k + e - 1;
+                ko[e] = kk < 0 ? 0 : (kk > nz - 1 ? nz - 1 : kk);
+            }
+            uint16_t* dst = sX + r * LX + w * 80;
+#pragma unroll
+            for (int g8 = 0; g8 < 10; g8++) {
+                u16x8 v;
+#pragma unroll
+                for (int e = 0; e < 8; e++) {
+                    const int pos = 8 * g8 + e;
+                    uint16_t out = 0;
+                    if (pos < 75) {
+                        const int a5 = pos / 15, b5 = (pos / 3) % 5, c3 = pos % 3;
+                        const double x = fld[ao[a5] + bo[b5] + ko[c3]];
+                        out = valid ? f2bf((float)((x - mean) * inv)) : (uint16_t)0;
+                    }
+                    v.v[e] = out;
+                }
+                *reinterpret_cast<uint4*>(dst + 8 * g8) = __builtin_bit_cast(uint4, v);
+            }
+        }
+        __syncthreads();
+
+        // ---- layer 1: Z1 = X W1^T + b1 ----
+        {
+            f32x16_t acc = {};
+#pragma unroll
+            for (int kk = 0; kk < KP / 16; kk++) {
+                const int ks = kslot(kk, h);
+                acc = mfma(ld8(sX + (32 * rt + (lane & 31)) * LX + ks),
+                           ld8(sw + S_W1 + (32 * ct + (lane & 31)) * LW1 + ks), acc);
+            }
+#pragma unroll
+            for (int r = 0; r < 16; r++) {
+                const int lr = 32 * rt + acc_row(r, lane), col = 32 * ct + (lane & 31);
+                const float z = acc[r] + sb[col];
+                sH1[lr * LWH + col] = f2bf(gelu(z));
+                sG1[lr * HID + col] = gelu_grad(z);
+            }
+        }
+        __syncthreads();
+        // ---- layer 2 ----
+        {
+            f32x16_t acc = {};
+#pragma unroll
+            for (int kk = 0; kk < HID / 16; kk++)
+                acc = mfma(ld8(sH1 + (32 * rt + (lane & 31)) * LWH + 16 * kk + kh),
+                           ld8(sw + S_W2 + (32 * ct + (lane & 31)) * LWH + 16 * kk + kh), acc);
+#pragma unroll
+            for (int r = 0; r < 16; r++) {
+                const int lr = 32 * rt + acc_row(r, lane), col = 32 * ct + (lane & 31);
+                const float z = acc[r] + sb[HID + col];
+                sH2[lr * LWH + col] = f2bf(gelu(z));
+                sG2[lr * HID + col] = gelu_grad(z);
+            }
+        }
+        __syncthreads();
+        // ---- layer 3 (4 outputs, padded to a 32-wide tile): waves 0, 1 ----
+        if (w < 2) {
+            f32x16_t acc = {};
+#pragma unroll
+            for (int kk = 0; kk < HID / 16; kk++)
+                acc = mfma(ld8(sH2 + (32 * w + (lane & 31)) * LWH + 16 * kk + kh),
+                           ld8(sw + S_W3 + (lane & 31) * LWH + 16 * kk + kh), acc);
+            const int col = lane & 31;
+            if (col < NO) {
+#pragma unroll
+                for (int r = 0; r < 16; r++)
+                    sY[(32 * w + acc_row(r, lane)) * NO + col] = acc[r] + sb[2 * HID + col];
+            }
+        }
+        __syncthreads();
+        // ---- loss terms and dY: wave 0, lane = (cell, field) ----
+        if (w == 0) {
+            const int cl = lane >> 2, q = lane & 3, sq = q < 2 ? 1 - q : q;
+            const int b = c * TR_CELLS + cl;
+            int cell = b < a.B ? a.cells[b] : -1;
+            const bool valid = (unsigned)cell < ncell;
+            if (!valid) cell = 0;
+            const int k = cell % nz, j = (cell / nz) % ny, i = cell / (nz * ny);
+            const long g = ((long)(i + 2) * (ny + 4) + (j + 2)) * nz + k;
+            const float yxp = sY[cl * NO + q], yxm = sY[(TR_CELLS + cl) * NO + q];
+            const float yyp = sY[(2 * TR_CELLS + cl) * NO + sq],
+                        yym = sY[(3 * TR_CELLS + cl) * NO + sq];
+            const float rh = (float)(q == 2 ? a.rho[k] / a.rho[0] : a.rhon[k] / a.rhon[0]);
+            const double* f0 = pick4(q, a.c0[0], a.c0[1], a.c0[2], a.c0[3]);
+            const double* f1 = pick4(q, a.c1[0], a.c1[1], a.c1[2], a.c1[3]);
+            const double* ft = pick4(q, a.tend[0], a.tend[1], a.tend[2], a.tend[3]);
+            const double isc = pick4(q, a.inv_scale[0], a.inv_scale[1], a.inv_scale[2],
+                                     a.inv_scale[3]);
+            const float tgt = (float)(((f1[g] - f0[g]) * a.inv_dt - ft[g]) * isc);
+            const float msk = (!valid || (q == 2 && k == nz - 1)) ? 0.0f : 1.0f;
+            const float cc = -(yxp - yxm + yyp - yym) / rh;
+            const float err = (cc - tgt) * msk;
+            lsum += (double)err * (double)err;
+            const float gr = (float)(2.0 * (double)err * a.inv_n) / rh;
+            sdY[cl * NO + q] = -gr;
+            sdY[(TR_CELLS + cl) * NO + q] = gr;
+            sdY[(2 * TR_CELLS + cl) * NO + sq] = -gr;
+            sdY[(3 * TR_CELLS + cl) * NO + sq] = gr;
+        }
+        __syncthreads();
+
+        // ---- backward ----
+        // dW3[q][j2] += sum_rows dY[row][q] H2[row][j2]; db3
+        {
+            const int q = tid / HID, j2 = tid % HID;  // 256 = 4 x 64
+            for (int r = 0; r < TR_ROWS; r++) sW3acc += sdY[r * NO + q] * bf2f(sH2[r * LWH + j2]);
+            if (tid < NO)
+                for (int r = 0; r < TR_ROWS; r++) sB3acc += sdY[r * NO + tid];
+        }
+        // dZ2 = (dY W3) * gelu'(Z2), kept in registers until H2 is no longer read
+        float dz2[TR_ROWS / 4];
+        {
+            const int col = tid & 63;
+#pragma unroll
+            for (int q4 = 0; q4 < TR_ROWS / 4; q4++) {
+                const int r = (tid >> 6) + 4 * q4;
+                float dh = 0.0f;
+#pragma unroll
+                for (int q = 0; q < NO; q++) dh += sdY[r * NO + q] * sW3[q * HID + col];
+                const float dz = dh * sG2[r * HID + col];
+                db2 += dz;
+                dz2[q4] = dz;
+            }
+        }
+        __syncthreads();
+        uint16_t* sdZ2 = sH2;
+        {
+            const int col = tid & 63;
+#pragma unroll
+            for (int q4 = 0; q4 < TR_ROWS / 4; q4++)
+                sdZ2[((tid >> 6) + 4 * q4) * LWH + col] = f2bf(dz2[q4]);
+        }
+        __syncthreads();
+        // dH1 = dZ2 W2 (MFMA), dZ1 = dH1 * gelu'(Z1); b1 sums the FP32 dZ1
+        {
+            f32x16_t acc = {};
+#pragma unroll
+            for (int kk = 0; kk < HID / 16; kk++)
+                acc = mfma(ld8(sdZ2 + (32 * rt + (lane & 31)) * LWH + 16 * kk + kh),
+                           gather8(sw + S_W2 + (16 * kk + kh) * LWH + 32 * ct + (lane & 31), LWH),
+                           acc);
+#pragma unroll
+            for (int r = 0; r < 16; r++) {
+                const int lr = 32 * rt + acc_row(r, lane), col = 32 * ct + (lane & 31);
+                const float dz = acc[r] * sG1[lr * HID + col];
+                sdZ1[lr * HID + col] = f2bf(dz);
+                colsum1 += dz;
+            }
+        }
+        __syncthreads();
+        // dW2[j2][j1] += sum_rows dZ2[row][j2] H1[row][j1]
+#pragma unroll
+        for (int kk = 0; kk < TR_ROWS / 16; kk++)
+            accW2 = mfma(gather8(sdZ2 + (16 * kk + kh) * LWH + 32 * rt + (lane & 31), LWH),
+                         gather8(sH1 + (16 * kk + kh) * LWH + 32 * ct + (lane & 31), LWH), accW2);
+        // dW1[j][k] += sum_rows dZ1[row][j] X[row][k]: tiles tt = w + 4 q
+#pragma unroll
+        for (int q = 0; q < 5; q++) {
+            const int tt = w + 4 * q, it = tt / 10, kt = tt % 10;
+#pragma unroll
+            for (int kk = 0; kk < TR_ROWS / 16; kk++)
+                accW1[q] = mfma(gather8(sdZ1 + (16 * kk + kh) * HID + 32 * it + (lane & 31), HID),
+                                gather8(sX + (16 * kk + kh) * LX + 32 * kt + (lane & 31), LX),
+                                accW1[q]);
+        }
+    }
+
+    // ---- the workgroup's partial row and loss ----
+    float* part = a.partials + (size_t)blockIdx.x * NPARAM;
+    __syncthreads();
+    float* red = reinterpret_cast<float*>(smem + TR_SX);  // [2][256]
+    red[tid] = db2;
+    red[256 + (2 * rt + (lane >> 5)) * HID + 32 * ct + (lane & 31)] = colsum1;
+    __syncthreads();
+    if (tid < HID) {
+        part[OFF_B2 + tid] = red[tid] + red[tid + 64] + red[tid + 128] + red[tid + 192];
+        part[OFF_B1 + tid] = red[256 + tid] + red[256 + HID + tid] + red[256 + 2 * HID + tid] +
+                             red[256 + 3 * HID + tid];
+    }
+#pragma unroll
+    for (int r = 0; r < 16; r++) {
+        const int j2 = 32 * rt + acc_row(r, lane), j1 = 32 * ct + (lane & 31);
+        part[OFF_W2 + j2 * HID + j1] = accW2[r];
+    }
+#pragma unroll
+    for (int q = 0; q < 5; q++) {
+        const int tt = w + 4 * q, it = tt / 10, kt = tt % 10;
+#pragma unroll
+        for (int r = 0; r < 16; r++) {
+            const int j = 32 * it + acc_row(r, lane), k = 32 * kt + (lane & 31);
+            part[OFF_W1 + j * KP + k] = accW1[q][r];
+        }
+    }
+    {
+        const int q = tid / HID, j2 = tid % HID;
+        part[OFF_W3 + q * HID + j2] = sW3acc;
+        if (tid < NO) part[OFF_B3 + tid] = sB3acc;
+    }
+    if (w == 0) {
+        double v = lsum;
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        if (lane == 0) a.loss_part[blockIdx.x] = v * a.inv_n;
+    }
+}
+
+// The update after mlp_train: a workgroup of 16 waves takes 64 parameters;
+// wave g sums rows g*per .. g*per + per - 1 of their partial rows in order (all
+// its loads in flight at once: the sum is bound by latency, not bytes), then
+// wave 0 adds the 16 group sums in order, writes the gradient, takes the Adam
+// step and writes the BF16 pack entries of the weights; workgroup 0 also sums
+// the loss partials.
+constexpr int UPD_GROUPS = 16;
+constexpr int UPD_PER_MAX = TR_GRID / UPD_GROUPS;
+static_assert(TR_GRID % UPD_GROUPS == 0 && TR_GRID <= 256, "row groups");
+
+struct UpdateArgs {
+    const float* partials;
+    int nb;
+    const double* loss_part;
+    float* grad;
+    float* p;
+    float* m1;
+    float* m2;
+    uint16_t* wpack;
+    float* loss;
+    float lr, b1, omb1, b2, omb2, eps, c1, c2;
+};
+
+__global__ void __launch_bounds__(64 * UPD_GROUPS) mlp_update(UpdateArgs a) {
+    __shared__ float qs[UPD_GROUPS][64];
+    __shared__ double red[256];
+    const int tid = threadIdx.x, lane = tid & 63, grp = tid >> 6;
+    const int p = blockIdx.x * 64 + lane;
+    const int per = (a.nb + UPD_GROUPS - 1) / UPD_GROUPS;
+    const int r0 = grp * per;
+    float v[UPD_PER_MAX];
+#pragma unroll
+    for (int e = 0; e < UPD_PER_MAX; e++) {
+        const int r = r0 + e;
+        v[e] = (e < per && r < a.nb && p < NPARAM) ? a.partials[(size_t)r * NPARAM + p] : 0.0f;
+    }
+    float s = 0.0f;
+#pragma unroll
+    for (int e = 0; e < UPD_PER_MAX; e++) s += v[e];  // rows in order; absent rows add 0
+    qs[grp][lane] = s;
+    if (blockIdx.x == 0 && tid < 256) {
+        double l = 0.0;
+        for (int r = tid; r < a.nb; r += 256) l += a.loss_part[r];
+        red[tid] = l;
+    }
+    __syncthreads();
+    if (grp == 0 && p < NPARAM) {
+        float gt = qs[0][lane];
+#pragma unroll
+        for (int g = 1; g < UPD_GROUPS; g++) gt += qs[g][lane];
+        a.grad[p] = gt;
+        const float m = a.b1 * a.m1[p] + a.omb1 * gt;
+        const float v2 = a.b2 * a.m2[p] + a.omb2 * gt * gt;
+        a.m1[p] = m;
+        a.m2[p] = v2;
+        const float np = a.p[p] - a.lr * (m / a.c1) / (sqrtf(v2 / a.c2) + a.eps);
+        a.p[p] = np;
+        int pk = -1;  // the pack entry of a weight (biases are not packed)
+        if (p < OFF_B1) pk = PK_W1 + p;
+        else if (p >= OFF_W2 && p < OFF_B2) pk = PK_W2 + (p - OFF_W2);
+        else if (p >= OFF_W3 && p < OFF_B3) pk = PK_W3 + (p - OFF_W3);
+        if (pk >= 0) a.wpack[pk] = f2bf(np);
+    }
+    if (blockIdx.x == 0) {
+        for (int q = 128; q > 0; q >>= 1) {
+            if (tid < q) red[tid] += red[tid + q];
+            __syncthreads();
+        }
+        if (tid == 0) a.loss[0] = (float)red[0];
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Corrected coarse step: state_out = state_in + dt (tend + c), with c the flux
 // divergence of the network's face fluxes (times the per-field scale).
 // Guards, in order:
@@ -1331,6 +1740,70 @@ hipError_t launch_mlp_adam(float* params, float* m1, float* m2, const float* gra
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return launch_mlp_pack(params, wpack, s);
+}
+
+size_t mlp_train_workspace(int b) {
+    const size_t g = (size_t)train_grid(b);
+    return g * NPARAM * sizeof(float) + g * sizeof(double);
+}
+
+hipError_t launch_mlp_train(const double* const* c0, const double* const* c1,
+                            const double* const* tend, int nx, int ny, int nz, const double* norm,
+                            const int* cells, int b, double dt, const double* scale,
+                            const double* rho, const double* rhon, double inv_n, float* params,
+                            float* m1, float* m2, int t, double lr, double b1, double b2,
+                            double eps, uint16_t* wpack, float* grad, float* loss, void* ws,
+                            hipStream_t s) {
+    static std::atomic<unsigned long long> attr{0};
+    hipError_t e = set_lds_limit_once((const void*)mlp_train, TR_LDS, &attr);
+    if (e != hipSuccess) return e;
+    const int grid = train_grid(b);
+    TrainArgs a;
+    for (int q = 0; q < 4; q++) {
+        a.c0[q] = c0[q];
+        a.c1[q] = c1[q];
+        a.tend[q] = tend[q];
+        a.mean[q] = norm[2 * q];
+        a.inv_std[q] = 1.0 / norm[2 * q + 1];
+        a.inv_scale[q] = 1.0 / scale[q];
+    }
+    a.nx = nx;
+    a.ny = ny;
+    a.nz = nz;
+    a.cells = cells;
+    a.B = b;
+    a.inv_dt = 1.0 / dt;
+    a.rho = rho;
+    a.rhon = rhon;
+    a.inv_n = inv_n;
+    a.params = params;
+    a.wpack = wpack;
+    a.partials = (float*)ws;
+    a.loss_part = (double*)((float*)ws + (size_t)grid * NPARAM);
+    mlp_train<<<grid, 256, TR_LDS, s>>>(a);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    UpdateArgs u;
+    u.partials = a.partials;
+    u.nb = grid;
+    u.loss_part = a.loss_part;
+    u.grad = grad;
+    u.p = params;
+    u.m1 = m1;
+    u.m2 = m2;
+    u.wpack = wpack;
+    u.loss = loss;
+    // as in launch_mlp_adam
+    u.lr = (float)lr;
+    u.b1 = (float)b1;
+    u.omb1 = (float)(1.0 - b1);
+    u.b2 = (float)b2;
+    u.omb2 = (float)(1.0 - b2);
+    u.eps = (float)eps;
+    u.c1 = (float)(1.0 - pow(b1, t));
+    u.c2 = (float)(1.0 - pow(b2, t));
+    mlp_update<<<(NPARAM + 63) / 64, 64 * UPD_GROUPS, 0, s>>>(u);
+    return hipGetLastError();
 }
 
 size_t correct_step_workspace_bytes(int nx, int ny, int nz) {

@@ -129,6 +129,14 @@ hipError_t launch_mlp_loss(const float* Y4, int b, const int* cells, const doubl
 hipError_t launch_mlp_adam(float* params, float* m1, float* m2, const float* grad, int t,
                            double lr, double b1, double b2, double eps, uint16_t* wpack,
                            hipStream_t s);
+size_t mlp_train_workspace(int b);
+hipError_t launch_mlp_train(const double* const* c0, const double* const* c1,
+                            const double* const* tend, int nx, int ny, int nz, const double* norm,
+                            const int* cells, int b, double dt, const double* scale,
+                            const double* rho, const double* rhon, double inv_n, float* params,
+                            float* m1, float* m2, int t, double lr, double b1, double b2,
+                            double eps, uint16_t* wpack, float* grad, float* loss, void* ws,
+                            hipStream_t s);
 hipError_t launch_pw_scaled(int dtype, const AdvArgs& a, hipStream_t s);
 size_t correct_step_workspace_bytes(int nx, int ny, int nz);
 hipError_t launch_correct_step(double* const* in, double* const* tend, const float* gx,

@@ -176,6 +176,8 @@ class Correction:
                                 device=device)
         self.ws_l = torch.zeros(M.monc_mlp_loss_workspace_bytes(batch), dtype=torch.uint8,
                                 device=device)
+        self.ws_t = torch.zeros(M.monc_mlp_train_workspace_bytes(batch), dtype=torch.uint8,
+                                device=device)
         self.loss = torch.zeros(1, dtype=torch.float32, device=device)
         self.cells = torch.zeros(batch, dtype=torch.int32, device=device)
         self.cx = torch.zeros(2 * batch, dtype=torch.int32, device=device)
@@ -217,7 +219,30 @@ class Correction:
                         1.0 / nterm, self.dY, self.loss, self.ws_l)
 
     def train_step(self, ser, n, rng, lr=1e-3):
-        """One Adam step; returns the (device) loss before the update."""
+        """One Adam step on B seeded random cells of snapshot pair n of a
+        series (the fused step: two launches); returns the (device) loss
+        before the update."""
+        torch = _torch()
+        NX, NY, NZ = _coarse_dims(ser)
+        c, _, _, nterm = self.sample(rng, NX, NY, NZ)
+        self.cells.copy_(torch.from_numpy(c.astype(np.int32)).to(self.device))
+        self.device_step(ser, n, nterm, lr)
+        return self.loss
+
+    def device_step(self, ser, n, nterm, lr=1e-3):
+        """The device work of one training step on the cells already in
+        `cells`: no host sampling or copies, so it can be captured in a
+        graph."""
+        self.t += 1
+        M.monc_mlp_train_step(ser.snaps[n], ser.snaps[n + 1], ser.tend[n], self.norm, self.cells,
+                              ser.dtc, self.scale, ser.prof_c, 1.0 / nterm, self.params, self.m1,
+                              self.m2, self.t, lr, 0.9, 0.999, 1e-8, self.wpack, self.grad,
+                              self.loss, self.ws_t)
+
+    def train_step_separate(self, ser, n, rng, lr=1e-3):
+        """The same step through the separate entry points (features, forward
+        with saved activations, loss, backward with its gradient reduction,
+        Adam and pack)."""
         self._forward_loss(ser, n, rng, save=True)
         self._backward_adam(lr)
         return self.loss
@@ -229,10 +254,9 @@ class Correction:
         M.monc_mlp_adam(self.params, self.m1, self.m2, self.grad, self.t, lr, 0.9, 0.999, 1e-8,
                         self.wpack)
 
-    def device_step(self, ser, n, nterm, lr=1e-3):
-        """The device work of one training step on the cells already in
-        cx, cy, cells (features, forward, loss, backward, Adam): no host
-        sampling or copies, so it can be captured in a graph."""
+    def device_step_separate(self, ser, n, nterm, lr=1e-3):
+        """The device work of train_step_separate on the cells already in cx,
+        cy, cells."""
         B = self.B
         c0, c1, td = ser.snaps[n], ser.snaps[n + 1], ser.tend[n]
         M.monc_mlp_features(c0, self.norm, 0, self.cx, self.X.narrow(0, 0, 2 * B))
@@ -417,31 +441,39 @@ def run_experiment(nx=512, ny=512, nz=128, seeds=range(2000, 2016), n_train=12, 
                               for n in range(0, len(ser.tend), max(1, len(ser.tend) // 8))]))
 
     loss_zero, loss_trained = held_loss(zero), held_loss(model)
-    # one training step (features, forward, loss, backward with its gradient
-    # reduction, Adam) on its own, timed on a separate copy of the network
+    # one training step on its own, timed on a separate copy of the network:
+    # the fused step (two launches) as issued from Python (host sampling and a
+    # copy of the cell list included), and its device work captured once in a
+    # graph and replayed; the same step through the separate entry points (ten
+    # launches), replayed likewise
     probe = Correction(device, seed=0, norm=norm, scale=scale, batch=batch)
     prng = np.random.default_rng(7)
     probe.train_step(train_set[0], 0, prng)
     treps = 50
     t_step = _event_ms(lambda: [probe.train_step(train_set[0], n % len(train_set[0].tend), prng)
                                 for n in range(treps)]) / treps
-    # the same step's device work alone: captured once in a graph and replayed
-    # (the host samples no cells and issues no launches in between)
-    t_graph = None
-    try:
-        ser0 = train_set[0]
-        nterm = 4 * batch
-        probe.device_step(ser0, 0, nterm)
-        torch.cuda.synchronize()
-        graph = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(graph):
-            probe.device_step(ser0, 0, nterm)
-        graph.replay()
-        torch.cuda.synchronize()
-        t_graph = _event_ms(lambda: [graph.replay() for _ in range(treps)]) / treps
-        del graph
-    except Exception as exc:  # graph capture unavailable: report the eager time only
-        say(f"  training-step graph not captured: {exc}")
+    t_graph = t_graph_sep = None
+    ser0 = train_set[0]
+    nterm = 4 * batch
+    probe.train_step_separate(ser0, 0, prng)  # leaves cx, cy, cells of one sample
+    for fn, key in ((probe.device_step, "fused"), (probe.device_step_separate, "separate")):
+        try:
+            fn(ser0, 0, nterm)
+            torch.cuda.synchronize()
+            graph = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(graph):
+                fn(ser0, 0, nterm)
+            graph.replay()
+            torch.cuda.synchronize()
+            ms = _event_ms(lambda: [graph.replay() for _ in range(treps)]) / treps
+            del graph
+        except Exception as exc:  # graph capture unavailable: report the eager time only
+            say(f"  training-step graph ({key}) not captured: {exc}")
+            ms = None
+        if key == "fused":
+            t_graph = ms
+        else:
+            t_graph_sep = ms
     del probe
     nsteps = min(coarse_steps, len(held[0].tend))
     err_plain, err_learned, fb = [], [], [0, 0, 0]
@@ -488,8 +520,10 @@ def run_experiment(nx=512, ny=512, nz=128, seeds=range(2000, 2016), n_train=12, 
         # correction helps)
         "gain": [p / l for p, l in zip(mean(err_plain), mean(err_learned))],
         # one training step as issued from Python (host sampling, a copy of
-        # the cell lists, ten launches) and its device work replayed as a graph
+        # the cell list, two launches) and its device work replayed as a
+        # graph; the separate entry points' ten launches replayed likewise
         "train_step_ms": t_step, "train_step_graph_ms": t_graph,
+        "train_step_separate_graph_ms": t_graph_sep,
         "fallback_nonfinite": fb[0], "fallback_growth": fb[1], "theta_faces_clamped": fb[2],
         "t_fine_ms": t_fine, "t_coarse_plain_ms": t_plain, "t_coarse_learned_ms": t_learned,
         "speedup_vs_fine": t_fine / t_learned,

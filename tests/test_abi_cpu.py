@@ -227,6 +227,26 @@ def test_learned_entry_points_validate_before_launch():
                                None) == M.MONC_EINVAL
     assert M.monc_correct_step_workspace_bytes(8, 8, 8) > 0
     assert M.monc_mlp_backward_workspace_bytes(0) == 0
+    # fused training step: empty batch, t < 1, bad beta, zero scale, zero
+    # std, misaligned pack
+    fields3 = (_block(4, 0x10000), _block(4, 0x20000), _block(4, 0x30000), 4, 4, 4)
+
+    def train(nrm, b, scl, t, b1, wpack=FAKE):
+        return L.monc_mlp_train_step(*fields3, nrm, FAKE, b, 2.0, scl, FAKE, FAKE, 0.01, FAKE,
+                                     FAKE, FAKE, t, 1e-3, b1, 0.999, 1e-8, wpack, FAKE, FAKE,
+                                     FAKE, None)
+
+    zscale = (d * 4)(1, 1, 0, 1)
+    assert train(norm, 0, scale, 1, 0.9) == M.MONC_EINVAL
+    assert train(norm, 8, scale, 0, 0.9) == M.MONC_EINVAL
+    assert train(norm, 8, scale, 1, 1.0) == M.MONC_EINVAL
+    assert train(norm, 8, zscale, 1, 0.9) == M.MONC_EINVAL
+    assert train(bad, 8, scale, 1, 0.9) == M.MONC_EINVAL
+    assert train(norm, 8, scale, 1, 0.9, C.c_void_p(0x1008)) == M.MONC_EINVAL
+    assert b"16-byte" in L.monc_last_error()
+    assert M.monc_mlp_train_workspace_bytes(0) == 0
+    assert M.monc_mlp_train_workspace_bytes(16) < M.monc_mlp_train_workspace_bytes(32)
+    assert M.monc_mlp_train_workspace_bytes(100000) == M.monc_mlp_train_workspace_bytes(8192)
 
 
 def test_dynamics_entries_reject_bad_arguments():

@@ -307,6 +307,149 @@ def test_adam_and_pack_match_oracle():
     assert np.all(w3[4:] == 0.0)
 
 
+def train_case(NX, NY, NZ, B, seed):
+    """Coarse snapshots, tendencies, profiles and B cells (lid cells and one
+    cell outside the grid included) for a training step."""
+    rng = np.random.default_rng(seed)
+    c0 = coarse_state(NX, NY, NZ, seed)
+    c1 = [a + 0.5 * rng.standard_normal(a.shape) for a in c0]
+    c1[2][:, :, -1] = 0.0
+    tend = [0.1 * rng.standard_normal(a.shape) for a in c0]
+    rho = np.exp(-np.arange(NZ) / 5.0) * 1.2
+    rhon = np.exp(-(np.arange(NZ) + 0.5) / 5.0) * 1.2
+    n = NX * NY * NZ
+    cells = np.sort(rng.integers(0, n, B)).astype(np.int32)
+    cells[:min(B, 2)] = [NZ - 1, n - 1][:min(B, 2)]          # lid cells
+    if B > 3:
+        cells[B // 2] = n                                     # outside the grid
+    return c0, c1, tend, rho, rhon, cells
+
+
+@pytest.mark.parametrize("shape,B", [((12, 10, 7), 5), ((12, 10, 7), 300),
+                                     ((128, 128, 32), 8192)])
+def test_fused_train_step_matches_oracle(shape, B):
+    """monc_mlp_train_step against the oracle.  Its rows are the separate
+    entry points' rows (features, forward, loss), so the oracle's gradient is
+    taken from those kernels' activations and dY and the fused gradient must
+    lie within backward_bounds of it; the loss within a float rounding of the
+    separate loss and 1e-5 of the oracle's; the Adam step and the pack as in
+    test_adam_and_pack_match_oracle.  B = 5 (one partial chunk: every row
+    weighs on the gradient, so a wrong feature would show), 300 (ragged
+    chunks) and the 8192-cell training batch (two chunks per workgroup)."""
+    NX, NY, NZ = shape
+    say(f"fused training step {shape} B={B}")
+    T = torch()
+    c0, c1, tend, rho, rhon, cells = train_case(NX, NY, NZ, B, 61 + B)
+    n = NX * NY * NZ
+    norm = [1.0, 3.0, -0.5, 2.0, 0.0, 0.7, 300.0, 0.5]
+    dt, scale = 2.0, [0.3, 0.2, 0.05, 0.01]
+    k = cells % NZ
+    valid = cells < n
+    nterm = float(4 * valid.sum() - np.sum(valid & (k == NZ - 1)))
+    d0, d1, dte = to_dev(c0), to_dev(c1), to_dev(tend)
+    prof = to_dev([np.zeros(NZ), rho, rhon])
+    p = R.init_params(17).astype(np.float32)
+    rng = np.random.default_rng(3)
+    m1 = (0.01 * rng.standard_normal(R.NPARAM)).astype(np.float32)
+    m2 = (1e-4 * rng.random(R.NPARAM)).astype(np.float32)
+
+    # the separate entry points: features of x(i), x(i-1), y(j), y(j-1)
+    # rows (an outside cell gives four zero rows), forward, loss
+    ci = np.where(valid, cells, 0)
+    i, j = ci // (NY * NZ), (ci // NZ) % NY
+    xm = np.where(valid, (((i - 1) % NX) * NY + j) * NZ + k, n).astype(np.int32)
+    ym = np.where(valid, (i * NY + (j - 1) % NY) * NZ + k, n).astype(np.int32)
+    cx, cy, cd = to_dev([np.concatenate([cells, xm]), np.concatenate([cells, ym]), cells])
+    m = 4 * B
+    pd = T.from_numpy(p.copy()).to(dev())
+    wp = T.zeros(M.MONC_MLP_WPACK, dtype=T.int16, device=dev())
+    M.monc_mlp_pack(pd, wp)
+    X = T.zeros((m, R.K), dtype=T.int16, device=dev())
+    M.monc_mlp_features(d0, norm, 0, cx, X.narrow(0, 0, 2 * B))
+    M.monc_mlp_features(d0, norm, 1, cy, X.narrow(0, 2 * B, 2 * B))
+    Y = T.zeros((m, 4), dtype=T.float32, device=dev())
+    H1 = T.zeros((m, 64), dtype=T.int16, device=dev())
+    H2 = T.zeros_like(H1)
+    Z1 = T.zeros((m, 64), dtype=T.float32, device=dev())
+    Z2 = T.zeros_like(Z1)
+    M.monc_mlp_forward(X, m, pd, wp, Y, H1, H2, Z1, Z2)
+    dY = T.zeros((m, 4), dtype=T.float32, device=dev())
+    loss_sep = T.zeros(1, dtype=T.float32, device=dev())
+    wsl = T.zeros(M.monc_mlp_loss_workspace_bytes(B), dtype=T.uint8, device=dev())
+    M.monc_mlp_loss(Y, B, cd, d0, d1, dte, dt, scale, prof, 1.0 / nterm, dY, loss_sep, wsl)
+
+    # the fused step, twice from the same start (determinism)
+    ws = T.zeros(M.monc_mlp_train_workspace_bytes(B), dtype=T.uint8, device=dev())
+    runs = []
+    for _ in range(2):
+        pf = T.from_numpy(p.copy()).to(dev())
+        m1f, m2f = T.from_numpy(m1.copy()).to(dev()), T.from_numpy(m2.copy()).to(dev())
+        wpf = wp.clone()
+        grad = T.full((R.NPARAM,), np.nan, dtype=T.float32, device=dev())
+        loss = T.full((1,), np.nan, dtype=T.float32, device=dev())
+        M.monc_mlp_train_step(d0, d1, dte, norm, cd, dt, scale, prof, 1.0 / nterm, pf, m1f, m2f,
+                              3, 1e-3, 0.9, 0.999, 1e-8, wpf, grad, loss, ws)
+        runs.append((pf, m1f, m2f, wpf, grad, loss))
+    T.cuda.synchronize()
+    for a, b in zip(runs[0], runs[1]):
+        assert T.equal(a, b), "the fused step is not deterministic"
+    pf, m1f, m2f, wpf, grad, loss = runs[0]
+
+    # loss
+    Yh = Y.double().cpu().numpy()
+    ls, lf = float(loss_sep.item()), float(loss.item())
+    assert abs(lf - ls) <= 2 * np.finfo(np.float32).eps * ls, (lf, ls)
+    ii, jj = i + 2, j + 2
+    tgt = np.stack([((c1[q] - c0[q]) / dt - tend[q])[ii, jj, k] / scale[q] for q in range(4)],
+                   axis=1)
+    rh = np.stack([rhon[k] / rhon[0], rhon[k] / rhon[0], rho[k] / rho[0], rhon[k] / rhon[0]],
+                  axis=1)
+    mask = np.ones((B, 4))
+    mask[k == NZ - 1, 2] = 0.0
+    mask[~valid] = 0.0
+    loss_ref, _ = R.loss_and_grad(Yh, tgt, rh, mask)
+    assert abs(lf - loss_ref) <= 1e-5 * loss_ref
+
+    # gradient against the oracle from the separate kernels' activations
+    _, b1, W2, b2, W3, b3 = R.unpack(p.astype(np.float64))
+    cache = dict(Xb=bf16_bits_to_f64(X), Z1=Z1.double().cpu().numpy(), H1=bf16_bits_to_f64(H1),
+                 Z2=Z2.double().cpu().numpy(), H2=bf16_bits_to_f64(H2), W2b=R.bf16(W2),
+                 W3b=R.bf16(W3))
+    dYh = dY.double().cpu().numpy()
+    ref = R.backward(dYh, cache, emulate=True)
+    g = grad.double().cpu().numpy()
+    gb, rb = R.unpack(g), R.unpack(ref)
+    bounds = backward_bounds(dYh, cache, rb)
+    # b3's gradient, the sum of dY over the rows, is exactly 0 (a cell's four
+    # rows cancel: a constant flux has no divergence); its FP32 sum is bounded
+    # by the recursive-summation bound (m - 1) u sum |dY|
+    bounds[5] = np.maximum(bounds[5], m * U32 * np.abs(dYh).sum(axis=0))
+    for name, a, b, bd in zip(["W1", "b1", "W2", "b2", "W3", "b3"], gb, rb, bounds):
+        worst = float(np.max(np.abs(a - b) / bd))
+        say(f"  {name}: largest |error| / entry bound {worst:.3f}")
+        assert np.all(np.abs(a - b) <= bd), (name, worst)
+    assert np.all(gb[0][:, R.PAD] == 0.0)
+
+    # Adam on that gradient, and the pack of the new weights
+    pr, mr, vr = R.adam(p.astype(np.float64), m1.astype(np.float64), m2.astype(np.float64), g, 3,
+                        lr=1e-3)
+    got = pf.double().cpu().numpy()
+    assert np.abs(got - pr).max() <= 1e-6 * np.abs(pr).max()
+    eps32 = np.finfo(np.float32).eps
+    assert np.all(np.abs(m1f.double().cpu().numpy() - mr) <=
+                  4 * eps32 * (0.9 * np.abs(m1) + 0.1 * np.abs(g)))
+    assert np.all(np.abs(m2f.double().cpu().numpy() - vr) <=
+                  4 * eps32 * (0.999 * m2 + 0.001 * g * g))
+    W1n, _, W2n, _, W3n, _ = R.unpack(got)
+    packed = bf16_bits_to_f64(wpf)
+    n1, n2 = R.H * R.K, R.H * R.H
+    np.testing.assert_array_equal(packed[:n1], R.bf16(W1n).ravel())
+    np.testing.assert_array_equal(packed[n1:n1 + n2], R.bf16(W2n).ravel())
+    w3 = packed[n1 + n2:].reshape(32, R.H)
+    np.testing.assert_array_equal(w3[:4], R.bf16(W3n))
+    assert np.all(w3[4:] == 0.0)
+
+
 def corrected_case(NX, NY, NZ, seed, theta_scale=1.0):
     rng = np.random.default_rng(seed)
     s = coarse_state(NX, NY, NZ, seed)
