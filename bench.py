@@ -273,6 +273,77 @@ def learned_gradient_check(torch, M, dev, m=32768, seed=5):
     return {"rows": m, "block_rel_err": out}
 
 
+def learned_fused_gradient_check(torch, M, dev, B=8192, seed=6):
+    """The fused training step's gradient (monc_mlp_train_step, B cells on a
+    128 x 128 x 32 coarse grid of seeded fields: 4 B rows) against the FP64
+    oracle's backward from the separate kernels' activations and dY for the
+    same rows (the fused step computes each row with the same operations);
+    per parameter block, max |gpu - oracle| / max |oracle|."""
+    from oracle import mlp_ref as R
+    NX, NY, NZ = 128, 128, 32
+    rng = np.random.default_rng(seed)
+    mk = lambda a, b: rng.standard_normal((NX + 4, NY + 4, NZ)) * a + b
+    c0 = [mk(3.0, 1.0), mk(2.0, -0.5), mk(0.7, 0.0), mk(0.5, 300.0)]
+    c0[2][:, :, -1] = 0.0
+    c1 = [a + 0.5 * rng.standard_normal(a.shape) for a in c0]
+    c1[2][:, :, -1] = 0.0
+    tend = [0.1 * rng.standard_normal(a.shape) for a in c0]
+    dv = lambda arrs: [torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in arrs]
+    d0, d1, dte = dv(c0), dv(c1), dv(tend)
+    prof = dv([np.zeros(NZ), 1.2 * np.exp(-np.arange(NZ) / 5.0),
+               1.2 * np.exp(-(np.arange(NZ) + 0.5) / 5.0)])
+    n = NX * NY * NZ
+    cells = np.sort(rng.integers(0, n, B)).astype(np.int32)
+    k = cells % NZ
+    i, j = cells // (NY * NZ), (cells // NZ) % NY
+    xm = ((((i - 1) % NX) * NY + j) * NZ + k).astype(np.int32)
+    ym = ((i * NY + (j - 1) % NY) * NZ + k).astype(np.int32)
+    cx, cy, cd = dv([np.concatenate([cells, xm]), np.concatenate([cells, ym]), cells])
+    nterm = 4 * B - int(np.sum(k == NZ - 1))
+    norm = [1.0, 3.0, -0.5, 2.0, 0.0, 0.7, 300.0, 0.5]
+    scale, dt, m = [0.3, 0.2, 0.05, 0.01], 2.0, 4 * B
+    p = R.init_params(seed).astype(np.float32)
+    pd = torch.from_numpy(p.copy()).to(dev)
+    wp = torch.zeros(M.MONC_MLP_WPACK, dtype=torch.int16, device=dev)
+    M.monc_mlp_pack(pd, wp)
+    X = torch.zeros((m, R.K), dtype=torch.int16, device=dev)
+    M.monc_mlp_features(d0, norm, 0, cx, X.narrow(0, 0, 2 * B))
+    M.monc_mlp_features(d0, norm, 1, cy, X.narrow(0, 2 * B, 2 * B))
+    Y = torch.zeros((m, 4), dtype=torch.float32, device=dev)
+    H1 = torch.zeros((m, 64), dtype=torch.int16, device=dev)
+    H2 = torch.zeros_like(H1)
+    Z1 = torch.zeros((m, 64), dtype=torch.float32, device=dev)
+    Z2 = torch.zeros_like(Z1)
+    M.monc_mlp_forward(X, m, pd, wp, Y, H1, H2, Z1, Z2)
+    dY = torch.zeros((m, 4), dtype=torch.float32, device=dev)
+    loss = torch.zeros(1, dtype=torch.float32, device=dev)
+    wsl = torch.zeros(M.monc_mlp_loss_workspace_bytes(B), dtype=torch.uint8, device=dev)
+    M.monc_mlp_loss(Y, B, cd, d0, d1, dte, dt, scale, prof, 1.0 / nterm, dY, loss, wsl)
+    m1, m2 = torch.zeros_like(pd), torch.zeros_like(pd)
+    grad = torch.zeros_like(pd)
+    lf = torch.zeros(1, dtype=torch.float32, device=dev)
+    ws = torch.zeros(M.monc_mlp_train_workspace_bytes(B), dtype=torch.uint8, device=dev)
+    M.monc_mlp_train_step(d0, d1, dte, norm, cd, dt, scale, prof, 1.0 / nterm, pd, m1, m2, 1,
+                          1e-3, 0.9, 0.999, 1e-8, wp, grad, lf, ws)
+    torch.cuda.synchronize()
+    bf = lambda t: t.view(torch.bfloat16).double().cpu().numpy()
+    _, b1, W2, b2, W3, b3 = R.unpack(p.astype(np.float64))
+    cache = dict(Xb=bf(X), Z1=Z1.double().cpu().numpy(), H1=bf(H1), Z2=Z2.double().cpu().numpy(),
+                 H2=bf(H2), W2b=R.bf16(W2), W3b=R.bf16(W3))
+    ref = R.unpack(R.backward(dY.double().cpu().numpy(), cache, emulate=True))
+    got = R.unpack(grad.double().cpu().numpy())
+    out = {}
+    for name, a, b in zip(["W1", "b1", "W2", "b2", "W3"], got, ref):
+        out[name] = float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-30))
+    # b3's exact gradient is 0 (a constant flux has no divergence): report
+    # its largest entry against the sum of |dY|
+    out["b3_abs_over_sum_abs_dY"] = float(np.abs(got[5]).max() /
+                                          np.abs(dY.double().cpu().numpy()).sum(axis=0).max())
+    return {"rows": m, "cells": B, "block_rel_err": out,
+            "loss_rel_diff_vs_separate": abs(float(lf.item()) - float(loss.item())) /
+            float(loss.item())}
+
+
 def cpu_baseline():
     """The FP64 oracle, unchanged, timed on the host cores with one thread and
     with all of them: one forward step (every source term and the update) of
@@ -685,6 +756,8 @@ def main():
         if forms is not None and "learned" in forms:
             log("learned form: gradient check against the oracle")
             forms["learned"]["gradient_check"] = learned_gradient_check(torch, M, dev)
+            forms["learned"]["gradient_check"]["fused_step"] = learned_fused_gradient_check(
+                torch, M, dev)
     del host
 
     rec = {
