@@ -402,9 +402,11 @@ int monc_mlp_train_step(const double *const *c0, const double *const *c1,
  *    `growth` times that of the plain step from the same state, the step is
  *    the plain one.
  * flags: device int[4]; flags[0] is scratch, flags[1] and flags[2] count the
- * steps that fell back (non-finite, growth), flags[3] counts clamped theta
- * faces; the caller zeroes flags[1..3] once.  workspace: device memory of at
- * least monc_correct_step_workspace_bytes(nx, ny, nz) bytes; deterministic. */
+ * steps that fell back (non-finite, growth), flags[3] counts the clamped theta
+ * faces of the steps that did not fall back for non-finite outputs; the
+ * caller zeroes flags[1..3] once.  gx, gy 16-byte aligned.  workspace: device
+ * memory of at least monc_correct_step_workspace_bytes(nx, ny, nz) bytes;
+ * deterministic. */
 size_t monc_correct_step_workspace_bytes(int nx, int ny, int nz);
 int monc_correct_step(double *const *state_in, double *const *tend, const float *gx,
                       const float *gy, double *const *state_out, int nx, int ny, int nz,

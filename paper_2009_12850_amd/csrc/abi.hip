@@ -895,6 +895,8 @@ int monc_correct_step(double* const* state_in, double* const* tend, const float*
     if (!(growth > 0.0)) return fail(MONC_EINVAL, "growth must be > 0 (got %g)", growth);
     for (int q = 0; q < 4; q++)
         if (!isfinite(scale[q])) return fail(MONC_EINVAL, "scale[%d] is not finite", q);
+    if (((uintptr_t)gx | (uintptr_t)gy) & 15)
+        return fail(MONC_EINVAL, "gx, gy must be 16-byte aligned (one row of 4 floats per load)");
     return hip_status(launch_correct_step(state_in, tend, gx, gy, state_out, nx, ny, nz, dx, dy,
                                           scale, rdz, rho, rhon, dt, growth, flags, workspace,
                                           (hipStream_t)stream),

@@ -1359,9 +1359,13 @@ __global__ void __launch_bounds__(64 * UPD_GROUPS) mlp_update(UpdateArgs a) {
 //  * growth: if the corrected state's kinetic energy or theta variance exceeds
 //    `growth` times the plain step's, the whole step is the plain one (bit 2).
 // ---------------------------------------------------------------------------
+// The corrected step is computed unconditionally; the thread of a cell also
+// checks that cell's face outputs and sets bit 1 of flags[0] if one is not
+// finite, and corr_decide then makes the whole step the plain one.
 // partial sums: KE corrected, KE plain, m th^2 and m th corrected, the same
-// plain, and the mass m
-constexpr int CORR_NSUM = 7;
+// plain, the mass m, and the clamped theta faces (added to flags[3] unless
+// the step falls back for non-finite outputs)
+constexpr int CORR_NSUM = 8;
 
 struct CorrArgs {
     const double* in[4];
@@ -1371,6 +1375,7 @@ struct CorrArgs {
     const float* gy;
     int nx, ny, nz;
     double dx, dy, dt;
+    double rdx, rdy, dt_dx, dt_dy;  // 1/dx, 1/dy, dt/dx, dt/dy
     double scale[4];
     const double *rdz, *rho, *rhon;
     int* flags;
@@ -1380,14 +1385,6 @@ struct CorrArgs {
 
 __global__ void __launch_bounds__(256) corr_clear(int* flags) {
     if (threadIdx.x == 0) flags[0] = 0;
-}
-
-__global__ void __launch_bounds__(256) corr_check(const float* __restrict__ gx,
-                                                  const float* __restrict__ gy, long n,
-                                                  int* flags) {
-    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n) return;
-    if (!isfinite(gx[t]) || !isfinite(gy[t])) atomicOr(flags, 1);
 }
 
 // ULTIMATE-limited QUICKEST value of a face and its admissible interval
@@ -1432,32 +1429,54 @@ __device__ __forceinline__ double clamp_face(double a, const double* p, double d
     return Fc - F;
 }
 
+// Per-level factors of the corrected step: mass rhon dz, w mass rho dz (0 on
+// the lid), the inverse density ratios of the correction, 1/rhon.
+enum { CL_M, CL_MW, CL_RHN, CL_RHW, CL_RMK, CL_N };
+
 __global__ void __launch_bounds__(256) corr_step(CorrArgs a) {
-    __shared__ double red[CORR_NSUM][256];
+    __shared__ double lev[CL_N][MONC_MAX_NZ];
+    __shared__ double red[4][CORR_NSUM];
     const long n = (long)a.nx * a.ny * a.nz;
     const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool plain = (a.flags[0] & 1) != 0;
-    __shared__ int nclamp_block;
-    if (threadIdx.x == 0) nclamp_block = 0;
-    double sum[CORR_NSUM] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    int nclamp = 0;
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    for (int k = threadIdx.x; k < nz; k += blockDim.x) {
+        lev[CL_M][k] = a.rhon[k] / a.rdz[k];
+        lev[CL_MW][k] = k < nz - 1 ? a.rho[k] / a.rdz[k] : 0.0;
+        lev[CL_RHN][k] = a.rhon[0] / a.rhon[k];
+        lev[CL_RHW][k] = a.rho[0] / a.rho[k];
+        lev[CL_RMK][k] = 1.0 / a.rhon[k];
+    }
+    __syncthreads();
+    double sum[CORR_NSUM] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     if (t < n) {
-        const int nx = a.nx, ny = a.ny, nz = a.nz;
         const int k = (int)(t % nz), j = (int)((t / nz) % ny), i = (int)(t / ((long)nz * ny));
         const int im = i == 0 ? nx - 1 : i - 1, jm = j == 0 ? ny - 1 : j - 1;
         const long cm_x = ((long)im * ny + j) * nz + k, cm_y = ((long)i * ny + jm) * nz + k;
         const long sx = (long)(ny + 4) * nz;
         const long g = (long)(i + 2) * sx + (long)(j + 2) * nz + k;
-        const int sw[4] = {1, 0, 2, 3};
-        const double m = a.rhon[k] / a.rdz[k], mw = k < nz - 1 ? a.rho[k] / a.rdz[k] : 0.0;
-        double cq[4] = {0.0, 0.0, 0.0, 0.0};
-        if (!plain) {
+        const double m = lev[CL_M][k], mw = lev[CL_MW][k];
+        // this cell's face outputs, each checked once (by its cell's thread)
+        const float4 gxc = reinterpret_cast<const float4*>(a.gx)[t];
+        const float4 gyc = reinterpret_cast<const float4*>(a.gy)[t];
+        const float4 gxm = reinterpret_cast<const float4*>(a.gx)[cm_x];
+        const float4 gym = reinterpret_cast<const float4*>(a.gy)[cm_y];
+        const bool bad = !(isfinite(gxc.x) && isfinite(gxc.y) && isfinite(gxc.z) &&
+                           isfinite(gxc.w) && isfinite(gyc.x) && isfinite(gyc.y) &&
+                           isfinite(gyc.z) && isfinite(gyc.w));
+        if (bad) atomicOr(a.flags, 1);
+        double cq[4];
+        {
+            // y outputs are in the exchanged frame: u and v swapped
+            const double gxq[3] = {gxc.x, gxc.y, gxc.z}, gxmq[3] = {gxm.x, gxm.y, gxm.z};
+            const double gyq[3] = {gyc.y, gyc.x, gyc.z}, gymq[3] = {gym.y, gym.x, gym.z};
+#pragma unroll
             for (int q = 0; q < 3; q++) {
-                const double rh = q == 2 ? a.rho[k] / a.rho[0] : a.rhon[k] / a.rhon[0];
-                const double div = (double)a.gx[t * 4 + q] - (double)a.gx[cm_x * 4 + q] +
-                                   (double)a.gy[t * 4 + sw[q]] - (double)a.gy[cm_y * 4 + sw[q]];
-                cq[q] = -a.scale[q] * div / rh;
+                const double rhi = q == 2 ? lev[CL_RHW][k] : lev[CL_RHN][k];
+                const double div = gxq[q] - gxmq[q] + gyq[q] - gymq[q];
+                cq[q] = -a.scale[q] * div * rhi;
             }
+        }
+        {
             // theta: clamped face fluxes; G = h rhon(0) S g for a face of width h
             const double* th = a.in[3];
             const double* u = a.in[0];
@@ -1473,26 +1492,25 @@ __global__ void __launch_bounds__(256) corr_step(CorrArgs a) {
             // (-1, 0, +1, +2 from its left cell) start at index 1 for the face
             // i+1/2 (left cell i) and at index 0 for i-1/2 (left cell i-1)
             double px[5], py[5];
+#pragma unroll
             for (int o = 0; o < 5; o++) {
                 px[o] = at(th, wx(i - 2 + o), j);
                 py[o] = at(th, i, wy(j - 2 + o));
             }
             bool c1, c2, c3, c4;
-            const double Gxp = clamp_face(at(u, i, j), px + 1, a.dt / a.dx, mk,
-                                          cx * (double)a.gx[t * 4 + 3], c1);
-            const double Gxm = clamp_face(at(u, im, j), px, a.dt / a.dx, mk,
-                                          cx * (double)a.gx[cm_x * 4 + 3], c2);
-            const double Gyp = clamp_face(at(v, i, j), py + 1, a.dt / a.dy, mk,
-                                          cy * (double)a.gy[t * 4 + 3], c3);
-            const double Gym = clamp_face(at(v, i, jm), py, a.dt / a.dy, mk,
-                                          cy * (double)a.gy[cm_y * 4 + 3], c4);
-            cq[3] = -((Gxp - Gxm) / a.dx + (Gyp - Gym) / a.dy) / mk;
-            nclamp = (int)c1 + (int)c3;  // faces i+1/2 and j+1/2 belong to this cell
+            const double Gxp = clamp_face(at(u, i, j), px + 1, a.dt_dx, mk, cx * (double)gxc.w, c1);
+            const double Gxm = clamp_face(at(u, im, j), px, a.dt_dx, mk, cx * (double)gxm.w, c2);
+            const double Gyp = clamp_face(at(v, i, j), py + 1, a.dt_dy, mk, cy * (double)gyc.w, c3);
+            const double Gym = clamp_face(at(v, i, jm), py, a.dt_dy, mk, cy * (double)gym.w, c4);
+            cq[3] = -((Gxp - Gxm) * a.rdx + (Gyp - Gym) * a.rdy) * lev[CL_RMK][k];
+            sum[7] = (double)((int)c1 + (int)c3);  // faces i+1/2 and j+1/2 belong to this cell
         }
         double o[4], pl[4];
+#pragma unroll
         for (int q = 0; q < 4; q++) {
-            pl[q] = a.in[q][g] + a.dt * a.tend[q][g];
-            o[q] = a.in[q][g] + a.dt * (a.tend[q][g] + cq[q]);
+            const double in = a.in[q][g], td = a.tend[q][g];
+            pl[q] = in + a.dt * td;
+            o[q] = in + a.dt * (td + cq[q]);
             if (q == 2 && k == nz - 1) o[q] = pl[q] = 0.0;
             a.out[q][g] = o[q];
         }
@@ -1504,25 +1522,30 @@ __global__ void __launch_bounds__(256) corr_step(CorrArgs a) {
         sum[5] = m * pl[3];
         sum[6] = m;
     }
-    for (int q = 0; q < CORR_NSUM; q++) red[q][threadIdx.x] = sum[q];
-    __syncthreads();  // also orders the zeroing of nclamp_block before the adds
-    if (nclamp) atomicAdd(&nclamp_block, nclamp);
-    for (int st = 128; st > 0; st >>= 1) {
-        if (threadIdx.x < st)
-            for (int q = 0; q < CORR_NSUM; q++) red[q][threadIdx.x] += red[q][threadIdx.x + st];
-        __syncthreads();
+    // fixed-order workgroup sums: each wave by shuffles, then the four waves
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < CORR_NSUM; q++) {
+        double v = sum[q];
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        if (lane == 0) red[w][q] = v;
     }
-    if (threadIdx.x < CORR_NSUM) a.partial[(long)blockIdx.x * CORR_NSUM + threadIdx.x] = red[threadIdx.x][0];
-    // one global add per workgroup for the clamp count
-    if (threadIdx.x == 0 && nclamp_block) atomicAdd(a.flags + 3, nclamp_block);
+    __syncthreads();
+    if (threadIdx.x < CORR_NSUM) {
+        const int q = threadIdx.x;
+        a.partial[(long)blockIdx.x * CORR_NSUM + q] =
+            ((red[0][q] + red[1][q]) + red[2][q]) + red[3][q];
+    }
 }
 
 // Sums the block partials in a fixed order and takes the step's decision:
-// flags[1] counts non-finite fallbacks, flags[2] growth fallbacks.
+// flags[1] counts non-finite fallbacks, flags[2] growth fallbacks, flags[3]
+// the clamped theta faces of the steps that keep their correction; bit 2 of
+// flags[0] tells corr_revert to write the plain step.
 __global__ void __launch_bounds__(256) corr_decide(const double* __restrict__ partial, int nb,
                                                    double growth, int* flags) {
     __shared__ double red[CORR_NSUM][256];
-    double s[CORR_NSUM] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    double s[CORR_NSUM] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     for (int b = threadIdx.x; b < nb; b += 256)
         for (int q = 0; q < CORR_NSUM; q++) s[q] += partial[(long)b * CORR_NSUM + q];
     for (int q = 0; q < CORR_NSUM; q++) red[q][threadIdx.x] = s[q];
@@ -1534,9 +1557,11 @@ __global__ void __launch_bounds__(256) corr_decide(const double* __restrict__ pa
     }
     if (threadIdx.x == 0) {
         if (flags[0] & 1) {
+            flags[0] |= 2;
             flags[1] += 1;
             return;
         }
+        flags[3] += (int)red[7][0];
         const double ke_c = red[0][0], ke_p = red[1][0], mass = red[6][0];
         const double var_c = red[2][0] / mass - (red[3][0] / mass) * (red[3][0] / mass);
         const double var_p = red[4][0] / mass - (red[5][0] / mass) * (red[5][0] / mass);
@@ -1830,6 +1855,10 @@ hipError_t launch_correct_step(double* const* in, double* const* tend, const flo
     a.dx = dx;
     a.dy = dy;
     a.dt = dt;
+    a.rdx = 1.0 / dx;
+    a.rdy = 1.0 / dy;
+    a.dt_dx = dt / dx;
+    a.dt_dy = dt / dy;
     a.rdz = rdz;
     a.rho = rho;
     a.rhon = rhon;
@@ -1839,7 +1868,6 @@ hipError_t launch_correct_step(double* const* in, double* const* tend, const flo
     const long n = (long)nx * ny * nz;
     const int nb = blocks_for(n);
     corr_clear<<<1, 64, 0, s>>>(flags);
-    corr_check<<<blocks_for(n * 4), 256, 0, s>>>(gx, gy, n * 4, flags);
     corr_step<<<nb, 256, 0, s>>>(a);
     corr_decide<<<1, 256, 0, s>>>(a.partial, nb, growth, flags);
     corr_revert<<<nb, 256, 0, s>>>(a);

@@ -225,6 +225,11 @@ def test_learned_entry_points_validate_before_launch():
              50.0)
     assert L.monc_correct_step(*alias, scale, *prof, 2.0, 1.01, FAKE, FAKE,
                                None) == M.MONC_EINVAL
+    misaligned = (_block(4, 0x10000), _block(4, 0x20000), C.c_void_p(0x1004), FAKE,
+                  _block(4, 0x30000), 4, 4, 4, 50.0, 50.0)
+    assert L.monc_correct_step(*misaligned, scale, *prof, 2.0, 1.01, FAKE, FAKE,
+                               None) == M.MONC_EINVAL
+    assert b"16-byte" in L.monc_last_error()
     assert M.monc_correct_step_workspace_bytes(8, 8, 8) > 0
     assert M.monc_mlp_backward_workspace_bytes(0) == 0
     # fused training step: empty batch, t < 1, bad beta, zero scale, zero
