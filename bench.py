@@ -31,7 +31,8 @@ HBM_PEAK = 8.0e12  # B/s, MI355X HBM3E
 # Sources of the dominant kernel (the timed launch: the FP64 step with budgets):
 # a measured HBM traffic figure is reported
 # only while these files are unchanged since the counters were taken.
-KERNEL_SOURCES = ["paper_2009_12850_amd/csrc/march.hpp",
+KERNEL_SOURCES = ["paper_2009_12850_amd/build.py",  # compile flags
+                  "paper_2009_12850_amd/csrc/march.hpp",
                   "paper_2009_12850_amd/csrc/march_launch.hpp",
                   "paper_2009_12850_amd/csrc/march_step64.hip",
                   "paper_2009_12850_amd/csrc/monc_scheme.hpp",
