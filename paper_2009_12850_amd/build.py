@@ -27,21 +27,28 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # also lowers their register counts: 2-4 % faster on those forms, measured on
 # one box against the ILP ordering; the FP32/BF16 march, the work-scaled sweep
 # and the learned kernels keep the ILP ordering, which was as fast or faster
-# for them.
+# for them.  The step's unit also has the scheduler track register pressure
+# with the AMDGPU trackers (the budgeted step 1.3-1.7 % faster on two boxes;
+# the other units gained nothing from it).
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-ffp-contract=on",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-mllvm", "-amdgpu-sched-strategy=max-ilp",
          "-Wall", "-Wno-unused-function", "-Wno-unknown-pragmas"]
 MEMORY_CLAUSE_SOURCES = {"march_step64.hip", "march_f64.hip", "march_stepmix.hip",
                          "ensemble.hip"}
+RP_TRACKER_SOURCES = {"march_step64.hip"}
 
 
 def flags_for(src: str) -> list:
     """The compile flags of one source file."""
-    if os.path.basename(src) in MEMORY_CLAUSE_SOURCES:
-        return [("-amdgpu-sched-strategy=max-memory-clause"
-                 if f == "-amdgpu-sched-strategy=max-ilp" else f) for f in FLAGS]
-    return list(FLAGS)
+    name = os.path.basename(src)
+    flags = list(FLAGS)
+    if name in MEMORY_CLAUSE_SOURCES:
+        flags = [("-amdgpu-sched-strategy=max-memory-clause"
+                  if f == "-amdgpu-sched-strategy=max-ilp" else f) for f in flags]
+    if name in RP_TRACKER_SOURCES:
+        flags += ["-mllvm", "-amdgpu-use-amdgpu-trackers=1"]
+    return flags
 
 
 # Extra compile flags for build-time tuning, e.g. MONC_HIPCC_FLAGS=-DMONC_MARCH_WAVES64=4
