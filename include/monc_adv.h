@@ -151,6 +151,31 @@ int monc_advect_tvd(const double *u, const double *v, const double *w,
                     const double *rdz, const double *rho, const double *rhon,
                     double dt, monc_stream_t stream);
 
+/* The PW part and the TVD part of monc_advect for one narrow storage type
+ * (Sec. 4.1's single-precision advection as separate calls): FP32 copies
+ * (_f32) or bfloat16 bits (_bf16) in, FP32 arithmetic, FP32 source terms out;
+ * the layout, validation and aliasing rules of monc_advect_pw and
+ * monc_advect_tvd, and phi0 (host [nscal], or NULL for zeros) as for
+ * monc_advect.  The results are those of monc_advect with the same dtype. */
+int monc_advect_pw_f32(const float *u, const float *v, const float *w, float *su, float *sv,
+                       float *sw, int nx, int ny, int nz, double dx, double dy,
+                       const double *rdz, const double *rho, const double *rhon,
+                       monc_stream_t stream);
+int monc_advect_pw_bf16(const uint16_t *u, const uint16_t *v, const uint16_t *w, float *su,
+                        float *sv, float *sw, int nx, int ny, int nz, double dx, double dy,
+                        const double *rdz, const double *rho, const double *rhon,
+                        monc_stream_t stream);
+int monc_advect_tvd_f32(const float *u, const float *v, const float *w, int nscal,
+                        const float *const *q, float *const *sq, const double *phi0, int nx,
+                        int ny, int nz, double dx, double dy, const double *rdz,
+                        const double *rho, const double *rhon, double dt,
+                        monc_stream_t stream);
+int monc_advect_tvd_bf16(const uint16_t *u, const uint16_t *v, const uint16_t *w, int nscal,
+                         const uint16_t *const *q, float *const *sq, const double *phi0,
+                         int nx, int ny, int nz, double dx, double dy, const double *rdz,
+                         const double *rho, const double *rhon, double dt,
+                         monc_stream_t stream);
+
 /* ---------------------------------------------------------------------------
  * Fused source terms: PW for u, v, w and TVD for nscal scalars in one pass, in the
  * storage type `dtype` (MONC_F64: double in, double out; MONC_F32: float in,

@@ -49,6 +49,12 @@ _SIGS = {
                               ip),
     "monc_advect_tvd": ([vp, vp, vp, ip, PP, PP, ip, ip, ip, dp, dp, vp, vp, vp, dp, vp], ip),
     "monc_advect": ([ip, PP, PP, ip, DPTR, ip, ip, ip, dp, dp, vp, vp, vp, dp, vp], ip),
+    "monc_advect_pw_f32": ([vp, vp, vp, vp, vp, vp, ip, ip, ip, dp, dp, vp, vp, vp, vp], ip),
+    "monc_advect_pw_bf16": ([vp, vp, vp, vp, vp, vp, ip, ip, ip, dp, dp, vp, vp, vp, vp], ip),
+    "monc_advect_tvd_f32": ([vp, vp, vp, ip, PP, PP, DPTR, ip, ip, ip, dp, dp, vp, vp, vp, dp,
+                             vp], ip),
+    "monc_advect_tvd_bf16": ([vp, vp, vp, ip, PP, PP, DPTR, ip, ip, ip, dp, dp, vp, vp, vp, dp,
+                              vp], ip),
     "monc_step_workspace_bytes": ([ip, ip, ip, ip], C.c_size_t),
     "monc_step": ([PP, PP, ip, ip, ip, ip, dp, dp, vp, vp, vp, dp, vp, vp, vp], ip),
     "monc_step_static": ([PP, PP, ip, ip, ip, ip, dp, dp, vp, vp, vp, dp, vp, vp], ip),
@@ -255,6 +261,37 @@ def monc_advect(dtype, inputs, outputs, dx, dy, prof, dt, phi0=None, stream=None
         p0 = (C.c_double * max(nscal, 1))(*[float(x) for x in phi0])
     _check(lib().monc_advect(dtype, ia, oa, nscal, p0, nx, ny, nz, float(dx), float(dy),
                              *_prof(prof), float(dt), _stream(stream)), "monc_advect")
+
+
+def monc_advect_pw_narrow(dtype, u, v, w, su, sv, sw, dx, dy, prof, stream=None):
+    """monc_advect_pw_f32 (dtype MONC_F32: float32 velocities) or
+    monc_advect_pw_bf16 (MONC_BF16: int16 tensors holding bfloat16 bits);
+    float32 source terms."""
+    torch = _torch()
+    fn = {MONC_F32: "monc_advect_pw_f32", MONC_BF16: "monc_advect_pw_bf16"}[dtype]
+    nx, ny, nz = _grid(u)
+    sh = tuple(u.shape)
+    vel = [_ptr(x, _dtypes()[dtype], sh, n) for x, n in ((u, "u"), (v, "v"), (w, "w"))]
+    out = [_ptr(x, torch.float32, sh, n) for x, n in ((su, "su"), (sv, "sv"), (sw, "sw"))]
+    _check(getattr(lib(), fn)(*vel, *out, nx, ny, nz, float(dx), float(dy), *_prof(prof),
+                              _stream(stream)), fn)
+
+
+def monc_advect_tvd_narrow(dtype, u, v, w, q, sq, dx, dy, prof, dt, phi0=None, stream=None):
+    """monc_advect_tvd_f32 / _bf16: TVD source terms of the narrow scalar
+    copies q (list), float32 results into sq (list)."""
+    torch = _torch()
+    fn = {MONC_F32: "monc_advect_tvd_f32", MONC_BF16: "monc_advect_tvd_bf16"}[dtype]
+    nx, ny, nz = _grid(u)
+    sh = tuple(u.shape)
+    vel = [_ptr(x, _dtypes()[dtype], sh, n) for x, n in ((u, "u"), (v, "v"), (w, "w"))]
+    qa = _ptrs(q, _dtypes()[dtype], sh, "q")
+    sa = _ptrs(sq, torch.float32, sh, "sq")
+    p0 = None
+    if phi0 is not None:
+        p0 = (C.c_double * max(len(q), 1))(*[float(x) for x in phi0])
+    _check(getattr(lib(), fn)(*vel, len(q), qa, sa, p0, nx, ny, nz, float(dx), float(dy),
+                              *_prof(prof), float(dt), _stream(stream)), fn)
 
 
 def monc_step_workspace_bytes(nx, ny, nz, nscal):

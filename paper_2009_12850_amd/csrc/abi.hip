@@ -317,6 +317,85 @@ int monc_advect(int dtype, const void* const* in, void* const* out, int nscal,
         launch_advect(dtype, TEND, true, nscal > 0, false, a, (hipStream_t)stream), "advect");
 }
 
+// The PW or TVD part of monc_advect for one storage type (the precision
+// form's separate entry points).
+static int advect_part(int dtype, bool pw, const void* u, const void* v, const void* w,
+                       int nscal, const void* const* q, void* const* sq, void* su, void* sv,
+                       void* sw, const double* phi0, int nx, int ny, int nz, double dx,
+                       double dy, const double* rdz, const double* rho, const double* rhon,
+                       double dt, hipStream_t stream, const char* what) {
+    TRY(check_grid(nx, ny, nz));
+    TRY(check_spacing(dx, dy));
+    TRY(check_prof(rdz, rho, rhon));
+    const void* vel[3] = {u, v, w};
+    TRY(check_ptrs(3, vel, "velocity"));
+    AdvArgs a;
+    if (pw) {
+        const void* out[3] = {su, sv, sw};
+        TRY(check_ptrs(3, out, "tendency"));
+        TRY(check_alias(3, vel, 3, out));
+        fill_args(a, nx, ny, nz, dx, dy, 1.0, rdz, rho, rhon, 0);
+        for (int f = 0; f < 3; f++) {
+            a.in[f] = vel[f];
+            a.out[f] = const_cast<void*>(out[f]);
+        }
+    } else {
+        TRY(check_dt(dt));
+        TRY(check_nscal(nscal));
+        if (nscal < 1) return fail(MONC_EINVAL, "%s needs nscal >= 1", what);
+        TRY(check_ptrs(nscal, q, "q"));
+        TRY(check_ptrs(nscal, (const void* const*)sq, "sq"));
+        const void* in[3 + MONC_MAX_SCALARS];
+        for (int f = 0; f < 3; f++) in[f] = vel[f];
+        for (int s = 0; s < nscal; s++) in[3 + s] = q[s];
+        TRY(check_alias(3 + nscal, in, nscal, (const void* const*)sq));
+        fill_args(a, nx, ny, nz, dx, dy, dt, rdz, rho, rhon, nscal);
+        for (int f = 0; f < 3 + nscal; f++) a.in[f] = in[f];
+        for (int s = 0; s < nscal; s++) a.out[3 + s] = sq[s];
+        if (phi0)
+            for (int s = 0; s < nscal; s++) a.phi0[s] = phi0[s];
+    }
+    return hip_status(launch_advect(dtype, TEND, pw, !pw, false, a, stream), what);
+}
+
+int monc_advect_pw_f32(const float* u, const float* v, const float* w, float* su, float* sv,
+                       float* sw, int nx, int ny, int nz, double dx, double dy,
+                       const double* rdz, const double* rho, const double* rhon,
+                       monc_stream_t stream) {
+    return advect_part(MONC_F32, true, u, v, w, 0, nullptr, nullptr, su, sv, sw, nullptr, nx,
+                       ny, nz, dx, dy, rdz, rho, rhon, 0.0, (hipStream_t)stream,
+                       "advect_pw_f32");
+}
+
+int monc_advect_pw_bf16(const uint16_t* u, const uint16_t* v, const uint16_t* w, float* su,
+                        float* sv, float* sw, int nx, int ny, int nz, double dx, double dy,
+                        const double* rdz, const double* rho, const double* rhon,
+                        monc_stream_t stream) {
+    return advect_part(MONC_BF16, true, u, v, w, 0, nullptr, nullptr, su, sv, sw, nullptr, nx,
+                       ny, nz, dx, dy, rdz, rho, rhon, 0.0, (hipStream_t)stream,
+                       "advect_pw_bf16");
+}
+
+int monc_advect_tvd_f32(const float* u, const float* v, const float* w, int nscal,
+                        const float* const* q, float* const* sq, const double* phi0, int nx,
+                        int ny, int nz, double dx, double dy, const double* rdz,
+                        const double* rho, const double* rhon, double dt,
+                        monc_stream_t stream) {
+    return advect_part(MONC_F32, false, u, v, w, nscal, (const void* const*)q,
+                       (void* const*)sq, nullptr, nullptr, nullptr, phi0, nx, ny, nz, dx, dy,
+                       rdz, rho, rhon, dt, (hipStream_t)stream, "advect_tvd_f32");
+}
+
+int monc_advect_tvd_bf16(const uint16_t* u, const uint16_t* v, const uint16_t* w, int nscal,
+                         const uint16_t* const* q, float* const* sq, const double* phi0,
+                         int nx, int ny, int nz, double dx, double dy, const double* rdz,
+                         const double* rho, const double* rhon, double dt,
+                         monc_stream_t stream) {
+    return advect_part(MONC_BF16, false, u, v, w, nscal, (const void* const*)q,
+                       (void* const*)sq, nullptr, nullptr, nullptr, phi0, nx, ny, nz, dx, dy,
+                       rdz, rho, rhon, dt, (hipStream_t)stream, "advect_tvd_bf16");
+}
+
 size_t monc_step_workspace_bytes(int nx, int ny, int nz, int nscal) {
     (void)nscal;
     if (nx < 1 || ny < 1 || nz < 1) return 0;

@@ -120,6 +120,22 @@ def test_advect_rejects_unknown_dtype_and_tvd_needs_scalars():
     assert rc == M.MONC_EINVAL and b"aligned" in L.monc_last_error()
 
 
+def test_narrow_separate_entry_points_validate():
+    L = M.lib()
+    prof = _prof3()
+    assert L.monc_advect_pw_f32(FAKE, FAKE, None, FAKE, FAKE, FAKE, 8, 8, 8, 50.0, 50.0, *prof,
+                                None) == M.MONC_EINVAL
+    assert L.monc_advect_pw_bf16(FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, 8, 8, 1, 50.0, 50.0,
+                                 *prof, None) == M.MONC_EINVAL
+    assert L.monc_advect_tvd_f32(FAKE, C.c_void_p(0x2000), C.c_void_p(0x3000), 0,
+                                 _block(1, 0x10000), _block(1, 0x20000), None, 8, 8, 8, 50.0,
+                                 50.0, *prof, 0.5, None) == M.MONC_EINVAL
+    assert b"nscal" in L.monc_last_error()
+    assert L.monc_advect_tvd_bf16(FAKE, C.c_void_p(0x2000), C.c_void_p(0x3000), 1,
+                                  _block(1, 0x10000), _block(1, 0x20000), None, 8, 8, 8, 50.0,
+                                  50.0, *prof, -1.0, None) == M.MONC_EINVAL
+
+
 def test_budgets_check_maps_device_flags():
     b = np.zeros(M.MONC_NBUDGET)
     b[M.B_COURANT] = 0.3

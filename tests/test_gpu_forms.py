@@ -62,6 +62,34 @@ def test_fp32_tendencies_within_1e5_of_oracle(shape):
     assert max(errs) <= 1e-5, errs
 
 
+@pytest.mark.parametrize("dtype", [M.MONC_F32, M.MONC_BF16])
+@pytest.mark.parametrize("shape", [(37, 29, 45), (17, 23, 96)])
+def test_separate_narrow_entry_points_equal_the_fused_call(dtype, shape):
+    """monc_advect_pw_f32/_bf16 and monc_advect_tvd_f32/_bf16 give bitwise the
+    momentum and scalar outputs of monc_advect with the same dtype (whose
+    parity with the oracle the tests above establish)."""
+    nx, ny, nz = shape
+    say(f"separate narrow entry points dtype={dtype} {shape}")
+    T = torch()
+    g, host = case(nx, ny, nz, 2, seed=640 + nz)
+    dt, phi0 = 0.5, [300.0, 0.0]
+    d = to_dev(host)
+    tdt = T.float32 if dtype == M.MONC_F32 else T.int16
+    work = [T.empty(x.shape, dtype=tdt, device=dev()) for x in d]
+    M.monc_cast_working(dtype, d, work, [0.0, 0.0, 0.0] + phi0)
+    fused = [T.full(x.shape, np.nan, dtype=T.float32, device=dev()) for x in d]
+    M.monc_advect(dtype, work, fused, g.dx, g.dy, prof_dev(g), dt, phi0=phi0)
+    sep = [T.full(x.shape, np.nan, dtype=T.float32, device=dev()) for x in d]
+    M.monc_advect_pw_narrow(dtype, *work[:3], *sep[:3], g.dx, g.dy, prof_dev(g))
+    M.monc_advect_tvd_narrow(dtype, *work[:3], work[3:], sep[3:], g.dx, g.dy, prof_dev(g), dt,
+                             phi0=phi0)
+    T.cuda.synchronize()
+    for n, (a, b) in enumerate(zip(sep, fused)):
+        ia, ib = I.interior(a.cpu().numpy()), I.interior(b.cpu().numpy())
+        assert np.all(np.isfinite(ia)), n
+        np.testing.assert_array_equal(ia, ib)
+
+
 @pytest.mark.parametrize("shape", [(32, 32, 32), (40, 36, 128)])
 def test_bf16_storage_error_is_bounded(shape):
     nx, ny, nz = shape
