@@ -529,4 +529,6 @@ def run_experiment(nx=512, ny=512, nz=128, seeds=range(2000, 2016), n_train=12, 
         "speedup_vs_fine": t_fine / t_learned,
         "mlp_infer_ms": fwd_ms, "mlp_rows": 2 * N,
         "mlp_tflops": 2 * N * flop / (fwd_ms * 1e-3) / 1e12,
+        # against the dense BF16 MFMA peak of the device (2.5 PFLOP/s)
+        "mlp_frac_of_bf16_peak": 2 * N * flop / (fwd_ms * 1e-3) / 2.5e15,
     }
