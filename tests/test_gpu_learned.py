@@ -326,7 +326,7 @@ def train_case(NX, NY, NZ, B, seed):
 
 
 @pytest.mark.parametrize("shape,B", [((12, 10, 7), 5), ((12, 10, 7), 300),
-                                     ((128, 128, 32), 8192)])
+                                     ((128, 128, 32), 8192), ((128, 128, 32), 20000)])
 def test_fused_train_step_matches_oracle(shape, B):
     """monc_mlp_train_step against the oracle.  Its rows are the separate
     entry points' rows (features, forward, loss), so the oracle's gradient is
@@ -335,7 +335,8 @@ def test_fused_train_step_matches_oracle(shape, B):
     separate loss and 1e-5 of the oracle's; the Adam step and the pack as in
     test_adam_and_pack_match_oracle.  B = 5 (one partial chunk: every row
     weighs on the gradient, so a wrong feature would show), 300 (ragged
-    chunks) and the 8192-cell training batch (two chunks per workgroup)."""
+    chunks), the 8192-cell training batch (two chunks per workgroup) and
+    20000 cells (four or five chunks per workgroup)."""
     NX, NY, NZ = shape
     say(f"fused training step {shape} B={B}")
     T = torch()
