@@ -23,14 +23,18 @@
 // own dt/spacing factor, so the w faces pass the mass flux itself.
 //
 // One thread per grid point of a column's 64-level chunk.  A workgroup is
-// four columns along y (one wave each) that march together through a segment
-// of x-planes: the x-stencil of each column stays in a four-plane register
-// window, the east face of a plane is the next plane's west face, and the
-// north face of a column is handed to the next column's wave through LDS, so
-// a lateral face is evaluated once (the faces on segment and workgroup edges
-// twice).  The z-faces of a column are evaluated by both levels that share
-// them.  The per-level geometry is built once per workgroup in LDS.  Periodic
-// neighbours are read at wrapped indices; halos are neither read nor written.
+// four columns along y, one wave per column and chunk (every chunk of those
+// columns), that march together through a segment of x-planes: the x-stencil
+// of each column stays in a four-plane register window, the east face of a
+// plane is the next plane's west face, and the north face of a column is
+// handed to the next column's wave through LDS, so a lateral face is
+// evaluated once (the faces on segment and workgroup edges twice).  A level
+// evaluates its top z-faces; its bottom faces are the top faces of the level
+// below, from the lane below, or across a chunk boundary from the chunk
+// below's last lane through LDS; only the lowest level evaluates the w face at
+// the centre of the lowest cell (nothing passes the ground for u and v).  The
+// per-level geometry is built once per workgroup in LDS.  Periodic neighbours
+// are read at wrapped indices; halos are neither read nor written.
 #include "monc_internal.hpp"
 #include "monc_scheme.hpp"
 
@@ -38,10 +42,12 @@ namespace monc {
 
 namespace {
 
-constexpr int TM_TJ = 4;   // columns (waves) per workgroup, along y
+constexpr int TM_TJ = 2;   // columns per workgroup, along y
 constexpr int TM_TI = 64;  // x-planes per segment
-// Level table of the chunk: levels k0-1 .. k0+64.
-constexpr int TM_LEV = 66;
+constexpr int TM_NCH = 2;  // 64-level chunks per column at most
+// Level table: levels -1 .. nz (entry q + 1 for level q).
+constexpr int TM_LEV = MONC_MAX_NZ + 2;
+static_assert(MONC_MAX_NZ <= 64 * TM_NCH, "columns fit the chunks of a workgroup");
 enum { L_RDZ, L_RHON, L_RHO, L_RHONI, L_RHOI, L_RDZN, L_DZN, L_ALPHA, L_BETA, L_CZ, L_RZ, L_N };
 
 // Flux through a z-face whose far-upwind value may not exist (next to the
@@ -63,14 +69,15 @@ __global__ void tvdmom_clear(double* cmax) {
     if (threadIdx.x == 0) cmax[0] = 0.0;
 }
 
-// Two waves per SIMD: the march holds 215 registers without spilling.  A
-// three-wave ceiling (168) spills 21 of them inside the plane loop and ran
+// Two waves per SIMD: the march holds about 210 registers without spilling.
+// A three-wave ceiling (168) spilled 21 of them inside the plane loop and ran
 // 38 % slower; with scheduling barriers between the loop's phases it still
-// spills 12 and ran 9 % slower.
+// spilled 12 and ran 9 % slower.
 template <bool STEPF>
-__global__ void __launch_bounds__(64 * TM_TJ) tvdmom_kernel(TvdMomArgs A) {
+__global__ void __launch_bounds__(64 * TM_TJ * TM_NCH) tvdmom_kernel(TvdMomArgs A) {
     __shared__ double tab[L_N][TM_LEV];
-    __shared__ double north[2][TM_TJ][3][64];  // by plane parity
+    __shared__ double north[2][TM_NCH][TM_TJ][3][64];  // by plane parity
+    __shared__ double zlast[2][TM_NCH][TM_TJ][3];     // top faces of a chunk's last level
     const int nx = A.nx, ny = A.ny, nz = A.nz;
     // Consecutive workgroups go to the same XCD (they are dealt to the 8 XCDs
     // round-robin); neighbouring column groups of one segment are consecutive,
@@ -78,12 +85,11 @@ __global__ void __launch_bounds__(64 * TM_TJ) tvdmom_kernel(TvdMomArgs A) {
     int b = blockIdx.x;
     const int nb = gridDim.x;
     if ((nb & 7) == 0) b = (b & 7) * (nb >> 3) + (b >> 3);
-    const int nchunk = (nz + 63) / 64;
     const int njt = (ny + TM_TJ - 1) / TM_TJ;
-    const int chunk = b % nchunk;
-    const int jt = (b / nchunk) % njt;
-    const int seg = b / (nchunk * njt);
-    const int wv = (int)threadIdx.y;  // column in the workgroup
+    const int jt = b % njt;
+    const int seg = b / njt;
+    const int wv = (int)threadIdx.y % TM_TJ;  // column in the workgroup
+    const int chunk = (int)threadIdx.y / TM_TJ;
     const int lane = (int)threadIdx.x;
     const int k0 = 64 * chunk;
     const int k = k0 + lane;
@@ -96,9 +102,9 @@ __global__ void __launch_bounds__(64 * TM_TJ) tvdmom_kernel(TvdMomArgs A) {
 
     // level table (one division set per level per workgroup)
     {
-        const int t = wv * 64 + lane;
-        if (t < TM_LEV) {
-            const int q = k0 - 1 + t;
+        const int t = (int)threadIdx.y * 64 + lane;
+        if (t < nz + 2) {
+            const int q = t - 1;
             double row[L_N];
             for (int e = 0; e < L_N; e++) row[e] = 0.0;
             if (q >= 0 && q < nz) {
@@ -170,21 +176,19 @@ __global__ void __launch_bounds__(64 * TM_TJ) tvdmom_kernel(TvdMomArgs A) {
     }
 
     __syncthreads();  // level table ready
-    const int r = kc - k0 + 1;  // row of level k; k-1 and k+1 are its neighbours
+    const int r = kc + 1;  // row of level k; k-1 and k+1 are its neighbours
     const double rdz_k = tab[L_RDZ][r], rhon_k = tab[L_RHON][r], rho_k = tab[L_RHO][r];
     const double rhon_inv = tab[L_RHONI][r], rho_inv = tab[L_RHOI][r];
     const double rdzn_k = tab[L_RDZN][r], dzn_k = tab[L_DZN][r];
     const double alpha = tab[L_ALPHA][r], beta = tab[L_BETA][r];
     const double cz_b = tab[L_CZ][r], rz_b = tab[L_RZ][r];
     const double cz_t = tab[L_CZ][r + 1], rz_t = tab[L_RZ][r + 1], rho_kp = tab[L_RHO][r + 1];
-    const double rho_km = tab[L_RHO][r - 1], rdzn_km = tab[L_RDZN][r - 1],
-                 dzn_km = tab[L_DZN][r - 1];
+    const double rho_km = tab[L_RHO][r - 1];
 
     const double cdx = A.cdx, cdy = A.cdy, rfx = A.rfx, rfy = A.rfy;
     const double cwx = cdx * rho_inv, cwy = cdy * rho_inv;
     const double rwx = rfx * rho_k, rwy = rfy * rho_k;
     const double czu_t = A.dt * rdzn_k, rzu_t = dzn_k * A.rdt;
-    const double czu_b = A.dt * rdzn_km, rzu_b = dzn_km * A.rdt;
 
     // west faces of the first plane: the east faces of the plane before it,
     // evaluated the same way
@@ -224,15 +228,13 @@ __global__ void __launch_bounds__(64 * TM_TJ) tvdmom_kernel(TvdMomArgs A) {
         const double wyp1 = wlev ? W[p0 + ojp1 + kc] : 0.0;
         const double wyp2 = wlev ? W[p0 + ojp2 + kc] : 0.0;
         // z-stencils of the own column at plane i, from the neighbouring lanes
-        const double uzm2 = below(u0, U, c00, 2, zm2), uzm1 = below(u0, U, c00, 1, zm1);
+        const double uzm1 = below(u0, U, c00, 1, zm1);
         const double uzp1 = above(u0, U, c00, 1, zp1), uzp2 = above(u0, U, c00, 2, zp2);
-        const double vzm2 = below(v0, V, c00, 2, zm2), vzm1 = below(v0, V, c00, 1, zm1);
+        const double vzm1 = below(v0, V, c00, 1, zm1);
         const double vzp1 = above(v0, V, c00, 1, zp1), vzp2 = above(v0, V, c00, 2, zp2);
         const double wzm1 = below(w0, W, c00, 1, zm1), wzm2 = below(w0, W, c00, 2, zm2);
         const double wzp1 = above(w0, W, c00, 1, kc + 1 <= nz - 2);
         const double wzp2 = above(w0, W, c00, 2, kc + 2 <= nz - 2);
-        const double w_xp1zm1 = below(xw[2], W, pp1 + oj, 1, zm1);
-        const double w_yp1zm1 = below(wyp1, W, p0 + ojp1, 1, zm1);
 
         // ---- east faces (the next plane's west faces) ----
         const double a_ue = 0.5 * (u0 + xu[2]), a_ve = 0.5 * (u0 + uyp1);
@@ -247,9 +249,9 @@ __global__ void __launch_bounds__(64 * TM_TJ) tvdmom_kernel(TvdMomArgs A) {
         const double fn_v = tvd_flux(a_vn, vym1, v0, vyp1, vyp2, cdy, rfy, rhon_k);
         const double fn_w = tvd_flux(m_wn, wym1, w0, wyp1, wyp2, cwy, rwy, 1.0);
         const int par = i & 1;
-        north[par][wv][0][lane] = fn_u;
-        north[par][wv][1][lane] = fn_v;
-        north[par][wv][2][lane] = fn_w;
+        north[par][chunk][wv][0][lane] = fn_u;
+        north[par][chunk][wv][1][lane] = fn_v;
+        north[par][chunk][wv][2][lane] = fn_w;
         // ---- south faces: evaluated by the first column of the workgroup ----
         double fs_u = 0.0, fs_v = 0.0, fs_w = 0.0;
         if (wv == 0) {
@@ -264,35 +266,51 @@ __global__ void __launch_bounds__(64 * TM_TJ) tvdmom_kernel(TvdMomArgs A) {
             fs_w = tvd_flux(m_ws, wym2, wym1, w0, wyp1, cwy, rwy, 1.0);
             cm = fmax(cm, fmax(fmax(fabs(a_us), fabs(a_vs)) * cdy, wlev ? fabs(m_ws) * cwy : 0.0));
         }
-        // ---- z faces (top k+1/2 and bottom k-1/2 of u, v; centres k+1 and k of w) ----
-        const double a_ut = 0.5 * (w0 + xw[2]), a_ub = 0.5 * (wzm1 + w_xp1zm1);
-        const double a_vt = 0.5 * (w0 + wyp1), a_vb = 0.5 * (wzm1 + w_yp1zm1);
+        // ---- z faces: top k+1/2 of u, v and the centre k+1 of w; the bottom
+        // faces are the top faces of the level below ----
+        const double a_ut = 0.5 * (w0 + xw[2]), a_vt = 0.5 * (w0 + wyp1);
         const double ft_u = wlev ? zface(a_ut, uzm1, u0, uzp1, uzp2, zm1, zp2, czu_t, rzu_t, rho_k)
                                  : 0.0;
-        const double fb_u = zm1 ? zface(a_ub, uzm2, uzm1, u0, uzp1, zm2, zp1, czu_b, rzu_b, rho_km)
-                                : 0.0;
         const double ft_v = wlev ? zface(a_vt, vzm1, v0, vzp1, vzp2, zm1, zp2, czu_t, rzu_t, rho_k)
                                  : 0.0;
-        const double fb_v = zm1 ? zface(a_vb, vzm2, vzm1, v0, vzp1, zm2, zp1, czu_b, rzu_b, rho_km)
-                                : 0.0;
         const double m_wt = 0.5 * (rho_k * w0 + rho_kp * wzp1);
         const double m_wb = 0.5 * (rho_km * wzm1 + rho_k * w0);
         // top: between w_k and w_{k+1}, far values w_{k-1} (always there: the
         // ground at k = 0) and w_{k+2} (there up to the lid)
         const double ft_w = zface(m_wt, wzm1, w0, wzp1, wzp2, true, kc + 2 <= nz - 1, cz_t, rz_t,
                                   1.0);
-        // bottom: between w_{k-1} and w_k, far values w_{k-2} (there from k = 1)
-        // and w_{k+1}
-        const double fb_w = zface(m_wb, wzm2, wzm1, w0, wzp1, zm1, true, cz_b, rz_b, 1.0);
+        double fb_u = __shfl_up(ft_u, 1, 64), fb_v = __shfl_up(ft_v, 1, 64),
+               fb_w = __shfl_up(ft_w, 1, 64);
+        if (chunk == 0) {
+            // the lowest level: nothing passes the ground for u and v; the w
+            // face at the centre of the lowest cell, between the ground and w_0
+            const double fw0 = zface(m_wb, wzm2, wzm1, w0, wzp1, zm1, true, cz_b, rz_b, 1.0);
+            if (lane == 0) {
+                fb_u = 0.0;
+                fb_v = 0.0;
+                fb_w = fw0;
+            }
+        }
+        // a chunk's last level hands its top faces to the next chunk's first
+        if (lane == 63) {
+            zlast[par][chunk][wv][0] = ft_u;
+            zlast[par][chunk][wv][1] = ft_v;
+            zlast[par][chunk][wv][2] = ft_w;
+        }
 
         // The north faces of this plane are in LDS.  They are double-buffered
         // by plane parity: a wave writes the other buffer next, and cannot
         // reach the plane after that before every wave has passed this barrier.
         __syncthreads();
         if (wv > 0) {
-            fs_u = north[par][wv - 1][0][lane];
-            fs_v = north[par][wv - 1][1][lane];
-            fs_w = north[par][wv - 1][2][lane];
+            fs_u = north[par][chunk][wv - 1][0][lane];
+            fs_v = north[par][chunk][wv - 1][1][lane];
+            fs_w = north[par][chunk][wv - 1][2][lane];
+        }
+        if (chunk > 0 && lane == 0) {
+            fb_u = zlast[par][chunk - 1][wv][0];
+            fb_v = zlast[par][chunk - 1][wv][1];
+            fb_w = zlast[par][chunk - 1][wv][2];
         }
 
         const double su =
@@ -317,12 +335,13 @@ __global__ void __launch_bounds__(64 * TM_TJ) tvdmom_kernel(TvdMomArgs A) {
         if (A.cmax) {
             cm = fmax(cm, fmax(fmax(fabs(a_ue), fabs(a_ve)) * cdx,
                                fmax(fabs(a_un), fabs(a_vn)) * cdy));
+            // a bottom face is the top face of the level below, counted there;
+            // the lowest level also counts the w face at the lowest centre
             if (wlev) {
                 cm = fmax(cm, fmax(fabs(a_ut), fabs(a_vt)) * czu_t);
                 cm = fmax(cm, fmax(fabs(m_we) * cwx, fabs(m_wn) * cwy));
                 cm = fmax(cm, fmax(fabs(m_wt) * cz_t, fabs(m_wb) * cz_b));
             }
-            if (zm1) cm = fmax(cm, fmax(fabs(a_ub), fabs(a_vb)) * czu_b);
         }
 
         fw_u = fe_u;
@@ -361,13 +380,14 @@ hipError_t launch_tvd_momentum(const TvdMomArgs& a, bool step, hipStream_t s) {
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    const long nb = (long)((a.nz + 63) / 64) * ((a.ny + TM_TJ - 1) / TM_TJ) *
-                    ((a.nx + TM_TI - 1) / TM_TI);
+    const int nch = (a.nz + 63) / 64;
+    if (nch > TM_NCH) return hipErrorInvalidValue;
+    const long nb = (long)((a.ny + TM_TJ - 1) / TM_TJ) * ((a.nx + TM_TI - 1) / TM_TI);
     if (nb > 0x7fffffffL) return hipErrorInvalidValue;
     if (step)
-        tvdmom_kernel<true><<<(unsigned)nb, dim3(64, TM_TJ), 0, s>>>(a);
+        tvdmom_kernel<true><<<(unsigned)nb, dim3(64, TM_TJ * nch), 0, s>>>(a);
     else
-        tvdmom_kernel<false><<<(unsigned)nb, dim3(64, TM_TJ), 0, s>>>(a);
+        tvdmom_kernel<false><<<(unsigned)nb, dim3(64, TM_TJ * nch), 0, s>>>(a);
     return hipGetLastError();
 }
 
