@@ -23,7 +23,7 @@
 // own dt/spacing factor, so the w faces pass the mass flux itself.
 //
 // One thread per grid point of a column's 64-level chunk.  A workgroup is
-// four columns along y, one wave per column and chunk (every chunk of those
+// two columns along y, one wave per column and chunk (every chunk of those
 // columns), that march together through a segment of x-planes: the x-stencil
 // of each column stays in a four-plane register window, the east face of a
 // plane is the next plane's west face, and the north face of a column is
@@ -69,10 +69,11 @@ __global__ void tvdmom_clear(double* cmax) {
     if (threadIdx.x == 0) cmax[0] = 0.0;
 }
 
-// Two waves per SIMD: the march holds about 210 registers without spilling.
-// A three-wave ceiling (168) spilled 21 of them inside the plane loop and ran
-// 38 % slower; with scheduling barriers between the loop's phases it still
-// spilled 12 and ran 9 % slower.
+// Two waves per SIMD: the march holds about 195 registers without spilling.
+// A three-wave ceiling (168) spilled about 20 of them inside the plane loop
+// and ran 38 % slower; with scheduling barriers between the loop's phases it
+// still spilled 12 and ran 9 % slower.  Four columns per workgroup (eight
+// waves, one workgroup per CU) ran 17 % slower than two.
 template <bool STEPF>
 __global__ void __launch_bounds__(64 * TM_TJ * TM_NCH) tvdmom_kernel(TvdMomArgs A) {
     __shared__ double tab[L_N][TM_LEV];
