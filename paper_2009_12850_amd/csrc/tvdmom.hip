@@ -70,10 +70,9 @@ __global__ void tvdmom_clear(double* cmax) {
 }
 
 // Two waves per SIMD: the march holds about 195 registers without spilling.
-// A three-wave ceiling (168) spilled about 20 of them inside the plane loop
-// and ran 38 % slower; with scheduling barriers between the loop's phases it
-// still spilled 12 and ran 9 % slower.  Four columns per workgroup (eight
-// waves, one workgroup per CU) ran 17 % slower than two.
+// A three-wave ceiling (168) spills 8-10 of them and ran 10-17 % slower.
+// Four columns per workgroup (eight waves, one workgroup per CU) ran 17 %
+// slower than two.
 template <bool STEPF>
 __global__ void __launch_bounds__(64 * TM_TJ * TM_NCH) tvdmom_kernel(TvdMomArgs A) {
     __shared__ double tab[L_N][TM_LEV];
