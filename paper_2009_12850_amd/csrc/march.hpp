@@ -475,7 +475,7 @@ __device__ __forceinline__ void march_tile(const AdvArgs& a, const TileJob& tj,
     Ahead S[DEPTH];
     double acc[BUD ? NACC : 1];
     int nonfinite = 0;  // non-finite values written by this wave
-    double amax[3] = {0.0, 0.0, 0.0};  // largest |u|, |v|, |w| (FP32 compute only)
+    double amax[3] = {0.0, 0.0, 0.0};  // largest |u|, |v|, |w| over the march
     if constexpr (BUD) {
 #pragma unroll
         for (int q = 0; q < NACC; q++) acc[q] = bud_ident(bud_op(q));
@@ -575,12 +575,12 @@ __device__ __forceinline__ void march_tile(const AdvArgs& a, const TileJob& tj,
                 const double nsv = (double)pown + dt * (double)val;
                 bstore(plane_rsrc((double*)a.out[3 + tj.s0 + s] + gplane, wbytes64), woff64, nsv);
                 if constexpr (BUD) {
-                    if (store) {
-                        const double phd = (double)pown;
-                        acc[MONC_B_SCALAR0 + 3 * s] += (double)val;
-                        acc[MONC_B_SCALAR0 + 3 * s + 1] += phd;
-                        acc[MONC_B_SCALAR0 + 3 * s + 2] = fmin(acc[MONC_B_SCALAR0 + 3 * s + 2], phd);
-                    }
+                    // every lane sums; a lane that stores nothing drops its
+                    // sums after the march
+                    const double phd = (double)pown;
+                    acc[MONC_B_SCALAR0 + 3 * s] += (double)val;
+                    acc[MONC_B_SCALAR0 + 3 * s + 1] += phd;
+                    acc[MONC_B_SCALAR0 + 3 * s + 2] = fmin(acc[MONC_B_SCALAR0 + 3 * s + 2], phd);
                     nonfinite += __popcll(__ballot(store && !isfinite(nsv)));
                 }
             }
@@ -740,33 +740,27 @@ __device__ __forceinline__ void march_tile(const AdvArgs& a, const TileJob& tj,
                     // Per-lane sums over the march (one level k per lane): the
                     // level's weights (rhon dz, rho dzn, -dz/4) multiply once at
                     // the end, and non-finite values are counted per wave.
-                    if (store) {
-                        const double ucd = (double)U[1], umd = (double)U[0];
-                        const double vcd = (double)V[1], vsd = (double)vs;
-                        const double wcd = (double)W[1], wbd = (double)wb;
-                        const double Dd = (double)D;
-                        acc[MONC_B_CU] += (double)su;
-                        acc[MONC_B_CV] += (double)sv;
-                        acc[MONC_B_PU] = fma(ucd, (double)su, acc[MONC_B_PU]);
-                        acc[MONC_B_PV] = fma(vcd, (double)sv, acc[MONC_B_PV]);
-                        acc[MONC_B_QU] = fma(Dd, fma(ucd, ucd, umd * umd), acc[MONC_B_QU]);
-                        acc[MONC_B_QV] = fma(Dd, fma(vcd, vcd, vsd * vsd), acc[MONC_B_QV]);
-                        acc[MONC_B_QW] = fma(Dd, fma(wcd, wcd, wbd * wbd), acc[MONC_B_QW]);
-                        acc[MONC_B_CW] += (double)sw;
-                        acc[MONC_B_PW] = fma(wcd, (double)sw, acc[MONC_B_PW]);
-                        if constexpr (std::is_same<T, double>::value) {
-                            const double cr = fmax(fmax(fabs(ucd) * cdx, fabs(vcd) * cdy),
-                                                   fabs(wcd) * dt * (double)L.rdzn);
-                            acc[MONC_B_COURANT] = fmax(acc[MONC_B_COURANT], cr);
-                        } else {
-                            // FP32 level table: keep |u|, |v|, |w| and scale by
-                            // the FP64 spacings at the end (scaling is monotone,
-                            // so the maximum is the same)
-                            amax[0] = fmax(amax[0], fabs(ucd));
-                            amax[1] = fmax(amax[1], fabs(vcd));
-                            amax[2] = fmax(amax[2], fabs(wcd));
-                        }
-                    }
+                    // Every lane sums (whether a lane stores is fixed for the
+                    // march); one that stores nothing drops its sums at the
+                    // end.  The Courant number keeps the largest |u|, |v|,
+                    // |w| and scales them at the end: scaling by a positive
+                    // factor is monotone, so the maximum is the same.
+                    const double ucd = (double)U[1], umd = (double)U[0];
+                    const double vcd = (double)V[1], vsd = (double)vs;
+                    const double wcd = (double)W[1], wbd = (double)wb;
+                    const double Dd = (double)D;
+                    acc[MONC_B_CU] += (double)su;
+                    acc[MONC_B_CV] += (double)sv;
+                    acc[MONC_B_PU] = fma(ucd, (double)su, acc[MONC_B_PU]);
+                    acc[MONC_B_PV] = fma(vcd, (double)sv, acc[MONC_B_PV]);
+                    acc[MONC_B_QU] = fma(Dd, fma(ucd, ucd, umd * umd), acc[MONC_B_QU]);
+                    acc[MONC_B_QV] = fma(Dd, fma(vcd, vcd, vsd * vsd), acc[MONC_B_QV]);
+                    acc[MONC_B_QW] = fma(Dd, fma(wcd, wcd, wbd * wbd), acc[MONC_B_QW]);
+                    acc[MONC_B_CW] += (double)sw;
+                    acc[MONC_B_PW] = fma(wcd, (double)sw, acc[MONC_B_PW]);
+                    amax[0] = fmax(amax[0], fabs(ucd));
+                    amax[1] = fmax(amax[1], fabs(vcd));
+                    amax[2] = fmax(amax[2], fabs(wcd));
                     nonfinite += __popcll(__ballot(store && !isfinite(nu))) +
                                  __popcll(__ballot(store && !isfinite(nv))) +
                                  __popcll(__ballot(store && !isfinite(nw)));
@@ -835,6 +829,10 @@ __device__ __forceinline__ void march_tile(const AdvArgs& a, const TileJob& tj,
         // the level's weights in FP64 from the profiles (the level table may
         // be FP32), the wave's count (lane 0)
         {
+            if (!store) {
+#pragma unroll
+                for (int q = 0; q < NACC; q++) acc[q] = bud_ident(bud_op(q));
+            }
             double mass = 0.0, wmass = 0.0, qf = 0.0, rdzn = 0.0;
             if (k < nz) {
                 const double dzk = 1.0 / a.rdz[k];
@@ -860,9 +858,15 @@ __device__ __forceinline__ void march_tile(const AdvArgs& a, const TileJob& tj,
                 acc[MONC_B_SCALAR0 + 3 * s] *= mass;
                 acc[MONC_B_SCALAR0 + 3 * s + 1] *= mass;
             }
-            if constexpr (PW && !std::is_same<T, double>::value)
-                acc[MONC_B_COURANT] =
-                    fmax(fmax(amax[0] * cdx, amax[1] * cdy), amax[2] * dt * rdzn);
+            if constexpr (PW) {
+                // FP64 compute scales by the level table's 1/dzn, which is
+                // what the faces use
+                const double rz =
+                    std::is_same<T, double>::value ? (double)lev[LV_RDZN * NZP + k] : rdzn;
+                if (store)
+                    acc[MONC_B_COURANT] =
+                        fmax(fmax(amax[0] * cdx, amax[1] * cdy), amax[2] * dt * rz);
+            }
             (void)rdzn;
             acc[MONC_B_NONFINITE] = lane == 0 ? (double)nonfinite : 0.0;
         }
