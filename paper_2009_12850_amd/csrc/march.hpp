@@ -474,7 +474,7 @@ __device__ __forceinline__ void march_tile(const AdvArgs& a, const TileJob& tj,
     constexpr int DEPTH = 2;
     Ahead S[DEPTH];
     double acc[BUD ? NACC : 1];
-    int nonfinite = 0;  // non-finite values written by this wave
+    int nonfinite = 0;  // non-finite values written by this lane
     double amax[3] = {0.0, 0.0, 0.0};  // largest |u|, |v|, |w| over the march
     if constexpr (BUD) {
 #pragma unroll
@@ -575,13 +575,13 @@ __device__ __forceinline__ void march_tile(const AdvArgs& a, const TileJob& tj,
                 const double nsv = (double)pown + dt * (double)val;
                 bstore(plane_rsrc((double*)a.out[3 + tj.s0 + s] + gplane, wbytes64), woff64, nsv);
                 if constexpr (BUD) {
-                    // every lane sums; a lane that stores nothing drops its
-                    // sums after the march
+                    // every lane sums and counts; a lane that stores nothing
+                    // drops its sums and count after the march
                     const double phd = (double)pown;
                     acc[MONC_B_SCALAR0 + 3 * s] += (double)val;
                     acc[MONC_B_SCALAR0 + 3 * s + 1] += phd;
                     acc[MONC_B_SCALAR0 + 3 * s + 2] = fmin(acc[MONC_B_SCALAR0 + 3 * s + 2], phd);
-                    nonfinite += __popcll(__ballot(store && !isfinite(nsv)));
+                    nonfinite += !isfinite(nsv);
                 }
             }
         }
@@ -737,12 +737,11 @@ __device__ __forceinline__ void march_tile(const AdvArgs& a, const TileJob& tj,
                 bstore(plane_rsrc((double*)a.out[1] + gplane, wbytes64), woff64, nv);
                 bstore(plane_rsrc((double*)a.out[2] + gplane, wbytes64), woff64, nw);
                 if constexpr (BUD) {
-                    // Per-lane sums over the march (one level k per lane): the
-                    // level's weights (rhon dz, rho dzn, -dz/4) multiply once at
-                    // the end, and non-finite values are counted per wave.
-                    // Every lane sums (whether a lane stores is fixed for the
-                    // march); one that stores nothing drops its sums at the
-                    // end.  The Courant number keeps the largest |u|, |v|,
+                    // Per-lane sums and non-finite counts over the march (one
+                    // level k per lane): the level's weights (rhon dz, rho
+                    // dzn, -dz/4) multiply once at the end.  Every lane sums
+                    // and counts (whether a lane stores is fixed for the
+                    // march); one that stores nothing drops them at the end.  The Courant number keeps the largest |u|, |v|,
                     // |w| and scales them at the end: scaling by a positive
                     // factor is monotone, so the maximum is the same.
                     const double ucd = (double)U[1], umd = (double)U[0];
@@ -761,9 +760,7 @@ __device__ __forceinline__ void march_tile(const AdvArgs& a, const TileJob& tj,
                     amax[0] = fmax(amax[0], fabs(ucd));
                     amax[1] = fmax(amax[1], fabs(vcd));
                     amax[2] = fmax(amax[2], fabs(wcd));
-                    nonfinite += __popcll(__ballot(store && !isfinite(nu))) +
-                                 __popcll(__ballot(store && !isfinite(nv))) +
-                                 __popcll(__ballot(store && !isfinite(nw)));
+                    nonfinite += !isfinite(nu) + !isfinite(nv) + !isfinite(nw);
                 }
             }
         }
@@ -827,7 +824,7 @@ __device__ __forceinline__ void march_tile(const AdvArgs& a, const TileJob& tj,
 
     if constexpr (BUD) {
         // the level's weights in FP64 from the profiles (the level table may
-        // be FP32), the wave's count (lane 0)
+        // be FP32), the lane's count
         {
             if (!store) {
 #pragma unroll
@@ -868,7 +865,7 @@ __device__ __forceinline__ void march_tile(const AdvArgs& a, const TileJob& tj,
                         fmax(fmax(amax[0] * cdx, amax[1] * cdy), amax[2] * dt * rz);
             }
             (void)rdzn;
-            acc[MONC_B_NONFINITE] = lane == 0 ? (double)nonfinite : 0.0;
+            acc[MONC_B_NONFINITE] = store ? (double)nonfinite : 0.0;
         }
         // block reduction in a fixed order, reusing the LDS
         __syncthreads();
