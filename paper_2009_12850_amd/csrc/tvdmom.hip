@@ -22,13 +22,11 @@
 // upwind value.  tvd_flux takes any flux-like advecting quantity a with its
 // own dt/spacing factor, so the w faces pass the mass flux itself.
 //
-// One thread per grid point of a column's 64-level chunk.  A workgroup is
-// two columns along y, one wave per column and chunk (every chunk of those
-// columns), that march together through a segment of x-planes: the x-stencil
-// of each column stays in a four-plane register window, the east face of a
-// plane is the next plane's west face, and the north face of a column is
-// handed to the next column's wave through LDS, so a lateral face is
-// evaluated once (the faces on segment and workgroup edges twice).  A level
+// One thread per grid point of a column's 64-level chunk.  A workgroup is one
+// column, one wave per chunk, marching through a segment of x-planes: the
+// x-stencil stays in a four-plane register window and the east face of a
+// plane is the next plane's west face, so an x-face is evaluated once (twice
+// on segment edges); a wave evaluates both y-faces of its column.  A level
 // evaluates its top z-faces; its bottom faces are the top faces of the level
 // below, from the lane below, or across a chunk boundary from the chunk
 // below's last lane through LDS; only the lowest level evaluates the w face at
@@ -42,7 +40,6 @@ namespace monc {
 
 namespace {
 
-constexpr int TM_TJ = 2;   // columns per workgroup, along y
 constexpr int TM_TI = 64;  // x-planes per segment
 constexpr int TM_NCH = 2;  // 64-level chunks per column at most
 // Level table: levels -1 .. nz (entry q + 1 for level q).
@@ -69,41 +66,36 @@ __global__ void tvdmom_clear(double* cmax) {
     if (threadIdx.x == 0) cmax[0] = 0.0;
 }
 
-// Two waves per SIMD: the march holds about 195 registers without spilling.
-// A three-wave ceiling (168) spills 8-10 of them and ran 10-17 % slower.
-// Four columns per workgroup (eight waves, one workgroup per CU) ran 17 %
-// slower than two.
+// Two waves per SIMD: the march holds about 230 registers without spilling.
+// Columns that share their y-faces through LDS (two or four per workgroup,
+// one barrier per plane) ran 5 and 22 % slower: the exchange and the waves
+// left waiting at the barrier cost more than the faces it saves.
 template <bool STEPF>
-__global__ void __launch_bounds__(64 * TM_TJ * TM_NCH) tvdmom_kernel(TvdMomArgs A) {
+__global__ void __launch_bounds__(64 * TM_NCH) tvdmom_kernel(TvdMomArgs A) {
     __shared__ double tab[L_N][TM_LEV];
-    __shared__ double north[2][TM_NCH][TM_TJ][3][64];  // by plane parity
-    __shared__ double zlast[2][TM_NCH][TM_TJ][3];     // top faces of a chunk's last level
+    __shared__ double zlast[2][TM_NCH][3];  // top faces of a chunk's last level, by plane parity
     const int nx = A.nx, ny = A.ny, nz = A.nz;
     // Consecutive workgroups go to the same XCD (they are dealt to the 8 XCDs
-    // round-robin); neighbouring column groups of one segment are consecutive,
-    // so the columns they share are still in that XCD's L2.
+    // round-robin); neighbouring columns of one segment are consecutive, so
+    // the columns they share are still in that XCD's L2.
     int b = blockIdx.x;
     const int nb = gridDim.x;
     if ((nb & 7) == 0) b = (b & 7) * (nb >> 3) + (b >> 3);
-    const int njt = (ny + TM_TJ - 1) / TM_TJ;
-    const int jt = b % njt;
-    const int seg = b / njt;
-    const int wv = (int)threadIdx.y % TM_TJ;  // column in the workgroup
-    const int chunk = (int)threadIdx.y / TM_TJ;
+    const int j = b % ny;
+    const int seg = b / ny;
+    const int chunk = (int)threadIdx.y;
     const int lane = (int)threadIdx.x;
     const int k0 = 64 * chunk;
     const int k = k0 + lane;
-    const int j = __builtin_amdgcn_readfirstlane(TM_TJ * jt + wv);
     const int i0 = TM_TI * seg;
     const int i1 = min(i0 + TM_TI, nx);
-    const bool live = k < nz && j < ny;
+    const bool live = k < nz;
     const int kc = k < nz ? k : nz - 1;  // dead lanes load in bounds, store nothing
-    const int jc = j < ny ? j : ny - 1;
+    const int jc = j;
 
     // level table (one division set per level per workgroup)
     {
-        const int t = (int)threadIdx.y * 64 + lane;
-        if (t < nz + 2) {
+        for (int t = (int)threadIdx.y * 64 + lane; t < nz + 2; t += 64 * (int)blockDim.y) {
             const int q = t - 1;
             double row[L_N];
             for (int e = 0; e < L_N; e++) row[e] = 0.0;
@@ -242,30 +234,23 @@ __global__ void __launch_bounds__(64 * TM_TJ * TM_NCH) tvdmom_kernel(TvdMomArgs 
         const double fe_u = tvd_flux(a_ue, xu[0], u0, xu[2], xu[3], cdx, rfx, rhon_k);
         const double fe_v = tvd_flux(a_ve, xv[0], v0, xv[2], xv[3], cdx, rfx, rhon_k);
         const double fe_w = tvd_flux(m_we, xw[0], w0, xw[2], xw[3], cwx, rwx, 1.0);
-        // ---- north faces (the next column's south faces) ----
+        // ---- north faces ----
         const double a_un = 0.5 * (v0 + xv[2]), a_vn = 0.5 * (v0 + vyp1);
         const double m_wn = alpha * v0 + beta * vzp1;
         const double fn_u = tvd_flux(a_un, uym1, u0, uyp1, uyp2, cdy, rfy, rhon_k);
         const double fn_v = tvd_flux(a_vn, vym1, v0, vyp1, vyp2, cdy, rfy, rhon_k);
         const double fn_w = tvd_flux(m_wn, wym1, w0, wyp1, wyp2, cwy, rwy, 1.0);
-        const int par = i & 1;
-        north[par][chunk][wv][0][lane] = fn_u;
-        north[par][chunk][wv][1][lane] = fn_v;
-        north[par][chunk][wv][2][lane] = fn_w;
-        // ---- south faces: evaluated by the first column of the workgroup ----
-        double fs_u = 0.0, fs_v = 0.0, fs_w = 0.0;
-        if (wv == 0) {
-            const double uym2 = U[p0 + ojm2 + kc], vym2 = V[p0 + ojm2 + kc];
-            const double wym2 = wlev ? W[p0 + ojm2 + kc] : 0.0;
-            const double v_xp1ym1 = V[pp1 + ojm1 + kc];
-            const double v_ym1zp1 = above(vym1, V, p0 + ojm1, 1, zp1);
-            const double a_us = 0.5 * (vym1 + v_xp1ym1), a_vs = 0.5 * (vym1 + v0);
-            const double m_ws = alpha * vym1 + beta * v_ym1zp1;
-            fs_u = tvd_flux(a_us, uym2, uym1, u0, uyp1, cdy, rfy, rhon_k);
-            fs_v = tvd_flux(a_vs, vym2, vym1, v0, vyp1, cdy, rfy, rhon_k);
-            fs_w = tvd_flux(m_ws, wym2, wym1, w0, wyp1, cwy, rwy, 1.0);
-            cm = fmax(cm, fmax(fmax(fabs(a_us), fabs(a_vs)) * cdy, wlev ? fabs(m_ws) * cwy : 0.0));
-        }
+        // ---- south faces (the previous column's north faces, evaluated the
+        // same way) ----
+        const double uym2 = U[p0 + ojm2 + kc], vym2 = V[p0 + ojm2 + kc];
+        const double wym2 = wlev ? W[p0 + ojm2 + kc] : 0.0;
+        const double v_xp1ym1 = V[pp1 + ojm1 + kc];
+        const double v_ym1zp1 = above(vym1, V, p0 + ojm1, 1, zp1);
+        const double a_us = 0.5 * (vym1 + v_xp1ym1), a_vs = 0.5 * (vym1 + v0);
+        const double m_ws = alpha * vym1 + beta * v_ym1zp1;
+        const double fs_u = tvd_flux(a_us, uym2, uym1, u0, uyp1, cdy, rfy, rhon_k);
+        const double fs_v = tvd_flux(a_vs, vym2, vym1, v0, vyp1, cdy, rfy, rhon_k);
+        const double fs_w = tvd_flux(m_ws, wym2, wym1, w0, wyp1, cwy, rwy, 1.0);
         // ---- z faces: top k+1/2 of u, v and the centre k+1 of w; the bottom
         // faces are the top faces of the level below ----
         const double a_ut = 0.5 * (w0 + xw[2]), a_vt = 0.5 * (w0 + wyp1);
@@ -292,25 +277,21 @@ __global__ void __launch_bounds__(64 * TM_TJ * TM_NCH) tvdmom_kernel(TvdMomArgs 
             }
         }
         // a chunk's last level hands its top faces to the next chunk's first
+        const int par = i & 1;
         if (lane == 63) {
-            zlast[par][chunk][wv][0] = ft_u;
-            zlast[par][chunk][wv][1] = ft_v;
-            zlast[par][chunk][wv][2] = ft_w;
+            zlast[par][chunk][0] = ft_u;
+            zlast[par][chunk][1] = ft_v;
+            zlast[par][chunk][2] = ft_w;
         }
 
-        // The north faces of this plane are in LDS.  They are double-buffered
-        // by plane parity: a wave writes the other buffer next, and cannot
-        // reach the plane after that before every wave has passed this barrier.
+        // The handed faces are double-buffered by plane parity: a wave writes
+        // the other buffer next, and cannot reach the plane after that before
+        // every wave has passed this barrier.
         __syncthreads();
-        if (wv > 0) {
-            fs_u = north[par][chunk][wv - 1][0][lane];
-            fs_v = north[par][chunk][wv - 1][1][lane];
-            fs_w = north[par][chunk][wv - 1][2][lane];
-        }
         if (chunk > 0 && lane == 0) {
-            fb_u = zlast[par][chunk - 1][wv][0];
-            fb_v = zlast[par][chunk - 1][wv][1];
-            fb_w = zlast[par][chunk - 1][wv][2];
+            fb_u = zlast[par][chunk - 1][0];
+            fb_v = zlast[par][chunk - 1][1];
+            fb_w = zlast[par][chunk - 1][2];
         }
 
         const double su =
@@ -333,6 +314,7 @@ __global__ void __launch_bounds__(64 * TM_TJ * TM_NCH) tvdmom_kernel(TvdMomArgs 
             }
         }
         if (A.cmax) {
+            // a south face is the previous column's north face, counted there
             cm = fmax(cm, fmax(fmax(fabs(a_ue), fabs(a_ve)) * cdx,
                                fmax(fabs(a_un), fabs(a_vn)) * cdy));
             // a bottom face is the top face of the level below, counted there;
@@ -357,7 +339,8 @@ __global__ void __launch_bounds__(64 * TM_TJ * TM_NCH) tvdmom_kernel(TvdMomArgs 
 
     if (A.cmax) {
         // largest Courant number of the faces this wave evaluated; every face
-        // of a live point is evaluated by some wave of its workgroup
+        // of a live point is evaluated by its wave (a bottom face as the top
+        // face of the level below)
         if (!live) cm = 0.0;
         for (int o = 32; o > 0; o >>= 1) cm = fmax(cm, __shfl_xor(cm, o, 64));
         // Non-negative doubles order like their bit patterns.  The atomic is
@@ -382,12 +365,12 @@ hipError_t launch_tvd_momentum(const TvdMomArgs& a, bool step, hipStream_t s) {
     }
     const int nch = (a.nz + 63) / 64;
     if (nch > TM_NCH) return hipErrorInvalidValue;
-    const long nb = (long)((a.ny + TM_TJ - 1) / TM_TJ) * ((a.nx + TM_TI - 1) / TM_TI);
+    const long nb = (long)a.ny * ((a.nx + TM_TI - 1) / TM_TI);
     if (nb > 0x7fffffffL) return hipErrorInvalidValue;
     if (step)
-        tvdmom_kernel<true><<<(unsigned)nb, dim3(64, TM_TJ * nch), 0, s>>>(a);
+        tvdmom_kernel<true><<<(unsigned)nb, dim3(64, nch), 0, s>>>(a);
     else
-        tvdmom_kernel<false><<<(unsigned)nb, dim3(64, TM_TJ * nch), 0, s>>>(a);
+        tvdmom_kernel<false><<<(unsigned)nb, dim3(64, nch), 0, s>>>(a);
     return hipGetLastError();
 }
 
