@@ -91,7 +91,6 @@ __global__ void __launch_bounds__(64 * TM_NCH) tvdmom_kernel(TvdMomArgs A) {
     const int i1 = min(i0 + TM_TI, nx);
     const bool live = k < nz;
     const int kc = k < nz ? k : nz - 1;  // dead lanes load in bounds, store nothing
-    const int jc = j;
 
     // level table (one division set per level per workgroup)
     {
@@ -131,8 +130,8 @@ __global__ void __launch_bounds__(64 * TM_NCH) tvdmom_kernel(TvdMomArgs A) {
     const long sx = (long)(ny + 4) * nz;
     auto px = [&](int ii) -> long { return (long)(wrap(ii, nx) + 2) * sx; };
     auto oy = [&](int jj) -> long { return (long)(wrap(jj, ny) + 2) * nz; };
-    const long oj = oy(jc), ojm1 = oy(jc - 1), ojm2 = oy(jc - 2), ojp1 = oy(jc + 1),
-               ojp2 = oy(jc + 2);
+    const long oj = oy(j), ojm1 = oy(j - 1), ojm2 = oy(j - 2), ojp1 = oy(j + 1),
+               ojp2 = oy(j + 2);
 
     // A value of this column (or of a neighbouring one) at level k - d or
     // k + d of the same plane: the lane d below or above holds it; the lanes
@@ -338,9 +337,10 @@ __global__ void __launch_bounds__(64 * TM_NCH) tvdmom_kernel(TvdMomArgs A) {
     }
 
     if (A.cmax) {
-        // largest Courant number of the faces this wave evaluated; every face
-        // of a live point is evaluated by its wave (a bottom face as the top
-        // face of the level below)
+        // largest Courant number of the faces this wave counted; every face
+        // of a live point is counted by some wave (a south face as the
+        // previous column's north face, a bottom face as the top face of the
+        // level below)
         if (!live) cm = 0.0;
         for (int o = 32; o > 0; o >>= 1) cm = fmax(cm, __shfl_xor(cm, o, 64));
         // Non-negative doubles order like their bit patterns.  The atomic is
