@@ -741,9 +741,10 @@ __device__ __forceinline__ void march_tile(const AdvArgs& a, const TileJob& tj,
                     // level k per lane): the level's weights (rhon dz, rho
                     // dzn, -dz/4) multiply once at the end.  Every lane sums
                     // and counts (whether a lane stores is fixed for the
-                    // march); one that stores nothing drops them at the end.  The Courant number keeps the largest |u|, |v|,
-                    // |w| and scales them at the end: scaling by a positive
-                    // factor is monotone, so the maximum is the same.
+                    // march); one that stores nothing drops them at the end.
+                    // The Courant number keeps the largest |u|, |v|, |w| and
+                    // scales them at the end: scaling by a positive factor is
+                    // monotone, so the maximum is the same.
                     const double ucd = (double)U[1], umd = (double)U[0];
                     const double vcd = (double)V[1], vsd = (double)vs;
                     const double wcd = (double)W[1], wbd = (double)wb;
